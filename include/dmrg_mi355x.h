@@ -1,0 +1,163 @@
+/*
+ * dmrg_mi355x: two-site DMRG effective-Hamiltonian path for MI355X (gfx950).
+ *
+ * The DMRG node of the paper maps active-space integrals (h_act, B^Q_act) to a
+ * converged matrix-product state (Sec. II.C); its sweep is a two-site solve of
+ * the effective Hamiltonian with a matrix-free Davidson against an MPO, followed
+ * by SVD decimation to the bond dimension and a discarded weight
+ * tau = sum of squared discarded singular values (Sec. II.H, Fig. 2).  The
+ * two-electron integrals enter through Cholesky vectors,
+ * (pq|rs) = sum_Q B^Q_pq B^Q_rs (Sec. II.A).  The active space is
+ * (N_el, n_act) in the sector with fixed particle number and S_z (Sec. II.F).
+ *
+ * Conventions for every call:
+ *  - Host pointers are borrowed for the duration of the call and copied.
+ *  - Device pointers must be on the solver's device; work is ordered on the
+ *    stream given at solver creation (a hipStream_t, may be NULL = default).
+ *    Calls that return host values synchronise that stream.
+ *  - Matrices are row-major, double precision.
+ *  - Every function returns a dmrg_status; on failure dmrg_last_error() gives
+ *    a message (thread-local, valid until the next call on the thread).  No
+ *    C++ exception crosses this boundary.
+ *  - One solver per thread; a solver must not be used concurrently.
+ *
+ * Storage of block-sparse tensors (quantum numbers (N, 2 S_z)):
+ *  - A bond is a list of sectors (N, 2Sz, dim) sorted ascending by (N, 2Sz).
+ *  - Site states s = 0..3 are |0>, |alpha>, |beta>, |alpha beta> with quantum
+ *    numbers (0,0), (1,+1), (1,-1), (2,0); spin orbitals are ordered
+ *    0a,0b,1a,1b,... (the Jordan-Wigner order of the MPS).
+ *  - A three-leg tensor (site tensor: 4 physical states; two-site vector at
+ *    sites (k, k+1): 16 states s = 4 s1 + s2) is stored slab by slab: for each
+ *    left sector in bond order, a row-major m_left x W matrix whose column
+ *    ranges are the blocks of the physical states in order whose right sector
+ *    (left QN + state QN) exists, each m_right wide.
+ */
+#ifndef DMRG_MI355X_H
+#define DMRG_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dmrg_problem dmrg_problem; /* opaque */
+typedef struct dmrg_solver dmrg_solver;   /* opaque */
+
+typedef enum {
+  DMRG_OK = 0,
+  DMRG_EINVAL = -1,   /* invalid argument (non-symmetric h or B, bad sizes, ...) */
+  DMRG_ENOMEM = -2,   /* device allocation failed */
+  DMRG_EHIP = -3,     /* HIP / ROCm library failure */
+  DMRG_ENOCONV = -4,  /* Davidson did not reach the tolerance (outputs still filled) */
+  DMRG_ESECTOR = -5,  /* empty or inconsistent quantum-number sector */
+  DMRG_ESTATE = -6    /* call out of order (e.g. no MPS / step not prepared) */
+} dmrg_status;
+
+typedef enum { DMRG_FP64 = 0, DMRG_FP32 = 1, DMRG_BF16 = 2 } dmrg_precision;
+typedef enum { DMRG_PRECOND_DIAG = 0, DMRG_PRECOND_LEARNED = 1 } dmrg_precond;
+
+typedef struct {
+  int M;               /* bond dimension (kept states per bond) */
+  int n_states;        /* roots, state-averaged when > 1 (1..8) */
+  const double* weights; /* n_states state-averaging weights, NULL = equal */
+  double davidson_tol; /* ||H_eff x - theta x||_2 per root, with ||x|| = 1 */
+  int max_iter;        /* Davidson iterations per step */
+  int max_subspace;    /* Davidson subspace size (<= 64) */
+  int precision;       /* dmrg_precision of the sigma products in Davidson */
+  int precond;         /* dmrg_precond */
+  unsigned long long seed; /* initial MPS and extra-root start vectors */
+  double tie_rtol;     /* truncation never splits singular values closer than tie_rtol * s_1 */
+  double cut_rtol;     /* singular values <= cut_rtol * s_1 are always dropped */
+  int verbose;         /* 0 quiet, 1 per step, 2 per Davidson iteration (stderr) */
+} dmrg_options;
+
+/* Fills *o with defaults: M=256, 1 state, tol 1e-10, 200 iterations, subspace
+ * 32, FP64, diagonal preconditioner, seed 1, tie_rtol 1e-10, cut_rtol 1e-14. */
+void dmrg_options_default(dmrg_options* o);
+
+/* Active-space problem (Sec. II.A): n_orb spatial orbitals, n_alpha / n_beta
+ * electrons (S_z = (n_alpha - n_beta)/2), h[n_orb*n_orb] one-electron integrals,
+ * B[n_chol*n_orb*n_orb] Cholesky vectors B^Q_pq (row-major over Q, p, q),
+ * e_core a constant added to energies.  h and every B^Q must be symmetric to
+ * 1e-12 (else DMRG_EINVAL).  Builds the Cholesky-channel MPO on the host. */
+dmrg_status dmrg_problem_create(int n_orb, int n_alpha, int n_beta, int n_chol, const double* h,
+                                const double* B, double e_core, dmrg_problem** out);
+void dmrg_problem_destroy(dmrg_problem* p);
+
+/* MPO inspection (host only, no GPU needed).  dims[0..n_orb] receives the MPO
+ * bond dimension of every cut.  dmrg_mpo_site_nnz gives the number of entries
+ * W_k[a][b] = c * O (O a 4x4 site operator); dmrg_mpo_site copies them out:
+ * a[i], b[i] channel indices at cuts k and k+1, c[i] coefficient, op[16*i..]
+ * the row-major 4x4 operator <s|O|s'>.  Caller-owned arrays of nnz entries. */
+dmrg_status dmrg_mpo_dims(const dmrg_problem* p, int* dims);
+dmrg_status dmrg_mpo_site_nnz(const dmrg_problem* p, int site, int* nnz);
+dmrg_status dmrg_mpo_site(const dmrg_problem* p, int site, int* a, int* b, double* c, double* op);
+
+/* Solver on the current device.  Allocates its device memory (environments,
+ * MPS, Davidson basis) and initialises a seeded right-canonical random MPS. */
+dmrg_status dmrg_solver_create(const dmrg_problem* p, const dmrg_options* o, void* hip_stream,
+                               dmrg_solver** out);
+void dmrg_solver_destroy(dmrg_solver* s);
+
+/* Replace the MPS.  n_sec[c] (c = 0..n_orb) sectors per bond, concatenated
+ * sector tables sec[3*i] = N, sec[3*i+1] = 2Sz, sec[3*i+2] = dim; data = all
+ * site tensors concatenated in the slab layout (host, double).  Bond 0 must be
+ * the single vacuum sector, bond n_orb the single target sector. */
+dmrg_status dmrg_set_mps(dmrg_solver* s, const int* n_sec, const int* sec, const double* data);
+
+/* Current bond tables: n_sec[0..n_orb] and up to cap sector triples. */
+dmrg_status dmrg_get_bonds(const dmrg_solver* s, int* n_sec, int* sec, int cap);
+
+/* Environments and plan for the two-site step on sites (k, k+1) of the current
+ * MPS (any gauge); *n receives the two-site vector length. */
+dmrg_status dmrg_prepare(dmrg_solver* s, int k, int64_t* n);
+
+/* sigma = H_eff psi for the prepared step k (the effective Hamiltonian excludes
+ * e_core).  psi, sigma: device arrays of the two-site length, slab layout.
+ * precision: DMRG_FP64 (fp64 MFMA), DMRG_FP32 (fp32 MFMA) or DMRG_BF16 (bf16
+ * inputs, fp32 accumulation); the output is always fp64.  If flops is not NULL
+ * it receives the useful (unpadded) floating-point operation count. */
+dmrg_status dmrg_sigma(dmrg_solver* s, int k, int precision, const double* psi, double* sigma,
+                       double* flops);
+
+/* Diagonal of H_eff of the prepared step k into a device array. */
+dmrg_status dmrg_diag(dmrg_solver* s, int k, double* diag);
+
+/* Two-site sweeps (left-to-right then right-to-left, (n_orb-1) steps each).
+ * energies[n_states] (host): final Davidson Ritz values + e_core; tau: the
+ * largest discarded weight of the last sweep.  DMRG_ENOCONV if a step did not
+ * reach the tolerance (results still written). */
+dmrg_status dmrg_sweep(dmrg_solver* s, int n_sweeps, double* energies, double* tau);
+
+/* <Psi|H|Psi>/<Psi|Psi> + e_core of the current MPS (per root after a sweep). */
+dmrg_status dmrg_energy(dmrg_solver* s, double* energies);
+
+/* Diagnostic export of an environment of the current MPS: side 0 = left block
+ * (sites < cut), 1 = right block (sites >= cut).  Copies min(cap, size) doubles
+ * of the channel arrays (channels grouped by quantum-number shift, each a list
+ * of dense row-major blocks) to host and writes the full size to *size. */
+dmrg_status dmrg_get_env(dmrg_solver* s, int cut, int side, double* host, int64_t cap, int64_t* size);
+
+/* The block-GEMM engine on one block, for tests: C (M x N, ldc) = coef * op(A) op(B)
+ * on the given stream.  mode 0: A M x K, B K x N; 1: A M x K, B N x K (B^T);
+ * 2: A K x M (A^T), B K x N; all row-major device arrays.  precision
+ * DMRG_FP64: double A, B, C; DMRG_FP32: float A, B, C; DMRG_BF16: bf16 bit
+ * patterns (uint16) A, B, float C (modes 0 and 1). */
+dmrg_status dmrg_block_gemm(int precision, int mode, int M, int N, int K, const void* A, int lda,
+                            const void* B, int ldb, void* C, int ldc, double coef, void* hip_stream);
+
+/* Run statistics (host doubles): [0] matvecs, [1] Davidson iterations,
+ * [2] sigma ms, [3] env-update ms, [4] SVD ms, [5] sigma flops, [6] tau,
+ * [7] max bond dimension, [8] preconditioner fallbacks, [9] converged (0/1).
+ * n: capacity of out. */
+dmrg_status dmrg_get_stats(const dmrg_solver* s, double* out, int n);
+
+const char* dmrg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DMRG_MI355X_H */

@@ -1,0 +1,36 @@
+"""Thin Python binding of libdmrg_mi355x (the two-site DMRG sigma path on MI355X).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  PyTorch (when used) provides device memory and the stream; it is
+imported before the library so both share one HIP runtime.  There is no CPU
+fallback: if the shared library is missing, importing this package raises.
+"""
+from ._lib import (  # noqa: F401
+    DMRGError,
+    LIB_PATH,
+    Problem,
+    Solver,
+    dmrg_block_gemm,
+    dmrg_diag,
+    dmrg_energy,
+    dmrg_get_bonds,
+    dmrg_get_env,
+    dmrg_get_stats,
+    dmrg_last_error,
+    dmrg_mpo_dims,
+    dmrg_mpo_site,
+    dmrg_mpo_site_nnz,
+    dmrg_options,
+    dmrg_options_default,
+    dmrg_prepare,
+    dmrg_problem_create,
+    dmrg_problem_destroy,
+    dmrg_set_mps,
+    dmrg_sigma,
+    dmrg_solver_create,
+    dmrg_solver_destroy,
+    dmrg_sweep,
+    lib,
+)
+
+FP64, FP32, BF16 = 0, 1, 2

@@ -1,0 +1,197 @@
+"""ctypes declarations of include/dmrg_mi355x.h and small owning wrappers."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+try:  # torch first: the library then binds to the HIP runtime torch already loaded
+    import torch  # noqa: F401
+except Exception:  # pragma: no cover - torch is optional for host-only use
+    torch = None
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdmrg_mi355x.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2609_09990_amd.build` "
+                      "(there is no CPU fallback)")
+lib = C.CDLL(LIB_PATH)
+
+_p, _i, _d, _i64 = C.c_void_p, C.c_int, C.c_double, C.c_int64
+
+
+class dmrg_options(C.Structure):
+    _fields_ = [("M", C.c_int), ("n_states", C.c_int), ("weights", C.POINTER(C.c_double)),
+                ("davidson_tol", C.c_double), ("max_iter", C.c_int), ("max_subspace", C.c_int),
+                ("precision", C.c_int), ("precond", C.c_int), ("seed", C.c_ulonglong),
+                ("tie_rtol", C.c_double), ("cut_rtol", C.c_double), ("verbose", C.c_int)]
+
+
+def _decl(name, args, res=C.c_int):
+    f = getattr(lib, name)
+    f.argtypes = args
+    f.restype = res
+    return f
+
+
+dmrg_options_default = _decl("dmrg_options_default", [C.POINTER(dmrg_options)], None)
+dmrg_problem_create = _decl("dmrg_problem_create", [_i, _i, _i, _i, _p, _p, _d, C.POINTER(_p)])
+dmrg_problem_destroy = _decl("dmrg_problem_destroy", [_p], None)
+dmrg_mpo_dims = _decl("dmrg_mpo_dims", [_p, _p])
+dmrg_mpo_site_nnz = _decl("dmrg_mpo_site_nnz", [_p, _i, C.POINTER(_i)])
+dmrg_mpo_site = _decl("dmrg_mpo_site", [_p, _i, _p, _p, _p, _p])
+dmrg_solver_create = _decl("dmrg_solver_create", [_p, C.POINTER(dmrg_options), _p, C.POINTER(_p)])
+dmrg_solver_destroy = _decl("dmrg_solver_destroy", [_p], None)
+dmrg_set_mps = _decl("dmrg_set_mps", [_p, _p, _p, _p])
+dmrg_get_bonds = _decl("dmrg_get_bonds", [_p, _p, _p, _i])
+dmrg_prepare = _decl("dmrg_prepare", [_p, _i, C.POINTER(_i64)])
+dmrg_sigma = _decl("dmrg_sigma", [_p, _i, _i, _p, _p, C.POINTER(_d)])
+dmrg_diag = _decl("dmrg_diag", [_p, _i, _p])
+dmrg_sweep = _decl("dmrg_sweep", [_p, _i, _p, C.POINTER(_d)])
+dmrg_energy = _decl("dmrg_energy", [_p, _p])
+dmrg_get_stats = _decl("dmrg_get_stats", [_p, _p, _i])
+dmrg_block_gemm = _decl("dmrg_block_gemm", [_i, _i, _i, _i, _i, _p, _i, _p, _i, _p, _i, _d, _p])
+dmrg_get_env = _decl("dmrg_get_env", [_p, _i, _i, _p, _i64, C.POINTER(_i64)])
+dmrg_last_error = _decl("dmrg_last_error", [], C.c_char_p)
+
+STATUS = {0: "DMRG_OK", -1: "DMRG_EINVAL", -2: "DMRG_ENOMEM", -3: "DMRG_EHIP", -4: "DMRG_ENOCONV",
+          -5: "DMRG_ESECTOR", -6: "DMRG_ESTATE"}
+
+
+class DMRGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(code):
+    if code != 0:
+        raise DMRGError(code, (dmrg_last_error() or b"").decode())
+
+
+def _ptr(a):
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data_as(C.c_void_p)
+    return C.c_void_p(a.data_ptr())  # torch tensor
+
+
+class Problem:
+    """dmrg_problem: active-space integrals and the MPO built from them (host)."""
+
+    def __init__(self, h, B, n_alpha, n_beta, e_core=0.0):
+        h = np.ascontiguousarray(h, dtype=np.float64)
+        B = np.ascontiguousarray(B, dtype=np.float64)
+        n = h.shape[0]
+        nq = B.shape[0] if B.ndim == 3 else 0
+        self.n, self.n_alpha, self.n_beta, self.n_chol = n, n_alpha, n_beta, nq
+        self._keep = (h, B)
+        self.h = C.c_void_p()
+        _check(dmrg_problem_create(n, n_alpha, n_beta, nq, _ptr(h), _ptr(B), float(e_core),
+                                   C.byref(self.h)))
+
+    def mpo_dims(self):
+        d = np.zeros(self.n + 1, dtype=np.int32)
+        _check(dmrg_mpo_dims(self.h, _ptr(d)))
+        return d
+
+    def mpo_site(self, k):
+        nnz = C.c_int()
+        _check(dmrg_mpo_site_nnz(self.h, k, C.byref(nnz)))
+        m = nnz.value
+        a = np.zeros(m, np.int32)
+        b = np.zeros(m, np.int32)
+        c = np.zeros(m)
+        op = np.zeros((m, 16))
+        _check(dmrg_mpo_site(self.h, k, _ptr(a), _ptr(b), _ptr(c), _ptr(op)))
+        return a, b, c, op.reshape(m, 4, 4)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            dmrg_problem_destroy(self.h)
+            self.h = None
+
+
+class Solver:
+    """dmrg_solver on the current device; device arrays are torch tensors."""
+
+    def __init__(self, problem: Problem, M=256, n_states=1, weights=None, tol=1e-10, max_iter=200,
+                 max_subspace=32, precision=0, precond=0, seed=1, tie_rtol=1e-10, cut_rtol=1e-14,
+                 verbose=0, stream=None):
+        o = dmrg_options()
+        dmrg_options_default(C.byref(o))
+        o.M, o.n_states, o.davidson_tol, o.max_iter = M, n_states, tol, max_iter
+        o.max_subspace, o.precision, o.precond, o.seed = max_subspace, precision, precond, seed
+        o.tie_rtol, o.cut_rtol, o.verbose = tie_rtol, cut_rtol, verbose
+        self._w = None
+        if weights is not None:
+            self._w = np.ascontiguousarray(weights, dtype=np.float64)
+            o.weights = self._w.ctypes.data_as(C.POINTER(C.c_double))
+        if stream is None and torch is not None and torch.cuda.is_available():
+            stream = torch.cuda.current_stream().cuda_stream
+        self.problem = problem
+        self.n_states = n_states
+        self.h = C.c_void_p()
+        _check(dmrg_solver_create(problem.h, C.byref(o), C.c_void_p(stream or 0), C.byref(self.h)))
+
+    def set_mps(self, bonds, sites):
+        n_sec = np.array([len(b) for b in bonds], dtype=np.int32)
+        sec = np.array([x for b in bonds for s in b for x in s], dtype=np.int32)
+        data = np.ascontiguousarray(np.concatenate(sites), dtype=np.float64)
+        _check(dmrg_set_mps(self.h, _ptr(n_sec), _ptr(sec), _ptr(data)))
+
+    def bonds(self):
+        n_sec = np.zeros(self.problem.n + 1, dtype=np.int32)
+        cap = 1 << 16
+        sec = np.zeros(3 * cap, dtype=np.int32)
+        _check(dmrg_get_bonds(self.h, _ptr(n_sec), _ptr(sec), cap))
+        out, i = [], 0
+        for c in range(self.problem.n + 1):
+            out.append([tuple(int(v) for v in sec[3 * j:3 * j + 3]) for j in range(i, i + n_sec[c])])
+            i += n_sec[c]
+        return out
+
+    def prepare(self, k):
+        n = C.c_int64()
+        _check(dmrg_prepare(self.h, k, C.byref(n)))
+        return n.value
+
+    def sigma(self, k, psi, out, precision=0):
+        fl = C.c_double()
+        _check(dmrg_sigma(self.h, k, precision, _ptr(psi), _ptr(out), C.byref(fl)))
+        return fl.value
+
+    def diag(self, k, out):
+        _check(dmrg_diag(self.h, k, _ptr(out)))
+
+    def sweep(self, n_sweeps=1):
+        e = np.zeros(self.n_states)
+        tau = C.c_double()
+        code = dmrg_sweep(self.h, n_sweeps, _ptr(e), C.byref(tau))
+        if code not in (0, -4):
+            _check(code)
+        return e, tau.value, code == 0
+
+    def energy(self):
+        e = np.zeros(self.n_states)
+        _check(dmrg_energy(self.h, _ptr(e)))
+        return e
+
+    def env(self, cut, side):
+        """Environment arrays of the current MPS (side 0 left, 1 right), host copy."""
+        n = C.c_int64()
+        _check(dmrg_get_env(self.h, cut, side, None, 0, C.byref(n)))
+        out = np.zeros(n.value)
+        _check(dmrg_get_env(self.h, cut, side, _ptr(out), n.value, C.byref(n)))
+        return out
+
+    def stats(self):
+        s = np.zeros(10)
+        _check(dmrg_get_stats(self.h, _ptr(s), 10))
+        keys = ["matvecs", "davidson_iters", "sigma_ms", "env_ms", "svd_ms", "sigma_flops", "tau",
+                "max_bond", "fallbacks", "converged"]
+        return dict(zip(keys, s.tolist()))
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            dmrg_solver_destroy(self.h)
+            self.h = None

@@ -1,0 +1,309 @@
+// C ABI over the solver: argument checks, exception-to-status translation.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "../../include/dmrg_mi355x.h"
+#include "solver.hpp"
+
+using namespace dmrg;
+
+struct dmrg_problem {
+  Problem p;
+};
+struct dmrg_solver {
+  Solver* s = nullptr;
+  const dmrg_problem* prob = nullptr;
+};
+
+namespace {
+thread_local std::string g_err;
+
+template <class F>
+dmrg_status guard(F&& f) {
+  try {
+    g_err.clear();
+    f();
+    return DMRG_OK;
+  } catch (const Error& e) {
+    g_err = e.what();
+    return (dmrg_status)e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return DMRG_ENOMEM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return DMRG_EINVAL;
+  }
+}
+}  // namespace
+
+extern "C" {
+
+const char* dmrg_last_error(void) { return g_err.c_str(); }
+
+void dmrg_options_default(dmrg_options* o) {
+  if (!o) return;
+  o->M = 256;
+  o->n_states = 1;
+  o->weights = nullptr;
+  o->davidson_tol = 1e-10;
+  o->max_iter = 200;
+  o->max_subspace = 32;
+  o->precision = DMRG_FP64;
+  o->precond = DMRG_PRECOND_DIAG;
+  o->seed = 1;
+  o->tie_rtol = 1e-10;
+  o->cut_rtol = 1e-14;
+  o->verbose = 0;
+}
+
+dmrg_status dmrg_problem_create(int n, int na, int nb, int nq, const double* h, const double* B,
+                                double e_core, dmrg_problem** out) {
+  return guard([&] {
+    DMRG_REQUIRE(out, ST_EINVAL, "out is NULL");
+    *out = nullptr;
+    DMRG_REQUIRE(n >= 2 && n <= 64, ST_EINVAL, "n_orb must be in [2, 64]");
+    DMRG_REQUIRE(na >= 0 && nb >= 0 && na <= n && nb <= n, ST_ESECTOR, "electron counts outside [0, n_orb]");
+    DMRG_REQUIRE(nq >= 0, ST_EINVAL, "n_chol must be >= 0");
+    DMRG_REQUIRE(h && (nq == 0 || B), ST_EINVAL, "h or B is NULL");
+    for (int p = 0; p < n; ++p)
+      for (int q = 0; q < n; ++q) {
+        DMRG_REQUIRE(std::isfinite(h[p * n + q]), ST_EINVAL, "h has a non-finite entry");
+        DMRG_REQUIRE(std::fabs(h[p * n + q] - h[q * n + p]) <= 1e-12, ST_EINVAL, "h is not symmetric");
+      }
+    for (int Q = 0; Q < nq; ++Q)
+      for (int p = 0; p < n; ++p)
+        for (int q = 0; q < n; ++q) {
+          double x = B[((size_t)Q * n + p) * n + q], y = B[((size_t)Q * n + q) * n + p];
+          DMRG_REQUIRE(std::isfinite(x), ST_EINVAL, "B has a non-finite entry");
+          DMRG_REQUIRE(std::fabs(x - y) <= 1e-12, ST_EINVAL, "B^Q is not symmetric");
+        }
+    auto* P = new dmrg_problem;
+    P->p.n = n;
+    P->p.n_alpha = na;
+    P->p.n_beta = nb;
+    P->p.nq = nq;
+    P->p.e_core = e_core;
+    P->p.h.assign(h, h + (size_t)n * n);
+    if (nq) P->p.B.assign(B, B + (size_t)nq * n * n);
+    try {
+      P->p.mpo = build_mpo(n, nq, P->p.h.data(), P->p.B.data());
+    } catch (...) {
+      delete P;
+      throw;
+    }
+    *out = P;
+  });
+}
+
+void dmrg_problem_destroy(dmrg_problem* p) { delete p; }
+
+dmrg_status dmrg_mpo_dims(const dmrg_problem* p, int* dims) {
+  return guard([&] {
+    DMRG_REQUIRE(p && dims, ST_EINVAL, "NULL argument");
+    for (int c = 0; c <= p->p.n; ++c) dims[c] = p->p.mpo.dim(c);
+  });
+}
+
+dmrg_status dmrg_mpo_site_nnz(const dmrg_problem* p, int site, int* nnz) {
+  return guard([&] {
+    DMRG_REQUIRE(p && nnz, ST_EINVAL, "NULL argument");
+    DMRG_REQUIRE(site >= 0 && site < p->p.n, ST_EINVAL, "site out of range");
+    *nnz = (int)p->p.mpo.W[site].size();
+  });
+}
+
+dmrg_status dmrg_mpo_site(const dmrg_problem* p, int site, int* a, int* b, double* c, double* op) {
+  return guard([&] {
+    DMRG_REQUIRE(p && a && b && c && op, ST_EINVAL, "NULL argument");
+    DMRG_REQUIRE(site >= 0 && site < p->p.n, ST_EINVAL, "site out of range");
+    const auto& W = p->p.mpo.W[site];
+    for (size_t i = 0; i < W.size(); ++i) {
+      a[i] = W[i].a;
+      b[i] = W[i].b;
+      c[i] = W[i].c;
+      std::memcpy(op + 16 * i, p->p.mpo.ops[W[i].op].data(), 16 * sizeof(double));
+    }
+  });
+}
+
+dmrg_status dmrg_solver_create(const dmrg_problem* p, const dmrg_options* o, void* stream,
+                               dmrg_solver** out) {
+  return guard([&] {
+    DMRG_REQUIRE(p && out, ST_EINVAL, "NULL argument");
+    *out = nullptr;
+    Options op;
+    dmrg_options d;
+    dmrg_options_default(&d);
+    if (!o) o = &d;
+    op.M = o->M;
+    op.n_states = o->n_states;
+    if (o->weights) op.weights.assign(o->weights, o->weights + std::max(o->n_states, 0));
+    op.davidson_tol = o->davidson_tol;
+    op.max_iter = o->max_iter;
+    op.max_subspace = o->max_subspace;
+    op.precision = o->precision;
+    op.precond = o->precond;
+    op.seed = o->seed;
+    op.tie_rtol = o->tie_rtol;
+    op.cut_rtol = o->cut_rtol;
+    op.verbose = o->verbose;
+    DMRG_REQUIRE(op.precision >= 0 && op.precision <= 2, ST_EINVAL, "unknown precision");
+    DMRG_REQUIRE(op.davidson_tol > 0, ST_EINVAL, "davidson_tol must be positive");
+    DMRG_REQUIRE(op.max_iter >= 1, ST_EINVAL, "max_iter must be >= 1");
+    auto* S = new dmrg_solver;
+    S->prob = p;
+    try {
+      S->s = new Solver(&p->p, op, (hipStream_t)stream);
+    } catch (...) {
+      delete S;
+      throw;
+    }
+    *out = S;
+  });
+}
+
+void dmrg_solver_destroy(dmrg_solver* s) {
+  if (!s) return;
+  try {
+    delete s->s;
+  } catch (...) {
+  }
+  delete s;
+}
+
+dmrg_status dmrg_set_mps(dmrg_solver* s, const int* n_sec, const int* sec, const double* data) {
+  return guard([&] {
+    DMRG_REQUIRE(s && n_sec && sec && data, ST_EINVAL, "NULL argument");
+    int L = s->prob->p.n;
+    std::vector<Bond> bonds(L + 1);
+    long idx = 0;
+    for (int c = 0; c <= L; ++c) {
+      DMRG_REQUIRE(n_sec[c] >= 1, ST_EINVAL, "every bond needs at least one sector");
+      for (int i = 0; i < n_sec[c]; ++i, ++idx)
+        bonds[c].sec.push_back({{sec[3 * idx], sec[3 * idx + 1]}, sec[3 * idx + 2]});
+    }
+    std::vector<const double*> sites(L);
+    long off = 0;
+    for (int k = 0; k < L; ++k) {
+      sites[k] = data + off;
+      off += make_tensor_layout(bonds[k], bonds[k + 1], site_phys_qn()).size;
+    }
+    s->s->set_mps(bonds, sites);
+  });
+}
+
+dmrg_status dmrg_get_bonds(const dmrg_solver* s, int* n_sec, int* sec, int cap) {
+  return guard([&] {
+    DMRG_REQUIRE(s && n_sec && sec, ST_EINVAL, "NULL argument");
+    const auto& b = s->s->bonds();
+    int idx = 0;
+    for (size_t c = 0; c < b.size(); ++c) {
+      n_sec[c] = (int)b[c].sec.size();
+      for (auto& x : b[c].sec) {
+        DMRG_REQUIRE(idx < cap, ST_EINVAL, "sector capacity too small");
+        sec[3 * idx] = x.q.n;
+        sec[3 * idx + 1] = x.q.sz;
+        sec[3 * idx + 2] = x.dim;
+        ++idx;
+      }
+    }
+  });
+}
+
+dmrg_status dmrg_prepare(dmrg_solver* s, int k, int64_t* n) {
+  return guard([&] {
+    DMRG_REQUIRE(s, ST_EINVAL, "NULL solver");
+    s->s->prepare(k);
+    if (n) *n = s->s->twosite_size(k);
+  });
+}
+
+dmrg_status dmrg_sigma(dmrg_solver* s, int k, int precision, const double* psi, double* sigma,
+                       double* flops) {
+  return guard([&] {
+    DMRG_REQUIRE(s && psi && sigma, ST_EINVAL, "NULL argument");
+    DMRG_REQUIRE(precision >= 0 && precision <= 2, ST_EINVAL, "unknown precision");
+    s->s->sigma(k, precision, psi, sigma);
+    if (flops) *flops = s->s->last_sigma_flops();
+  });
+}
+
+dmrg_status dmrg_diag(dmrg_solver* s, int k, double* diag) {
+  return guard([&] {
+    DMRG_REQUIRE(s && diag, ST_EINVAL, "NULL argument");
+    s->s->diag(k, diag);
+    hip_check(hipDeviceSynchronize(), "diag");
+  });
+}
+
+dmrg_status dmrg_sweep(dmrg_solver* s, int n_sweeps, double* energies, double* tau) {
+  dmrg_status st = guard([&] {
+    DMRG_REQUIRE(s && energies, ST_EINVAL, "NULL argument");
+    DMRG_REQUIRE(n_sweeps >= 1, ST_EINVAL, "n_sweeps must be >= 1");
+    std::vector<double> e;
+    double t = s->s->sweep(n_sweeps, e);
+    for (size_t i = 0; i < e.size(); ++i) energies[i] = e[i];
+    if (tau) *tau = t;
+  });
+  if (st == DMRG_OK && s && !s->s->stats().converged) {
+    g_err = "Davidson did not reach the tolerance in at least one step";
+    return DMRG_ENOCONV;
+  }
+  return st;
+}
+
+dmrg_status dmrg_energy(dmrg_solver* s, double* energies) {
+  return guard([&] {
+    DMRG_REQUIRE(s && energies, ST_EINVAL, "NULL argument");
+    auto e = s->s->mps_energy();
+    for (size_t i = 0; i < e.size(); ++i) energies[i] = e[i];
+  });
+}
+
+dmrg_status dmrg_get_env(dmrg_solver* s, int cut, int side, double* host, int64_t cap, int64_t* size) {
+  return guard([&] {
+    DMRG_REQUIRE(s && size && (host || cap == 0), ST_EINVAL, "NULL argument");
+    DMRG_REQUIRE(cut >= 0 && cut <= s->prob->p.n && (side == 0 || side == 1), ST_EINVAL, "bad cut/side");
+    std::vector<double> v = s->s->env_host(cut, side);
+    *size = (int64_t)v.size();
+    std::memcpy(host, v.data(), std::min<int64_t>(cap, (int64_t)v.size()) * sizeof(double));
+  });
+}
+
+dmrg_status dmrg_block_gemm(int precision, int mode, int M, int N, int K, const void* A, int lda,
+                            const void* B, int ldb, void* C, int ldc, double coef, void* stream) {
+  return guard([&] {
+    DMRG_REQUIRE(A && B && C, ST_EINVAL, "NULL argument");
+    DMRG_REQUIRE(M > 0 && N > 0 && K > 0, ST_EINVAL, "sizes must be positive");
+    DMRG_REQUIRE(mode >= 0 && mode <= 2 && precision >= 0 && precision <= 2, ST_EINVAL, "bad mode/precision");
+    DMRG_REQUIRE(!(precision == 2 && mode == 2), ST_EINVAL, "bf16 has no transposed-A mode");
+    DMRG_REQUIRE(lda >= (mode == 2 ? M : K) && ldb >= (mode == 1 ? K : N) && ldc >= N, ST_EINVAL,
+                 "leading dimension too small");
+    hipStream_t st = (hipStream_t)stream;
+    GemmItem it{A, B, lda, ldb, K, 0, coef};
+    std::vector<GemmUnit> units;
+    for (int m0 = 0; m0 < M; m0 += 64)
+      for (int n0 = 0; n0 < N; n0 += 64) units.push_back({C, ldc, M, N, m0, n0, 0, 1, 0});
+    DevMem di, du;
+    di.reserve(sizeof(GemmItem));
+    du.reserve(units.size() * sizeof(GemmUnit));
+    hip_check(hipMemcpyAsync(di.p, &it, sizeof(GemmItem), hipMemcpyHostToDevice, st), "gemm item");
+    hip_check(hipMemcpyAsync(du.p, units.data(), units.size() * sizeof(GemmUnit), hipMemcpyHostToDevice, st), "gemm units");
+    launch_gemm(precision, mode, du.as<GemmUnit>(), (int)units.size(), di.as<GemmItem>(), st);
+    hip_check(hipStreamSynchronize(st), "gemm");
+  });
+}
+
+dmrg_status dmrg_get_stats(const dmrg_solver* s, double* out, int n) {
+  return guard([&] {
+    DMRG_REQUIRE(s && out, ST_EINVAL, "NULL argument");
+    const Stats& t = s->s->stats();
+    double v[10] = {(double)t.matvecs, (double)t.davidson_iters, t.sigma_ms, t.env_ms, t.svd_ms,
+                    t.sigma_flops, t.tau, (double)t.max_bond, (double)t.fallbacks, (double)t.converged};
+    for (int i = 0; i < n && i < 10; ++i) out[i] = v[i];
+  });
+}
+
+}  // extern "C"

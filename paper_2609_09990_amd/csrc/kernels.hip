@@ -1,0 +1,657 @@
+// gfx950 kernels for the two-site sigma path.
+//
+// The workhorse is a grouped block GEMM: every output block of sigma (or of a
+// new environment, or of an intermediate T = X psi) is owned by one workgroup
+// per 64x64 tile, which accumulates all of its block products ("items") in a
+// fixed order with MFMA (64-wide wavefronts, 4 waves per workgroup, each wave a
+// 32x32 sub-tile).  No atomics: results are bitwise reproducible.
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include "kernels.hpp"
+
+namespace dmrg {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int TM = 64, TN = 64, TK = 16, LDP = TM + 2;
+
+__device__ inline float to_f(float x) { return x; }
+__device__ inline float to_f(double x) { return (float)x; }
+__device__ inline float to_f(uint16_t x) { return __uint_as_float(((uint32_t)x) << 16); }
+__device__ inline double to_d(double x) { return x; }
+__device__ inline double to_d(float x) { return (double)x; }
+__device__ inline uint16_t f2bf(float x) {
+  // round to nearest even
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf / nan
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// Loads a 64 x 16 A tile (k-major into LDS) and a 16 x 64 B tile, scaling A by coef.
+template <int MODE, typename TA, typename TB, typename TS>
+__device__ inline void load_tiles(TS (*As)[LDP], TS (*Bs)[LDP], const TA* A, const TB* B, int lda,
+                                  int ldb, int K, int k0, int m0, int M, int n0, int N,
+                                  double coef, int tid) {
+  if (MODE == GEMM_NN || MODE == GEMM_NT) {
+    int m = tid >> 2, kq = (tid & 3) * 4;
+    int gm = m0 + m;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int k = kq + j;
+      double v = 0.0;
+      if (gm < M && k0 + k < K) v = to_d(A[(long)gm * lda + k0 + k]) * coef;
+      As[k][m] = (TS)v;
+    }
+  } else {
+    int k = tid >> 4, mq = (tid & 15) * 4;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int m = mq + j;
+      double v = 0.0;
+      if (m0 + m < M && k0 + k < K) v = to_d(A[(long)(k0 + k) * lda + m0 + m]) * coef;
+      As[k][m] = (TS)v;
+    }
+  }
+  if (MODE == GEMM_NN || MODE == GEMM_TN) {
+    int k = tid >> 4, nq = (tid & 15) * 4;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int n = nq + j;
+      TS v = (TS)0;
+      if (n0 + n < N && k0 + k < K) v = (TS)to_d(B[(long)(k0 + k) * ldb + n0 + n]);
+      Bs[k][n] = v;
+    }
+  } else {
+    int n = tid >> 2, kq = (tid & 3) * 4;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int k = kq + j;
+      TS v = (TS)0;
+      if (n0 + n < N && k0 + k < K) v = (TS)to_d(B[(long)(n0 + n) * ldb + k0 + k]);
+      Bs[k][n] = v;
+    }
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void gemm_f64(const GemmUnit* __restrict__ units,
+                                                const GemmItem* __restrict__ items) {
+  __shared__ double As[TK][LDP];
+  __shared__ double Bs[TK][LDP];
+  const GemmUnit u = units[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  v4d acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+  for (int it = u.ib; it < u.ie; ++it) {
+    const GemmItem g = items[it];
+    const double* A = (const double*)g.A;
+    const double* B = (const double*)g.B;
+    for (int k0 = 0; k0 < g.K; k0 += TK) {
+      load_tiles<MODE, double, double, double>(As, Bs, A, B, g.lda, g.ldb, g.K, k0, u.m0, u.M,
+                                               u.n0, u.N, g.coef, tid);
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < TK; kk += 4) {
+        double a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = As[kk + (lane >> 4)][wr + 16 * i + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = Bs[kk + (lane >> 4)][wc + 16 * j + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+      __syncthreads();
+    }
+  }
+  double* C = (double*)u.C;
+  // v_mfma_f64_16x16x4f64 accumulator: lane l, element r holds row l/16 + 4r,
+  // column l%16 (measured; the f32/bf16 16x16 ops hold row 4(l/16) + r instead)
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int gm = u.m0 + wr + 16 * i + (lane >> 4) + 4 * r;
+        int gn = u.n0 + wc + 16 * j + (lane & 15);
+        if (gm < u.M && gn < u.N) {
+          long idx = (long)gm * u.ldc + gn;
+          double v = acc[i][j][r];
+          C[idx] = u.accumulate ? C[idx] + v : v;
+        }
+      }
+}
+
+template <int MODE, typename TA, typename TB>
+__global__ __launch_bounds__(256) void gemm_f32(const GemmUnit* __restrict__ units,
+                                                const GemmItem* __restrict__ items) {
+  __shared__ float As[TK][LDP];
+  __shared__ float Bs[TK][LDP];
+  const GemmUnit u = units[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  v4f acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = (v4f){0.f, 0.f, 0.f, 0.f};
+  for (int it = u.ib; it < u.ie; ++it) {
+    const GemmItem g = items[it];
+    for (int k0 = 0; k0 < g.K; k0 += TK) {
+      load_tiles<MODE, TA, TB, float>(As, Bs, (const TA*)g.A, (const TB*)g.B, g.lda, g.ldb, g.K,
+                                      k0, u.m0, u.M, u.n0, u.N, g.coef, tid);
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < TK; kk += 4) {
+        float a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = As[kk + (lane >> 4)][wr + 16 * i + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = Bs[kk + (lane >> 4)][wc + 16 * j + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+      __syncthreads();
+    }
+  }
+  float* C = (float*)u.C;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int gm = u.m0 + wr + 16 * i + 4 * (lane >> 4) + r;
+        int gn = u.n0 + wc + 16 * j + (lane & 15);
+        if (gm < u.M && gn < u.N) {
+          long idx = (long)gm * u.ldc + gn;
+          float v = acc[i][j][r];
+          C[idx] = u.accumulate ? C[idx] + v : v;
+        }
+      }
+}
+
+// bf16 operands, fp32 accumulation: A given as TA (bf16 bits or fp32, rounded to
+// bf16 in LDS), B as bf16 bits.  One v_mfma_f32_16x16x16_bf16 per 16-deep k tile.
+template <int MODE, typename TA>
+__global__ __launch_bounds__(256) void gemm_bf16(const GemmUnit* __restrict__ units,
+                                                 const GemmItem* __restrict__ items) {
+  __shared__ uint16_t As[TK][LDP];
+  __shared__ uint16_t Bs[TK][LDP];
+  const GemmUnit u = units[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  v4f acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = (v4f){0.f, 0.f, 0.f, 0.f};
+  for (int it = u.ib; it < u.ie; ++it) {
+    const GemmItem g = items[it];
+    const TA* A = (const TA*)g.A;
+    const uint16_t* B = (const uint16_t*)g.B;
+    const float coef = (float)g.coef;
+    for (int k0 = 0; k0 < g.K; k0 += TK) {
+      if (MODE == GEMM_NN || MODE == GEMM_NT) {
+        int m = tid >> 2, kq = (tid & 3) * 4;
+        int gm = u.m0 + m;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          int k = kq + j;
+          float v = 0.f;
+          if (gm < u.M && k0 + k < g.K) v = to_f(A[(long)gm * g.lda + k0 + k]) * coef;
+          As[k][m] = f2bf(v);
+        }
+      } else {
+        int k = tid >> 4, mq = (tid & 15) * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          int m = mq + j;
+          float v = 0.f;
+          if (u.m0 + m < u.M && k0 + k < g.K) v = to_f(A[(long)(k0 + k) * g.lda + u.m0 + m]) * coef;
+          As[k][m] = f2bf(v);
+        }
+      }
+      if (MODE == GEMM_NN || MODE == GEMM_TN) {
+        int k = tid >> 4, nq = (tid & 15) * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          int n = nq + j;
+          uint16_t v = 0;
+          if (u.n0 + n < u.N && k0 + k < g.K) v = B[(long)(k0 + k) * g.ldb + u.n0 + n];
+          Bs[k][n] = v;
+        }
+      } else {
+        int n = tid >> 2, kq = (tid & 3) * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          int k = kq + j;
+          uint16_t v = 0;
+          if (u.n0 + n < u.N && k0 + k < g.K) v = B[(long)(u.n0 + n) * g.ldb + k0 + k];
+          Bs[k][n] = v;
+        }
+      }
+      __syncthreads();
+      v4s a[2], b[2];
+      const int kb = 4 * (lane >> 4);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[i][q] = (short)As[kb + q][wr + 16 * i + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) b[j][q] = (short)Bs[kb + q][wc + 16 * j + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+      __syncthreads();
+    }
+  }
+  float* C = (float*)u.C;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int gm = u.m0 + wr + 16 * i + 4 * (lane >> 4) + r;
+        int gn = u.n0 + wc + 16 * j + (lane & 15);
+        if (gm < u.M && gn < u.N) {
+          long idx = (long)gm * u.ldc + gn;
+          float v = acc[i][j][r];
+          C[idx] = u.accumulate ? C[idx] + v : v;
+        }
+      }
+}
+
+__global__ void premix_kernel(double* __restrict__ out, const double* const* __restrict__ srcs,
+                              const int* __restrict__ ptr, const double* __restrict__ coef,
+                              long nnz) {
+  const int f = blockIdx.y;
+  const int b = ptr[f], e = ptr[f + 1];
+  for (long j = (long)blockIdx.x * blockDim.x + threadIdx.x; j < nnz;
+       j += (long)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int i = b; i < e; ++i) acc += coef[i] * srcs[i][j];
+    out[(long)f * nnz + j] = acc;
+  }
+}
+
+__global__ void fill_kernel(double* x, long n, double v) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+
+__global__ void copy_blocks_kernel(const int64_t* __restrict__ desc, const double* __restrict__ src,
+                                   double* __restrict__ dst) {
+  const int64_t* d = desc + 9 * blockIdx.x;
+  const long so = d[0], srs = d[1], scs = d[2], dof = d[3], drs = d[4], dcs = d[5];
+  const int rows = (int)d[6], cols = (int)d[7];
+  const double sc = __longlong_as_double((long long)d[8]);
+  for (int e = threadIdx.x; e < rows * cols; e += blockDim.x) {
+    int r = e / cols, c = e % cols;
+    dst[dof + (long)r * drs + (long)c * dcs] = sc * src[so + (long)r * srs + (long)c * scs];
+  }
+}
+
+__global__ void axpy_dev_kernel(double* __restrict__ y, const double* __restrict__ x,
+                                const double* __restrict__ a, double sign, long n) {
+  const double s = sign * a[0];
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    y[i] += s * x[i];
+}
+
+__global__ void copy_kernel(double* __restrict__ dst, const double* __restrict__ src, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+__global__ void fill_f32_kernel(float* x, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    x[i] = 0.f;
+}
+
+__global__ void dots_partial(const double* __restrict__ V, long ldv, const double* __restrict__ x,
+                             long n, long chunk, double* __restrict__ partial) {
+  const int c = blockIdx.x, i = blockIdx.y;
+  const long b = (long)c * chunk, e = min(n, b + chunk);
+  const double* v = V + (long)i * ldv;
+  double acc = 0.0;
+  for (long j = b + threadIdx.x; j < e; j += blockDim.x) acc += v[j] * x[j];
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[(long)i * gridDim.x + c] = red[0];
+}
+
+__global__ void dots_final(const double* __restrict__ partial, int nchunk, double* __restrict__ out) {
+  const int i = blockIdx.x;
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int c = threadIdx.x; c < nchunk; c += blockDim.x) acc += partial[(long)i * nchunk + c];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = red[0];
+}
+
+__global__ void gemv_kernel(const double* __restrict__ V, long ldv, int k,
+                            const double* __restrict__ coef, double alpha, double* __restrict__ out,
+                            double beta, long n) {
+  __shared__ double cs[128];
+  for (int i = threadIdx.x; i < k; i += blockDim.x) cs[i] = coef[i];
+  __syncthreads();
+  for (long j = (long)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (long)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int i = 0; i < k; ++i) acc += cs[i] * V[(long)i * ldv + j];
+    out[j] = (beta == 0.0 ? 0.0 : beta * out[j]) + alpha * acc;
+  }
+}
+
+__global__ void scale_by_norm_kernel(double* x, long n, const double* nrm2) {
+  const double s = 1.0 / sqrt(nrm2[0]);
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    x[i] *= s;
+}
+
+__global__ void precond_diag_kernel(const double* __restrict__ r, const double* __restrict__ d,
+                                    const double* __restrict__ theta, double* __restrict__ out, long n) {
+  const double th = theta[0];
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    double den = th - d[i];
+    if (fabs(den) < 1e-8) den = den < 0 ? -1e-8 : 1e-8;
+    out[i] = r[i] / den;
+  }
+}
+
+// Symmetric eigensolver for k <= 64 in one workgroup: cyclic Jacobi with the
+// round-robin (circle) pairing, so each round rotates k/2 disjoint pairs in parallel.
+__global__ __launch_bounds__(256) void jacobi_eig_kernel(const double* __restrict__ G, int ldg, int k,
+                                                         double* __restrict__ evals,
+                                                         double* __restrict__ evecs) {
+  __shared__ double A[64][65];
+  __shared__ double V[64][65];
+  __shared__ double cs[32], sn[32];
+  __shared__ int P[32], Q[32];
+  __shared__ double red[256];
+  __shared__ int order[64];
+  const int t = threadIdx.x;
+  for (int e = t; e < k * k; e += blockDim.x) {  // lower triangle holds the matrix
+    int i = e / k, j = e % k;
+    A[i][j] = i >= j ? G[(long)i * ldg + j] : G[(long)j * ldg + i];
+    V[i][j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int n = k + (k & 1);
+  const int half = n / 2;
+  for (int sweep = 0; sweep < 40 && k > 1; ++sweep) {
+    double off = 0.0, dg = 0.0;
+    for (int e = t; e < k * k; e += blockDim.x) {
+      int i = e / k, j = e % k;
+      if (i != j) off += A[i][j] * A[i][j];
+      else dg += A[i][j] * A[i][j];
+    }
+    red[t] = off;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (t < s) red[t] += red[t + s];
+      __syncthreads();
+    }
+    double offsum = red[0];
+    __syncthreads();
+    red[t] = dg;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (t < s) red[t] += red[t + s];
+      __syncthreads();
+    }
+    double dgsum = red[0];
+    __syncthreads();
+    if (offsum <= 1e-32 * (dgsum > 1e-300 ? dgsum : 1e-300)) break;
+    for (int round = 0; round < n - 1; ++round) {
+      if (t < half) {
+        int p, q;
+        if (t == 0) {
+          p = round % (n - 1);
+          q = n - 1;
+        } else {
+          p = (round + t) % (n - 1);
+          q = (round - t + (n - 1)) % (n - 1);
+        }
+        if (p > q) {
+          int tmp = p;
+          p = q;
+          q = tmp;
+        }
+        double c = 1.0, s = 0.0;
+        if (q < k) {
+          double apq = A[p][q];
+          if (fabs(apq) > 1e-300) {
+            double theta = (A[q][q] - A[p][p]) / (2.0 * apq);
+            double tt = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            c = 1.0 / sqrt(tt * tt + 1.0);
+            s = tt * c;
+          }
+        }
+        P[t] = p;
+        Q[t] = q;
+        cs[t] = c;
+        sn[t] = s;
+      }
+      __syncthreads();
+      for (int e = t; e < half * k; e += blockDim.x) {  // rows
+        int pr = e / k, j = e % k;
+        int p = P[pr], q = Q[pr];
+        if (q >= k) continue;
+        double c = cs[pr], s = sn[pr];
+        double ap = A[p][j], aq = A[q][j];
+        A[p][j] = c * ap - s * aq;
+        A[q][j] = s * ap + c * aq;
+      }
+      __syncthreads();
+      for (int e = t; e < half * k; e += blockDim.x) {  // columns, and V
+        int pr = e / k, i = e % k;
+        int p = P[pr], q = Q[pr];
+        if (q >= k) continue;
+        double c = cs[pr], s = sn[pr];
+        double ap = A[i][p], aq = A[i][q];
+        A[i][p] = c * ap - s * aq;
+        A[i][q] = s * ap + c * aq;
+        double vp = V[i][p], vq = V[i][q];
+        V[i][p] = c * vp - s * vq;
+        V[i][q] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+  }
+  if (t == 0) {
+    for (int i = 0; i < k; ++i) order[i] = i;
+    for (int i = 0; i < k; ++i)
+      for (int j = i + 1; j < k; ++j)
+        if (A[order[j]][order[j]] < A[order[i]][order[i]]) {
+          int tmp = order[i];
+          order[i] = order[j];
+          order[j] = tmp;
+        }
+  }
+  __syncthreads();
+  for (int e = t; e < k * k; e += blockDim.x) {
+    int j = e / k, i = e % k;  // eigenvector j, component i
+    evecs[(long)j * k + i] = V[i][order[j]];
+  }
+  for (int j = t; j < k; j += blockDim.x) evals[j] = A[order[j]][order[j]];
+}
+
+__global__ void f64_to_f32_kernel(const double* x, float* y, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
+__global__ void f64_to_bf16_kernel(const double* x, uint16_t* y, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    y[i] = f2bf((float)x[i]);
+}
+__global__ void f32_to_f64_kernel(const float* x, double* y, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    y[i] = (double)x[i];
+}
+
+__global__ void diag_kernel(double* __restrict__ out, const DiagBlock* __restrict__ blocks,
+                            const DiagTerm* __restrict__ terms) {
+  const DiagBlock b = blocks[blockIdx.x];
+  for (int e = threadIdx.x; e < b.rows * b.cols; e += blockDim.x) {
+    int i = e / b.cols, j = e % b.cols;
+    double acc = 0.0;
+    for (int tt = b.t0; tt < b.t1; ++tt) {
+      const DiagTerm& d = terms[tt];
+      acc += d.w * d.x[i] * d.y[j];
+    }
+    out[b.out_off + (long)i * b.ld + j] = acc;
+  }
+}
+
+// desc: src_off, ld, n, dst_off
+__global__ void extract_diag_kernel(const int64_t* __restrict__ desc, const double* __restrict__ src,
+                                    double* __restrict__ dst) {
+  const int64_t* d = desc + 4 * blockIdx.x;
+  for (int i = threadIdx.x; i < (int)d[2]; i += blockDim.x) dst[d[3] + i] = src[d[0] + (long)i * (d[1] + 1)];
+}
+
+inline int grid_for(long n, int bs = 256, int cap = 4096) {
+  long g = (n + bs - 1) / bs;
+  if (g < 1) g = 1;
+  return (int)(g > cap ? cap : g);
+}
+
+}  // namespace
+
+void launch_gemm(int prec, int mode, const GemmUnit* units, int n_units, const GemmItem* items,
+                 hipStream_t s) {
+  if (n_units <= 0) return;
+  dim3 grid(n_units), block(256);
+  if (prec == PREC_F64) {
+    if (mode == GEMM_NN) gemm_f64<GEMM_NN><<<grid, block, 0, s>>>(units, items);
+    else if (mode == GEMM_NT) gemm_f64<GEMM_NT><<<grid, block, 0, s>>>(units, items);
+    else gemm_f64<GEMM_TN><<<grid, block, 0, s>>>(units, items);
+  } else if (prec == PREC_F32) {
+    if (mode == GEMM_NN) gemm_f32<GEMM_NN, float, float><<<grid, block, 0, s>>>(units, items);
+    else if (mode == GEMM_NT) gemm_f32<GEMM_NT, float, float><<<grid, block, 0, s>>>(units, items);
+    else gemm_f32<GEMM_TN, float, float><<<grid, block, 0, s>>>(units, items);
+  } else if (prec == PREC_BF16) {  // A: bf16, B: bf16
+    if (mode == GEMM_NN) gemm_bf16<GEMM_NN, uint16_t><<<grid, block, 0, s>>>(units, items);
+    else gemm_bf16<GEMM_NT, uint16_t><<<grid, block, 0, s>>>(units, items);
+  } else {  // A: fp32 rounded to bf16 on load, B: bf16
+    if (mode == GEMM_NN) gemm_bf16<GEMM_NN, float><<<grid, block, 0, s>>>(units, items);
+    else gemm_bf16<GEMM_NT, float><<<grid, block, 0, s>>>(units, items);
+  }
+}
+
+void launch_premix(double* out, const double* const* srcs, const int* ptr, const double* coef,
+                   int n_out, long nnz, hipStream_t s) {
+  if (n_out <= 0 || nnz <= 0) return;
+  dim3 grid(grid_for(nnz, 256, 64), n_out);
+  premix_kernel<<<grid, 256, 0, s>>>(out, srcs, ptr, coef, nnz);
+}
+
+void launch_fill(double* x, long n, double v, hipStream_t s) {
+  if (n <= 0) return;
+  fill_kernel<<<grid_for(n), 256, 0, s>>>(x, n, v);
+}
+
+void launch_copy_blocks(const int64_t* desc, int n_blocks, const double* src, double* dst,
+                        hipStream_t s) {
+  if (n_blocks <= 0) return;
+  copy_blocks_kernel<<<n_blocks, 256, 0, s>>>(desc, src, dst);
+}
+
+void launch_axpy_dev(double* y, const double* x, const double* a, double sign, long n, hipStream_t s) {
+  if (n > 0) axpy_dev_kernel<<<grid_for(n), 256, 0, s>>>(y, x, a, sign, n);
+}
+
+void launch_copy(double* dst, const double* src, long n, hipStream_t s) {
+  if (n > 0) copy_kernel<<<grid_for(n), 256, 0, s>>>(dst, src, n);
+}
+
+void launch_fill_f32(float* x, long n, hipStream_t s) {
+  if (n > 0) fill_f32_kernel<<<grid_for(n), 256, 0, s>>>(x, n);
+}
+
+void launch_dots(const double* V, long ldv, int k, const double* x, long n, double* partial,
+                 double* out, hipStream_t s) {
+  if (k <= 0) return;
+  long chunk = 8192;
+  int nchunk = (int)((n + chunk - 1) / chunk);
+  if (nchunk > 512) {
+    nchunk = 512;
+    chunk = (n + nchunk - 1) / nchunk;
+  }
+  if (nchunk < 1) nchunk = 1;
+  dots_partial<<<dim3(nchunk, k), 256, 0, s>>>(V, ldv, x, n, chunk, partial);
+  dots_final<<<k, 256, 0, s>>>(partial, nchunk, out);
+}
+
+void launch_gemv(const double* V, long ldv, int k, const double* coef, double alpha, double* out,
+                 double beta, long n, hipStream_t s) {
+  gemv_kernel<<<grid_for(n), 256, 0, s>>>(V, ldv, k, coef, alpha, out, beta, n);
+}
+
+void launch_scale_by_norm(double* x, long n, const double* nrm2, hipStream_t s) {
+  scale_by_norm_kernel<<<grid_for(n), 256, 0, s>>>(x, n, nrm2);
+}
+
+void launch_precond_diag(const double* r, const double* diag, const double* theta, double* out,
+                         long n, hipStream_t s) {
+  precond_diag_kernel<<<grid_for(n), 256, 0, s>>>(r, diag, theta, out, n);
+}
+
+void launch_jacobi_eig(const double* G, int ldg, int k, double* evals, double* evecs,
+                       hipStream_t s) {
+  jacobi_eig_kernel<<<1, 256, 0, s>>>(G, ldg, k, evals, evecs);
+}
+
+void launch_f64_to_f32(const double* x, float* y, long n, hipStream_t s) {
+  if (n > 0) f64_to_f32_kernel<<<grid_for(n), 256, 0, s>>>(x, y, n);
+}
+void launch_f64_to_bf16(const double* x, uint16_t* y, long n, hipStream_t s) {
+  if (n > 0) f64_to_bf16_kernel<<<grid_for(n), 256, 0, s>>>(x, y, n);
+}
+void launch_f32_to_f64(const float* x, double* y, long n, hipStream_t s) {
+  if (n > 0) f32_to_f64_kernel<<<grid_for(n), 256, 0, s>>>(x, y, n);
+}
+
+void launch_diag(double* out, const DiagBlock* blocks, int n_blocks, const DiagTerm* terms,
+                 hipStream_t s) {
+  if (n_blocks > 0) diag_kernel<<<n_blocks, 256, 0, s>>>(out, blocks, terms);
+}
+
+void launch_extract_diag(const int64_t* desc, int n, const double* src, double* dst,
+                         hipStream_t s) {
+  if (n > 0) extract_diag_kernel<<<n, 64, 0, s>>>(desc, src, dst);
+}
+
+}  // namespace dmrg

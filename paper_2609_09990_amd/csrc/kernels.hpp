@@ -1,0 +1,82 @@
+// Device kernels (gfx950) and their host launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dmrg {
+
+// One product term of a grouped block GEMM: acc += coef * op(A) * op(B), K deep.
+struct GemmItem {
+  const void* A;
+  const void* B;
+  int lda, ldb, K, pad;
+  double coef;
+};
+
+// One output tile (rows m0.., cols n0.., at most 64 x 64) of an M x N output
+// block; it accumulates items [ib, ie) in order (no atomics: deterministic).
+struct GemmUnit {
+  void* C;
+  int ldc, M, N, m0, n0, ib, ie, accumulate;
+};
+
+enum GemmMode : int {
+  GEMM_NN = 0,  // A: M x K row-major, B: K x N row-major
+  GEMM_NT = 1,  // A: M x K row-major, B: N x K row-major (B transposed)
+  GEMM_TN = 2,  // A: K x M row-major (A transposed), B: K x N row-major
+};
+
+// Element precision of A and B (C is fp64 for FP64, fp32 otherwise).
+enum GemmPrec : int { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2 };
+
+void launch_gemm(int prec, int mode, const GemmUnit* units, int n_units, const GemmItem* items,
+                 hipStream_t s);
+
+// out[f][j] = sum_{i in [ptr[f], ptr[f+1])} coef[i] * src[idx[i]][j], j < nnz.
+void launch_premix(double* out, const double* const* srcs, const int* ptr, const double* coef,
+                   int n_out, long nnz, hipStream_t s);
+
+void launch_fill(double* x, long n, double v, hipStream_t s);
+// desc per block (9 x int64): src_off, src_row_stride, src_col_stride, dst_off,
+// dst_row_stride, dst_col_stride, rows, cols, scale (bits of a double)
+void launch_copy_blocks(const int64_t* desc, int n_blocks, const double* src, double* dst,
+                        hipStream_t s);
+void launch_axpy_dev(double* y, const double* x, const double* a, double sign, long n, hipStream_t s);
+void launch_copy(double* dst, const double* src, long n, hipStream_t s);
+
+// Davidson helpers (all fp64, deterministic two-pass reductions).
+void launch_dots(const double* V, long ldv, int k, const double* x, long n, double* partial,
+                 double* out, hipStream_t s);
+void launch_fill_f32(float* x, long n, hipStream_t s);
+void launch_gemv(const double* V, long ldv, int k, const double* coef, double alpha,
+                 double* out, double beta, long n, hipStream_t s);
+void launch_scale_by_norm(double* x, long n, const double* nrm2, hipStream_t s);
+void launch_precond_diag(const double* r, const double* diag, const double* theta, double* out,
+                         long n, hipStream_t s);
+void launch_jacobi_eig(const double* G, int ldg, int k, double* evals, double* evecs,
+                       hipStream_t s);
+
+// precision conversions
+void launch_f64_to_f32(const double* x, float* y, long n, hipStream_t s);
+void launch_f64_to_bf16(const double* x, uint16_t* y, long n, hipStream_t s);
+void launch_f32_to_f64(const float* x, double* y, long n, hipStream_t s);
+
+// H_eff diagonal: out[e] = sum_t w_t * xd[tx_t][ia] * yd[ty_t][ib] per block.
+struct DiagBlock {
+  long out_off;
+  int ld, rows, cols, t0, t1;  // rows x cols block at out_off with row stride ld; terms [t0,t1)
+};
+struct DiagTerm {
+  const double* x;  // diagonal of the left factor restricted to the block's row sector
+  const double* y;  // diagonal of the right factor restricted to the block's col sector
+  double w;
+};
+void launch_diag(double* out, const DiagBlock* blocks, int n_blocks, const DiagTerm* terms,
+                 hipStream_t s);
+// diag of each env block: out[j] = blk[j*(ld+1)], used to extract factor diagonals.
+void launch_extract_diag(const int64_t* desc, int n, const double* src, double* dst,
+                         hipStream_t s);
+
+}  // namespace dmrg

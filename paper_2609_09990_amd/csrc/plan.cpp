@@ -1,0 +1,649 @@
+// Environment layouts, factor premixing, and the grouped-GEMM plans of the
+// environment updates and of sigma.
+//
+// The two-site effective Hamiltonian of sites (k, k+1) is written through the
+// channels beta of the middle cut k+1:
+//   H_eff = sum_beta  [sum_alpha L_k[alpha] (x) W_k[alpha,beta]]
+//                  (x) [sum_gamma W_{k+1}[beta,gamma] (x) R_{k+2}[gamma]].
+// Grouping W_k[., beta] by site operator gives left factors X_{beta,op} =
+// sum_alpha c L_k[alpha] (a single channel when there is one source: no copy);
+// likewise right factors Y_{beta,op}.  Sigma is then
+//   T_X = X psi                       (phase A, one GEMM per factor and psi slab)
+//   sigma = sum_terms c (op_l (x) op_r) T_X Y^T   (phase B, long-K GEMM per block)
+// and the left (right) environment update reuses the same factors with the site
+// tensor in place of psi.
+#include <algorithm>
+#include <cstring>
+
+#include "solver.hpp"
+
+namespace dmrg {
+
+void Solver::make_env_layout(Env& e, int cut, const Bond& b) {
+  const auto& ch = prob_->mpo.chans[cut];
+  std::vector<QN> dqs;
+  e.chan_class.assign(ch.size(), -1);
+  e.chan_slot.assign(ch.size(), -1);
+  std::vector<int> count;
+  for (size_t i = 0; i < ch.size(); ++i) {
+    int c = -1;
+    for (size_t j = 0; j < dqs.size(); ++j)
+      if (dqs[j] == ch[i].dq) c = (int)j;
+    if (c < 0) {
+      c = (int)dqs.size();
+      dqs.push_back(ch[i].dq);
+      count.push_back(0);
+    }
+    e.chan_class[i] = c;
+    e.chan_slot[i] = count[c]++;
+  }
+  e.classes = make_env_classes(b, dqs);
+  e.class_base.assign(dqs.size(), 0);
+  long off = 0;
+  for (size_t c = 0; c < dqs.size(); ++c) {
+    e.class_base[c] = off;
+    off += e.classes[c].nnz * count[c];
+  }
+  e.size = off;
+  e.buf.reserve(std::max<long>(off, 1) * sizeof(double));
+}
+
+void Solver::build_factor_side(FactorSide& fs, bool left, int site) {
+  const MPO& mpo = prob_->mpo;
+  const Env& env = left ? left_[site] : right_[site + 1];
+  int mid_cut = left ? site + 1 : site;
+  fs = FactorSide();
+  fs.cut = left ? site : site + 1;
+  fs.by_mid.assign(mpo.chans[mid_cut].size(), {});
+  // group W entries by (middle channel, op)
+  std::map<std::pair<int, int>, std::vector<std::pair<int, double>>> groups;
+  for (const auto& e : mpo.W[site]) {
+    int mid = left ? e.b : e.a;
+    int src = left ? e.a : e.b;
+    groups[{mid, e.op}].push_back({src, e.c});
+  }
+  std::map<int, int> alias_of;
+  std::map<std::vector<std::pair<int, double>>, int> mixed_of;
+  std::vector<std::vector<std::pair<int, double>>> mixed_src;
+  for (auto& g : groups) {
+    auto& src = g.second;
+    std::sort(src.begin(), src.end());
+    int f;
+    double scale;
+    if (src.size() == 1) {
+      auto it = alias_of.find(src[0].first);
+      if (it == alias_of.end()) {
+        f = (int)fs.fac.size();
+        int ch = src[0].first;
+        fs.fac.push_back({env.chan_class[ch], true, env.chan_off(ch)});
+        alias_of[ch] = f;
+      } else {
+        f = it->second;
+      }
+      scale = src[0].second;
+    } else {
+      scale = src[0].second;
+      std::vector<std::pair<int, double>> norm;
+      for (auto& s : src) norm.push_back({s.first, s.second / scale});
+      auto it = mixed_of.find(norm);
+      if (it == mixed_of.end()) {
+        f = (int)fs.fac.size();
+        fs.fac.push_back({env.chan_class[src[0].first], false, -1});
+        mixed_of[norm] = f;
+        mixed_src.push_back(norm);
+      } else {
+        f = it->second;
+      }
+    }
+    fs.by_mid[g.first.first].push_back({g.first.second, f, scale});
+  }
+  // premix program, outputs grouped by class (one kernel launch per class)
+  std::vector<int> mixed_ids;
+  for (size_t f = 0; f < fs.fac.size(); ++f)
+    if (!fs.fac[f].alias) mixed_ids.push_back((int)f);
+  std::stable_sort(mixed_ids.begin(), mixed_ids.end(),
+                   [&](int a, int b) { return fs.fac[a].cls < fs.fac[b].cls; });
+  std::map<int, int> mix_index;  // factor -> index into mixed_src
+  {
+    int i = 0;
+    for (size_t f = 0; f < fs.fac.size(); ++f)
+      if (!fs.fac[f].alias) mix_index[(int)f] = i++;
+  }
+  long off = 0;
+  fs.ptr.push_back(0);
+  for (int f : mixed_ids) {
+    const auto& src = mixed_src[mix_index[f]];
+    long nnz = env.classes[fs.fac[f].cls].nnz;
+    fs.fac[f].off = off;
+    fs.out_off.push_back(off);
+    fs.out_nnz.push_back(nnz);
+    off += nnz;
+    for (auto& s : src) {
+      DMRG_REQUIRE(env.chan_class[s.first] == fs.fac[f].cls, ST_EINVAL, "premix sources of different classes");
+      fs.src_off.push_back(env.chan_off(s.first));
+      fs.coef.push_back(s.second);
+    }
+    fs.ptr.push_back((int)fs.coef.size());
+  }
+  fs.premix_size = off;
+}
+
+void Solver::run_premix(FactorSide& fs, const Env& env) {
+  int n_out = (int)fs.out_off.size();
+  if (n_out == 0) return;
+  fs.mix.reserve(std::max<long>(fs.premix_size, 1) * sizeof(double));
+  std::vector<const double*>& srcs = fs.h_srcs;
+  srcs.resize(fs.src_off.size());
+  for (size_t i = 0; i < srcs.size(); ++i) srcs[i] = env.buf.as<double>() + fs.src_off[i];
+  fs.d_srcs.reserve(srcs.size() * sizeof(void*) + 8);
+  fs.d_ptr.reserve(fs.ptr.size() * sizeof(int) + 8);
+  fs.d_coef.reserve(fs.coef.size() * sizeof(double) + 8);
+  hip_check(hipMemcpyAsync(fs.d_srcs.p, srcs.data(), srcs.size() * sizeof(void*), hipMemcpyHostToDevice, st), "premix srcs");
+  hip_check(hipMemcpyAsync(fs.d_ptr.p, fs.ptr.data(), fs.ptr.size() * sizeof(int), hipMemcpyHostToDevice, st), "premix ptr");
+  hip_check(hipMemcpyAsync(fs.d_coef.p, fs.coef.data(), fs.coef.size() * sizeof(double), hipMemcpyHostToDevice, st), "premix coef");
+  // launch per run of equal nnz (outputs of one class are contiguous)
+  int b = 0;
+  while (b < n_out) {
+    int e = b + 1;
+    while (e < n_out && fs.out_nnz[e] == fs.out_nnz[b] && fs.out_off[e] == fs.out_off[e - 1] + fs.out_nnz[e - 1]) ++e;
+    launch_premix(fs.mix.as<double>() + fs.out_off[b], fs.d_srcs.as<const double*>(), fs.d_ptr.as<int>() + b,
+                  fs.d_coef.as<double>(), e - b, fs.out_nnz[b], st);
+    b = e;
+  }
+}
+
+static void add_units(std::vector<PUnit>& units, int cbuf, long coff, int ldc, int M, int N, int ib,
+                      int ie, int acc) {
+  for (int m0 = 0; m0 < M; m0 += 64)
+    for (int n0 = 0; n0 < N; n0 += 64) units.push_back({cbuf, coff, ldc, M, N, m0, n0, ib, ie, acc});
+}
+
+// Host check that every tile of every item stays inside its buffer (in
+// elements); a plan bug becomes an error instead of a device fault.
+static void validate_phase(const Phase& ph, const long* sizes) {
+  for (const PUnit& u : ph.units) {
+    long cmax = u.coff + (long)(u.M - 1) * u.ldc + (u.N - 1);
+    if (u.coff < 0 || cmax >= sizes[u.cbuf]) throw Error(ST_EINVAL, "plan: output block out of bounds");
+    for (int i = u.ib; i < u.ie; ++i) {
+      const PItem& it = ph.items[i];
+      long amax, bmax;
+      if (ph.mode == GEMM_TN) amax = it.aoff + (long)(it.K - 1) * it.lda + (u.M - 1);
+      else amax = it.aoff + (long)(u.M - 1) * it.lda + (it.K - 1);
+      if (ph.mode == GEMM_NT) bmax = it.boff + (long)(u.N - 1) * it.ldb + (it.K - 1);
+      else bmax = it.boff + (long)(it.K - 1) * it.ldb + (u.N - 1);
+      if (it.K <= 0 || it.aoff < 0 || it.boff < 0 || amax >= sizes[it.abuf] || bmax >= sizes[it.bbuf])
+        throw Error(ST_EINVAL, "plan: operand block out of bounds");
+    }
+  }
+}
+
+void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* esz, const long* sizes) {
+  if (ph.units.empty()) return;
+  int slot = prec == PREC_F64 ? 0 : (prec == PREC_F32 ? 1 : 2);
+  bool same = ph.uploaded[slot];
+  for (int b = 0; b < B_NBUF && same; ++b) same = ph.last_bases[slot][b] == bases[b];
+  if (same) {  // plan already resolved against these buffers
+    launch_gemm(prec, ph.mode, ph.d_units[slot].as<GemmUnit>(), (int)ph.units.size(),
+                ph.d_items[slot].as<GemmItem>(), st);
+    return;
+  }
+  validate_phase(ph, sizes);
+  for (int b = 0; b < B_NBUF; ++b) ph.last_bases[slot][b] = bases[b];
+  ph.uploaded[slot] = true;
+  std::vector<GemmItem>& items = ph.h_items[slot];
+  items.resize(ph.items.size());
+  for (size_t i = 0; i < items.size(); ++i) {
+    const PItem& p = ph.items[i];
+    items[i].A = (const char*)bases[p.abuf] + p.aoff * esz[p.abuf];
+    items[i].B = (const char*)bases[p.bbuf] + p.boff * esz[p.bbuf];
+    items[i].lda = p.lda;
+    items[i].ldb = p.ldb;
+    items[i].K = p.K;
+    items[i].pad = 0;
+    items[i].coef = p.coef;
+  }
+  std::vector<GemmUnit>& units = ph.h_units[slot];
+  units.resize(ph.units.size());
+  for (size_t i = 0; i < units.size(); ++i) {
+    const PUnit& u = ph.units[i];
+    units[i].C = (char*)bases[u.cbuf] + u.coff * esz[u.cbuf];
+    units[i].ldc = u.ldc;
+    units[i].M = u.M;
+    units[i].N = u.N;
+    units[i].m0 = u.m0;
+    units[i].n0 = u.n0;
+    units[i].ib = u.ib;
+    units[i].ie = u.ie;
+    units[i].accumulate = u.acc;
+  }
+  ph.d_items[slot].reserve(items.size() * sizeof(GemmItem) + 64);
+  ph.d_units[slot].reserve(units.size() * sizeof(GemmUnit) + 64);
+  hip_check(hipMemcpyAsync(ph.d_items[slot].p, items.data(), items.size() * sizeof(GemmItem), hipMemcpyHostToDevice, st), "items");
+  hip_check(hipMemcpyAsync(ph.d_units[slot].p, units.data(), units.size() * sizeof(GemmUnit), hipMemcpyHostToDevice, st), "units");
+  launch_gemm(prec, ph.mode, ph.d_units[slot].as<GemmUnit>(), (int)units.size(), ph.d_items[slot].as<GemmItem>(), st);
+}
+
+// L_{k+1}[beta] = sum_{(op,X)} s sum_{ss'} op[s][s'] A_s^T X A_{s'}
+void Solver::env_update_left(int k, const FactorSide& fs) {
+  const MPO& mpo = prob_->mpo;
+  const Bond& bk = bonds_[k];
+  const Env& envk = left_[k];
+  const SiteTensor& A = mps_[k];
+  Env& out = left_[k + 1];
+  make_env_layout(out, k + 1, bonds_[k + 1]);
+  // phase A: Z_X = X A for every factor used
+  std::vector<char> used(fs.fac.size(), 0);
+  for (auto& v : fs.by_mid)
+    for (auto& u : v) used[u.f] = 1;
+  Phase pa;
+  pa.mode = GEMM_NN;
+  std::vector<std::vector<long>> zoff(fs.fac.size());  // per factor, per A slab: offset or -1
+  long zsize = 0;
+  for (size_t f = 0; f < fs.fac.size(); ++f) {
+    if (!used[f]) continue;
+    const EnvClass& cls = envk.classes[fs.fac[f].cls];
+    zoff[f].assign(A.lay.slabs.size(), -1);
+    for (size_t si = 0; si < A.lay.slabs.size(); ++si) {
+      const Slab& sl = A.lay.slabs[si];
+      int bi = cls.block_of_col[sl.li];
+      if (bi < 0) continue;
+      const EnvBlock& eb = cls.blocks[bi];
+      zoff[f][si] = zsize;
+      int ib = (int)pa.items.size();
+      pa.items.push_back({fs.fac[f].alias ? B_ENVL : B_XMIX, fs.fac[f].off + eb.off, B_PSI, sl.off,
+                          eb.mc, sl.width, eb.mc, 1.0});
+      add_units(pa.units, B_T, zsize, sl.width, eb.mr, sl.width, ib, ib + 1, 0);
+      pa.flops += 2.0 * eb.mr * eb.mc * sl.width;
+      zsize += (long)eb.mr * sl.width;
+    }
+  }
+  // phase B
+  Phase pb;
+  pb.mode = GEMM_TN;
+  const auto& mids = mpo.chans[k + 1];
+  for (size_t beta = 0; beta < mids.size(); ++beta) {
+    const EnvClass& ocls = out.classes[out.chan_class[beta]];
+    long cbase = out.chan_off((int)beta);
+    std::vector<std::vector<PItem>> per_block(ocls.blocks.size());
+    for (const auto& u : fs.by_mid[beta]) {
+      const Mat4& op = mpo.ops[u.op];
+      const EnvClass& icls = envk.classes[fs.fac[u.f].cls];
+      for (int s = 0; s < 4; ++s)
+        for (int sp = 0; sp < 4; ++sp) {
+          double w = op[s * 4 + sp];
+          if (w == 0.0) continue;
+          for (size_t si = 0; si < A.lay.slabs.size(); ++si) {
+            if (zoff[u.f][si] < 0) continue;
+            const Slab& sl = A.lay.slabs[si];
+            int bi = icls.block_of_col[sl.li];
+            int lo = icls.blocks[bi].ri;  // row sector of X A
+            int slo = A.lay.slab_of_left[lo];
+            if (slo < 0) continue;
+            const Slab& slab_lo = A.lay.slabs[slo];
+            // block (s', ri) of the source slab gives Z columns
+            for (const auto& blk : sl.blocks) {
+              if (blk.phys != sp) continue;
+              int ri = blk.ri;
+              int ob = ocls.block_of_col[ri];
+              if (ob < 0) continue;
+              int ro = ocls.blocks[ob].ri;
+              int ab = slab_lo.block_of(s, ro);
+              if (ab < 0) continue;
+              const SlabBlock& ablk = slab_lo.blocks[ab];
+              per_block[ob].push_back({B_PSI, slab_lo.off + ablk.col0, B_T, zoff[u.f][si] + blk.col0,
+                                       slab_lo.width, sl.width, slab_lo.ml, u.scale * w});
+              pb.flops += 2.0 * ablk.mr * blk.mr * slab_lo.ml;
+            }
+          }
+        }
+    }
+    for (size_t ob = 0; ob < per_block.size(); ++ob) {
+      if (per_block[ob].empty()) continue;
+      int ib = (int)pb.items.size();
+      pb.items.insert(pb.items.end(), per_block[ob].begin(), per_block[ob].end());
+      const EnvBlock& eb = ocls.blocks[ob];
+      add_units(pb.units, B_OUT, cbase + eb.off, eb.mc, eb.mr, eb.mc, ib, (int)pb.items.size(), 0);
+    }
+  }
+  t_buf_.reserve(std::max<long>(zsize, 1) * sizeof(double));
+  launch_fill(out.buf.as<double>(), out.size, 0.0, st);
+  void* bases[B_NBUF] = {};
+  bases[B_PSI] = A.buf.p;
+  bases[B_OUT] = out.buf.p;
+  bases[B_T] = t_buf_.p;
+  bases[B_XMIX] = fs.mix.p;
+  bases[B_ENVL] = envk.buf.p;
+  size_t esz[B_NBUF] = {8, 8, 8, 8, 8, 8, 8, 8};
+  long sizes[B_NBUF] = {};
+  sizes[B_PSI] = A.lay.size;
+  sizes[B_OUT] = out.size;
+  sizes[B_T] = zsize;
+  sizes[B_XMIX] = fs.premix_size;
+  sizes[B_ENVL] = envk.size;
+  run_phase(pa, PREC_F64, bases, esz, sizes);
+  run_phase(pb, PREC_F64, bases, esz, sizes);
+  hip_check(hipStreamSynchronize(st), "env update");  // local plan buffers die here
+  out.valid = true;
+}
+
+// R_j[beta] = sum_{(op,Y)} s sum_{ss'} op[s][s'] B_s Y B_{s'}^T
+void Solver::env_update_right(int j, const FactorSide& fs) {
+  const MPO& mpo = prob_->mpo;
+  const Bond& bj1 = bonds_[j + 1];
+  const Env& envr = right_[j + 1];
+  const SiteTensor& Bt = mps_[j];
+  Env& out = right_[j];
+  make_env_layout(out, j, bonds_[j]);
+  std::vector<char> used(fs.fac.size(), 0);
+  for (auto& v : fs.by_mid)
+    for (auto& u : v) used[u.f] = 1;
+  // phase A: U_Y = B Y, stored per (factor, slab) as a slab of blocks (s, c)
+  struct USlab {
+    long off = -1;
+    int width = 0;
+    std::vector<std::array<int, 3>> blocks;  // s, c (bond j+1 sector), col0
+  };
+  std::vector<std::vector<USlab>> U(fs.fac.size());
+  Phase pa;
+  pa.mode = GEMM_NN;
+  long usize = 0;
+  for (size_t f = 0; f < fs.fac.size(); ++f) {
+    if (!used[f]) continue;
+    const EnvClass& cls = envr.classes[fs.fac[f].cls];
+    U[f].resize(Bt.lay.slabs.size());
+    for (size_t si = 0; si < Bt.lay.slabs.size(); ++si) {
+      const Slab& sl = Bt.lay.slabs[si];
+      USlab& us = U[f][si];
+      for (const auto& blk : sl.blocks) {
+        int c = bj1.find(bj1.sec[blk.ri].q - cls.dq);
+        if (c < 0) continue;
+        int ybi = cls.block_of_col[c];
+        if (ybi < 0 || cls.blocks[ybi].ri != blk.ri) continue;
+        us.blocks.push_back({blk.phys, c, us.width});
+        us.width += bj1.sec[c].dim;
+      }
+      if (us.width == 0) continue;
+      us.off = usize;
+      for (const auto& ub : us.blocks) {
+        const SlabBlock* blk = nullptr;
+        for (const auto& b2 : sl.blocks)
+          if (b2.phys == ub[0]) blk = &b2;  // one block per physical state in a slab
+        const EnvBlock& yb = cls.blocks[cls.block_of_col[ub[1]]];
+        int ib = (int)pa.items.size();
+        pa.items.push_back({B_SITE2, sl.off + blk->col0, fs.fac[f].alias ? B_ENVR : B_YMIX,
+                            fs.fac[f].off + yb.off, sl.width, yb.mc, blk->mr, 1.0});
+        add_units(pa.units, B_T, usize + ub[2], us.width, sl.ml, yb.mc, ib, ib + 1, 0);
+        pa.flops += 2.0 * sl.ml * blk->mr * yb.mc;
+      }
+      usize += (long)sl.ml * us.width;
+    }
+  }
+  Phase pb;
+  pb.mode = GEMM_NT;
+  const Bond& bj = bonds_[j];
+  const auto& mids = mpo.chans[j];
+  for (size_t beta = 0; beta < mids.size(); ++beta) {
+    const EnvClass& ocls = out.classes[out.chan_class[beta]];
+    long cbase = out.chan_off((int)beta);
+    std::vector<std::vector<PItem>> per_block(ocls.blocks.size());
+    for (const auto& u : fs.by_mid[beta]) {
+      const Mat4& op = mpo.ops[u.op];
+      for (int s = 0; s < 4; ++s)
+        for (int sp = 0; sp < 4; ++sp) {
+          double w = op[s * 4 + sp];
+          if (w == 0.0) continue;
+          for (size_t si = 0; si < Bt.lay.slabs.size(); ++si) {
+            const USlab& us = U[u.f][si];
+            if (us.off < 0) continue;
+            const Slab& sa = Bt.lay.slabs[si];
+            for (const auto& ub : us.blocks) {
+              if (ub[0] != s) continue;
+              int c = ub[1];
+              int lap = bj.find(bj1.sec[c].q - site_qn(sp));
+              if (lap < 0) continue;
+              int slp = Bt.lay.slab_of_left[lap];
+              if (slp < 0) continue;
+              const Slab& sb = Bt.lay.slabs[slp];
+              int bb = sb.block_of(sp, c);
+              if (bb < 0) continue;
+              int ob = ocls.block_of_col[lap];
+              if (ob < 0 || ocls.blocks[ob].ri != sa.li) continue;
+              per_block[ob].push_back({B_T, us.off + ub[2], B_SITE2, sb.off + sb.blocks[bb].col0, us.width,
+                                       sb.width, bj1.sec[c].dim, u.scale * w});
+              pb.flops += 2.0 * sa.ml * sb.ml * bj1.sec[c].dim;
+            }
+          }
+        }
+    }
+    for (size_t ob = 0; ob < per_block.size(); ++ob) {
+      if (per_block[ob].empty()) continue;
+      int ib = (int)pb.items.size();
+      pb.items.insert(pb.items.end(), per_block[ob].begin(), per_block[ob].end());
+      const EnvBlock& eb = ocls.blocks[ob];
+      add_units(pb.units, B_OUT, cbase + eb.off, eb.mc, eb.mr, eb.mc, ib, (int)pb.items.size(), 0);
+    }
+  }
+  t_buf_.reserve(std::max<long>(usize, 1) * sizeof(double));
+  launch_fill(out.buf.as<double>(), out.size, 0.0, st);
+  void* bases[B_NBUF] = {};
+  bases[B_OUT] = out.buf.p;
+  bases[B_T] = t_buf_.p;
+  bases[B_YMIX] = fs.mix.p;
+  bases[B_ENVR] = envr.buf.p;
+  bases[B_SITE2] = Bt.buf.p;
+  size_t esz[B_NBUF] = {8, 8, 8, 8, 8, 8, 8, 8};
+  long sizes[B_NBUF] = {};
+  sizes[B_OUT] = out.size;
+  sizes[B_T] = usize;
+  sizes[B_YMIX] = fs.premix_size;
+  sizes[B_ENVR] = envr.size;
+  sizes[B_SITE2] = Bt.lay.size;
+  run_phase(pa, PREC_F64, bases, esz, sizes);
+  run_phase(pb, PREC_F64, bases, esz, sizes);
+  hip_check(hipStreamSynchronize(st), "env update");  // local plan buffers die here
+  out.valid = true;
+}
+
+void Solver::build_sigma_plan(int k) {
+  const MPO& mpo = prob_->mpo;
+  const Env& envl = left_[k];
+  const Env& envr = right_[k + 2];
+  psi_lay_ = make_tensor_layout(bonds_[k], bonds_[k + 2], twosite_phys_qn());
+  const TensorLayout& P = psi_lay_;
+  const Bond& bk2 = bonds_[k + 2];
+  int nmid = (int)mpo.chans[k + 1].size();
+  // which left factors are used by terms
+  std::vector<char> used(lf_.fac.size(), 0);
+  for (int b = 0; b < nmid; ++b)
+    if (!rf_.by_mid[b].empty())
+      for (auto& u : lf_.by_mid[b]) used[u.f] = 1;
+  phA_ = Phase();
+  phA_.mode = GEMM_NN;
+  std::vector<std::vector<long>> toff(lf_.fac.size());
+  std::vector<std::vector<int>> trow(lf_.fac.size());
+  long tsize = 0;
+  for (size_t f = 0; f < lf_.fac.size(); ++f) {
+    if (!used[f]) continue;
+    const EnvClass& cls = envl.classes[lf_.fac[f].cls];
+    toff[f].assign(P.slabs.size(), -1);
+    trow[f].assign(P.slabs.size(), -1);
+    for (size_t si = 0; si < P.slabs.size(); ++si) {
+      const Slab& sl = P.slabs[si];
+      int bi = cls.block_of_col[sl.li];
+      if (bi < 0) continue;
+      const EnvBlock& eb = cls.blocks[bi];
+      if (P.slab_of_left[eb.ri] < 0) continue;  // output rows would fall outside sigma
+      toff[f][si] = tsize;
+      trow[f][si] = eb.ri;
+      int ib = (int)phA_.items.size();
+      phA_.items.push_back({lf_.fac[f].alias ? B_ENVL : B_XMIX, lf_.fac[f].off + eb.off, B_PSI, sl.off,
+                            eb.mc, sl.width, eb.mc, 1.0});
+      add_units(phA_.units, B_T, tsize, sl.width, eb.mr, sl.width, ib, ib + 1, 0);
+      phA_.flops += 2.0 * eb.mr * eb.mc * sl.width;
+      tsize += (long)eb.mr * sl.width;
+    }
+  }
+  t_size_ = tsize;
+  // phase B: gather items per output block of sigma
+  phB_ = Phase();
+  phB_.mode = GEMM_NT;
+  std::vector<std::vector<std::vector<PItem>>> per(P.slabs.size());
+  for (size_t si = 0; si < P.slabs.size(); ++si) per[si].resize(P.slabs[si].blocks.size());
+  for (int b = 0; b < nmid; ++b) {
+    if (lf_.by_mid[b].empty() || rf_.by_mid[b].empty()) continue;
+    for (const auto& ul : lf_.by_mid[b]) {
+      const Mat4& opl = mpo.ops[ul.op];
+      for (const auto& ur : rf_.by_mid[b]) {
+        const Mat4& opr = mpo.ops[ur.op];
+        const EnvClass& ycls = envr.classes[rf_.fac[ur.f].cls];
+        double sc = ul.scale * ur.scale;
+        for (int s1 = 0; s1 < 4; ++s1)
+          for (int t1 = 0; t1 < 4; ++t1) {
+            double wl = opl[s1 * 4 + t1];
+            if (wl == 0.0) continue;
+            for (int s2 = 0; s2 < 4; ++s2)
+              for (int t2 = 0; t2 < 4; ++t2) {
+                double wr = opr[s2 * 4 + t2];
+                if (wr == 0.0) continue;
+                int sout = 4 * s1 + s2, sin = 4 * t1 + t2;
+                for (size_t si = 0; si < P.slabs.size(); ++si) {
+                  if (toff[ul.f][si] < 0) continue;
+                  const Slab& src = P.slabs[si];
+                  int lo = trow[ul.f][si];
+                  int so = P.slab_of_left[lo];
+                  const Slab& dst = P.slabs[so];
+                  for (const auto& blk : src.blocks) {
+                    if (blk.phys != sin) continue;
+                    int ro = bk2.find(bk2.sec[blk.ri].q + ycls.dq);
+                    if (ro < 0) continue;
+                    int yb = ycls.block_of_col[blk.ri];
+                    if (yb < 0 || ycls.blocks[yb].ri != ro) continue;
+                    int ob = dst.block_of(sout, ro);
+                    if (ob < 0) continue;
+                    per[so][ob].push_back({B_T, toff[ul.f][si] + blk.col0,
+                                           rf_.fac[ur.f].alias ? B_ENVR : B_YMIX,
+                                           rf_.fac[ur.f].off + ycls.blocks[yb].off, src.width,
+                                           blk.mr, blk.mr, sc * wl * wr});
+                    phB_.flops += 2.0 * dst.ml * dst.blocks[ob].mr * blk.mr;
+                  }
+                }
+              }
+          }
+      }
+    }
+  }
+  for (size_t so = 0; so < P.slabs.size(); ++so)
+    for (size_t ob = 0; ob < per[so].size(); ++ob) {
+      auto& v = per[so][ob];  // blocks without items still get (zero-writing) tiles
+      int ib = (int)phB_.items.size();
+      phB_.items.insert(phB_.items.end(), v.begin(), v.end());
+      const Slab& dst = P.slabs[so];
+      add_units(phB_.units, B_OUT, dst.off + dst.blocks[ob].col0, dst.width, dst.ml, dst.blocks[ob].mr, ib,
+                (int)phB_.items.size(), 0);
+    }
+}
+
+void Solver::build_diag_plan(int k) {
+  const MPO& mpo = prob_->mpo;
+  const Env& envl = left_[k];
+  const Env& envr = right_[k + 2];
+  const TensorLayout& P = psi_lay_;
+  const Bond& bk = bonds_[k];
+  const Bond& bk2 = bonds_[k + 2];
+  dblocks_.clear();
+  dterms_host_.clear();
+  diag_desc_.clear();
+  // diagonals of shift-0 factors, per sector
+  long dsize = 0;
+  std::vector<std::vector<long>> xd(lf_.fac.size()), yd(rf_.fac.size());
+  auto extract = [&](const Factor& fac, const Env& env, const Bond& b, std::vector<long>& dst, long base_ofs) {
+    const EnvClass& cls = env.classes[fac.cls];
+    dst.assign(b.sec.size(), -1);
+    if (cls.dq != QN{0, 0}) return;
+    for (size_t ci = 0; ci < b.sec.size(); ++ci) {
+      int bi = cls.block_of_col[ci];
+      if (bi < 0) continue;
+      const EnvBlock& eb = cls.blocks[bi];
+      dst[ci] = dsize;
+      diag_desc_.insert(diag_desc_.end(), {base_ofs + fac.off + eb.off, (int64_t)eb.mc, (int64_t)eb.mc, dsize});
+      dsize += eb.mc;
+    }
+  };
+  // the descriptor's source offset is resolved against one buffer per pass; record which
+  std::vector<int> desc_buf;
+  for (size_t f = 0; f < lf_.fac.size(); ++f) {
+    size_t before = diag_desc_.size();
+    extract(lf_.fac[f], envl, bk, xd[f], 0);
+    for (size_t i = before; i < diag_desc_.size(); i += 4) desc_buf.push_back(lf_.fac[f].alias ? B_ENVL : B_XMIX);
+  }
+  for (size_t f = 0; f < rf_.fac.size(); ++f) {
+    size_t before = diag_desc_.size();
+    extract(rf_.fac[f], envr, bk2, yd[f], 0);
+    for (size_t i = before; i < diag_desc_.size(); i += 4) desc_buf.push_back(rf_.fac[f].alias ? B_ENVR : B_YMIX);
+  }
+  diagvec_.reserve(std::max<long>(dsize, 1) * sizeof(double));
+  // run the extraction now, one launch per source buffer
+  for (int bufid : {B_ENVL, B_XMIX, B_ENVR, B_YMIX}) {
+    std::vector<int64_t> d;
+    for (size_t i = 0; i < desc_buf.size(); ++i)
+      if (desc_buf[i] == bufid) d.insert(d.end(), diag_desc_.begin() + 4 * i, diag_desc_.begin() + 4 * i + 4);
+    if (d.empty()) continue;
+    const double* src = bufid == B_ENVL ? left_[k].buf.as<double>()
+                        : bufid == B_XMIX ? lf_.mix.as<double>()
+                        : bufid == B_ENVR ? right_[k + 2].buf.as<double>()
+                                          : rf_.mix.as<double>();
+    DevMem dd;
+    dd.reserve(d.size() * sizeof(int64_t));
+    hip_check(hipMemcpyAsync(dd.p, d.data(), d.size() * sizeof(int64_t), hipMemcpyHostToDevice, st), "diag desc");
+    launch_extract_diag(dd.as<int64_t>(), (int)(d.size() / 4), src, diagvec_.as<double>(), st);
+    hip_check(hipStreamSynchronize(st), "diag extract");
+  }
+  // terms per output block
+  std::vector<std::vector<std::vector<DiagTerm>>> per(P.slabs.size());
+  for (size_t si = 0; si < P.slabs.size(); ++si) per[si].resize(P.slabs[si].blocks.size());
+  int nmid = (int)mpo.chans[k + 1].size();
+  const double* dv = diagvec_.as<double>();
+  for (int b = 0; b < nmid; ++b)
+    for (const auto& ul : lf_.by_mid[b]) {
+      if (envl.classes[lf_.fac[ul.f].cls].dq != QN{0, 0}) continue;
+      const Mat4& opl = mpo.ops[ul.op];
+      for (const auto& ur : rf_.by_mid[b]) {
+        if (envr.classes[rf_.fac[ur.f].cls].dq != QN{0, 0}) continue;
+        const Mat4& opr = mpo.ops[ur.op];
+        for (int s1 = 0; s1 < 4; ++s1) {
+          double wl = opl[s1 * 5];
+          if (wl == 0.0) continue;
+          for (int s2 = 0; s2 < 4; ++s2) {
+            double wr = opr[s2 * 5];
+            if (wr == 0.0) continue;
+            for (size_t si = 0; si < P.slabs.size(); ++si) {
+              const Slab& sl = P.slabs[si];
+              long xo = xd[ul.f][sl.li];
+              if (xo < 0) continue;
+              for (size_t bi = 0; bi < sl.blocks.size(); ++bi) {
+                if (sl.blocks[bi].phys != 4 * s1 + s2) continue;
+                long yo = yd[ur.f][sl.blocks[bi].ri];
+                if (yo < 0) continue;
+                per[si][bi].push_back({dv + xo, dv + yo, ul.scale * ur.scale * wl * wr});
+              }
+            }
+          }
+        }
+      }
+    }
+  for (size_t si = 0; si < P.slabs.size(); ++si)
+    for (size_t bi = 0; bi < per[si].size(); ++bi) {
+      const Slab& sl = P.slabs[si];
+      int t0 = (int)dterms_host_.size();
+      dterms_host_.insert(dterms_host_.end(), per[si][bi].begin(), per[si][bi].end());
+      dblocks_.push_back({sl.off + sl.blocks[bi].col0, sl.width, sl.ml, sl.blocks[bi].mr, t0,
+                          (int)dterms_host_.size()});
+    }
+  d_dblocks_.reserve(dblocks_.size() * sizeof(DiagBlock) + 64);
+  d_dterms_.reserve(dterms_host_.size() * sizeof(DiagTerm) + 64);
+  hip_check(hipMemcpyAsync(d_dblocks_.p, dblocks_.data(), dblocks_.size() * sizeof(DiagBlock), hipMemcpyHostToDevice, st), "dblocks");
+  hip_check(hipMemcpyAsync(d_dterms_.p, dterms_host_.data(), dterms_host_.size() * sizeof(DiagTerm), hipMemcpyHostToDevice, st), "dterms");
+  diag_ready_ = true;
+}
+
+}  // namespace dmrg

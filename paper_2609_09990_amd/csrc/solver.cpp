@@ -1,0 +1,956 @@
+// Two-site sweep driver: MPS setup, environments, sigma, Davidson, SVD truncation.
+#include "solver.hpp"
+
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+namespace dmrg {
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess)
+    throw Error(ST_EHIP, std::string("HIP error in ") + what + ": " + hipGetErrorString(e));
+}
+
+DevMem::~DevMem() { release(); }
+void DevMem::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+void DevMem::reserve(size_t b) {
+  if (b <= bytes && p) return;
+  release();
+  if (b == 0) b = 8;
+  hipError_t e = hipMalloc(&p, b);
+  if (e != hipSuccess) {
+    p = nullptr;
+    throw Error(ST_ENOMEM, "device allocation of " + std::to_string(b) + " bytes failed");
+  }
+  bytes = b;
+}
+
+namespace {
+
+struct Rng {  // splitmix64 + Box-Muller: a seeded, platform-independent normal stream
+  uint64_t s;
+  explicit Rng(uint64_t seed) : s(seed) {}
+  uint64_t next() {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+  double uniform() { return ((next() >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
+  double normal() {
+    double u1 = uniform(), u2 = uniform();
+    return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+  }
+};
+
+long binom(int n, int k) {
+  if (k < 0 || k > n) return 0;
+  long r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+// Host check of block-copy descriptors against source / destination sizes.
+void check_desc(const std::vector<int64_t>& d, size_t begin, size_t end, long src_n, long dst_n) {
+  for (size_t i = begin; i < end; i += 9) {
+    long rows = d[i + 6], cols = d[i + 7];
+    if (rows <= 0 || cols <= 0) continue;
+    long smax = d[i] + (rows - 1) * d[i + 1] + (cols - 1) * d[i + 2];
+    long dmax = d[i + 3] + (rows - 1) * d[i + 4] + (cols - 1) * d[i + 5];
+    if (d[i] < 0 || d[i + 3] < 0 || smax >= src_n || dmax >= dst_n)
+      throw Error(ST_EINVAL, "block copy out of bounds");
+  }
+}
+
+int64_t dbits(double x) {
+  int64_t b;
+  std::memcpy(&b, &x, 8);
+  return b;
+}
+
+}  // namespace
+
+Solver::Solver(const Problem* p, const Options& o, hipStream_t s) : prob_(p), opt_(o), st(s) {
+  L_ = p->n;
+  bonds_.resize(L_ + 1);
+  mps_.resize(L_);
+  left_.resize(L_ + 1);
+  right_.resize(L_ + 1);
+  DMRG_REQUIRE(opt_.n_states >= 1 && opt_.n_states <= 8, ST_EINVAL, "n_states must be in [1, 8]");
+  DMRG_REQUIRE(opt_.M >= 1, ST_EINVAL, "M must be positive");
+  if (opt_.weights.empty()) opt_.weights.assign(opt_.n_states, 1.0 / opt_.n_states);
+  DMRG_REQUIRE((int)opt_.weights.size() == opt_.n_states, ST_EINVAL, "weights size mismatch");
+  opt_.max_subspace = std::max(std::min(opt_.max_subspace, 64), 2 * opt_.n_states + 2);
+  if (rocblas_create_handle(&rb_) != rocblas_status_success) throw Error(ST_EHIP, "rocblas handle");
+  rocblas_set_stream(rb_, st);
+  init_random_mps();
+}
+
+Solver::~Solver() {
+  if (rb_) rocblas_destroy_handle(rb_);
+}
+
+// Right-canonical random MPS in the target sector: every slab (rows of one
+// left sector) has orthonormal rows.  Bond sectors are the full sector
+// dimensions scaled to fit M, clipped so each slab has at least as many
+// columns as rows.
+void Solver::init_random_mps() {
+  const int L = L_, na = prob_->n_alpha, nb = prob_->n_beta;
+  for (int c = 0; c <= L; ++c) {
+    Bond b;
+    long tot = 0;
+    for (int a = 0; a <= std::min(c, na); ++a)
+      for (int bb = 0; bb <= std::min(c, nb); ++bb) {
+        if (na - a > L - c || nb - bb > L - c) continue;
+        long d = std::min(binom(c, a) * binom(c, bb), binom(L - c, na - a) * binom(L - c, nb - bb));
+        if (d <= 0) continue;
+        b.sec.push_back({{a + bb, a - bb}, (int)std::min<long>(d, 1 << 30)});
+        tot += d;
+      }
+    std::sort(b.sec.begin(), b.sec.end(), [](const Sector& x, const Sector& y) { return x.q < y.q; });
+    if (tot > opt_.M)
+      for (auto& s : b.sec) s.dim = (int)std::max<long>(1, (long)s.dim * opt_.M / tot);
+    bonds_[c] = b;
+  }
+  DMRG_REQUIRE(!bonds_[L].sec.empty() && !bonds_[0].sec.empty(), ST_ESECTOR, "empty target sector");
+  for (int c = L - 1; c >= 0; --c) {
+    Bond& b = bonds_[c];
+    for (auto& s : b.sec) {
+      int cap = 0;
+      for (int p = 0; p < 4; ++p) {
+        int ri = bonds_[c + 1].find(s.q + site_qn(p));
+        if (ri >= 0) cap += bonds_[c + 1].sec[ri].dim;
+      }
+      s.dim = std::min(s.dim, cap);
+    }
+    b.sec.erase(std::remove_if(b.sec.begin(), b.sec.end(), [](const Sector& x) { return x.dim <= 0; }),
+                b.sec.end());
+  }
+  DMRG_REQUIRE(!bonds_[0].sec.empty(), ST_ESECTOR, "empty target sector");
+  Rng rng(opt_.seed);
+  for (int k = 0; k < L; ++k) {
+    SiteTensor& t = mps_[k];
+    t.lay = make_tensor_layout(bonds_[k], bonds_[k + 1], site_phys_qn());
+    std::vector<double> h(t.lay.size);
+    for (const Slab& sl : t.lay.slabs) {
+      double* S = h.data() + sl.off;
+      for (long i = 0; i < (long)sl.ml * sl.width; ++i) S[i] = rng.normal();
+      for (int pass = 0; pass < 2; ++pass)
+        for (int r = 0; r < sl.ml; ++r) {
+          double* row = S + (long)r * sl.width;
+          for (int q = 0; q < r; ++q) {
+            const double* prev = S + (long)q * sl.width;
+            double d = 0;
+            for (int c = 0; c < sl.width; ++c) d += prev[c] * row[c];
+            for (int c = 0; c < sl.width; ++c) row[c] -= d * prev[c];
+          }
+          double nrm = 0;
+          for (int c = 0; c < sl.width; ++c) nrm += row[c] * row[c];
+          nrm = std::sqrt(nrm);
+          for (int c = 0; c < sl.width; ++c) row[c] /= nrm;
+        }
+    }
+    t.buf.reserve(std::max<long>(t.lay.size, 1) * sizeof(double));
+    hip_check(hipMemcpy(t.buf.p, h.data(), t.lay.size * sizeof(double), hipMemcpyHostToDevice), "mps upload");
+  }
+  for (auto& e : left_) e.valid = false;
+  for (auto& e : right_) e.valid = false;
+  plan_k_ = -1;
+  center_site_ = -1;
+}
+
+void Solver::set_mps(const std::vector<Bond>& bonds, const std::vector<const double*>& sites) {
+  DMRG_REQUIRE((int)bonds.size() == L_ + 1 && (int)sites.size() == L_, ST_EINVAL, "MPS size mismatch");
+  DMRG_REQUIRE((bonds[0].sec.size() == 1 && bonds[0].sec[0].q == QN{0, 0} && bonds[0].sec[0].dim == 1),
+               ST_EINVAL, "left boundary bond must be the single vacuum state");
+  DMRG_REQUIRE(bonds[L_].sec.size() == 1 && bonds[L_].sec[0].q == prob_->target() && bonds[L_].sec[0].dim == 1,
+               ST_EINVAL, "right boundary bond must be the single target state");
+  for (int c = 0; c <= L_; ++c)
+    for (size_t i = 0; i < bonds[c].sec.size(); ++i) {
+      DMRG_REQUIRE(bonds[c].sec[i].dim >= 1, ST_EINVAL, "sector dims must be positive");
+      if (i) DMRG_REQUIRE(bonds[c].sec[i - 1].q < bonds[c].sec[i].q, ST_EINVAL, "sectors must be sorted");
+    }
+  bonds_ = bonds;
+  for (int k = 0; k < L_; ++k) {
+    SiteTensor& t = mps_[k];
+    t.lay = make_tensor_layout(bonds_[k], bonds_[k + 1], site_phys_qn());
+    t.buf.reserve(std::max<long>(t.lay.size, 1) * sizeof(double));
+    hip_check(hipMemcpy(t.buf.p, sites[k], t.lay.size * sizeof(double), hipMemcpyHostToDevice), "mps upload");
+  }
+  for (auto& e : left_) e.valid = false;
+  for (auto& e : right_) e.valid = false;
+  plan_k_ = -1;
+  center_site_ = -1;
+}
+
+void Solver::ensure_left(int c) {
+  if (left_[c].valid) return;
+  if (c == 0) {
+    Env& e = left_[0];
+    make_env_layout(e, 0, bonds_[0]);
+    launch_fill(e.buf.as<double>(), e.size, 0.0, st);
+    int I = prob_->mpo.chan_I[0];
+    DMRG_REQUIRE(I >= 0, ST_EINVAL, "no identity channel at the left end");
+    double one = 1.0;
+    hip_check(hipMemcpyAsync(e.buf.as<double>() + e.chan_off(I), &one, 8, hipMemcpyHostToDevice, st), "env0");
+    hip_check(hipStreamSynchronize(st), "env0");
+    e.valid = true;
+    return;
+  }
+  ensure_left(c - 1);
+  FactorSide fs;
+  build_factor_side(fs, true, c - 1);
+  run_premix(fs, left_[c - 1]);
+  env_update_left(c - 1, fs);
+  hip_check(hipStreamSynchronize(st), "env left");
+}
+
+void Solver::ensure_right(int c) {
+  if (right_[c].valid) return;
+  if (c == L_) {
+    Env& e = right_[L_];
+    make_env_layout(e, L_, bonds_[L_]);
+    launch_fill(e.buf.as<double>(), e.size, 0.0, st);
+    int H = prob_->mpo.chan_H[L_];
+    DMRG_REQUIRE(H >= 0, ST_EINVAL, "no closing channel at the right end");
+    double one = 1.0;
+    hip_check(hipMemcpyAsync(e.buf.as<double>() + e.chan_off(H), &one, 8, hipMemcpyHostToDevice, st), "envL");
+    hip_check(hipStreamSynchronize(st), "envL");
+    e.valid = true;
+    return;
+  }
+  ensure_right(c + 1);
+  FactorSide fs;
+  build_factor_side(fs, false, c);
+  run_premix(fs, right_[c + 1]);
+  env_update_right(c, fs);
+  hip_check(hipStreamSynchronize(st), "env right");
+}
+
+void Solver::prepare(int k) {
+  DMRG_REQUIRE(k >= 0 && k + 1 < L_, ST_EINVAL, "two-site step out of range");
+  ensure_left(k);
+  ensure_right(k + 2);
+  build_factor_side(lf_, true, k);
+  run_premix(lf_, left_[k]);
+  build_factor_side(rf_, false, k + 1);
+  run_premix(rf_, right_[k + 2]);
+  build_sigma_plan(k);
+  t_buf_.reserve(std::max<long>(t_size_, 1) * sizeof(double));
+  psi_in_.reserve(std::max<long>(psi_lay_.size, 1) * sizeof(double));
+  out_buf_.reserve(std::max<long>(psi_lay_.size, 1) * sizeof(double));
+  for (int i = 0; i < 3; ++i) {
+    phA_.uploaded[i] = phB_.uploaded[i] = false;
+  }
+  lowp_prec_ = -1;
+  diag_ready_ = false;
+  plan_k_ = k;
+  hip_check(hipStreamSynchronize(st), "prepare");
+}
+
+std::vector<double> Solver::env_host(int cut, int side) {
+  Env& e = side == 0 ? left_[cut] : right_[cut];
+  if (side == 0) ensure_left(cut);
+  else ensure_right(cut);
+  std::vector<double> v(e.size);
+  hip_check(hipMemcpy(v.data(), e.buf.p, e.size * sizeof(double), hipMemcpyDeviceToHost), "env copy");
+  return v;
+}
+
+long Solver::twosite_size(int k) const {
+  DMRG_REQUIRE(k >= 0 && k + 1 < L_, ST_EINVAL, "two-site step out of range");
+  return make_tensor_layout(bonds_[k], bonds_[k + 2], twosite_phys_qn()).size;
+}
+
+double Solver::last_sigma_flops() const { return phA_.flops + phB_.flops; }
+
+void Solver::ensure_lowp(int prec) {
+  if (lowp_prec_ == prec) return;
+  const int k = plan_k_;
+  struct Src { int id; const double* p; long n; };
+  Src src[] = {{B_ENVL, left_[k].buf.as<double>(), left_[k].size},
+               {B_ENVR, right_[k + 2].buf.as<double>(), right_[k + 2].size},
+               {B_XMIX, lf_.mix.as<double>(), lf_.premix_size},
+               {B_YMIX, rf_.mix.as<double>(), rf_.premix_size}};
+  size_t esz = prec == PREC_F32 ? 4 : 2;
+  for (auto& s : src) {
+    lowp_[s.id].reserve(std::max<long>(s.n, 1) * esz);
+    if (s.n <= 0 || !s.p) continue;
+    if (prec == PREC_F32) launch_f64_to_f32(s.p, lowp_[s.id].as<float>(), s.n, st);
+    else launch_f64_to_bf16(s.p, lowp_[s.id].as<uint16_t>(), s.n, st);
+  }
+  lowp_[B_PSI].reserve(std::max<long>(psi_lay_.size, 1) * esz);
+  lowp_[B_T].reserve(std::max<long>(t_size_, 1) * 4);
+  lowp_[B_OUT].reserve(std::max<long>(psi_lay_.size, 1) * 4);
+  lowp_prec_ = prec;
+  phA_.uploaded[1] = phA_.uploaded[2] = phB_.uploaded[1] = phB_.uploaded[2] = false;
+}
+
+void Solver::sigma(int k, int prec, const double* psi, double* out) {
+  if (plan_k_ != k) prepare(k);
+  const long n = psi_lay_.size;
+  long sizes[B_NBUF] = {};
+  sizes[B_PSI] = n;
+  sizes[B_OUT] = n;
+  sizes[B_T] = t_size_;
+  sizes[B_XMIX] = lf_.premix_size;
+  sizes[B_YMIX] = rf_.premix_size;
+  sizes[B_ENVL] = left_[k].size;
+  sizes[B_ENVR] = right_[k + 2].size;
+  hipEvent_t e0, e1, e2;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  (void)hipEventCreate(&e2);
+  if (prec == PREC_F64) {
+    void* bases[B_NBUF] = {};
+    bases[B_PSI] = (void*)psi;
+    bases[B_OUT] = (void*)out;
+    bases[B_T] = t_buf_.p;
+    bases[B_XMIX] = lf_.mix.p;
+    bases[B_YMIX] = rf_.mix.p;
+    bases[B_ENVL] = left_[k].buf.p;
+    bases[B_ENVR] = right_[k + 2].buf.p;
+    size_t esz[B_NBUF] = {8, 8, 8, 8, 8, 8, 8, 8};
+    (void)hipEventRecord(e0, st);
+    run_phase(phA_, PREC_F64, bases, esz, sizes);
+    (void)hipEventRecord(e1, st);
+    run_phase(phB_, PREC_F64, bases, esz, sizes);
+    (void)hipEventRecord(e2, st);
+  } else {
+    ensure_lowp(prec);
+    void* bases[B_NBUF] = {};
+    for (int i = 0; i < B_NBUF; ++i) bases[i] = lowp_[i].p;
+    size_t le = prec == PREC_F32 ? 4 : 2;
+    size_t esz[B_NBUF] = {le, 4, 4, le, le, le, le, le};
+    if (prec == PREC_F32) launch_f64_to_f32(psi, lowp_[B_PSI].as<float>(), n, st);
+    else launch_f64_to_bf16(psi, lowp_[B_PSI].as<uint16_t>(), n, st);
+    (void)hipEventRecord(e0, st);
+    run_phase(phA_, prec == PREC_F32 ? PREC_F32 : PREC_BF16, bases, esz, sizes);
+    (void)hipEventRecord(e1, st);
+    run_phase(phB_, prec == PREC_F32 ? PREC_F32 : 3, bases, esz, sizes);
+    (void)hipEventRecord(e2, st);
+    launch_f32_to_f64(lowp_[B_OUT].as<float>(), out, n, st);
+  }
+  hip_check(hipEventSynchronize(e2), "sigma");
+  float a = 0, b = 0;
+  (void)hipEventElapsedTime(&a, e0, e1);
+  (void)hipEventElapsedTime(&b, e1, e2);
+  sigma_phase_ms_[0] = a;
+  sigma_phase_ms_[1] = b;
+  st_.sigma_ms += a + b;
+  st_.sigma_flops += phA_.flops + phB_.flops;
+  st_.matvecs++;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipEventDestroy(e2);
+}
+
+void Solver::diag(int k, double* out) {
+  if (plan_k_ != k) prepare(k);
+  if (!diag_ready_) build_diag_plan(k);
+  launch_diag(out, d_dblocks_.as<DiagBlock>(), (int)dblocks_.size(), d_dterms_.as<DiagTerm>(), st);
+}
+
+void Solver::gemm_once(int mode, std::vector<GemmItem>& items, std::vector<GemmUnit>& units) {
+  if (units.empty()) return;
+  scratch_h_items_ = items;
+  scratch_h_units_ = units;
+  scratch_items_.reserve(items.size() * sizeof(GemmItem) + 64);
+  scratch_units_.reserve(units.size() * sizeof(GemmUnit) + 64);
+  hip_check(hipMemcpyAsync(scratch_items_.p, scratch_h_items_.data(), items.size() * sizeof(GemmItem),
+                           hipMemcpyHostToDevice, st), "items");
+  hip_check(hipMemcpyAsync(scratch_units_.p, scratch_h_units_.data(), units.size() * sizeof(GemmUnit),
+                           hipMemcpyHostToDevice, st), "units");
+  launch_gemm(PREC_F64, mode, scratch_units_.as<GemmUnit>(), (int)units.size(), scratch_items_.as<GemmItem>(), st);
+  hip_check(hipStreamSynchronize(st), "gemm_once");
+}
+
+static void tile_units(std::vector<GemmUnit>& units, double* C, int ldc, int M, int N, int ib, int ie) {
+  for (int m0 = 0; m0 < M; m0 += 64)
+    for (int n0 = 0; n0 < N; n0 += 64) units.push_back({C, ldc, M, N, m0, n0, ib, ie, 0});
+}
+
+// out (two-site, sites k,k+1) = a (site k) * b (site k+1), contracted over bond k+1.
+void Solver::form_twosite(int k, const SiteTensor& a, const SiteTensor& b, double* out) {
+  TensorLayout P = make_tensor_layout(bonds_[k], bonds_[k + 2], twosite_phys_qn());
+  std::vector<GemmItem> items;
+  std::vector<GemmUnit> units;
+  for (const Slab& ps : P.slabs) {
+    int sa = a.lay.slab_of_left[ps.li];
+    for (const auto& pb : ps.blocks) {
+      int s1 = pb.phys / 4, s2 = pb.phys % 4;
+      int ib = (int)items.size();
+      if (sa >= 0) {
+        const Slab& as = a.lay.slabs[sa];
+        for (const auto& ab : as.blocks) {
+          if (ab.phys != s1) continue;
+          int sbi = b.lay.slab_of_left[ab.ri];
+          if (sbi < 0) continue;
+          const Slab& bs = b.lay.slabs[sbi];
+          int bb = bs.block_of(s2, pb.ri);
+          if (bb < 0) continue;
+          items.push_back({a.buf.as<double>() + as.off + ab.col0, b.buf.as<double>() + bs.off + bs.blocks[bb].col0,
+                           as.width, bs.width, ab.mr, 0, 1.0});
+        }
+      }
+      tile_units(units, out + ps.off + pb.col0, ps.width, ps.ml, pb.mr, ib, (int)items.size());
+    }
+  }
+  gemm_once(GEMM_NN, items, units);
+}
+
+// ---------------------------------------------------------------- Davidson --
+// Block Davidson for the n_states lowest roots of H_eff (fp64 basis, subspace
+// matrix, Rayleigh-Ritz and residuals).  With a low-precision sigma the basis
+// is expanded with low-precision products; convergence is only declared on the
+// fp64 residual of the Ritz vectors (defect correction: on a stall or on low-
+// precision convergence the Ritz vectors' fp64 sigma replaces the subspace).
+int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& evals) {
+  if (plan_k_ != k) prepare(k);
+  const long n = psi_lay_.size;
+  const int nr = opt_.n_states;
+  const int kmax = std::min<long>(opt_.max_subspace, std::max<long>(n, 1));
+  DMRG_REQUIRE(n >= nr, ST_ESECTOR, "two-site space smaller than the number of states");
+  dv_V_.reserve((size_t)kmax * n * 8);
+  dv_AV_.reserve((size_t)kmax * n * 8);
+  dv_G_.reserve((size_t)64 * 64 * 8);
+  dv_evals_.reserve(64 * 8);
+  dv_evecs_.reserve(64 * 64 * 8);
+  dv_X_.reserve((size_t)nr * n * 8);
+  dv_R_.reserve((size_t)nr * n * 8);
+  dv_C_.reserve((size_t)nr * n * 8);
+  dv_t_.reserve((size_t)n * 8);
+  dv_diag_.reserve((size_t)n * 8);
+  dv_part_.reserve((size_t)512 * 64 * 8);
+  dv_sc_.reserve(256 * 8);
+  double* V = dv_V_.as<double>();
+  double* AV = dv_AV_.as<double>();
+  double* G = dv_G_.as<double>();
+  double* ev = dv_evals_.as<double>();
+  double* evec = dv_evecs_.as<double>();
+  double* X = dv_X_.as<double>();
+  double* R = dv_R_.as<double>();
+  double* Cc = dv_C_.as<double>();
+  double* t = dv_t_.as<double>();
+  double* D = dv_diag_.as<double>();
+  double* part = dv_part_.as<double>();
+  double* sc = dv_sc_.as<double>();
+  const int ldg = 64;
+  diag(k, D);
+  const int prec = opt_.precision;
+  int kcur = 0, matvecs = 0;
+
+  auto host_scalar = [&](const double* dptr) {
+    double v;
+    hip_check(hipMemcpyAsync(&v, dptr, 8, hipMemcpyDeviceToHost, st), "scalar");
+    hip_check(hipStreamSynchronize(st), "scalar");
+    return v;
+  };
+  // orthonormalise t against V[0..kcur) (two passes of classical Gram-Schmidt), append
+  auto append = [&](const double* src, int sprec) -> bool {
+    if (src != t) launch_copy(t, src, n, st);
+    launch_dots(t, n, 1, t, n, part, sc + 1, st);
+    double n0 = host_scalar(sc + 1);
+    if (!(n0 > 0) || !std::isfinite(n0)) return false;
+    for (int pass = 0; pass < 2 && kcur > 0; ++pass) {
+      launch_dots(V, n, kcur, t, n, part, sc + 8, st);
+      launch_gemv(V, n, kcur, sc + 8, -1.0, t, 1.0, n, st);
+    }
+    launch_dots(t, n, 1, t, n, part, sc, st);
+    double nn = host_scalar(sc);
+    if (!(nn > 1e-20 * n0)) return false;
+    launch_scale_by_norm(t, n, sc, st);
+    launch_copy(V + (long)kcur * n, t, n, st);
+    sigma(k, sprec, V + (long)kcur * n, AV + (long)kcur * n);
+    ++matvecs;
+    launch_dots(V, n, kcur + 1, AV + (long)kcur * n, n, part, G + (long)kcur * ldg, st);
+    ++kcur;
+    return true;
+  };
+
+  for (int r = 0; r < nr && r < (int)guess.size(); ++r) append(guess[r].as<double>(), PREC_F64);
+  if (kcur < nr) {  // fill with unit vectors at the lowest diagonal entries
+    std::vector<double> hd(n);
+    hip_check(hipMemcpy(hd.data(), D, n * 8, hipMemcpyDeviceToHost), "diag");
+    std::vector<long> idx(n);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](long a, long b) { return hd[a] < hd[b]; });
+    for (long j = 0; j < n && kcur < nr; ++j) {
+      std::vector<double> e(n, 0.0);
+      e[idx[j]] = 1.0;
+      hip_check(hipMemcpy(t, e.data(), n * 8, hipMemcpyHostToDevice), "unit");
+      append(t, PREC_F64);
+    }
+  }
+  DMRG_REQUIRE(kcur >= nr, ST_ESECTOR, "could not build an initial Davidson basis");
+  evals.assign(nr, 0.0);
+  std::vector<double> rn(nr, 0.0), hv(2 * nr);
+  int iter = 0;
+  bool exact_basis = (prec == PREC_F64);
+  double best_lo = 1e300;
+  int stall = 0;
+  int conv = 0;
+  for (; iter < opt_.max_iter; ++iter) {
+    launch_jacobi_eig(G, ldg, kcur, ev, evec, st);
+    for (int i = 0; i < nr; ++i) {
+      launch_gemv(V, n, kcur, evec + (long)i * kcur, 1.0, X + (long)i * n, 0.0, n, st);
+      launch_gemv(AV, n, kcur, evec + (long)i * kcur, 1.0, R + (long)i * n, 0.0, n, st);
+      launch_axpy_dev(R + (long)i * n, X + (long)i * n, ev + i, -1.0, n, st);
+      launch_dots(R + (long)i * n, n, 1, R + (long)i * n, n, part, sc + 16 + i, st);
+    }
+    hip_check(hipMemcpyAsync(hv.data(), ev, nr * 8, hipMemcpyDeviceToHost, st), "evals");
+    hip_check(hipMemcpyAsync(hv.data() + nr, sc + 16, nr * 8, hipMemcpyDeviceToHost, st), "rnorm");
+    hip_check(hipStreamSynchronize(st), "davidson");
+    double rmax = 0;
+    for (int i = 0; i < nr; ++i) {
+      evals[i] = hv[i];
+      rn[i] = std::sqrt(std::max(0.0, hv[nr + i]));
+      rmax = std::max(rmax, rn[i]);
+    }
+    if (opt_.verbose > 1)
+      fprintf(stderr, "  dav k=%d it=%d sub=%d E=%.12f r=%.3e exact=%d\n", k, iter, kcur, evals[0], rmax,
+              (int)exact_basis);
+    if (!std::isfinite(rmax)) throw Error(ST_ENOCONV, "non-finite Davidson residual");
+    bool lo_done = rmax <= opt_.davidson_tol;
+    if (!exact_basis) {
+      if (rmax < 0.9 * best_lo) {
+        best_lo = rmax;
+        stall = 0;
+      } else {
+        ++stall;
+      }
+      if (lo_done || stall >= 3) {
+        // fp64 refinement: exact sigma of the Ritz vectors, restart from them
+        for (int i = 0; i < nr; ++i) launch_copy(V + (long)i * n, X + (long)i * n, n, st);
+        for (int i = 0; i < nr; ++i) {
+          sigma(k, PREC_F64, V + (long)i * n, AV + (long)i * n);
+          ++matvecs;
+        }
+        for (int i = 0; i < nr; ++i) launch_dots(V, n, i + 1, AV + (long)i * n, n, part, G + (long)i * ldg, st);
+        kcur = nr;
+        exact_basis = true;  // residual of the next RR is exact
+        best_lo = 1e300;
+        stall = 0;
+        continue;
+      }
+    } else if (lo_done) {
+      conv = 1;
+      break;
+    }
+    exact_basis = (prec == PREC_F64);
+    // corrections from the residuals of unconverged roots
+    int nnew = 0;
+    for (int i = 0; i < nr; ++i) {
+      if (rn[i] <= opt_.davidson_tol) continue;
+      launch_precond_diag(R + (long)i * n, D, ev + i, Cc + (long)nnew * n, n, st);
+      ++nnew;
+    }
+    if (kcur + nnew > kmax) {  // thick restart with the Ritz vectors
+      for (int i = 0; i < nr; ++i)
+        launch_gemv(AV, n, kcur, evec + (long)i * kcur, 1.0, R + (long)i * n, 0.0, n, st);
+      for (int i = 0; i < nr; ++i) {
+        launch_copy(V + (long)i * n, X + (long)i * n, n, st);
+        launch_copy(AV + (long)i * n, R + (long)i * n, n, st);
+      }
+      for (int i = 0; i < nr; ++i) launch_dots(V, n, i + 1, AV + (long)i * n, n, part, G + (long)i * ldg, st);
+      kcur = nr;
+    }
+    int added = 0;
+    for (int j = 0; j < nnew; ++j)
+      if (append(Cc + (long)j * n, prec)) ++added;
+    if (added == 0) {
+      conv = rmax <= 1e3 * opt_.davidson_tol;
+      break;
+    }
+  }
+  st_.davidson_iters += iter;
+  if (!conv) st_.converged = 0;
+  // converged Ritz vectors are in X
+  return matvecs;
+}
+
+// ----------------------------------------------------------------- SVD step --
+// Reshape psi to (a s1) x (s2 b); it is block diagonal in the middle-bond
+// sector q_m = q_a + q_s1.  One fp64 SVD per sector (state-averaged: of the
+// weighted concatenation of the roots), global truncation with the cluster rule,
+// new site tensors and next-step guesses.
+void Solver::svd_step(int k, bool l2r, int nr, std::vector<DevMem>& next_guess, double& tau) {
+  const TensorLayout& P = psi_lay_;
+  const Bond& bk = bonds_[k];
+  const Bond& bk2 = bonds_[k + 2];
+  const long n = P.size;
+  struct Part { int idx, dim; long off; };
+  struct Mid { QN q; std::vector<Part> rows, cols; int R = 0, C = 0; };
+  std::vector<Mid> mids;
+  auto mid_of = [&](QN q) {
+    for (size_t i = 0; i < mids.size(); ++i)
+      if (mids[i].q == q) return (int)i;
+    mids.push_back({q, {}, {}, 0, 0});
+    return (int)mids.size() - 1;
+  };
+  for (const Slab& sl : P.slabs)
+    for (const auto& b : sl.blocks) mid_of(bk.sec[sl.li].q + site_qn(b.phys / 4));
+  std::sort(mids.begin(), mids.end(), [](const Mid& a, const Mid& b) { return a.q < b.q; });
+  for (Mid& m : mids) {
+    for (int s1 = 0; s1 < 4; ++s1) {
+      int li = bk.find(m.q - site_qn(s1));
+      if (li < 0 || P.slab_of_left[li] < 0) { m.rows.push_back({li, 0, m.R}); continue; }
+      m.rows.push_back({li, bk.sec[li].dim, m.R});
+      m.R += bk.sec[li].dim;
+    }
+    for (int s2 = 0; s2 < 4; ++s2) {
+      int ri = bk2.find(m.q + site_qn(s2));
+      if (ri < 0) { m.cols.push_back({ri, 0, m.C}); continue; }
+      m.cols.push_back({ri, bk2.sec[ri].dim, m.C});
+      m.C += bk2.sec[ri].dim;
+    }
+  }
+  // gather: per root matrix (column-major, R x C) and the weighted SVD input
+  long tot_plain = 0, tot_svd = 0;
+  std::vector<long> off_plain(mids.size()), off_svd(mids.size());
+  for (size_t i = 0; i < mids.size(); ++i) {
+    off_plain[i] = tot_plain;
+    tot_plain += (long)mids[i].R * mids[i].C * nr;
+    off_svd[i] = tot_svd;
+    tot_svd += (long)mids[i].R * mids[i].C * nr;
+  }
+  DevMem plain, work, Sv, Uv, Vv, Ev, info;
+  plain.reserve(std::max<long>(tot_plain, 1) * 8);
+  work.reserve(std::max<long>(tot_svd, 1) * 8);
+  std::vector<int64_t> desc_plain, desc_svd;
+  for (size_t mi = 0; mi < mids.size(); ++mi) {
+    const Mid& m = mids[mi];
+    for (int s1 = 0; s1 < 4; ++s1) {
+      const Part& rp = m.rows[s1];
+      if (rp.dim == 0) continue;
+      const Slab& sl = P.slabs[P.slab_of_left[rp.idx]];
+      for (int s2 = 0; s2 < 4; ++s2) {
+        const Part& cp = m.cols[s2];
+        if (cp.dim == 0) continue;
+        int b = sl.block_of(4 * s1 + s2, cp.idx);
+        if (b < 0) continue;
+        for (int r = 0; r < nr; ++r) {
+          long src = (long)r * n + sl.off + sl.blocks[b].col0;
+          // plain per root: column-major R x C at off_plain + r*R*C
+          long dst = off_plain[mi] + (long)r * m.R * m.C + rp.off + (long)cp.off * m.R;
+          desc_plain.insert(desc_plain.end(), {src, sl.width, 1, dst, 1, m.R, rp.dim, cp.dim, dbits(1.0)});
+          double w = std::sqrt(opt_.weights[r]);
+          long dsv;
+          if (l2r)  // horizontal concatenation: R x (nr C), ld R
+            dsv = off_svd[mi] + rp.off + ((long)r * m.C + cp.off) * m.R;
+          else      // vertical: (nr R) x C, ld nr R
+            dsv = off_svd[mi] + (long)r * m.R + rp.off + (long)cp.off * nr * m.R;
+          long ld = l2r ? m.R : (long)nr * m.R;
+          desc_svd.insert(desc_svd.end(), {src, sl.width, 1, dsv, 1, ld, rp.dim, cp.dim, dbits(w)});
+        }
+      }
+    }
+  }
+  check_desc(desc_plain, 0, desc_plain.size(), (long)nr * n, tot_plain);
+  check_desc(desc_svd, 0, desc_svd.size(), (long)nr * n, tot_svd);
+  launch_fill(plain.as<double>(), tot_plain, 0.0, st);
+  launch_fill(work.as<double>(), tot_svd, 0.0, st);
+  DevMem dd;
+  dd.reserve((desc_plain.size() + desc_svd.size()) * 8 + 8);
+  std::vector<int64_t> all = desc_plain;
+  all.insert(all.end(), desc_svd.begin(), desc_svd.end());
+  hip_check(hipMemcpyAsync(dd.p, all.data(), all.size() * 8, hipMemcpyHostToDevice, st), "svd desc");
+  launch_copy_blocks(dd.as<int64_t>(), (int)(desc_plain.size() / 9), dv_X_.as<double>(), plain.as<double>(), st);
+  launch_copy_blocks(dd.as<int64_t>() + desc_plain.size(), (int)(desc_svd.size() / 9), dv_X_.as<double>(),
+                     work.as<double>(), st);
+  // SVDs
+  long sS = 0, sU = 0, sV = 0;
+  std::vector<long> oS(mids.size()), oU(mids.size()), oV(mids.size());
+  std::vector<int> mm(mids.size()), nn(mids.size()), kk(mids.size());
+  for (size_t i = 0; i < mids.size(); ++i) {
+    mm[i] = l2r ? mids[i].R : nr * mids[i].R;
+    nn[i] = l2r ? nr * mids[i].C : mids[i].C;
+    kk[i] = std::min(mm[i], nn[i]);
+    oS[i] = sS;
+    sS += kk[i];
+    oU[i] = sU;
+    sU += (long)mm[i] * kk[i];
+    oV[i] = sV;
+    sV += (long)kk[i] * nn[i];
+  }
+  Sv.reserve(std::max<long>(sS, 1) * 8);
+  Uv.reserve(std::max<long>(sU, 1) * 8);
+  Vv.reserve(std::max<long>(sV, 1) * 8);
+  Ev.reserve(std::max<long>(sS, 1) * 8);
+  info.reserve(mids.size() * sizeof(rocblas_int) + 8);
+  for (size_t i = 0; i < mids.size(); ++i) {
+    if (kk[i] == 0) continue;
+    rocblas_status rs = rocsolver_dgesvd(rb_, rocblas_svect_singular, rocblas_svect_singular, mm[i], nn[i],
+                                         work.as<double>() + off_svd[i], mm[i], Sv.as<double>() + oS[i],
+                                         Uv.as<double>() + oU[i], mm[i], Vv.as<double>() + oV[i], kk[i],
+                                         Ev.as<double>() + oS[i], rocblas_outofplace,
+                                         info.as<rocblas_int>() + i);
+    if (rs != rocblas_status_success) throw Error(ST_EHIP, "rocsolver_dgesvd failed");
+  }
+  std::vector<double> S(sS);
+  hip_check(hipMemcpyAsync(S.data(), Sv.p, sS * 8, hipMemcpyDeviceToHost, st), "S");
+  hip_check(hipStreamSynchronize(st), "svd");
+  // global truncation with the cluster rule
+  struct SV { double s; int mid, j; };
+  std::vector<SV> all_sv;
+  for (size_t i = 0; i < mids.size(); ++i)
+    for (int j = 0; j < kk[i]; ++j) all_sv.push_back({S[oS[i] + j], (int)i, j});
+  std::stable_sort(all_sv.begin(), all_sv.end(), [](const SV& a, const SV& b) { return a.s > b.s; });
+  double s1 = all_sv.empty() ? 0.0 : all_sv[0].s;
+  long keep = std::min<long>((long)all_sv.size(), opt_.M);
+  while (keep > 0 && all_sv[keep - 1].s <= opt_.cut_rtol * s1) --keep;
+  if (keep < (long)all_sv.size() && keep > 0) {
+    while (keep > 1 && all_sv[keep - 1].s - all_sv[keep].s <= opt_.tie_rtol * s1) --keep;
+  }
+  if (keep < 1) keep = 1;
+  tau = 0;
+  for (size_t i = keep; i < all_sv.size(); ++i) tau += all_sv[i].s * all_sv[i].s;
+  std::vector<int> kept(mids.size(), 0);
+  for (long i = 0; i < keep; ++i) kept[all_sv[i].mid]++;
+  // singular values within a sector are descending, so the kept ones are the first kept[i]
+  Bond nb;
+  std::vector<int> new_index(mids.size(), -1);
+  for (size_t i = 0; i < mids.size(); ++i)
+    if (kept[i] > 0) {
+      new_index[i] = (int)nb.sec.size();
+      nb.sec.push_back({mids[i].q, kept[i]});
+    }
+  bonds_[k + 1] = nb;
+  st_.max_bond = std::max(st_.max_bond, nb.total());
+  // new tensors
+  std::vector<GemmItem> items;
+  std::vector<GemmUnit> units;
+  std::vector<int64_t> cdesc;
+  SiteTensor fixed;  // the orthonormal side
+  TensorLayout clay;  // center layout
+  if (l2r) {
+    fixed.lay = make_tensor_layout(bonds_[k], nb, site_phys_qn());
+    clay = make_tensor_layout(nb, bonds_[k + 2], site_phys_qn());
+  } else {
+    fixed.lay = make_tensor_layout(nb, bonds_[k + 2], site_phys_qn());
+    clay = make_tensor_layout(bonds_[k], nb, site_phys_qn());
+  }
+  fixed.buf.reserve(std::max<long>(fixed.lay.size, 1) * 8);
+  launch_fill(fixed.buf.as<double>(), fixed.lay.size, 0.0, st);
+  centers_.resize(nr);
+  for (int r = 0; r < nr; ++r) {
+    centers_[r].reserve(std::max<long>(clay.size, 1) * 8);
+    launch_fill(centers_[r].as<double>(), clay.size, 0.0, st);
+  }
+  for (size_t i = 0; i < mids.size(); ++i) {
+    if (kept[i] == 0) continue;
+    const Mid& m = mids[i];
+    int nm = kept[i];
+    int qi = new_index[i];
+    if (l2r) {
+      // A_k[(li, s1), q_m] = U rows; center_r = U^T Psi_r
+      for (int s1 = 0; s1 < 4; ++s1) {
+        const Part& rp = m.rows[s1];
+        if (rp.dim == 0) continue;
+        const Slab& as = fixed.lay.slabs[fixed.lay.slab_of_left[rp.idx]];
+        int b = as.block_of(s1, qi);
+        cdesc.insert(cdesc.end(), {oU[i] + rp.off, 1, mm[i], as.off + as.blocks[b].col0, as.width, 1, rp.dim, nm,
+                                   dbits(1.0)});
+      }
+      const Slab& cs = clay.slabs[clay.slab_of_left[qi]];
+      for (int r = 0; r < nr; ++r) {
+        int ib = (int)items.size();
+        items.push_back({Uv.as<double>() + oU[i], plain.as<double>() + off_plain[i] + (long)r * m.R * m.C, mm[i],
+                         m.R, m.R, 0, 1.0});
+        tile_units(units, centers_[r].as<double>() + cs.off, cs.width, nm, m.C, ib, ib + 1);
+      }
+    } else {
+      // B_{k+1}[q_m, (s2, ri)] = Vt rows; center_r = Psi_r Vt^T
+      const Slab& bs = fixed.lay.slabs[fixed.lay.slab_of_left[qi]];
+      cdesc.insert(cdesc.end(), {oV[i], 1, kk[i], bs.off, bs.width, 1, nm, m.C, dbits(1.0)});
+      for (int s1 = 0; s1 < 4; ++s1) {
+        const Part& rp = m.rows[s1];
+        if (rp.dim == 0) continue;
+        const Slab& cs = clay.slabs[clay.slab_of_left[rp.idx]];
+        int b = cs.block_of(s1, qi);
+        for (int r = 0; r < nr; ++r) {
+          int ib = (int)items.size();
+          items.push_back({plain.as<double>() + off_plain[i] + (long)r * m.R * m.C + rp.off,
+                           Vv.as<double>() + oV[i], m.R, kk[i], m.C, 0, 1.0});
+          tile_units(units, centers_[r].as<double>() + cs.off + cs.blocks[b].col0, cs.width, rp.dim, nm, ib, ib + 1);
+        }
+      }
+    }
+  }
+  check_desc(cdesc, 0, cdesc.size(), l2r ? sU : sV, fixed.lay.size);
+  if (!cdesc.empty()) {
+    DevMem cd;
+    cd.reserve(cdesc.size() * 8);
+    hip_check(hipMemcpyAsync(cd.p, cdesc.data(), cdesc.size() * 8, hipMemcpyHostToDevice, st), "cdesc");
+    launch_copy_blocks(cd.as<int64_t>(), (int)(cdesc.size() / 9), l2r ? Uv.as<double>() : Vv.as<double>(),
+                       fixed.buf.as<double>(), st);
+    hip_check(hipStreamSynchronize(st), "cdesc");
+  }
+  gemm_once(l2r ? GEMM_NT : GEMM_TN, items, units);
+  center_lay_ = clay;
+  if (l2r) {
+    mps_[k] = std::move(fixed);
+    mps_[k + 1].lay = clay;
+    mps_[k + 1].buf.reserve(std::max<long>(clay.size, 1) * 8);
+    launch_copy(mps_[k + 1].buf.as<double>(), centers_[0].as<double>(), clay.size, st);
+    center_site_ = k + 1;
+  } else {
+    mps_[k + 1] = std::move(fixed);
+    mps_[k].lay = clay;
+    mps_[k].buf.reserve(std::max<long>(clay.size, 1) * 8);
+    launch_copy(mps_[k].buf.as<double>(), centers_[0].as<double>(), clay.size, st);
+    center_site_ = k;
+  }
+  hip_check(hipStreamSynchronize(st), "svd step");
+  // next guesses
+  next_guess.clear();
+  next_guess.resize(nr);
+  if (l2r && k + 2 < L_) {
+    long sz = make_tensor_layout(bonds_[k + 1], bonds_[k + 3], twosite_phys_qn()).size;
+    SiteTensor c;
+    c.lay = clay;
+    for (int r = 0; r < nr; ++r) {
+      next_guess[r].reserve(std::max<long>(sz, 1) * 8);
+      std::swap(c.buf, centers_[r]);
+      form_twosite(k + 1, c, mps_[k + 2], next_guess[r].as<double>());
+      std::swap(c.buf, centers_[r]);
+    }
+  } else if (!l2r && k >= 1) {
+    long sz = make_tensor_layout(bonds_[k - 1], bonds_[k + 1], twosite_phys_qn()).size;
+    SiteTensor c;
+    c.lay = clay;
+    for (int r = 0; r < nr; ++r) {
+      next_guess[r].reserve(std::max<long>(sz, 1) * 8);
+      std::swap(c.buf, centers_[r]);
+      form_twosite(k - 1, mps_[k - 1], c, next_guess[r].as<double>());
+      std::swap(c.buf, centers_[r]);
+    }
+  }
+}
+
+// ------------------------------------------------------------------- sweeps --
+double Solver::sweep(int n_sweeps, std::vector<double>& energies) {
+  const int nr = opt_.n_states;
+  energies.assign(nr, 0.0);
+  std::vector<DevMem> guess;
+  double tau_max = 0;
+  // two-site guesses at the start of a half sweep: per-root centers when the
+  // previous truncation left them on one of the two sites, else the MPS itself
+  // (root 0) and seeded random vectors (further roots)
+  auto twosite_guess = [&](int k) {
+    guess.clear();
+    guess.resize(nr);
+    long sz = twosite_size(k);
+    for (int r = 0; r < nr; ++r) guess[r].reserve(std::max<long>(sz, 1) * 8);
+    bool have = (int)centers_.size() == nr && (center_site_ == k || center_site_ == k + 1);
+    Rng rng(opt_.seed + 7919);
+    for (int r = 0; r < nr; ++r) {
+      if (have) {
+        SiteTensor c;
+        c.lay = center_lay_;
+        std::swap(c.buf, centers_[r]);
+        if (center_site_ == k) form_twosite(k, c, mps_[k + 1], guess[r].as<double>());
+        else form_twosite(k, mps_[k], c, guess[r].as<double>());
+        std::swap(c.buf, centers_[r]);
+      } else if (r == 0) {
+        form_twosite(k, mps_[k], mps_[k + 1], guess[0].as<double>());
+      } else {
+        std::vector<double> h(sz);
+        for (auto& x : h) x = rng.normal();
+        hip_check(hipMemcpy(guess[r].p, h.data(), sz * 8, hipMemcpyHostToDevice), "guess");
+      }
+    }
+  };
+  for (int sw = 0; sw < n_sweeps; ++sw) {
+    tau_max = 0;
+    // left to right
+    for (int k = 0; k + 1 < L_; ++k) {
+      if (k == 0) twosite_guess(0);
+      prepare(k);
+      std::vector<double> ev;
+      davidson(k, guess, ev);
+      energies = ev;
+      double tau = 0;
+      auto t0 = std::chrono::steady_clock::now();
+      svd_step(k, true, nr, guess, tau);
+      st_.svd_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      tau_max = std::max(tau_max, tau);
+      auto t1 = std::chrono::steady_clock::now();
+      env_update_left(k, lf_);
+      hip_check(hipStreamSynchronize(st), "env");
+      st_.env_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count();
+      // sites k, k+1 changed: left envs beyond k+1 and right envs up to k+1 are stale
+      for (int c = k + 2; c <= L_; ++c) left_[c].valid = false;
+      for (int c = 0; c <= k + 1; ++c) right_[c].valid = false;
+      plan_k_ = -1;
+      if (opt_.verbose) fprintf(stderr, "sweep %d L->R k=%d E=%.12f tau=%.2e M=%d\n", sw, k, ev[0], tau, bonds_[k + 1].total());
+    }
+    // right to left
+    for (int k = L_ - 2; k >= 0; --k) {
+      if (k == L_ - 2) twosite_guess(k);
+      prepare(k);
+      std::vector<double> ev;
+      davidson(k, guess, ev);
+      energies = ev;
+      double tau = 0;
+      auto t0 = std::chrono::steady_clock::now();
+      svd_step(k, false, nr, guess, tau);
+      st_.svd_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      tau_max = std::max(tau_max, tau);
+      auto t1 = std::chrono::steady_clock::now();
+      env_update_right(k + 1, rf_);
+      hip_check(hipStreamSynchronize(st), "env");
+      st_.env_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count();
+      for (int c = 0; c <= k; ++c) right_[c].valid = false;
+      for (int c = k + 1; c <= L_; ++c) left_[c].valid = false;
+      plan_k_ = -1;
+      if (opt_.verbose) fprintf(stderr, "sweep %d R->L k=%d E=%.12f tau=%.2e M=%d\n", sw, k, ev[0], tau, bonds_[k + 1].total());
+    }
+  }
+  for (auto& e : energies) e += prob_->e_core;
+  st_.tau = tau_max;
+  return tau_max;
+}
+
+// <Psi_r|H|Psi_r>/<Psi_r|Psi_r> of the current MPS (root r via its center tensor).
+std::vector<double> Solver::mps_energy() {
+  const int nr = (center_site_ == 0 && (int)centers_.size() == opt_.n_states) ? opt_.n_states : 1;
+  prepare(0);
+  const long n = psi_lay_.size;
+  DevMem psi, sig, part, sc;
+  psi.reserve(n * 8);
+  sig.reserve(n * 8);
+  part.reserve(512 * 8 * 4);
+  sc.reserve(64);
+  std::vector<double> out;
+  for (int r = 0; r < nr; ++r) {
+    if (nr > 1) {
+      SiteTensor c;
+      c.lay = center_lay_;
+      std::swap(c.buf, centers_[r]);
+      form_twosite(0, c, mps_[1], psi.as<double>());
+      std::swap(c.buf, centers_[r]);
+    } else {
+      form_twosite(0, mps_[0], mps_[1], psi.as<double>());
+    }
+    sigma(0, PREC_F64, psi.as<double>(), sig.as<double>());
+    launch_dots(psi.as<double>(), n, 1, sig.as<double>(), n, part.as<double>(), sc.as<double>(), st);
+    launch_dots(psi.as<double>(), n, 1, psi.as<double>(), n, part.as<double>(), sc.as<double>() + 1, st);
+    double h[2];
+    hip_check(hipMemcpyAsync(h, sc.p, 16, hipMemcpyDeviceToHost, st), "energy");
+    hip_check(hipStreamSynchronize(st), "energy");
+    out.push_back(h[0] / h[1] + prob_->e_core);
+  }
+  return out;
+}
+
+}  // namespace dmrg

@@ -1,0 +1,230 @@
+// Two-site DMRG solver: device-resident MPS, environments, step plans, Davidson,
+// SVD truncation and the sweep (the paper's decimation step, Fig. 2).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <array>
+#include <map>
+#include <vector>
+
+#include "kernels.hpp"
+#include "layout.hpp"
+#include "problem.hpp"
+
+namespace dmrg {
+
+struct Options {
+  int M = 256;
+  int n_states = 1;
+  std::vector<double> weights;
+  double davidson_tol = 1e-10;
+  int max_iter = 200;
+  int max_subspace = 32;
+  int precision = PREC_F64;
+  int precond = 0;
+  unsigned long long seed = 1;
+  double tie_rtol = 1e-10;
+  double cut_rtol = 1e-14;
+  int verbose = 0;
+};
+
+// Grow-only device buffer.
+struct DevMem {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevMem() = default;
+  DevMem(const DevMem&) = delete;
+  DevMem& operator=(const DevMem&) = delete;
+  DevMem(DevMem&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevMem& operator=(DevMem&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevMem();
+  void reserve(size_t b);
+  void release();
+  template <class T> T* as() const { return (T*)p; }
+};
+
+void hip_check(hipError_t e, const char* what);
+
+// Environment at one cut: channels grouped by quantum-number shift.
+struct Env {
+  bool valid = false;
+  std::vector<EnvClass> classes;
+  std::vector<int> chan_class, chan_slot;
+  std::vector<long> class_base;
+  long size = 0;
+  DevMem buf;
+  long chan_off(int ch) const {
+    return class_base[chan_class[ch]] + (long)chan_slot[ch] * classes[chan_class[ch]].nnz;
+  }
+};
+
+struct SiteTensor {
+  TensorLayout lay;
+  DevMem buf;
+};
+
+// Buffer ids used by the relocatable plans.
+enum BufId : int {
+  B_PSI = 0,   // two-site input vector (or site tensor for env updates)
+  B_OUT,       // sigma output / new environment
+  B_T,         // intermediates X psi (or X A, B Y)
+  B_XMIX,      // premixed left factors
+  B_YMIX,      // premixed right factors
+  B_ENVL,      // left environment at cut k
+  B_ENVR,      // right environment at cut k+2
+  B_SITE2,     // second site tensor (right env update: B_j itself)
+  B_NBUF
+};
+
+struct PItem {
+  int abuf; long aoff; int bbuf; long boff;
+  int lda, ldb, K;
+  double coef;
+};
+struct PUnit {
+  int cbuf; long coff;
+  int ldc, M, N, m0, n0, ib, ie, acc;
+};
+
+// A relocatable grouped GEMM: one launch, pointers resolved per precision.
+struct Phase {
+  int mode = GEMM_NN;
+  std::vector<PItem> items;
+  std::vector<PUnit> units;
+  double flops = 0.0;  // useful (unpadded) flops
+  // device copies per precision
+  DevMem d_items[3], d_units[3];
+  std::vector<GemmItem> h_items[3];  // host staging kept alive for async copies
+  std::vector<GemmUnit> h_units[3];
+  const void* last_bases[3][B_NBUF] = {};
+  bool uploaded[3] = {false, false, false};
+};
+
+// One side's factors for a middle cut: X_{beta,op} = sum_alpha c L[alpha] (left)
+// or Y_{beta,op} = sum_gamma c R[gamma] (right), deduplicated.
+struct Factor {
+  int cls;        // class index in the env
+  bool alias;     // true: a single env channel (off into env), else premixed
+  long off;       // element offset (env buffer if alias, premix buffer otherwise)
+};
+struct FactorUse {
+  int op;
+  int f;
+  double scale;
+};
+struct FactorSide {
+  int cut = -1;
+  std::vector<Factor> fac;
+  std::vector<std::vector<FactorUse>> by_mid;  // per middle-cut channel
+  // premix program
+  std::vector<int> ptr;
+  std::vector<long> src_off;
+  std::vector<double> coef;
+  std::vector<long> out_off;  // per premixed output (element offset in premix buffer)
+  std::vector<long> out_nnz;
+  long premix_size = 0;
+  DevMem mix;
+  DevMem d_srcs, d_ptr, d_coef;
+  std::vector<const double*> h_srcs;
+};
+
+struct Stats {
+  int matvecs = 0;
+  int davidson_iters = 0;
+  double sigma_ms = 0, env_ms = 0, svd_ms = 0, davidson_other_ms = 0, premix_ms = 0;
+  double sigma_flops = 0;
+  double tau = 0;
+  int max_bond = 0;
+  int fallbacks = 0;
+  int converged = 1;
+};
+
+class Solver {
+ public:
+  Solver(const Problem* p, const Options& o, hipStream_t s);
+  ~Solver();
+
+  // MPS management
+  void init_random_mps();
+  void set_mps(const std::vector<Bond>& bonds, const std::vector<const double*>& sites_host);
+  const std::vector<Bond>& bonds() const { return bonds_; }
+
+  // prepare environments and plans for the two-site step at sites (k, k+1)
+  void prepare(int k);
+  long twosite_size(int k) const;
+  void sigma(int k, int prec, const double* psi, double* out);
+  void diag(int k, double* out);
+  double sweep(int n_sweeps, std::vector<double>& energies);
+  std::vector<double> mps_energy();
+  const Stats& stats() const { return st_; }
+  std::vector<double> env_host(int cut, int side);
+  const Problem* prob() const { return prob_; }
+
+  // sigma phase timing helpers for measurement
+  double last_sigma_flops() const;
+  double sigma_phase_ms(int which) const { return sigma_phase_ms_[which]; }
+
+ private:
+  const Problem* prob_;
+  Options opt_;
+  hipStream_t st;
+  rocblas_handle rb_ = nullptr;
+  int L_;
+  std::vector<Bond> bonds_;
+  std::vector<SiteTensor> mps_;
+  std::vector<Env> left_, right_;  // left_[c]: env of cut c built from sites < c; right_[c]: sites >= c
+  Stats st_;
+  double sigma_phase_ms_[4] = {0, 0, 0, 0};
+
+  // step plan (cached for the prepared step)
+  int plan_k_ = -1;
+  FactorSide lf_, rf_;
+  TensorLayout psi_lay_;
+  Phase phA_, phB_;
+  long t_size_ = 0;
+  DevMem psi_in_, out_buf_, t_buf_;
+  DevMem lowp_[B_NBUF];  // low-precision copies per buffer id
+  int lowp_prec_ = -1;
+  long lowp_size_[B_NBUF] = {0};
+  // diag plan
+  std::vector<DiagBlock> dblocks_;
+  std::vector<DiagTerm> dterms_host_;
+  DevMem d_dblocks_, d_dterms_, diagvec_;
+  bool diag_ready_ = false;
+  std::vector<long> dterm_x_off_, dterm_y_off_;
+  std::vector<int64_t> diag_desc_;
+
+  // internals
+  void ensure_left(int c);
+  void ensure_right(int c);
+  void make_env_layout(Env& e, int cut, const Bond& b);
+  void build_factor_side(FactorSide& fs, bool left, int site);
+  void run_premix(FactorSide& fs, const Env& env);
+  void env_update_left(int k, const FactorSide& fs);
+  void env_update_right(int j, const FactorSide& fs);
+  void build_sigma_plan(int k);
+  void build_diag_plan(int k);
+  void run_phase(Phase& ph, int prec, void* const* bases, size_t const* esz, const long* sizes);
+  void ensure_lowp(int prec);
+  void svd_step(int k, bool left_to_right, int nr, std::vector<DevMem>& next_guess, double& tau);
+  void form_twosite(int k, const SiteTensor& a, const SiteTensor& b, double* out);
+  int davidson(int k, std::vector<DevMem>& guess, std::vector<double>& evals);
+  void gemm_once(int mode, std::vector<GemmItem>& items, std::vector<GemmUnit>& units);
+
+  // Davidson workspace
+  DevMem dv_V_, dv_AV_, dv_G_, dv_evals_, dv_evecs_, dv_X_, dv_R_, dv_C_, dv_t_, dv_diag_, dv_part_,
+      dv_sc_;
+  std::vector<DevMem> centers_;    // per-root center tensors after the last truncation
+  TensorLayout center_lay_;
+  int center_site_ = -1;
+  DevMem scratch_items_, scratch_units_;
+  std::vector<GemmItem> scratch_h_items_;
+  std::vector<GemmUnit> scratch_h_units_;
+};
+
+}  // namespace dmrg

@@ -1,0 +1,138 @@
+"""GPU parity of the HIP sigma path against the CPU oracle (through the C ABI)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import embed
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fci_energies.json")
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _setup(n, na, nb, nq, M, seed_h=0, seed_mps=5):
+    torch = _torch()
+    import paper_2609_09990_amd as pk
+    h, B, e0 = synth.make_hamiltonian(n, nq, seed_h)
+    prob = pk.Problem(h, B, na, nb, e0)
+    sol = pk.Solver(prob, M=M)
+    mps = synth.random_mps(n, na, nb, M, seed=seed_mps)
+    sol.set_mps(mps["bonds"], mps["sites"])
+    return torch, pk, h, B, prob, sol, mps
+
+
+@pytest.mark.parametrize("n,na,nb,nq,M,k", [
+    (4, 2, 2, 5, 16, 1),       # tiny, full bonds
+    (6, 3, 3, 8, 12, 0),       # left edge, truncated (ragged) sectors
+    (6, 3, 3, 8, 12, 2),
+    (6, 3, 2, 8, 20, 4),       # right edge, odd electron count
+    (8, 4, 4, 16, 40, 3),
+    (10, 5, 5, 12, 1024, 4),   # middle of CAS(10,10) at full bond: blocks of 100 (two tiles + tail)
+])
+def test_sigma_matches_oracle_projection(n, na, nb, nq, M, k):
+    torch, pk, h, B, prob, sol, mps = _setup(n, na, nb, nq, M)
+    print(f"case n={n} M={M} k={k}", flush=True)
+    size = sol.prepare(k)
+    psi = synth.random_twosite(mps["bonds"], k, seed=11)
+    assert psi.size == size
+    ref = embed.sigma_twosite(h, B, mps, k, psi, na, nb)
+    d_psi = torch.from_numpy(psi).cuda()
+    d_out = torch.zeros_like(d_psi)
+    flops = sol.sigma(k, d_psi, d_out)
+    torch.cuda.synchronize()
+    got = d_out.cpu().numpy()
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert err <= 1e-12, err
+    assert flops > 0
+
+
+def test_sigma_hermitian_and_deterministic():
+    torch, pk, h, B, prob, sol, mps = _setup(8, 4, 4, 16, 60)
+    k = 3
+    size = sol.prepare(k)
+    rng = np.random.default_rng(3)
+    x = torch.from_numpy(rng.standard_normal(size)).cuda()
+    y = torch.from_numpy(rng.standard_normal(size)).cuda()
+    hx, hy, hx2 = torch.zeros_like(x), torch.zeros_like(x), torch.zeros_like(x)
+    sol.sigma(k, x, hx)
+    sol.sigma(k, y, hy)
+    sol.sigma(k, x, hx2)
+    torch.cuda.synchronize()
+    a = float(torch.dot(x, hy))
+    b = float(torch.dot(y, hx))
+    assert abs(a - b) <= 1e-12 * float(torch.norm(hx)) * float(torch.norm(y))
+    assert torch.equal(hx, hx2)  # fixed summation order: bitwise reproducible
+
+
+def test_diag_matches_sigma_on_unit_vectors():
+    torch, pk, h, B, prob, sol, mps = _setup(6, 3, 3, 8, 30)
+    k = 2
+    size = sol.prepare(k)
+    d = torch.zeros(size, dtype=torch.float64, device="cuda")
+    sol.diag(k, d)
+    rng = np.random.default_rng(0)
+    idx = rng.choice(size, size=min(size, 25), replace=False)
+    for i in idx:
+        e = torch.zeros(size, dtype=torch.float64, device="cuda")
+        e[int(i)] = 1.0
+        out = torch.zeros_like(e)
+        sol.sigma(k, e, out)
+        torch.cuda.synchronize()
+        assert abs(float(out[int(i)]) - float(d[int(i)])) <= 1e-12 * max(1.0, abs(float(d[int(i)])))
+
+
+@pytest.mark.parametrize("prec,tol", [(1, 1e-5), (2, 3e-2)])
+def test_low_precision_sigma_close_to_fp64(prec, tol):
+    torch, pk, h, B, prob, sol, mps = _setup(8, 4, 4, 16, 60)
+    k = 3
+    size = sol.prepare(k)
+    psi = torch.from_numpy(synth.random_twosite(mps["bonds"], k, seed=4)).cuda()
+    o64, olo = torch.zeros_like(psi), torch.zeros_like(psi)
+    sol.sigma(k, psi, o64, 0)
+    sol.sigma(k, psi, olo, prec)
+    torch.cuda.synchronize()
+    err = float(torch.norm(olo - o64) / torch.norm(o64))
+    assert err < tol, err
+
+
+def _gold(name):
+    return json.load(open(GOLD))[name]
+
+
+def test_dmrg_full_bond_equals_fci_cas8():
+    """CAS(8,8), 32 Cholesky vectors, M = 256 = full middle bond: DMRG = FCI."""
+    torch = _torch()
+    import paper_2609_09990_amd as pk
+    g = _gold("cas8_nq32_s0")
+    h, B, e0 = synth.make_hamiltonian(8, 32, 0)
+    prob = pk.Problem(h, B, 4, 4, e0)
+    sol = pk.Solver(prob, M=256, tol=1e-10)
+    e, tau, ok = sol.sweep(4)
+    em = sol.energy()
+    print("cas8 E", e, "mps", em, "fci", g["energies"][0], "tau", tau, sol.stats(), flush=True)
+    assert ok
+    assert abs(e[0] - g["energies"][0]) <= 1e-10
+    assert abs(em[0] - g["energies"][0]) <= 1e-10
+
+
+def test_state_averaged_full_bond_cas6():
+    torch = _torch()
+    import paper_2609_09990_amd as pk
+    g = _gold("cas6_nq12_s3")
+    h, B, e0 = synth.make_hamiltonian(6, 12, 3)
+    prob = pk.Problem(h, B, 3, 3, e0)
+    sol = pk.Solver(prob, M=64, n_states=3, tol=1e-10)
+    e, tau, ok = sol.sweep(3)
+    print("cas6 SA", e, g["energies"], flush=True)
+    assert ok
+    assert np.max(np.abs(np.array(e) - np.array(g["energies"]))) <= 1e-10
