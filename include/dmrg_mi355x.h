@@ -131,6 +131,12 @@ dmrg_status dmrg_diag(dmrg_solver* s, int k, double* diag);
  * reach the tolerance (results still written). */
 dmrg_status dmrg_sweep(dmrg_solver* s, int n_sweeps, double* energies, double* tau);
 
+/* One two-site step on sites (k, k+1): Davidson on H_eff, SVD truncation to M,
+ * environment update; direction 0 moves the center right (k -> k+1), 1 moves
+ * it left.  A sweep is steps 0..n_orb-2 in direction 0 then n_orb-2..0 in 1.
+ * energies[n_states]: Ritz values + e_core; tau: discarded weight. */
+dmrg_status dmrg_step(dmrg_solver* s, int k, int direction, double* energies, double* tau);
+
 /* <Psi|H|Psi>/<Psi|Psi> + e_core of the current MPS (per root after a sweep). */
 dmrg_status dmrg_energy(dmrg_solver* s, double* energies);
 
@@ -150,8 +156,11 @@ dmrg_status dmrg_block_gemm(int precision, int mode, int M, int N, int K, const 
 
 /* Run statistics (host doubles): [0] matvecs, [1] Davidson iterations,
  * [2] sigma ms, [3] env-update ms, [4] SVD ms, [5] sigma flops, [6] tau,
- * [7] max bond dimension, [8] preconditioner fallbacks, [9] converged (0/1).
- * n: capacity of out. */
+ * [7] max bond dimension, [8] preconditioner fallbacks, [9] converged (0/1),
+ * [10] sigma phase-A ms (T = X psi), [11] sigma phase-B ms (long-K products),
+ * [12] phase-A flops, [13] phase-B flops, [14] environment-update flops,
+ * [15] fp64 refinements.  Times are HIP-event times on the solver stream and
+ * flops count unpadded block products.  n: capacity of out. */
 dmrg_status dmrg_get_stats(const dmrg_solver* s, double* out, int n);
 
 const char* dmrg_last_error(void);

@@ -29,6 +29,7 @@ from ._lib import (  # noqa: F401
     dmrg_sigma,
     dmrg_solver_create,
     dmrg_solver_destroy,
+    dmrg_step,
     dmrg_sweep,
     lib,
 )

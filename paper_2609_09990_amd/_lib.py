@@ -49,6 +49,7 @@ dmrg_sigma = _decl("dmrg_sigma", [_p, _i, _i, _p, _p, C.POINTER(_d)])
 dmrg_diag = _decl("dmrg_diag", [_p, _i, _p])
 dmrg_sweep = _decl("dmrg_sweep", [_p, _i, _p, C.POINTER(_d)])
 dmrg_energy = _decl("dmrg_energy", [_p, _p])
+dmrg_step = _decl("dmrg_step", [_p, _i, _i, _p, C.POINTER(_d)])
 dmrg_get_stats = _decl("dmrg_get_stats", [_p, _p, _i])
 dmrg_block_gemm = _decl("dmrg_block_gemm", [_i, _i, _i, _i, _i, _p, _i, _p, _i, _p, _i, _d, _p])
 dmrg_get_env = _decl("dmrg_get_env", [_p, _i, _i, _p, _i64, C.POINTER(_i64)])
@@ -171,6 +172,14 @@ class Solver:
             _check(code)
         return e, tau.value, code == 0
 
+    def step(self, k, direction=0):
+        e = np.zeros(self.n_states)
+        tau = C.c_double()
+        code = dmrg_step(self.h, k, direction, _ptr(e), C.byref(tau))
+        if code not in (0, -4):
+            _check(code)
+        return e, tau.value, code == 0
+
     def energy(self):
         e = np.zeros(self.n_states)
         _check(dmrg_energy(self.h, _ptr(e)))
@@ -185,10 +194,11 @@ class Solver:
         return out
 
     def stats(self):
-        s = np.zeros(10)
-        _check(dmrg_get_stats(self.h, _ptr(s), 10))
+        s = np.zeros(16)
+        _check(dmrg_get_stats(self.h, _ptr(s), 16))
         keys = ["matvecs", "davidson_iters", "sigma_ms", "env_ms", "svd_ms", "sigma_flops", "tau",
-                "max_bond", "fallbacks", "converged"]
+                "max_bond", "fallbacks", "converged", "sigma_a_ms", "sigma_b_ms", "sigma_a_flops",
+                "sigma_b_flops", "env_flops", "refinements"]
         return dict(zip(keys, s.tolist()))
 
     def __del__(self):

@@ -254,6 +254,22 @@ dmrg_status dmrg_sweep(dmrg_solver* s, int n_sweeps, double* energies, double* t
   return st;
 }
 
+dmrg_status dmrg_step(dmrg_solver* s, int k, int direction, double* energies, double* tau) {
+  dmrg_status st = guard([&] {
+    DMRG_REQUIRE(s && energies, ST_EINVAL, "NULL argument");
+    DMRG_REQUIRE(direction == 0 || direction == 1, ST_EINVAL, "direction must be 0 or 1");
+    std::vector<double> e;
+    double t = s->s->step(k, direction == 0, e);
+    for (size_t i = 0; i < e.size(); ++i) energies[i] = e[i];
+    if (tau) *tau = t;
+  });
+  if (st == DMRG_OK && s && !s->s->stats().converged) {
+    g_err = "Davidson did not reach the tolerance";
+    return DMRG_ENOCONV;
+  }
+  return st;
+}
+
 dmrg_status dmrg_energy(dmrg_solver* s, double* energies) {
   return guard([&] {
     DMRG_REQUIRE(s && energies, ST_EINVAL, "NULL argument");
@@ -300,9 +316,11 @@ dmrg_status dmrg_get_stats(const dmrg_solver* s, double* out, int n) {
   return guard([&] {
     DMRG_REQUIRE(s && out, ST_EINVAL, "NULL argument");
     const Stats& t = s->s->stats();
-    double v[10] = {(double)t.matvecs, (double)t.davidson_iters, t.sigma_ms, t.env_ms, t.svd_ms,
-                    t.sigma_flops, t.tau, (double)t.max_bond, (double)t.fallbacks, (double)t.converged};
-    for (int i = 0; i < n && i < 10; ++i) out[i] = v[i];
+    double v[16] = {(double)t.matvecs, (double)t.davidson_iters, t.sigma_ms, t.env_ms, t.svd_ms,
+                    t.sigma_flops, t.tau, (double)t.max_bond, (double)t.fallbacks, (double)t.converged,
+                    t.sigma_a_ms, t.sigma_b_ms, t.sigma_a_flops, t.sigma_b_flops, t.env_flops,
+                    (double)t.refinements};
+    for (int i = 0; i < n && i < 16; ++i) out[i] = v[i];
   });
 }
 

@@ -322,6 +322,7 @@ void Solver::env_update_left(int k, const FactorSide& fs) {
   sizes[B_ENVL] = envk.size;
   run_phase(pa, PREC_F64, bases, esz, sizes);
   run_phase(pb, PREC_F64, bases, esz, sizes);
+  st_.env_flops += pa.flops + pb.flops;
   hip_check(hipStreamSynchronize(st), "env update");  // local plan buffers die here
   out.valid = true;
 }
@@ -440,6 +441,7 @@ void Solver::env_update_right(int j, const FactorSide& fs) {
   sizes[B_SITE2] = Bt.lay.size;
   run_phase(pa, PREC_F64, bases, esz, sizes);
   run_phase(pb, PREC_F64, bases, esz, sizes);
+  st_.env_flops += pa.flops + pb.flops;
   hip_check(hipStreamSynchronize(st), "env update");  // local plan buffers die here
   out.valid = true;
 }

@@ -346,6 +346,10 @@ void Solver::sigma(int k, int prec, const double* psi, double* out) {
   (void)hipEventElapsedTime(&b, e1, e2);
   sigma_phase_ms_[0] = a;
   sigma_phase_ms_[1] = b;
+  st_.sigma_a_ms += a;
+  st_.sigma_b_ms += b;
+  st_.sigma_a_flops += phA_.flops;
+  st_.sigma_b_flops += phB_.flops;
   st_.sigma_ms += a + b;
   st_.sigma_flops += phA_.flops + phB_.flops;
   st_.matvecs++;
@@ -538,6 +542,7 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
         for (int i = 0; i < nr; ++i) launch_dots(V, n, i + 1, AV + (long)i * n, n, part, G + (long)i * ldg, st);
         kcur = nr;
         exact_basis = true;  // residual of the next RR is exact
+        st_.refinements++;
         best_lo = 1e300;
         stall = 0;
         continue;
@@ -838,85 +843,84 @@ void Solver::svd_step(int k, bool l2r, int nr, std::vector<DevMem>& next_guess, 
 }
 
 // ------------------------------------------------------------------- sweeps --
-double Solver::sweep(int n_sweeps, std::vector<double>& energies) {
+// Two-site guesses for step k: the truncation's next-step guesses when they
+// were made for this step, else the per-root centers when the last truncation
+// left them on site k or k+1, else the MPS itself (root 0) and seeded random
+// vectors (further roots).
+void Solver::make_guess(int k, bool l2r) {
   const int nr = opt_.n_states;
-  energies.assign(nr, 0.0);
-  std::vector<DevMem> guess;
-  double tau_max = 0;
-  // two-site guesses at the start of a half sweep: per-root centers when the
-  // previous truncation left them on one of the two sites, else the MPS itself
-  // (root 0) and seeded random vectors (further roots)
-  auto twosite_guess = [&](int k) {
-    guess.clear();
-    guess.resize(nr);
-    long sz = twosite_size(k);
-    for (int r = 0; r < nr; ++r) guess[r].reserve(std::max<long>(sz, 1) * 8);
-    bool have = (int)centers_.size() == nr && (center_site_ == k || center_site_ == k + 1);
-    Rng rng(opt_.seed + 7919);
-    for (int r = 0; r < nr; ++r) {
-      if (have) {
-        SiteTensor c;
-        c.lay = center_lay_;
-        std::swap(c.buf, centers_[r]);
-        if (center_site_ == k) form_twosite(k, c, mps_[k + 1], guess[r].as<double>());
-        else form_twosite(k, mps_[k], c, guess[r].as<double>());
-        std::swap(c.buf, centers_[r]);
-      } else if (r == 0) {
-        form_twosite(k, mps_[k], mps_[k + 1], guess[0].as<double>());
-      } else {
-        std::vector<double> h(sz);
-        for (auto& x : h) x = rng.normal();
-        hip_check(hipMemcpy(guess[r].p, h.data(), sz * 8, hipMemcpyHostToDevice), "guess");
-      }
-    }
-  };
-  for (int sw = 0; sw < n_sweeps; ++sw) {
-    tau_max = 0;
-    // left to right
-    for (int k = 0; k + 1 < L_; ++k) {
-      if (k == 0) twosite_guess(0);
-      prepare(k);
-      std::vector<double> ev;
-      davidson(k, guess, ev);
-      energies = ev;
-      double tau = 0;
-      auto t0 = std::chrono::steady_clock::now();
-      svd_step(k, true, nr, guess, tau);
-      st_.svd_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-      tau_max = std::max(tau_max, tau);
-      auto t1 = std::chrono::steady_clock::now();
-      env_update_left(k, lf_);
-      hip_check(hipStreamSynchronize(st), "env");
-      st_.env_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count();
-      // sites k, k+1 changed: left envs beyond k+1 and right envs up to k+1 are stale
-      for (int c = k + 2; c <= L_; ++c) left_[c].valid = false;
-      for (int c = 0; c <= k + 1; ++c) right_[c].valid = false;
-      plan_k_ = -1;
-      if (opt_.verbose) fprintf(stderr, "sweep %d L->R k=%d E=%.12f tau=%.2e M=%d\n", sw, k, ev[0], tau, bonds_[k + 1].total());
-    }
-    // right to left
-    for (int k = L_ - 2; k >= 0; --k) {
-      if (k == L_ - 2) twosite_guess(k);
-      prepare(k);
-      std::vector<double> ev;
-      davidson(k, guess, ev);
-      energies = ev;
-      double tau = 0;
-      auto t0 = std::chrono::steady_clock::now();
-      svd_step(k, false, nr, guess, tau);
-      st_.svd_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-      tau_max = std::max(tau_max, tau);
-      auto t1 = std::chrono::steady_clock::now();
-      env_update_right(k + 1, rf_);
-      hip_check(hipStreamSynchronize(st), "env");
-      st_.env_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count();
-      for (int c = 0; c <= k; ++c) right_[c].valid = false;
-      for (int c = k + 1; c <= L_; ++c) left_[c].valid = false;
-      plan_k_ = -1;
-      if (opt_.verbose) fprintf(stderr, "sweep %d R->L k=%d E=%.12f tau=%.2e M=%d\n", sw, k, ev[0], tau, bonds_[k + 1].total());
+  if (guess_k_ == k && guess_l2r_ == l2r && (int)guess_.size() == nr) return;
+  guess_.clear();
+  guess_.resize(nr);
+  long sz = twosite_size(k);
+  for (int r = 0; r < nr; ++r) guess_[r].reserve(std::max<long>(sz, 1) * 8);
+  bool have = (int)centers_.size() == nr && (center_site_ == k || center_site_ == k + 1);
+  Rng rng(opt_.seed + 7919);
+  for (int r = 0; r < nr; ++r) {
+    if (have) {
+      SiteTensor c;
+      c.lay = center_lay_;
+      std::swap(c.buf, centers_[r]);
+      if (center_site_ == k) form_twosite(k, c, mps_[k + 1], guess_[r].as<double>());
+      else form_twosite(k, mps_[k], c, guess_[r].as<double>());
+      std::swap(c.buf, centers_[r]);
+    } else if (r == 0) {
+      form_twosite(k, mps_[k], mps_[k + 1], guess_[0].as<double>());
+    } else {
+      std::vector<double> h(sz);
+      for (auto& x : h) x = rng.normal();
+      hip_check(hipMemcpy(guess_[r].p, h.data(), sz * 8, hipMemcpyHostToDevice), "guess");
     }
   }
+  guess_k_ = k;
+  guess_l2r_ = l2r;
+}
+
+// One two-site step (Fig. 2 of the paper): solve H_eff on sites (k, k+1) with
+// Davidson, decimate with the SVD, move the center, update the environment.
+double Solver::step(int k, bool l2r, std::vector<double>& energies) {
+  DMRG_REQUIRE(k >= 0 && k + 1 < L_, ST_EINVAL, "two-site step out of range");
+  make_guess(k, l2r);
+  prepare(k);
+  std::vector<double> ev;
+  davidson(k, guess_, ev);
+  energies = ev;
   for (auto& e : energies) e += prob_->e_core;
+  double tau = 0;
+  auto t0 = std::chrono::steady_clock::now();
+  svd_step(k, l2r, opt_.n_states, guess_, tau);
+  guess_k_ = l2r ? k + 1 : k - 1;
+  guess_l2r_ = l2r;
+  if (guess_k_ < 0 || guess_k_ + 1 >= L_) guess_k_ = -1;
+  st_.svd_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  auto t1 = std::chrono::steady_clock::now();
+  if (l2r) {
+    env_update_left(k, lf_);
+    // sites k, k+1 changed: left envs beyond k+1 and right envs up to k+1 are stale
+    for (int c = k + 2; c <= L_; ++c) left_[c].valid = false;
+    for (int c = 0; c <= k + 1; ++c) right_[c].valid = false;
+  } else {
+    env_update_right(k + 1, rf_);
+    for (int c = 0; c <= k; ++c) right_[c].valid = false;
+    for (int c = k + 1; c <= L_; ++c) left_[c].valid = false;
+  }
+  hip_check(hipStreamSynchronize(st), "env");
+  st_.env_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count();
+  plan_k_ = -1;
+  st_.tau = tau;
+  if (opt_.verbose)
+    fprintf(stderr, "%s k=%d E=%.12f tau=%.2e M=%d\n", l2r ? "L->R" : "R->L", k, energies[0], tau,
+            bonds_[k + 1].total());
+  return tau;
+}
+
+double Solver::sweep(int n_sweeps, std::vector<double>& energies) {
+  double tau_max = 0;
+  for (int sw = 0; sw < n_sweeps; ++sw) {
+    tau_max = 0;
+    for (int k = 0; k + 1 < L_; ++k) tau_max = std::max(tau_max, step(k, true, energies));
+    for (int k = L_ - 2; k >= 0; --k) tau_max = std::max(tau_max, step(k, false, energies));
+  }
   st_.tau = tau_max;
   return tau_max;
 }

@@ -138,10 +138,12 @@ struct Stats {
   int davidson_iters = 0;
   double sigma_ms = 0, env_ms = 0, svd_ms = 0, davidson_other_ms = 0, premix_ms = 0;
   double sigma_flops = 0;
+  double sigma_a_ms = 0, sigma_b_ms = 0, sigma_a_flops = 0, sigma_b_flops = 0, env_flops = 0;
   double tau = 0;
   int max_bond = 0;
   int fallbacks = 0;
   int converged = 1;
+  int refinements = 0;
 };
 
 class Solver {
@@ -160,6 +162,7 @@ class Solver {
   void sigma(int k, int prec, const double* psi, double* out);
   void diag(int k, double* out);
   double sweep(int n_sweeps, std::vector<double>& energies);
+  double step(int k, bool left_to_right, std::vector<double>& energies);
   std::vector<double> mps_energy();
   const Stats& stats() const { return st_; }
   std::vector<double> env_host(int cut, int side);
@@ -220,6 +223,10 @@ class Solver {
   DevMem dv_V_, dv_AV_, dv_G_, dv_evals_, dv_evecs_, dv_X_, dv_R_, dv_C_, dv_t_, dv_diag_, dv_part_,
       dv_sc_;
   std::vector<DevMem> centers_;    // per-root center tensors after the last truncation
+  std::vector<DevMem> guess_;      // Davidson start vectors for step guess_k_
+  int guess_k_ = -1;
+  bool guess_l2r_ = true;
+  void make_guess(int k, bool l2r);
   TensorLayout center_lay_;
   int center_site_ = -1;
   DevMem scratch_items_, scratch_units_;
