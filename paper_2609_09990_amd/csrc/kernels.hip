@@ -283,6 +283,111 @@ __global__ __launch_bounds__(256) void gemm_bf16(const GemmUnit* __restrict__ un
       }
 }
 
+// Small-tile fp64 GEMM: one wave owns a 32x32 tile (2x2 MFMA 16x16 blocks) and
+// loads its MFMA operands straight from global memory (k step 4, no LDS, no
+// barriers), so short-K items cost little padding and waves never wait on each
+// other.  Four independent waves per workgroup.  accumulate == 2 writes the
+// tile into a 32x32 partial slot (split-K), reduced later in a fixed order.
+template <int MODE>
+__device__ inline double ld_a(const double* A, int lda, int m, int k) {
+  return MODE == GEMM_TN ? A[(long)k * lda + m] : A[(long)m * lda + k];
+}
+template <int MODE>
+__device__ inline double ld_b(const double* B, int ldb, int k, int n) {
+  return MODE == GEMM_NT ? B[(long)n * ldb + k] : B[(long)k * ldb + n];
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void gemm_f64_w32(const GemmUnit* __restrict__ units,
+                                                    const GemmItem* __restrict__ items, int n_units) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ui = blockIdx.x * 4 + wave;
+  if (ui >= n_units) return;  // whole wave exits; the kernel has no barriers
+  const GemmUnit u = units[ui];
+  const int r = lane & 15, kq = lane >> 4;
+  const int am0 = u.m0 + r, am1 = u.m0 + 16 + r, bn0 = u.n0 + r, bn1 = u.n0 + 16 + r;
+  const bool av0 = am0 < u.M, av1 = am1 < u.M, bv0 = bn0 < u.N, bv1 = bn1 < u.N;
+  v4d acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+  for (int it = u.ib; it < u.ie; ++it) {
+    const GemmItem g = items[it];
+    const double* A = (const double*)g.A;
+    const double* B = (const double*)g.B;
+    const double c = g.coef;
+    int k0 = 0;
+    for (; k0 + 8 <= g.K; k0 += 8) {  // two k steps in flight
+      const int ka = k0 + kq, kb = k0 + 4 + kq;
+      double a0 = av0 ? ld_a<MODE>(A, g.lda, am0, ka) : 0.0;
+      double a1 = av1 ? ld_a<MODE>(A, g.lda, am1, ka) : 0.0;
+      double b0 = bv0 ? ld_b<MODE>(B, g.ldb, ka, bn0) : 0.0;
+      double b1 = bv1 ? ld_b<MODE>(B, g.ldb, ka, bn1) : 0.0;
+      double a2 = av0 ? ld_a<MODE>(A, g.lda, am0, kb) : 0.0;
+      double a3 = av1 ? ld_a<MODE>(A, g.lda, am1, kb) : 0.0;
+      double b2 = bv0 ? ld_b<MODE>(B, g.ldb, kb, bn0) : 0.0;
+      double b3 = bv1 ? ld_b<MODE>(B, g.ldb, kb, bn1) : 0.0;
+      a0 *= c;
+      a1 *= c;
+      a2 *= c;
+      a3 *= c;
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b2, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b3, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, b2, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, b3, acc[1][1], 0, 0, 0);
+    }
+    for (; k0 < g.K; k0 += 4) {
+      const int ka = k0 + kq;
+      const bool kv = ka < g.K;
+      double a0 = (av0 && kv) ? ld_a<MODE>(A, g.lda, am0, ka) * c : 0.0;
+      double a1 = (av1 && kv) ? ld_a<MODE>(A, g.lda, am1, ka) * c : 0.0;
+      double b0 = (bv0 && kv) ? ld_b<MODE>(B, g.ldb, ka, bn0) : 0.0;
+      double b1 = (bv1 && kv) ? ld_b<MODE>(B, g.ldb, ka, bn1) : 0.0;
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+  }
+  double* C = (double*)u.C;
+  // accumulator element q of lane l: row l/16 + 4q, column l%16 (fp64 16x16x4 layout)
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        int tr = 16 * i + kq + 4 * q, tc = 16 * j + r;
+        int gm = u.m0 + tr, gn = u.n0 + tc;
+        double v = acc[i][j][q];
+        if (u.accumulate == 2) {
+          C[tr * 32 + tc] = v;  // partial slot, full 32x32 (masked entries are zero)
+        } else if (gm < u.M && gn < u.N) {
+          long idx = (long)gm * u.ldc + gn;
+          C[idx] = u.accumulate ? C[idx] + v : v;
+        }
+      }
+}
+
+// Split-K reduction: out tile += nothing; out tile = sum of its partial slots in order.
+__global__ void splitk_reduce(const SplitTile* __restrict__ tiles, const double* __restrict__ slots) {
+  const SplitTile t = tiles[blockIdx.x];
+  double* C = (double*)t.C;
+  for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
+    int tr = e >> 5, tc = e & 31;
+    int gm = t.m0 + tr, gn = t.n0 + tc;
+    if (gm >= t.M || gn >= t.N) continue;
+    double acc = 0.0;
+    for (int s = 0; s < t.ns; ++s) acc += slots[(long)(t.s0 + s) * 1024 + e];
+    C[(long)gm * t.ldc + gn] = acc;
+  }
+}
+
 __global__ void premix_kernel(double* __restrict__ out, const double* const* __restrict__ srcs,
                               const int* __restrict__ ptr, const double* __restrict__ coef,
                               long nnz) {
@@ -549,6 +654,19 @@ inline int grid_for(long n, int bs = 256, int cap = 4096) {
 }
 
 }  // namespace
+
+void launch_gemm_w32(int mode, const GemmUnit* units, int n_units, const GemmItem* items,
+                     hipStream_t s) {
+  if (n_units <= 0) return;
+  dim3 grid((n_units + 3) / 4), block(256);
+  if (mode == GEMM_NN) gemm_f64_w32<GEMM_NN><<<grid, block, 0, s>>>(units, items, n_units);
+  else if (mode == GEMM_NT) gemm_f64_w32<GEMM_NT><<<grid, block, 0, s>>>(units, items, n_units);
+  else gemm_f64_w32<GEMM_TN><<<grid, block, 0, s>>>(units, items, n_units);
+}
+
+void launch_splitk_reduce(const SplitTile* tiles, int n, const double* slots, hipStream_t s) {
+  if (n > 0) splitk_reduce<<<n, 256, 0, s>>>(tiles, slots);
+}
 
 void launch_gemm(int prec, int mode, const GemmUnit* units, int n_units, const GemmItem* items,
                  hipStream_t s) {

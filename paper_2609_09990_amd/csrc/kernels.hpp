@@ -34,6 +34,19 @@ enum GemmPrec : int { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2 };
 void launch_gemm(int prec, int mode, const GemmUnit* units, int n_units, const GemmItem* items,
                  hipStream_t s);
 
+// fp64 32x32-tile variant (one wave per unit, operands from global memory).
+// Units with accumulate == 2 write a full 32x32 partial tile to C (split-K).
+void launch_gemm_w32(int mode, const GemmUnit* units, int n_units, const GemmItem* items,
+                     hipStream_t s);
+
+// Output tile (rows m0.., cols n0.. of an M x N block) = sum of ns partial slots
+// s0..s0+ns-1 (each 32x32, row-major), summed in slot order.
+struct SplitTile {
+  void* C;
+  int ldc, M, N, m0, n0, s0, ns;
+};
+void launch_splitk_reduce(const SplitTile* tiles, int n, const double* slots, hipStream_t s);
+
 // out[f][j] = sum_{i in [ptr[f], ptr[f+1])} coef[i] * src[idx[i]][j], j < nnz.
 void launch_premix(double* out, const double* const* srcs, const int* ptr, const double* coef,
                    int n_out, long nnz, hipStream_t s);

@@ -17,6 +17,11 @@
 
 #include "solver.hpp"
 
+// smallest split-K chunk, in MFMA k-steps of one 32x32 tile
+#ifndef DMRG_SPLIT_MIN
+#define DMRG_SPLIT_MIN 256.0
+#endif
+
 namespace dmrg {
 
 void Solver::make_env_layout(Env& e, int cut, const Bond& b) {
@@ -152,10 +157,11 @@ void Solver::run_premix(FactorSide& fs, const Env& env) {
   }
 }
 
+// One logical unit per output block; tiles are cut when the plan is resolved
+// (the tile shape depends on the kernel chosen for the precision).
 static void add_units(std::vector<PUnit>& units, int cbuf, long coff, int ldc, int M, int N, int ib,
                       int ie, int acc) {
-  for (int m0 = 0; m0 < M; m0 += 64)
-    for (int n0 = 0; n0 < N; n0 += 64) units.push_back({cbuf, coff, ldc, M, N, m0, n0, ib, ie, acc});
+  units.push_back({cbuf, coff, ldc, M, N, 0, 0, ib, ie, acc});
 }
 
 // Host check that every tile of every item stays inside its buffer (in
@@ -183,8 +189,7 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
   bool same = ph.uploaded[slot];
   for (int b = 0; b < B_NBUF && same; ++b) same = ph.last_bases[slot][b] == bases[b];
   if (same) {  // plan already resolved against these buffers
-    launch_gemm(prec, ph.mode, ph.d_units[slot].as<GemmUnit>(), (int)ph.units.size(),
-                ph.d_items[slot].as<GemmItem>(), st);
+    launch_resolved(ph, prec, slot);
     return;
   }
   validate_phase(ph, sizes);
@@ -203,24 +208,68 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
     items[i].coef = p.coef;
   }
   std::vector<GemmUnit>& units = ph.h_units[slot];
-  units.resize(ph.units.size());
-  for (size_t i = 0; i < units.size(); ++i) {
-    const PUnit& u = ph.units[i];
-    units[i].C = (char*)bases[u.cbuf] + u.coff * esz[u.cbuf];
-    units[i].ldc = u.ldc;
-    units[i].M = u.M;
-    units[i].N = u.N;
-    units[i].m0 = u.m0;
-    units[i].n0 = u.n0;
-    units[i].ib = u.ib;
-    units[i].ie = u.ie;
-    units[i].accumulate = u.acc;
+  units.clear();
+  std::vector<SplitTile>& tiles = ph.h_tiles[slot];
+  tiles.clear();
+  long n_slots = 0;
+  if (prec == PREC_F64) {
+    // 32x32 tiles; long item lists are cut into chunks of about `chunk` MFMA
+    // k-steps, each writing a partial tile that splitk_reduce sums in order.
+    double work = 0;
+    for (const PUnit& u : ph.units)
+      for (int i = u.ib; i < u.ie; ++i) work += ((u.M + 31) / 32) * ((u.N + 31) / 32) * ((ph.items[i].K + 3) / 4);
+    const double chunk = std::max(DMRG_SPLIT_MIN, work / 16384.0);
+    for (const PUnit& u : ph.units) {
+      char* C = (char*)bases[u.cbuf] + u.coff * esz[u.cbuf];
+      for (int m0 = 0; m0 < u.M; m0 += 32)
+        for (int n0 = 0; n0 < u.N; n0 += 32) {
+          double w = 0;
+          for (int i = u.ib; i < u.ie; ++i) w += (ph.items[i].K + 3) / 4;
+          if (w <= chunk || u.ie - u.ib <= 1) {
+            units.push_back({C, u.ldc, u.M, u.N, m0, n0, u.ib, u.ie, u.acc});
+            continue;
+          }
+          int s0 = (int)n_slots, b = u.ib;
+          while (b < u.ie) {
+            int e = b;
+            double cw = 0;
+            while (e < u.ie && (cw < chunk || e == b)) cw += (ph.items[e++].K + 3) / 4;
+            units.push_back({(void*)(intptr_t)(n_slots * 1024), 32, u.M, u.N, m0, n0, b, e, 2});
+            ++n_slots;
+            b = e;
+          }
+          tiles.push_back({C, u.ldc, u.M, u.N, m0, n0, s0, (int)(n_slots - s0)});
+        }
+    }
+    ph.slots.reserve(std::max<long>(n_slots, 1) * 1024 * sizeof(double));
+    for (auto& un : units)
+      if (un.accumulate == 2) un.C = ph.slots.as<double>() + (intptr_t)un.C;
+  } else {
+    for (const PUnit& u : ph.units) {
+      char* C = (char*)bases[u.cbuf] + u.coff * esz[u.cbuf];
+      for (int m0 = 0; m0 < u.M; m0 += 64)
+        for (int n0 = 0; n0 < u.N; n0 += 64) units.push_back({C, u.ldc, u.M, u.N, m0, n0, u.ib, u.ie, u.acc});
+    }
   }
+  ph.n_units[slot] = (int)units.size();
+  ph.n_tiles[slot] = (int)tiles.size();
   ph.d_items[slot].reserve(items.size() * sizeof(GemmItem) + 64);
   ph.d_units[slot].reserve(units.size() * sizeof(GemmUnit) + 64);
+  ph.d_tiles[slot].reserve(tiles.size() * sizeof(SplitTile) + 64);
   hip_check(hipMemcpyAsync(ph.d_items[slot].p, items.data(), items.size() * sizeof(GemmItem), hipMemcpyHostToDevice, st), "items");
   hip_check(hipMemcpyAsync(ph.d_units[slot].p, units.data(), units.size() * sizeof(GemmUnit), hipMemcpyHostToDevice, st), "units");
-  launch_gemm(prec, ph.mode, ph.d_units[slot].as<GemmUnit>(), (int)units.size(), ph.d_items[slot].as<GemmItem>(), st);
+  if (!tiles.empty())
+    hip_check(hipMemcpyAsync(ph.d_tiles[slot].p, tiles.data(), tiles.size() * sizeof(SplitTile), hipMemcpyHostToDevice, st), "tiles");
+  launch_resolved(ph, prec, slot);
+}
+
+void Solver::launch_resolved(Phase& ph, int prec, int slot) {
+  if (prec == PREC_F64) {
+    launch_gemm_w32(ph.mode, ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot], ph.d_items[slot].as<GemmItem>(), st);
+    launch_splitk_reduce(ph.d_tiles[slot].as<SplitTile>(), ph.n_tiles[slot], ph.slots.as<double>(), st);
+  } else {
+    launch_gemm(prec, ph.mode, ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot], ph.d_items[slot].as<GemmItem>(), st);
+  }
 }
 
 // L_{k+1}[beta] = sum_{(op,X)} s sum_{ss'} op[s][s'] A_s^T X A_{s'}
@@ -543,6 +592,29 @@ void Solver::build_sigma_plan(int k) {
       add_units(phB_.units, B_OUT, dst.off + dst.blocks[ob].col0, dst.width, dst.ml, dst.blocks[ob].mr, ib,
                 (int)phB_.items.size(), 0);
     }
+  if (opt_.verbose > 1) {
+    // shape statistics: executed (tile-padded) vs useful flops per phase
+    for (const Phase* ph : {&phA_, &phB_}) {
+      double padded = 0, kpad = 0, ksum = 0;
+      long nit = 0;
+      for (const PUnit& u : ph->units)
+        for (int i = u.ib; i < u.ie; ++i) {
+          int K = ph->items[i].K;
+          padded += 2.0 * 32 * 32 * ((u.M + 31) / 32) * ((u.N + 31) / 32) * ((K + 3) / 4 * 4);
+          kpad += (K + 3) / 4 * 4;
+          ksum += K;
+          ++nit;
+        }
+      fprintf(stderr, "plan k=%d phase %s: units %zu items %zu (unit-items %ld) useful %.3e padded %.3e (x%.1f) "
+              "mean K %.1f (padded %.1f)\n", k, ph == &phA_ ? "A" : "B", ph->units.size(), ph->items.size(), nit,
+              ph->flops, padded, padded / std::max(ph->flops, 1.0), ksum / std::max(nit, 1L), kpad / std::max(nit, 1L));
+    }
+    std::string dims;
+    for (auto& s : bonds_[k].sec) dims += std::to_string(s.dim) + " ";
+    fprintf(stderr, "bond %d sectors %zu dims: %s\n", k, bonds_[k].sec.size(), dims.c_str());
+    fprintf(stderr, "factors: left %zu (premixed %zu) right %zu (premixed %zu), T %ld doubles, psi %ld\n",
+            lf_.fac.size(), lf_.out_off.size(), rf_.fac.size(), rf_.out_off.size(), t_size_, P.size);
+  }
 }
 
 void Solver::build_diag_plan(int k) {

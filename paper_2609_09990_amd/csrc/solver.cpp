@@ -64,10 +64,13 @@ void check_desc(const std::vector<int64_t>& d, size_t begin, size_t end, long sr
   for (size_t i = begin; i < end; i += 9) {
     long rows = d[i + 6], cols = d[i + 7];
     if (rows <= 0 || cols <= 0) continue;
-    long smax = d[i] + (rows - 1) * d[i + 1] + (cols - 1) * d[i + 2];
-    long dmax = d[i + 3] + (rows - 1) * d[i + 4] + (cols - 1) * d[i + 5];
-    if (d[i] < 0 || d[i + 3] < 0 || smax >= src_n || dmax >= dst_n)
-      throw Error(ST_EINVAL, "block copy out of bounds");
+    for (int side = 0; side < 2; ++side) {  // all four corners (strides may be negative)
+      long base = d[i + 3 * side], rs = d[i + 1 + 3 * side], cs = d[i + 2 + 3 * side];
+      long lim = side ? dst_n : src_n;
+      long lo = base + std::min(0L, (rows - 1) * rs) + std::min(0L, (cols - 1) * cs);
+      long hi = base + std::max(0L, (rows - 1) * rs) + std::max(0L, (cols - 1) * cs);
+      if (lo < 0 || hi >= lim) throw Error(ST_EINVAL, "block copy out of bounds");
+    }
   }
 }
 
@@ -311,20 +314,23 @@ void Solver::sigma(int k, int prec, const double* psi, double* out) {
   (void)hipEventCreate(&e1);
   (void)hipEventCreate(&e2);
   if (prec == PREC_F64) {
+    // fixed input/output buffers keep the resolved plan valid for every call
     void* bases[B_NBUF] = {};
-    bases[B_PSI] = (void*)psi;
-    bases[B_OUT] = (void*)out;
+    bases[B_PSI] = psi_in_.p;
+    bases[B_OUT] = out_buf_.p;
     bases[B_T] = t_buf_.p;
     bases[B_XMIX] = lf_.mix.p;
     bases[B_YMIX] = rf_.mix.p;
     bases[B_ENVL] = left_[k].buf.p;
     bases[B_ENVR] = right_[k + 2].buf.p;
     size_t esz[B_NBUF] = {8, 8, 8, 8, 8, 8, 8, 8};
+    launch_copy(psi_in_.as<double>(), psi, n, st);
     (void)hipEventRecord(e0, st);
     run_phase(phA_, PREC_F64, bases, esz, sizes);
     (void)hipEventRecord(e1, st);
     run_phase(phB_, PREC_F64, bases, esz, sizes);
     (void)hipEventRecord(e2, st);
+    launch_copy(out, out_buf_.as<double>(), n, st);
   } else {
     ensure_lowp(prec);
     void* bases[B_NBUF] = {};
@@ -619,19 +625,16 @@ void Solver::svd_step(int k, bool l2r, int nr, std::vector<DevMem>& next_guess, 
       m.C += bk2.sec[ri].dim;
     }
   }
-  // gather: per root matrix (column-major, R x C) and the weighted SVD input
-  long tot_plain = 0, tot_svd = 0;
-  std::vector<long> off_plain(mids.size()), off_svd(mids.size());
+  // gather: per-root sector matrices Psi_r (column-major, R x C)
+  long tot_plain = 0;
+  std::vector<long> off_plain(mids.size());
   for (size_t i = 0; i < mids.size(); ++i) {
     off_plain[i] = tot_plain;
     tot_plain += (long)mids[i].R * mids[i].C * nr;
-    off_svd[i] = tot_svd;
-    tot_svd += (long)mids[i].R * mids[i].C * nr;
   }
-  DevMem plain, work, Sv, Uv, Vv, Ev, info;
+  DevMem plain, gram, evals, info, Uv, Vv;
   plain.reserve(std::max<long>(tot_plain, 1) * 8);
-  work.reserve(std::max<long>(tot_svd, 1) * 8);
-  std::vector<int64_t> desc_plain, desc_svd;
+  std::vector<int64_t> desc_plain;
   for (size_t mi = 0; mi < mids.size(); ++mi) {
     const Mid& m = mids[mi];
     for (int s1 = 0; s1 < 4; ++s1) {
@@ -645,65 +648,83 @@ void Solver::svd_step(int k, bool l2r, int nr, std::vector<DevMem>& next_guess, 
         if (b < 0) continue;
         for (int r = 0; r < nr; ++r) {
           long src = (long)r * n + sl.off + sl.blocks[b].col0;
-          // plain per root: column-major R x C at off_plain + r*R*C
           long dst = off_plain[mi] + (long)r * m.R * m.C + rp.off + (long)cp.off * m.R;
           desc_plain.insert(desc_plain.end(), {src, sl.width, 1, dst, 1, m.R, rp.dim, cp.dim, dbits(1.0)});
-          double w = std::sqrt(opt_.weights[r]);
-          long dsv;
-          if (l2r)  // horizontal concatenation: R x (nr C), ld R
-            dsv = off_svd[mi] + rp.off + ((long)r * m.C + cp.off) * m.R;
-          else      // vertical: (nr R) x C, ld nr R
-            dsv = off_svd[mi] + (long)r * m.R + rp.off + (long)cp.off * nr * m.R;
-          long ld = l2r ? m.R : (long)nr * m.R;
-          desc_svd.insert(desc_svd.end(), {src, sl.width, 1, dsv, 1, ld, rp.dim, cp.dim, dbits(w)});
         }
       }
     }
   }
   check_desc(desc_plain, 0, desc_plain.size(), (long)nr * n, tot_plain);
-  check_desc(desc_svd, 0, desc_svd.size(), (long)nr * n, tot_svd);
   launch_fill(plain.as<double>(), tot_plain, 0.0, st);
-  launch_fill(work.as<double>(), tot_svd, 0.0, st);
   DevMem dd;
-  dd.reserve((desc_plain.size() + desc_svd.size()) * 8 + 8);
-  std::vector<int64_t> all = desc_plain;
-  all.insert(all.end(), desc_svd.begin(), desc_svd.end());
-  hip_check(hipMemcpyAsync(dd.p, all.data(), all.size() * 8, hipMemcpyHostToDevice, st), "svd desc");
+  dd.reserve(desc_plain.size() * 8 + 8);
+  hip_check(hipMemcpyAsync(dd.p, desc_plain.data(), desc_plain.size() * 8, hipMemcpyHostToDevice, st), "svd desc");
   launch_copy_blocks(dd.as<int64_t>(), (int)(desc_plain.size() / 9), dv_X_.as<double>(), plain.as<double>(), st);
-  launch_copy_blocks(dd.as<int64_t>() + desc_plain.size(), (int)(desc_svd.size() / 9), dv_X_.as<double>(),
-                     work.as<double>(), st);
-  // SVDs
-  long sS = 0, sU = 0, sV = 0;
-  std::vector<long> oS(mids.size()), oU(mids.size()), oV(mids.size());
-  std::vector<int> mm(mids.size()), nn(mids.size()), kk(mids.size());
+  // Density matrix of the sector (the reduced density matrix of the kept side):
+  // moving right G = sum_r w_r Psi_r Psi_r^T (R x R), moving left sum_r w_r Psi_r^T Psi_r
+  // (C x C).  Its eigenvalues are the squared singular values of the weighted
+  // concatenation and its eigenvectors the kept singular vectors.  Sectors are
+  // padded with zeros into size buckets, one batched eigensolve per bucket.
+  auto bucket_of = [](int d) { return d <= 64 ? std::max(8, (d + 7) / 8 * 8) : (d + 63) / 64 * 64; };
+  std::vector<int> gd(mids.size()), gb(mids.size());
+  std::map<int, std::vector<int>> buckets;
   for (size_t i = 0; i < mids.size(); ++i) {
-    mm[i] = l2r ? mids[i].R : nr * mids[i].R;
-    nn[i] = l2r ? nr * mids[i].C : mids[i].C;
-    kk[i] = std::min(mm[i], nn[i]);
-    oS[i] = sS;
-    sS += kk[i];
-    oU[i] = sU;
-    sU += (long)mm[i] * kk[i];
-    oV[i] = sV;
-    sV += (long)kk[i] * nn[i];
+    gd[i] = l2r ? mids[i].R : mids[i].C;
+    gb[i] = bucket_of(std::max(gd[i], 1));
+    buckets[gb[i]].push_back((int)i);
   }
-  Sv.reserve(std::max<long>(sS, 1) * 8);
-  Uv.reserve(std::max<long>(sU, 1) * 8);
-  Vv.reserve(std::max<long>(sV, 1) * 8);
-  Ev.reserve(std::max<long>(sS, 1) * 8);
-  info.reserve(mids.size() * sizeof(rocblas_int) + 8);
+  std::vector<long> goff(mids.size()), eoff(mids.size());
+  long gtot = 0, etot = 0;
+  for (auto& bk_ : buckets)
+    for (int i : bk_.second) {
+      goff[i] = gtot;
+      gtot += (long)gb[i] * gb[i];
+      eoff[i] = etot;
+      etot += gb[i];
+    }
+  gram.reserve(std::max<long>(gtot, 1) * 8);
+  evals.reserve(std::max<long>(etot, 1) * 8 * 2);
+  info.reserve((mids.size() + 1) * sizeof(rocblas_int));
+  launch_fill(gram.as<double>(), gtot, 0.0, st);
+  {
+    std::vector<GemmItem> items;
+    std::vector<GemmUnit> units;
+    for (size_t i = 0; i < mids.size(); ++i) {
+      const Mid& m = mids[i];
+      if (m.R == 0 || m.C == 0) continue;
+      int ib = (int)items.size();
+      for (int r = 0; r < nr; ++r) {
+        const double* Pr = plain.as<double>() + off_plain[i] + (long)r * m.R * m.C;
+        // moving right: TN with K = C (A = B = Psi_r read as C x R row-major);
+        // moving left: NT with K = R (A = B = Psi_r read as C x R row-major)
+        items.push_back({Pr, Pr, m.R, m.R, l2r ? m.C : m.R, 0, opt_.weights[r]});
+      }
+      tile_units(units, gram.as<double>() + goff[i], gb[i], gd[i], gd[i], ib, (int)items.size());
+    }
+    gemm_once(l2r ? GEMM_TN : GEMM_NT, items, units);
+  }
+  for (auto& bk_ : buckets) {
+    int nbk = bk_.first;
+    int first = bk_.second[0];
+    rocblas_status rs = rocsolver_dsyevd_strided_batched(
+        rb_, rocblas_evect_original, rocblas_fill_upper, nbk, gram.as<double>() + goff[first], nbk,
+        (rocblas_stride)nbk * nbk, evals.as<double>() + eoff[first], nbk, evals.as<double>() + etot + eoff[first],
+        nbk, info.as<rocblas_int>(), (rocblas_int)bk_.second.size());
+    if (rs != rocblas_status_success) throw Error(ST_EHIP, "rocsolver_dsyevd_strided_batched failed");
+  }
+  std::vector<double> E(etot);
+  hip_check(hipMemcpyAsync(E.data(), evals.p, etot * 8, hipMemcpyDeviceToHost, st), "eigenvalues");
+  hip_check(hipStreamSynchronize(st), "eigensolve");
+  // singular values per sector, descending: the largest gd eigenvalues of each padded block
+  std::vector<long> oS(mids.size());
+  std::vector<int> kk(mids.size());
+  std::vector<double> S;
   for (size_t i = 0; i < mids.size(); ++i) {
-    if (kk[i] == 0) continue;
-    rocblas_status rs = rocsolver_dgesvd(rb_, rocblas_svect_singular, rocblas_svect_singular, mm[i], nn[i],
-                                         work.as<double>() + off_svd[i], mm[i], Sv.as<double>() + oS[i],
-                                         Uv.as<double>() + oU[i], mm[i], Vv.as<double>() + oV[i], kk[i],
-                                         Ev.as<double>() + oS[i], rocblas_outofplace,
-                                         info.as<rocblas_int>() + i);
-    if (rs != rocblas_status_success) throw Error(ST_EHIP, "rocsolver_dgesvd failed");
+    kk[i] = (mids[i].R == 0 || mids[i].C == 0) ? 0 : std::min(gd[i], l2r ? nr * mids[i].C : nr * mids[i].R);
+    oS[i] = (long)S.size();
+    for (int t = 0; t < kk[i]; ++t) S.push_back(std::sqrt(std::max(0.0, E[eoff[i] + gb[i] - 1 - t])));
   }
-  std::vector<double> S(sS);
-  hip_check(hipMemcpyAsync(S.data(), Sv.p, sS * 8, hipMemcpyDeviceToHost, st), "S");
-  hip_check(hipStreamSynchronize(st), "svd");
+  const long sS = (long)S.size();
   // global truncation with the cluster rule
   struct SV { double s; int mid, j; };
   std::vector<SV> all_sv;
@@ -712,7 +733,9 @@ void Solver::svd_step(int k, bool l2r, int nr, std::vector<DevMem>& next_guess, 
   std::stable_sort(all_sv.begin(), all_sv.end(), [](const SV& a, const SV& b) { return a.s > b.s; });
   double s1 = all_sv.empty() ? 0.0 : all_sv[0].s;
   long keep = std::min<long>((long)all_sv.size(), opt_.M);
-  while (keep > 0 && all_sv[keep - 1].s <= opt_.cut_rtol * s1) --keep;
+  // singular values from density-matrix eigenvalues resolve only down to ~1e-8 s_1
+  const double cut = std::max(opt_.cut_rtol, 1e-7);
+  while (keep > 0 && all_sv[keep - 1].s <= cut * s1) --keep;
   if (keep < (long)all_sv.size() && keep > 0) {
     while (keep > 1 && all_sv[keep - 1].s - all_sv[keep].s <= opt_.tie_rtol * s1) --keep;
   }
@@ -731,6 +754,38 @@ void Solver::svd_step(int k, bool l2r, int nr, std::vector<DevMem>& next_guess, 
     }
   bonds_[k + 1] = nb;
   st_.max_bond = std::max(st_.max_bond, nb.total());
+  // kept singular vectors in descending order: U (R x nm, column-major) moving
+  // right, V^T (nm x C, column-major) moving left
+  std::vector<long> oU(mids.size(), 0), oV(mids.size(), 0);
+  std::vector<int> mm(mids.size(), 0);
+  {
+    long su = 0;
+    std::vector<int64_t> vdesc;
+    for (size_t i = 0; i < mids.size(); ++i) {
+      if (kept[i] == 0) continue;
+      int d = gd[i], nm = kept[i];
+      long top = goff[i] + (long)(gb[i] - 1) * gb[i];  // column of the largest eigenvalue
+      if (l2r) {
+        oU[i] = su;
+        mm[i] = d;
+        vdesc.insert(vdesc.end(), {top, 1, -(int64_t)gb[i], su, 1, d, d, nm, dbits(1.0)});
+      } else {
+        oV[i] = su;
+        kk[i] = nm;
+        vdesc.insert(vdesc.end(), {top, 1, -(int64_t)gb[i], su, nm, 1, d, nm, dbits(1.0)});
+      }
+      su += (long)d * nm;
+    }
+    DevMem& dst = l2r ? Uv : Vv;
+    dst.reserve(std::max<long>(su, 1) * 8);
+    check_desc(vdesc, 0, vdesc.size(), gtot, su);
+    DevMem vd;
+    vd.reserve(vdesc.size() * 8 + 8);
+    hip_check(hipMemcpyAsync(vd.p, vdesc.data(), vdesc.size() * 8, hipMemcpyHostToDevice, st), "vdesc");
+    launch_copy_blocks(vd.as<int64_t>(), (int)(vdesc.size() / 9), gram.as<double>(), dst.as<double>(), st);
+    hip_check(hipStreamSynchronize(st), "vdesc");
+    sU_total_ = su;
+  }
   // new tensors
   std::vector<GemmItem> items;
   std::vector<GemmUnit> units;
@@ -791,7 +846,7 @@ void Solver::svd_step(int k, bool l2r, int nr, std::vector<DevMem>& next_guess, 
       }
     }
   }
-  check_desc(cdesc, 0, cdesc.size(), l2r ? sU : sV, fixed.lay.size);
+  check_desc(cdesc, 0, cdesc.size(), sU_total_, fixed.lay.size);
   if (!cdesc.empty()) {
     DevMem cd;
     cd.reserve(cdesc.size() * 8);

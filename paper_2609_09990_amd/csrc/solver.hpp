@@ -101,6 +101,9 @@ struct Phase {
   DevMem d_items[3], d_units[3];
   std::vector<GemmItem> h_items[3];  // host staging kept alive for async copies
   std::vector<GemmUnit> h_units[3];
+  std::vector<SplitTile> h_tiles[3];
+  DevMem d_tiles[3], slots;          // split-K tile table and partial slots (fp64)
+  int n_units[3] = {0, 0, 0}, n_tiles[3] = {0, 0, 0};
   const void* last_bases[3][B_NBUF] = {};
   bool uploaded[3] = {false, false, false};
 };
@@ -213,6 +216,7 @@ class Solver {
   void build_sigma_plan(int k);
   void build_diag_plan(int k);
   void run_phase(Phase& ph, int prec, void* const* bases, size_t const* esz, const long* sizes);
+  void launch_resolved(Phase& ph, int prec, int slot);
   void ensure_lowp(int prec);
   void svd_step(int k, bool left_to_right, int nr, std::vector<DevMem>& next_guess, double& tau);
   void form_twosite(int k, const SiteTensor& a, const SiteTensor& b, double* out);
@@ -228,6 +232,7 @@ class Solver {
   bool guess_l2r_ = true;
   void make_guess(int k, bool l2r);
   TensorLayout center_lay_;
+  long sU_total_ = 0;  // size of the kept singular-vector buffer of the last truncation
   int center_site_ = -1;
   DevMem scratch_items_, scratch_units_;
   std::vector<GemmItem> scratch_h_items_;
