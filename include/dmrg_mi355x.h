@@ -154,12 +154,19 @@ dmrg_status dmrg_get_env(dmrg_solver* s, int cut, int side, double* host, int64_
 dmrg_status dmrg_block_gemm(int precision, int mode, int M, int N, int K, const void* A, int lda,
                             const void* B, int ldb, void* C, int ldc, double coef, void* hip_stream);
 
+/* Profiling aid: the fp64 sigma kernels exist as two identical instantiations
+ * (names gemm_f64_w32<mode, 1|2> and <mode, 3|4>); tag 0 (default) launches the
+ * first pair, tag 1 the second, so a profiler can separate e.g. timed from
+ * untimed launches.  No effect on results. */
+dmrg_status dmrg_set_kernel_tag(dmrg_solver* s, int tag);
+
 /* Run statistics (host doubles): [0] matvecs, [1] Davidson iterations,
  * [2] sigma ms, [3] env-update ms, [4] SVD ms, [5] sigma flops, [6] tau,
  * [7] max bond dimension, [8] preconditioner fallbacks, [9] converged (0/1),
  * [10] sigma phase-A ms (T = X psi), [11] sigma phase-B ms (long-K products),
  * [12] phase-A flops, [13] phase-B flops, [14] environment-update flops,
- * [15] fp64 refinements.  Times are HIP-event times on the solver stream and
+ * [15] fp64 refinements, [16] phase-B GEMM kernel ms alone (fp64; without the
+ * split-K reduction).  Times are HIP-event times on the solver stream and
  * flops count unpadded block products.  n: capacity of out. */
 dmrg_status dmrg_get_stats(const dmrg_solver* s, double* out, int n);
 

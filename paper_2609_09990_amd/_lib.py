@@ -50,6 +50,7 @@ dmrg_diag = _decl("dmrg_diag", [_p, _i, _p])
 dmrg_sweep = _decl("dmrg_sweep", [_p, _i, _p, C.POINTER(_d)])
 dmrg_energy = _decl("dmrg_energy", [_p, _p])
 dmrg_step = _decl("dmrg_step", [_p, _i, _i, _p, C.POINTER(_d)])
+dmrg_set_kernel_tag = _decl("dmrg_set_kernel_tag", [_p, _i])
 dmrg_get_stats = _decl("dmrg_get_stats", [_p, _p, _i])
 dmrg_block_gemm = _decl("dmrg_block_gemm", [_i, _i, _i, _i, _i, _p, _i, _p, _i, _p, _i, _d, _p])
 dmrg_get_env = _decl("dmrg_get_env", [_p, _i, _i, _p, _i64, C.POINTER(_i64)])
@@ -180,6 +181,9 @@ class Solver:
             _check(code)
         return e, tau.value, code == 0
 
+    def set_kernel_tag(self, tag):
+        _check(dmrg_set_kernel_tag(self.h, tag))
+
     def energy(self):
         e = np.zeros(self.n_states)
         _check(dmrg_energy(self.h, _ptr(e)))
@@ -194,11 +198,11 @@ class Solver:
         return out
 
     def stats(self):
-        s = np.zeros(16)
-        _check(dmrg_get_stats(self.h, _ptr(s), 16))
+        s = np.zeros(17)
+        _check(dmrg_get_stats(self.h, _ptr(s), 17))
         keys = ["matvecs", "davidson_iters", "sigma_ms", "env_ms", "svd_ms", "sigma_flops", "tau",
                 "max_bond", "fallbacks", "converged", "sigma_a_ms", "sigma_b_ms", "sigma_a_flops",
-                "sigma_b_flops", "env_flops", "refinements"]
+                "sigma_b_flops", "env_flops", "refinements", "sigma_b_gemm_ms"]
         return dict(zip(keys, s.tolist()))
 
     def __del__(self):

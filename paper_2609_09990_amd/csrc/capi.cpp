@@ -312,15 +312,22 @@ dmrg_status dmrg_block_gemm(int precision, int mode, int M, int N, int K, const 
   });
 }
 
+dmrg_status dmrg_set_kernel_tag(dmrg_solver* s, int tag) {
+  return guard([&] {
+    DMRG_REQUIRE(s && (tag == 0 || tag == 1), ST_EINVAL, "tag must be 0 or 1");
+    s->s->set_kernel_tag(tag);
+  });
+}
+
 dmrg_status dmrg_get_stats(const dmrg_solver* s, double* out, int n) {
   return guard([&] {
     DMRG_REQUIRE(s && out, ST_EINVAL, "NULL argument");
     const Stats& t = s->s->stats();
-    double v[16] = {(double)t.matvecs, (double)t.davidson_iters, t.sigma_ms, t.env_ms, t.svd_ms,
+    double v[17] = {(double)t.matvecs, (double)t.davidson_iters, t.sigma_ms, t.env_ms, t.svd_ms,
                     t.sigma_flops, t.tau, (double)t.max_bond, (double)t.fallbacks, (double)t.converged,
                     t.sigma_a_ms, t.sigma_b_ms, t.sigma_a_flops, t.sigma_b_flops, t.env_flops,
-                    (double)t.refinements};
-    for (int i = 0; i < n && i < 16; ++i) out[i] = v[i];
+                    (double)t.refinements, t.sigma_b_gemm_ms};
+    for (int i = 0; i < n && i < 17; ++i) out[i] = v[i];
   });
 }
 

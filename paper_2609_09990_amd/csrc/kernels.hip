@@ -297,7 +297,9 @@ __device__ inline double ld_b(const double* B, int ldb, int k, int n) {
   return MODE == GEMM_NT ? B[(long)n * ldb + k] : B[(long)k * ldb + n];
 }
 
-template <int MODE>
+// TAG only names otherwise identical instantiations, so a profiler can tell
+// launches apart (e.g. sigma phases, timed and untimed work).
+template <int MODE, int TAG>
 __global__ __launch_bounds__(256) void gemm_f64_w32(const GemmUnit* __restrict__ units,
                                                     const GemmItem* __restrict__ items, int n_units) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -655,13 +657,22 @@ inline int grid_for(long n, int bs = 256, int cap = 4096) {
 
 }  // namespace
 
-void launch_gemm_w32(int mode, const GemmUnit* units, int n_units, const GemmItem* items,
+void launch_gemm_w32(int mode, int tag, const GemmUnit* units, int n_units, const GemmItem* items,
                      hipStream_t s) {
   if (n_units <= 0) return;
   dim3 grid((n_units + 3) / 4), block(256);
-  if (mode == GEMM_NN) gemm_f64_w32<GEMM_NN><<<grid, block, 0, s>>>(units, items, n_units);
-  else if (mode == GEMM_NT) gemm_f64_w32<GEMM_NT><<<grid, block, 0, s>>>(units, items, n_units);
-  else gemm_f64_w32<GEMM_TN><<<grid, block, 0, s>>>(units, items, n_units);
+#define DMRG_W32_LAUNCH(T)                                                                      \
+  if (mode == GEMM_NN) gemm_f64_w32<GEMM_NN, T><<<grid, block, 0, s>>>(units, items, n_units); \
+  else if (mode == GEMM_NT) gemm_f64_w32<GEMM_NT, T><<<grid, block, 0, s>>>(units, items, n_units); \
+  else gemm_f64_w32<GEMM_TN, T><<<grid, block, 0, s>>>(units, items, n_units);
+  switch (tag) {
+    case 1: DMRG_W32_LAUNCH(1) break;
+    case 2: DMRG_W32_LAUNCH(2) break;
+    case 3: DMRG_W32_LAUNCH(3) break;
+    case 4: DMRG_W32_LAUNCH(4) break;
+    default: DMRG_W32_LAUNCH(0) break;
+  }
+#undef DMRG_W32_LAUNCH
 }
 
 void launch_splitk_reduce(const SplitTile* tiles, int n, const double* slots, hipStream_t s) {

@@ -36,7 +36,7 @@ void launch_gemm(int prec, int mode, const GemmUnit* units, int n_units, const G
 
 // fp64 32x32-tile variant (one wave per unit, operands from global memory).
 // Units with accumulate == 2 write a full 32x32 partial tile to C (split-K).
-void launch_gemm_w32(int mode, const GemmUnit* units, int n_units, const GemmItem* items,
+void launch_gemm_w32(int mode, int tag, const GemmUnit* units, int n_units, const GemmItem* items,
                      hipStream_t s);
 
 // Output tile (rows m0.., cols n0.. of an M x N block) = sum of ns partial slots

@@ -265,7 +265,9 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
 
 void Solver::launch_resolved(Phase& ph, int prec, int slot) {
   if (prec == PREC_F64) {
-    launch_gemm_w32(ph.mode, ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot], ph.d_items[slot].as<GemmItem>(), st);
+    launch_gemm_w32(ph.mode, ph.tag, ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot],
+                    ph.d_items[slot].as<GemmItem>(), st);
+    if (ph.gemm_done) (void)hipEventRecord(ph.gemm_done, st);  // GEMM-only timing
     launch_splitk_reduce(ph.d_tiles[slot].as<SplitTile>(), ph.n_tiles[slot], ph.slots.as<double>(), st);
   } else {
     launch_gemm(prec, ph.mode, ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot], ph.d_items[slot].as<GemmItem>(), st);

@@ -94,6 +94,8 @@ struct PUnit {
 // A relocatable grouped GEMM: one launch, pointers resolved per precision.
 struct Phase {
   int mode = GEMM_NN;
+  int tag = 0;  // kernel instantiation name tag (profiling only)
+  hipEvent_t gemm_done = nullptr;  // if set, recorded between the GEMM and the split-K reduction
   std::vector<PItem> items;
   std::vector<PUnit> units;
   double flops = 0.0;  // useful (unpadded) flops
@@ -142,6 +144,7 @@ struct Stats {
   double sigma_ms = 0, env_ms = 0, svd_ms = 0, davidson_other_ms = 0, premix_ms = 0;
   double sigma_flops = 0;
   double sigma_a_ms = 0, sigma_b_ms = 0, sigma_a_flops = 0, sigma_b_flops = 0, env_flops = 0;
+  double sigma_b_gemm_ms = 0;  // phase-B GEMM kernel alone (without the split-K reduction)
   double tau = 0;
   int max_bond = 0;
   int fallbacks = 0;
@@ -173,6 +176,9 @@ class Solver {
 
   // sigma phase timing helpers for measurement
   double last_sigma_flops() const;
+  // 0: sigma phases launch the tag-1/2 kernel instantiations, 1: tag-3/4
+  void set_kernel_tag(int t) { kernel_tag_ = t ? 1 : 0; }
+  int kernel_tag_ = 0;
   double sigma_phase_ms(int which) const { return sigma_phase_ms_[which]; }
 
  private:
