@@ -61,7 +61,7 @@ typedef enum { DMRG_PRECOND_DIAG = 0, DMRG_PRECOND_LEARNED = 1 } dmrg_precond;
 typedef struct {
   int M;               /* bond dimension (kept states per bond) */
   int n_states;        /* roots, state-averaged when > 1 (1..8) */
-  const double* weights; /* n_states state-averaging weights, NULL = equal */
+  const double* weights; /* n_states state-averaging weights (>= 0, normalised to sum 1), NULL = equal */
   double davidson_tol; /* ||H_eff x - theta x||_2 per root, with ||x|| = 1 */
   int max_iter;        /* Davidson iterations per step */
   int max_subspace;    /* Davidson subspace size (<= 64) */
@@ -69,7 +69,8 @@ typedef struct {
   int precond;         /* dmrg_precond */
   unsigned long long seed; /* initial MPS and extra-root start vectors */
   double tie_rtol;     /* truncation never splits singular values closer than tie_rtol * s_1 */
-  double cut_rtol;     /* singular values <= cut_rtol * s_1 are always dropped */
+  double cut_rtol;     /* when truncating, singular values <= cut_rtol * s_1 go first; nothing is
+                          dropped while all states fit in M */
   int verbose;         /* 0 quiet, 1 per step, 2 per Davidson iteration (stderr) */
 } dmrg_options;
 
@@ -140,6 +141,25 @@ dmrg_status dmrg_step(dmrg_solver* s, int k, int direction, double* energies, do
 /* <Psi|H|Psi>/<Psi|Psi> + e_core of the current MPS (per root after a sweep). */
 dmrg_status dmrg_energy(dmrg_solver* s, double* energies);
 
+/* Integral gradient of the current MPS energy (Sec. II.C: the DMRG node's
+ * adjoint; the MPS is held fixed, i.e. the Hellmann-Feynman term, exact for a
+ * converged full-bond state; at truncated bond it is the gradient of
+ * <Psi|H|Psi>/<Psi|Psi> for the MPS as it stands, Sec. II.E).  Every entry of h
+ * and B is an independent variable:
+ *   dE/dh_pq = gamma_pq = sum_sigma <a+_{p sigma} a_{q sigma}>,
+ *   dE/dB^Q_pq = sum_rs Gamma'_pqrs B^Q_rs,
+ *   Gamma'_pqrs = sum_{sigma tau} <a+_{p sigma} a+_{r tau} a_{s tau} a_{q sigma}>
+ * (a symmetric parameterisation adds the (p,q) and (q,p) entries).
+ * state_weights[n_states] (host, may be NULL = root 0 only): the output is
+ * sum_r w_r dE_r; roots r > 0 need the centre tensors left by dmrg_step /
+ * dmrg_sweep (else DMRG_ESTATE when their weight is non-zero).  Outputs (host,
+ * caller-owned): dE_dh[n_orb*n_orb], dE_dB[n_chol*n_orb*n_orb] (row-major like
+ * the inputs; may be NULL when n_chol = 0), energies[n_states] (may be NULL):
+ * <Psi_r|H|Psi_r>/<Psi_r|Psi_r> + e_core of every root (0 for roots without a
+ * centre tensor).  Leaves the environments of root 0 in place. */
+dmrg_status dmrg_grad(dmrg_solver* s, const double* state_weights, double* dE_dh, double* dE_dB,
+                      double* energies);
+
 /* Diagnostic export of an environment of the current MPS: side 0 = left block
  * (sites < cut), 1 = right block (sites >= cut).  Copies min(cap, size) doubles
  * of the channel arrays (channels grouped by quantum-number shift, each a list
@@ -166,8 +186,10 @@ dmrg_status dmrg_set_kernel_tag(dmrg_solver* s, int tag);
  * [10] sigma phase-A ms (T = X psi), [11] sigma phase-B ms (long-K products),
  * [12] phase-A flops, [13] phase-B flops, [14] environment-update flops,
  * [15] fp64 refinements, [16] phase-B GEMM kernel ms alone (fp64; without the
- * split-K reduction).  Times are HIP-event times on the solver stream and
- * flops count unpadded block products.  n: capacity of out. */
+ * split-K reduction), [17] dmrg_grad wall ms, [18] dmrg_grad flops (without
+ * the environment updates it triggers).  Times of [2]-[4], [10], [11], [16] are
+ * HIP-event times on the solver stream and flops count unpadded block
+ * products.  n: capacity of out. */
 dmrg_status dmrg_get_stats(const dmrg_solver* s, double* out, int n);
 
 const char* dmrg_last_error(void);

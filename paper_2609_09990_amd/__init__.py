@@ -16,6 +16,7 @@ from ._lib import (  # noqa: F401
     dmrg_get_bonds,
     dmrg_get_env,
     dmrg_get_stats,
+    dmrg_grad,
     dmrg_last_error,
     dmrg_mpo_dims,
     dmrg_mpo_site,
@@ -33,5 +34,7 @@ from ._lib import (  # noqa: F401
     dmrg_sweep,
     lib,
 )
+
+from .autograd import DMRGEnergy, dmrg_energy  # noqa: F401,E402
 
 FP64, FP32, BF16 = 0, 1, 2

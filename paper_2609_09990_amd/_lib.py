@@ -54,6 +54,7 @@ dmrg_set_kernel_tag = _decl("dmrg_set_kernel_tag", [_p, _i])
 dmrg_get_stats = _decl("dmrg_get_stats", [_p, _p, _i])
 dmrg_block_gemm = _decl("dmrg_block_gemm", [_i, _i, _i, _i, _i, _p, _i, _p, _i, _p, _i, _d, _p])
 dmrg_get_env = _decl("dmrg_get_env", [_p, _i, _i, _p, _i64, C.POINTER(_i64)])
+dmrg_grad = _decl("dmrg_grad", [_p, _p, _p, _p, _p])
 dmrg_last_error = _decl("dmrg_last_error", [], C.c_char_p)
 
 STATUS = {0: "DMRG_OK", -1: "DMRG_EINVAL", -2: "DMRG_ENOMEM", -3: "DMRG_EHIP", -4: "DMRG_ENOCONV",
@@ -197,12 +198,27 @@ class Solver:
         _check(dmrg_get_env(self.h, cut, side, _ptr(out), n.value, C.byref(n)))
         return out
 
+    def grad(self, weights=None):
+        """dmrg_grad: (sum_r w_r dE_r/dh, sum_r w_r dE_r/dB, energies) as host arrays."""
+        p = self.problem
+        dh = np.zeros((p.n, p.n))
+        dB = np.zeros((max(p.n_chol, 0), p.n, p.n))
+        e = np.zeros(self.n_states)
+        w = None
+        if weights is not None:
+            w = np.ascontiguousarray(weights, dtype=np.float64)
+            if w.shape != (self.n_states,):
+                raise ValueError(f"weights must have shape ({self.n_states},)")
+        _check(dmrg_grad(self.h, None if w is None else _ptr(w), _ptr(dh),
+                         _ptr(dB) if p.n_chol > 0 else None, _ptr(e)))
+        return dh, dB, e
+
     def stats(self):
-        s = np.zeros(17)
-        _check(dmrg_get_stats(self.h, _ptr(s), 17))
+        s = np.zeros(19)
+        _check(dmrg_get_stats(self.h, _ptr(s), 19))
         keys = ["matvecs", "davidson_iters", "sigma_ms", "env_ms", "svd_ms", "sigma_flops", "tau",
                 "max_bond", "fallbacks", "converged", "sigma_a_ms", "sigma_b_ms", "sigma_a_flops",
-                "sigma_b_flops", "env_flops", "refinements", "sigma_b_gemm_ms"]
+                "sigma_b_flops", "env_flops", "refinements", "sigma_b_gemm_ms", "grad_ms", "grad_flops"]
         return dict(zip(keys, s.tolist()))
 
     def __del__(self):

@@ -278,6 +278,23 @@ dmrg_status dmrg_energy(dmrg_solver* s, double* energies) {
   });
 }
 
+dmrg_status dmrg_grad(dmrg_solver* s, const double* state_weights, double* dE_dh, double* dE_dB,
+                      double* energies) {
+  return guard([&] {
+    DMRG_REQUIRE(s && dE_dh && (dE_dB || s->prob->p.nq == 0), ST_EINVAL, "NULL argument");
+    const Problem& P = s->prob->p;
+    int ns = s->s->n_states();
+    std::vector<double> w(ns, 0.0);
+    if (state_weights) w.assign(state_weights, state_weights + ns);
+    else w[0] = 1.0;
+    std::vector<double> dh, dB, e;
+    s->s->grad(w, dh, dB, e);
+    std::memcpy(dE_dh, dh.data(), (size_t)P.n * P.n * sizeof(double));
+    if (P.nq > 0) std::memcpy(dE_dB, dB.data(), (size_t)P.nq * P.n * P.n * sizeof(double));
+    if (energies) std::memcpy(energies, e.data(), e.size() * sizeof(double));
+  });
+}
+
 dmrg_status dmrg_get_env(dmrg_solver* s, int cut, int side, double* host, int64_t cap, int64_t* size) {
   return guard([&] {
     DMRG_REQUIRE(s && size && (host || cap == 0), ST_EINVAL, "NULL argument");
@@ -323,11 +340,11 @@ dmrg_status dmrg_get_stats(const dmrg_solver* s, double* out, int n) {
   return guard([&] {
     DMRG_REQUIRE(s && out, ST_EINVAL, "NULL argument");
     const Stats& t = s->s->stats();
-    double v[17] = {(double)t.matvecs, (double)t.davidson_iters, t.sigma_ms, t.env_ms, t.svd_ms,
+    double v[19] = {(double)t.matvecs, (double)t.davidson_iters, t.sigma_ms, t.env_ms, t.svd_ms,
                     t.sigma_flops, t.tau, (double)t.max_bond, (double)t.fallbacks, (double)t.converged,
                     t.sigma_a_ms, t.sigma_b_ms, t.sigma_a_flops, t.sigma_b_flops, t.env_flops,
-                    (double)t.refinements, t.sigma_b_gemm_ms};
-    for (int i = 0; i < n && i < 17; ++i) out[i] = v[i];
+                    (double)t.refinements, t.sigma_b_gemm_ms, t.grad_ms, t.grad_flops};
+    for (int i = 0; i < n && i < 19; ++i) out[i] = v[i];
   });
 }
 

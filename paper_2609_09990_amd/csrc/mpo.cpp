@@ -353,12 +353,20 @@ MPO build_mpo(int L, int nq, const double* h, const double* B) {
     DMRG_REQUIRE(ih != b.chan_id[L].end(), ST_EINVAL, "MPO has no closing channel");
     bwd[L][ih->second] = 1;
   }
+  // An entry whose coefficient is an integral stays even when that integral is
+  // exactly zero: it adds nothing to H but carries dE/d(integral).
+  std::vector<std::vector<char>> live(L);
+  for (int k = 0; k < L; ++k) {
+    live[k].assign(b.W[k].size(), 0);
+    for (size_t i = 0; i < b.W[k].size(); ++i) live[k][i] = b.W[k][i].c != 0.0;
+    for (auto& p : b.prov[k]) live[k][p.entry] = 1;
+  }
   for (int k = 0; k < L; ++k)
-    for (auto& e : b.W[k])
-      if (fwd[k][e.a] && e.c != 0.0) fwd[k + 1][e.b] = 1;
+    for (size_t i = 0; i < b.W[k].size(); ++i)
+      if (fwd[k][b.W[k][i].a] && live[k][i]) fwd[k + 1][b.W[k][i].b] = 1;
   for (int k = L - 1; k >= 0; --k)
-    for (auto& e : b.W[k])
-      if (bwd[k + 1][e.b] && e.c != 0.0) bwd[k][e.a] = 1;
+    for (size_t i = 0; i < b.W[k].size(); ++i)
+      if (bwd[k + 1][b.W[k][i].b] && live[k][i]) bwd[k][b.W[k][i].a] = 1;
 
   MPO m;
   m.L = L;
@@ -393,7 +401,7 @@ MPO build_mpo(int L, int nq, const double* h, const double* B) {
     for (size_t i = 0; i < b.W[k].size(); ++i) {
       const auto& e = b.W[k][i];
       int a = remap[k][e.a], bb = remap[k + 1][e.b];
-      if (a < 0 || bb < 0 || e.c == 0.0) continue;
+      if (a < 0 || bb < 0 || !live[k][i]) continue;
       emap[i] = (int)m.W[k].size();
       m.W[k].push_back({a, bb, e.c, e.op});
     }

@@ -63,6 +63,7 @@ void Solver::build_factor_side(FactorSide& fs, bool left, int site) {
   // group W entries by (middle channel, op)
   std::map<std::pair<int, int>, std::vector<std::pair<int, double>>> groups;
   for (const auto& e : mpo.W[site]) {
+    if (e.c == 0.0) continue;  // kept in the MPO only for its gradient
     int mid = left ? e.b : e.a;
     int src = left ? e.a : e.b;
     groups[{mid, e.op}].push_back({src, e.c});

@@ -92,6 +92,15 @@ Solver::Solver(const Problem* p, const Options& o, hipStream_t s) : prob_(p), op
   DMRG_REQUIRE(opt_.M >= 1, ST_EINVAL, "M must be positive");
   if (opt_.weights.empty()) opt_.weights.assign(opt_.n_states, 1.0 / opt_.n_states);
   DMRG_REQUIRE((int)opt_.weights.size() == opt_.n_states, ST_EINVAL, "weights size mismatch");
+  {
+    double wsum = 0.0;
+    for (double w : opt_.weights) {
+      DMRG_REQUIRE(std::isfinite(w) && w >= 0.0, ST_EINVAL, "state weights must be finite and >= 0");
+      wsum += w;
+    }
+    DMRG_REQUIRE(wsum > 0.0, ST_EINVAL, "state weights must not all be zero");
+    for (double& w : opt_.weights) w /= wsum;
+  }
   opt_.max_subspace = std::max(std::min(opt_.max_subspace, 64), 2 * opt_.n_states + 2);
   if (rocblas_create_handle(&rb_) != rocblas_status_success) throw Error(ST_EHIP, "rocblas handle");
   rocblas_set_stream(rb_, st);
@@ -697,6 +706,25 @@ void Solver::svd_step(int k, bool l2r, int nr, std::vector<DevMem>& next_guess, 
   evals.reserve(std::max<long>(etot, 1) * 8 * 2);
   info.reserve((mids.size() + 1) * sizeof(rocblas_int));
   launch_fill(gram.as<double>(), gtot, 0.0, st);
+  // Padding rows/columns of a bucket get -4 on the diagonal: with normalised roots
+  // and weights summing to one every true eigenvalue lies in [0, 1], so padding
+  // eigenpairs sort below all of them and are never taken as kept vectors.
+  static const double kPad = -4.0;
+  DevMem pad_src, pad_desc;
+  std::vector<int64_t> pdesc;
+  for (size_t i = 0; i < mids.size(); ++i)
+    if (gb[i] > gd[i]) {
+      long d0 = goff[i] + (long)gd[i] * gb[i] + gd[i];
+      pdesc.insert(pdesc.end(), {0, 0, 0, d0, gb[i] + 1, 0, gb[i] - gd[i], 1, dbits(1.0)});
+    }
+  if (!pdesc.empty()) {
+    check_desc(pdesc, 0, pdesc.size(), 1, gtot);
+    pad_src.reserve(8);
+    pad_desc.reserve(pdesc.size() * 8);
+    hip_check(hipMemcpyAsync(pad_src.p, &kPad, 8, hipMemcpyHostToDevice, st), "pad value");
+    hip_check(hipMemcpyAsync(pad_desc.p, pdesc.data(), pdesc.size() * 8, hipMemcpyHostToDevice, st), "pad desc");
+    launch_copy_blocks(pad_desc.as<int64_t>(), (int)(pdesc.size() / 9), pad_src.as<double>(), gram.as<double>(), st);
+  }
   {
     std::vector<GemmItem> items;
     std::vector<GemmUnit> units;
@@ -744,10 +772,13 @@ void Solver::svd_step(int k, bool l2r, int nr, std::vector<DevMem>& next_guess, 
   std::stable_sort(all_sv.begin(), all_sv.end(), [](const SV& a, const SV& b) { return a.s > b.s; });
   double s1 = all_sv.empty() ? 0.0 : all_sv[0].s;
   long keep = std::min<long>((long)all_sv.size(), opt_.M);
-  // singular values from density-matrix eigenvalues resolve only down to ~1e-8 s_1
-  const double cut = std::max(opt_.cut_rtol, 1e-7);
-  while (keep > 0 && all_sv[keep - 1].s <= cut * s1) --keep;
-  if (keep < (long)all_sv.size() && keep > 0) {
+  // Nothing is dropped while every state fits (the exact regime: singular values
+  // from density-matrix eigenvalues resolve only down to ~1e-8 s_1, so a small
+  // one cannot be told from a zero one, and keeping both is exact).  When states
+  // must go, those at or below cut_rtol s_1 go first and a near-degenerate
+  // cluster is never split.
+  if (keep < (long)all_sv.size()) {
+    while (keep > 0 && all_sv[keep - 1].s <= opt_.cut_rtol * s1) --keep;
     while (keep > 1 && all_sv[keep - 1].s - all_sv[keep].s <= opt_.tie_rtol * s1) --keep;
   }
   if (keep < 1) keep = 1;

@@ -150,6 +150,7 @@ struct Stats {
   int fallbacks = 0;
   int converged = 1;
   int refinements = 0;
+  double grad_ms = 0, grad_flops = 0;  // integral-gradient passes
 };
 
 class Solver {
@@ -170,7 +171,11 @@ class Solver {
   double sweep(int n_sweeps, std::vector<double>& energies);
   double step(int k, bool left_to_right, std::vector<double>& energies);
   std::vector<double> mps_energy();
+  // Energies of the roots w refers to and sum_r w_r dE_r/dh (n*n), dE_r/dB (nq*n*n).
+  void grad(const std::vector<double>& w, std::vector<double>& dh, std::vector<double>& dB,
+            std::vector<double>& energies);
   const Stats& stats() const { return st_; }
+  int n_states() const { return opt_.n_states; }
   std::vector<double> env_host(int cut, int side);
   const Problem* prob() const { return prob_; }
 
@@ -228,6 +233,8 @@ class Solver {
   void form_twosite(int k, const SiteTensor& a, const SiteTensor& b, double* out);
   int davidson(int k, std::vector<DevMem>& guess, std::vector<double>& evals);
   void gemm_once(int mode, std::vector<GemmItem>& items, std::vector<GemmUnit>& units);
+  void grad_site(int k, std::vector<double>& g, double* norm);
+  DevMem grad_P_, grad_Q_, grad_G_;
 
   // Davidson workspace
   DevMem dv_V_, dv_AV_, dv_G_, dv_evals_, dv_evecs_, dv_X_, dv_R_, dv_C_, dv_t_, dv_diag_, dv_part_,

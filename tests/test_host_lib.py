@@ -86,3 +86,22 @@ def test_mpo_bond_dimensions_at_scale():
     full = 2 + 4 * n + nq + 8 * 36
     assert 2 + 4 * n + nq < d[6] <= full
     assert d[6] == max(d)
+
+
+def test_mpo_keeps_structure_of_exact_zero_integrals():
+    """Integrals that are exactly zero add nothing to H, yet their entries stay
+    in the MPO (their derivative is generally non-zero): the dense contraction
+    still equals the brute-force Hamiltonian and the channel counts equal those
+    of a generic Hamiltonian of the same shape."""
+    pk = _lib()
+    n, nq = 5, 3
+    h, B, _ = synth.make_hamiltonian(n, nq, 6)
+    ref_dims = pk.Problem(h, B, 3, 2).mpo_dims()
+    h[0, 3] = h[3, 0] = 0.0
+    h[1, 1] = 0.0
+    B[0, 0, 4] = B[0, 4, 0] = 0.0
+    B[2] = 0.0
+    prob = pk.Problem(h, B, 3, 2)
+    Hf = fock.hamiltonian(h, B, fock.site_product_basis(n), fock.interleaved_positions(n)).toarray()
+    assert np.max(np.abs(_dense_mpo(prob) - Hf)) < 1e-12
+    assert list(prob.mpo_dims()) == list(ref_dims)
