@@ -44,6 +44,7 @@ extern "C" {
 
 typedef struct dmrg_problem dmrg_problem; /* opaque */
 typedef struct dmrg_solver dmrg_solver;   /* opaque */
+typedef struct dmrg_mlp dmrg_mlp;         /* opaque: preconditioner network */
 
 typedef enum {
   DMRG_OK = 0,
@@ -159,6 +160,62 @@ dmrg_status dmrg_energy(dmrg_solver* s, double* energies);
  * centre tensor).  Leaves the environments of root 0 in place. */
 dmrg_status dmrg_grad(dmrg_solver* s, const double* state_weights, double* dE_dh, double* dE_dB,
                       double* energies);
+
+/* ---- Learned Davidson preconditioner ------------------------------------
+ * The paper's two-site Davidson takes a run-time-selectable preconditioner
+ * (Sec. III); this library adds a learned member.  A per-amplitude network
+ *   y = W3 relu(W2 relu(W1 x + b1) + b2) + b3   (x: n_in features, width hidden)
+ * maps 8 features of each amplitude of a correction to the correction itself:
+ *   f0 r_i sqrt(n)/|r|, f1 e_i/s_b, f2 clip(s_b/e_i, -10, 10), f3 t_i sqrt(n)/|t|,
+ *   f4 mean_b(e/s_b), f5 min_b(e/s_b), f6 log(block size)/10, f7 k/L,
+ * with e = diag(H_eff) - theta, t_i = r_i/(theta - d_i) the diagonal candidate
+ * (|theta - d_i| floored at 1e-8), b the dense block of the amplitude and s_b
+ * the mean of |e| over it.  Weights are fp32; the hidden layer runs in bf16 on
+ * the matrix cores inside Davidson.  Each learned candidate is judged: if it
+ * is not finite or keeps less than 1e-3 of its norm after orthogonalisation
+ * to the subspace, the diagonal candidate replaces it, and when three learned
+ * iterations cut the exact residual norm by less than 10% the rest of the
+ * step uses the diagonal candidate.  Convergence is always on the exact
+ * residual.  Parameters are one fp32 vector: W1[width][n_in], b1[width],
+ * W2[width][width], b2[width], W3[width], b3[1]. */
+
+/* Network with He-normal weights (seeded) and zero biases; work on hip_stream. */
+dmrg_status dmrg_mlp_create(int n_in, int width, unsigned long long seed, void* hip_stream, dmrg_mlp** out);
+void dmrg_mlp_destroy(dmrg_mlp* m);
+dmrg_status dmrg_mlp_num_params(const dmrg_mlp* m, int64_t* n);
+/* Host parameter vectors of exactly num_params floats; set also resets Adam. */
+dmrg_status dmrg_mlp_set_params(dmrg_mlp* m, const float* host, int64_t n);
+dmrg_status dmrg_mlp_get_params(const dmrg_mlp* m, float* host, int64_t n);
+/* y[rows] = net(X[rows][n_in]) (device fp32 arrays); precision DMRG_FP32 or
+ * DMRG_BF16 (hidden layer with bf16 inputs, fp32 accumulation).  Synchronous. */
+dmrg_status dmrg_mlp_forward(dmrg_mlp* m, int precision, const float* X, int64_t rows, float* y);
+/* Training loss on n_seg segments of seg_len rows (device X[n_seg*seg_len][n_in],
+ * target[n_seg*seg_len]): loss = mean over segments of 1 - cos(y_seg, target_seg)
+ * (scale-free: Davidson ignores the scale of a correction), fp32 forward and
+ * backward; the gradient is kept for dmrg_mlp_adam_step and copied to grad
+ * (host, num_params floats) when grad is not NULL. */
+dmrg_status dmrg_mlp_loss_grad(dmrg_mlp* m, const float* X, const float* target, int n_seg, int seg_len,
+                               double* loss, float* grad);
+/* Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with the last gradient. */
+dmrg_status dmrg_mlp_adam_step(dmrg_mlp* m, double lr);
+/* Preconditioner of later Davidson solves: DMRG_PRECOND_DIAG (net ignored) or
+ * DMRG_PRECOND_LEARNED with a network of n_in = 8 (borrowed: it must outlive
+ * its use by the solver). */
+dmrg_status dmrg_set_precond(dmrg_solver* s, int precond, dmrg_mlp* net);
+/* Training triples from later Davidson solves (root 0): at every iteration the
+ * features of `sample` amplitudes (a seeded draw per step), and once the step
+ * has converged the target Delta = P_perp psi* on the same amplitudes (psi* the
+ * converged vector oriented along the iterate psi_i, P_perp projecting out
+ * psi_i).  Steps that do not converge, or whose vector is shorter than
+ * `sample`, record nothing.  capacity 0 stops recording. */
+dmrg_status dmrg_record_triples(dmrg_solver* s, int capacity, int sample);
+/* Copies up to cap recorded triples into device arrays X[cap][sample][8] and
+ * target[cap][sample] (fp32), writes the count and empties the store. */
+dmrg_status dmrg_take_triples(dmrg_solver* s, float* X, float* target, int cap, int* count);
+/* The 8 features (device X[n][8], fp32) of the two-site step k for device
+ * vectors r (residual) and d (diagonal of H_eff) and eigenvalue estimate theta. */
+dmrg_status dmrg_precond_features(dmrg_solver* s, int k, const double* r, const double* d, double theta,
+                                  float* X);
 
 /* Diagnostic export of an environment of the current MPS: side 0 = left block
  * (sites < cut), 1 = right block (sites >= cut).  Copies min(cap, size) doubles

@@ -8,6 +8,7 @@ fallback: if the shared library is missing, importing this package raises.
 from ._lib import (  # noqa: F401
     DMRGError,
     LIB_PATH,
+    MLP,
     Problem,
     Solver,
     dmrg_block_gemm,

@@ -55,6 +55,18 @@ dmrg_get_stats = _decl("dmrg_get_stats", [_p, _p, _i])
 dmrg_block_gemm = _decl("dmrg_block_gemm", [_i, _i, _i, _i, _i, _p, _i, _p, _i, _p, _i, _d, _p])
 dmrg_get_env = _decl("dmrg_get_env", [_p, _i, _i, _p, _i64, C.POINTER(_i64)])
 dmrg_grad = _decl("dmrg_grad", [_p, _p, _p, _p, _p])
+dmrg_mlp_create = _decl("dmrg_mlp_create", [_i, _i, C.c_ulonglong, _p, C.POINTER(_p)])
+dmrg_mlp_destroy = _decl("dmrg_mlp_destroy", [_p], None)
+dmrg_mlp_num_params = _decl("dmrg_mlp_num_params", [_p, C.POINTER(_i64)])
+dmrg_mlp_set_params = _decl("dmrg_mlp_set_params", [_p, _p, _i64])
+dmrg_mlp_get_params = _decl("dmrg_mlp_get_params", [_p, _p, _i64])
+dmrg_mlp_forward = _decl("dmrg_mlp_forward", [_p, _i, _p, _i64, _p])
+dmrg_mlp_loss_grad = _decl("dmrg_mlp_loss_grad", [_p, _p, _p, _i, _i, C.POINTER(_d), _p])
+dmrg_mlp_adam_step = _decl("dmrg_mlp_adam_step", [_p, _d])
+dmrg_set_precond = _decl("dmrg_set_precond", [_p, _i, _p])
+dmrg_record_triples = _decl("dmrg_record_triples", [_p, _i, _i])
+dmrg_take_triples = _decl("dmrg_take_triples", [_p, _p, _p, _i, C.POINTER(_i)])
+dmrg_precond_features = _decl("dmrg_precond_features", [_p, _i, _p, _p, _d, _p])
 dmrg_last_error = _decl("dmrg_last_error", [], C.c_char_p)
 
 STATUS = {0: "DMRG_OK", -1: "DMRG_EINVAL", -2: "DMRG_ENOMEM", -3: "DMRG_EHIP", -4: "DMRG_ENOCONV",
@@ -111,6 +123,63 @@ class Problem:
     def __del__(self):
         if getattr(self, "h", None):
             dmrg_problem_destroy(self.h)
+            self.h = None
+
+
+class MLP:
+    """dmrg_mlp: the preconditioner network (parameters on the device)."""
+
+    def __init__(self, n_in=8, width=256, seed=0, stream=None):
+        if stream is None and torch is not None and torch.cuda.is_available():
+            stream = torch.cuda.current_stream().cuda_stream
+        self.n_in, self.width = n_in, width
+        self.h = C.c_void_p()
+        _check(dmrg_mlp_create(n_in, width, seed, C.c_void_p(stream or 0), C.byref(self.h)))
+        n = C.c_int64()
+        _check(dmrg_mlp_num_params(self.h, C.byref(n)))
+        self.n_params = n.value
+
+    def params(self):
+        p = np.zeros(self.n_params, dtype=np.float32)
+        _check(dmrg_mlp_get_params(self.h, _ptr(p), self.n_params))
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        _check(dmrg_mlp_set_params(self.h, _ptr(p), p.size))
+
+    def unpack(self, p=None):
+        """Parameter vector as {W1, b1, W2, b2, W3, b3} views (host)."""
+        p = self.params() if p is None else p
+        F, W = self.n_in, self.width
+        out, o = {}, 0
+        for k, shape in (("W1", (W, F)), ("b1", (W,)), ("W2", (W, W)), ("b2", (W,)), ("W3", (1, W)), ("b3", (1,))):
+            size = int(np.prod(shape))
+            out[k] = p[o:o + size].reshape(shape)
+            o += size
+        return out
+
+    @staticmethod
+    def pack(P):
+        return np.concatenate([np.asarray(P[k], dtype=np.float32).ravel()
+                               for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
+
+    def forward(self, X, y, precision=1):
+        _check(dmrg_mlp_forward(self.h, precision, _ptr(X), X.shape[0], _ptr(y)))
+
+    def loss_grad(self, X, T, n_seg, seg_len, want_grad=False):
+        loss = C.c_double()
+        g = np.zeros(self.n_params, dtype=np.float32) if want_grad else None
+        _check(dmrg_mlp_loss_grad(self.h, _ptr(X), _ptr(T), n_seg, seg_len, C.byref(loss),
+                                  None if g is None else _ptr(g)))
+        return (loss.value, g) if want_grad else loss.value
+
+    def adam_step(self, lr):
+        _check(dmrg_mlp_adam_step(self.h, lr))
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            dmrg_mlp_destroy(self.h)
             self.h = None
 
 
@@ -181,6 +250,23 @@ class Solver:
         if code not in (0, -4):
             _check(code)
         return e, tau.value, code == 0
+
+    def set_precond(self, precond, net=None):
+        """0: diagonal, 1: learned with the MLP `net` (kept alive by this object)."""
+        self._net = net
+        _check(dmrg_set_precond(self.h, precond, net.h if net is not None else None))
+
+    def record_triples(self, capacity, sample):
+        self._sample = sample
+        _check(dmrg_record_triples(self.h, capacity, sample))
+
+    def take_triples(self, X, T, cap):
+        cnt = C.c_int()
+        _check(dmrg_take_triples(self.h, _ptr(X), _ptr(T), cap, C.byref(cnt)))
+        return cnt.value
+
+    def features(self, k, r, d, theta, X):
+        _check(dmrg_precond_features(self.h, k, _ptr(r), _ptr(d), float(theta), _ptr(X)))
 
     def set_kernel_tag(self, tag):
         _check(dmrg_set_kernel_tag(self.h, tag))

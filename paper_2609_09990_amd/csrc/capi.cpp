@@ -4,6 +4,7 @@
 #include <string>
 
 #include "../../include/dmrg_mi355x.h"
+#include "mlp.hpp"
 #include "solver.hpp"
 
 using namespace dmrg;
@@ -14,6 +15,9 @@ struct dmrg_problem {
 struct dmrg_solver {
   Solver* s = nullptr;
   const dmrg_problem* prob = nullptr;
+};
+struct dmrg_mlp {
+  MLP* m = nullptr;
 };
 
 namespace {
@@ -292,6 +296,110 @@ dmrg_status dmrg_grad(dmrg_solver* s, const double* state_weights, double* dE_dh
     std::memcpy(dE_dh, dh.data(), (size_t)P.n * P.n * sizeof(double));
     if (P.nq > 0) std::memcpy(dE_dB, dB.data(), (size_t)P.nq * P.n * P.n * sizeof(double));
     if (energies) std::memcpy(energies, e.data(), e.size() * sizeof(double));
+  });
+}
+
+dmrg_status dmrg_mlp_create(int n_in, int width, unsigned long long seed, void* hip_stream, dmrg_mlp** out) {
+  return guard([&] {
+    DMRG_REQUIRE(out, ST_EINVAL, "NULL argument");
+    *out = nullptr;
+    auto* m = new dmrg_mlp;
+    try {
+      m->m = new MLP(n_in, width, seed, (hipStream_t)hip_stream);
+    } catch (...) {
+      delete m;
+      throw;
+    }
+    *out = m;
+  });
+}
+
+void dmrg_mlp_destroy(dmrg_mlp* m) {
+  if (!m) return;
+  delete m->m;
+  delete m;
+}
+
+dmrg_status dmrg_mlp_num_params(const dmrg_mlp* m, int64_t* n) {
+  return guard([&] {
+    DMRG_REQUIRE(m && n, ST_EINVAL, "NULL argument");
+    *n = m->m->n_params();
+  });
+}
+
+dmrg_status dmrg_mlp_set_params(dmrg_mlp* m, const float* host, int64_t n) {
+  return guard([&] {
+    DMRG_REQUIRE(m && host, ST_EINVAL, "NULL argument");
+    DMRG_REQUIRE(n == m->m->n_params(), ST_EINVAL, "parameter count mismatch");
+    m->m->set_params(host);
+  });
+}
+
+dmrg_status dmrg_mlp_get_params(const dmrg_mlp* m, float* host, int64_t n) {
+  return guard([&] {
+    DMRG_REQUIRE(m && host, ST_EINVAL, "NULL argument");
+    DMRG_REQUIRE(n == m->m->n_params(), ST_EINVAL, "parameter count mismatch");
+    m->m->get_params(host);
+  });
+}
+
+dmrg_status dmrg_mlp_forward(dmrg_mlp* m, int precision, const float* X, int64_t rows, float* y) {
+  return guard([&] {
+    DMRG_REQUIRE(m && (rows == 0 || (X && y)), ST_EINVAL, "NULL argument");
+    DMRG_REQUIRE(rows >= 0, ST_EINVAL, "negative row count");
+    m->m->forward(precision, X, rows, y);
+    hip_check(hipStreamSynchronize(m->m->stream()), "mlp forward");
+  });
+}
+
+dmrg_status dmrg_mlp_loss_grad(dmrg_mlp* m, const float* X, const float* target, int n_seg, int seg_len,
+                               double* loss, float* grad) {
+  return guard([&] {
+    DMRG_REQUIRE(m && X && target && loss, ST_EINVAL, "NULL argument");
+    *loss = m->m->loss_grad(X, target, n_seg, seg_len);
+    if (grad) {
+      hip_check(hipMemcpyAsync(grad, m->m->grad(), m->m->n_params() * 4, hipMemcpyDeviceToHost, m->m->stream()),
+                "mlp grad");
+      hip_check(hipStreamSynchronize(m->m->stream()), "mlp grad");
+    }
+  });
+}
+
+dmrg_status dmrg_mlp_adam_step(dmrg_mlp* m, double lr) {
+  return guard([&] {
+    DMRG_REQUIRE(m, ST_EINVAL, "NULL argument");
+    DMRG_REQUIRE(lr > 0 && std::isfinite(lr), ST_EINVAL, "learning rate must be positive");
+    m->m->adam((float)lr);
+  });
+}
+
+dmrg_status dmrg_set_precond(dmrg_solver* s, int precond, dmrg_mlp* net) {
+  return guard([&] {
+    DMRG_REQUIRE(s, ST_EINVAL, "NULL argument");
+    s->s->set_precond(precond, net ? net->m : nullptr);
+  });
+}
+
+dmrg_status dmrg_record_triples(dmrg_solver* s, int capacity, int sample) {
+  return guard([&] {
+    DMRG_REQUIRE(s, ST_EINVAL, "NULL argument");
+    s->s->record_triples(capacity, sample);
+  });
+}
+
+dmrg_status dmrg_take_triples(dmrg_solver* s, float* X, float* target, int cap, int* count) {
+  return guard([&] {
+    DMRG_REQUIRE(s && count && (cap == 0 || (X && target)), ST_EINVAL, "NULL argument");
+    *count = s->s->take_triples(X, target, cap);
+  });
+}
+
+dmrg_status dmrg_precond_features(dmrg_solver* s, int k, const double* r, const double* d, double theta,
+                                  float* X) {
+  return guard([&] {
+    DMRG_REQUIRE(s && r && d && X, ST_EINVAL, "NULL argument");
+    DMRG_REQUIRE(k >= 0 && k + 1 < s->prob->p.n, ST_EINVAL, "two-site step out of range");
+    s->s->features_host_theta(k, r, d, theta, X);
   });
 }
 

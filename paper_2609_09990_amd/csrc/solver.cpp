@@ -1,6 +1,8 @@
 // Two-site sweep driver: MPS setup, environments, sigma, Davidson, SVD truncation.
 #include "solver.hpp"
 
+#include "mlp.hpp"
+
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
@@ -102,6 +104,8 @@ Solver::Solver(const Problem* p, const Options& o, hipStream_t s) : prob_(p), op
     for (double& w : opt_.weights) w /= wsum;
   }
   opt_.max_subspace = std::max(std::min(opt_.max_subspace, 64), 2 * opt_.n_states + 2);
+  DMRG_REQUIRE(opt_.precond == 0 || opt_.precond == 1, ST_EINVAL, "unknown preconditioner");
+  precond_ = opt_.precond;
   if (rocblas_create_handle(&rb_) != rocblas_status_success) throw Error(ST_EHIP, "rocblas handle");
   rocblas_set_stream(rb_, st);
   init_random_mps();
@@ -265,6 +269,17 @@ void Solver::prepare(int k) {
   }
   lowp_prec_ = -1;
   diag_ready_ = false;
+  // dense blocks of the two-site vector, for the preconditioner features
+  fblocks_host_.clear();
+  for (const Slab& sl : psi_lay_.slabs)
+    for (const auto& b : sl.blocks)
+      fblocks_host_.insert(fblocks_host_.end(), {(int64_t)(sl.off + b.col0), (int64_t)sl.width, (int64_t)sl.ml,
+                                                 (int64_t)b.mr});
+  nfb_ = (int)(fblocks_host_.size() / 4);
+  d_fblocks_.reserve(fblocks_host_.size() * 8 + 8);
+  if (nfb_ > 0)
+    hip_check(hipMemcpyAsync(d_fblocks_.p, fblocks_host_.data(), fblocks_host_.size() * 8, hipMemcpyHostToDevice, st),
+              "feature blocks");
   plan_k_ = k;
   hip_check(hipStreamSynchronize(st), "prepare");
 }
@@ -486,7 +501,8 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
     return v;
   };
   // orthonormalise t against V[0..kcur) (two passes of classical Gram-Schmidt), append
-  auto append = [&](const double* src, int sprec) -> bool {
+  // min_ratio: smallest accepted |t after projection|^2 / |t|^2
+  auto append = [&](const double* src, int sprec, double min_ratio = 1e-20) -> bool {
     if (src != t) launch_copy(t, src, n, st);
     launch_dots(t, n, 1, t, n, part, sc + 1, st);
     double n0 = host_scalar(sc + 1);
@@ -497,7 +513,7 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
     }
     launch_dots(t, n, 1, t, n, part, sc, st);
     double nn = host_scalar(sc);
-    if (!(nn > 1e-20 * n0)) return false;
+    if (!(nn > min_ratio * n0) || !std::isfinite(nn)) return false;
     launch_scale_by_norm(t, n, sc, st);
     launch_copy(V + (long)kcur * n, t, n, st);
     sigma(k, sprec, V + (long)kcur * n, AV + (long)kcur * n);
@@ -522,6 +538,46 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
     }
   }
   DMRG_REQUIRE(kcur >= nr, ST_ESECTOR, "could not build an initial Davidson basis");
+  // learned preconditioner: judged by the exact residual, the diagonal one is the fallback
+  bool lrn_on = precond_ == 1;
+  DMRG_REQUIRE(!lrn_on || net_, ST_ESTATE, "learned preconditioner selected without a network");
+  int lw_count = 0;
+  double lw_r0 = 0.0;
+  float* F = nullptr;
+  float* Y = nullptr;
+  double* Lc = nullptr;
+  double* Tmp = nullptr;
+  const bool rec = rec_cap_ > 0 && n >= rec_sample_ && rec_sample_ > 0;
+  const int kRecHist = 64;
+  std::vector<int> rec_slots;
+  if (lrn_on || rec) {
+    feat_.reserve((size_t)n * 8 * 4);
+    nety_.reserve((size_t)n * 4);
+    dv_L_.reserve((size_t)nr * n * 8);
+    feat_t_.reserve((size_t)n * 8);
+    fstats_.reserve((size_t)std::max(nfb_, 1) * 4 * 8);
+    F = feat_.as<float>();
+    Y = nety_.as<float>();
+    Lc = dv_L_.as<double>();
+    Tmp = feat_t_.as<double>();
+  }
+  if (rec) {  // this step's amplitude sample: a seeded draw without replacement
+    rec_hist_.reserve((size_t)kRecHist * n * 8);
+    std::vector<int64_t> idx(n);
+    std::iota(idx.begin(), idx.end(), 0);
+    uint64_t z = 0x9E3779B97F4A7C15ull * (++rec_seed_ + 1);
+    for (int j = 0; j < rec_sample_; ++j) {
+      z ^= z >> 33;
+      z *= 0xff51afd7ed558ccdull;
+      z ^= z >> 33;
+      z = z * 0xc4ceb9fe1a85ec53ull + (uint64_t)j;
+      long pick = j + (long)(z % (uint64_t)(n - j));
+      std::swap(idx[j], idx[pick]);
+    }
+    rec_idx_.reserve((size_t)rec_sample_ * 8);
+    hip_check(hipMemcpyAsync(rec_idx_.p, idx.data(), (size_t)rec_sample_ * 8, hipMemcpyHostToDevice, st), "sample");
+    hip_check(hipStreamSynchronize(st), "sample");
+  }
   evals.assign(nr, 0.0);
   std::vector<double> rn(nr, 0.0), hv(2 * nr);
   int iter = 0;
@@ -578,11 +634,41 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
       break;
     }
     exact_basis = (prec == PREC_F64);
+    // training triple of root 0: features now, target once the step has converged
+    if (rec && rn[0] > opt_.davidson_tol && (int)rec_slots.size() < kRecHist &&
+        rec_count_ + (int)rec_slots.size() < rec_cap_) {
+      const int slot = rec_count_ + (int)rec_slots.size();
+      launch_precond_diag(R, D, ev, Tmp, n, st);
+      features(R, D, ev, Tmp, F);
+      launch_gather_rows(F, 8, rec_idx_.as<int64_t>(), rec_sample_, rec_X_.as<float>() + (size_t)slot * rec_sample_ * 8, st);
+      launch_copy(rec_hist_.as<double>() + (size_t)rec_slots.size() * n, X, n, st);
+      rec_slots.push_back(slot);
+    }
+    // learned candidates: stop using them when 3 iterations cut |r| by less than 10%
+    if (lrn_on) {
+      if (lw_count == 0) {
+        lw_r0 = rmax;
+      } else if (lw_count >= 3) {
+        if (rmax > 0.9 * lw_r0) {
+          lrn_on = false;
+          st_.fallbacks++;
+        } else {
+          lw_count = 0;
+          lw_r0 = rmax;
+        }
+      }
+      if (lrn_on) ++lw_count;
+    }
     // corrections from the residuals of unconverged roots
     int nnew = 0;
     for (int i = 0; i < nr; ++i) {
       if (rn[i] <= opt_.davidson_tol) continue;
       launch_precond_diag(R + (long)i * n, D, ev + i, Cc + (long)nnew * n, n, st);
+      if (lrn_on) {
+        features(R + (long)i * n, D, ev + i, Cc + (long)nnew * n, F);
+        net_->forward(PREC_BF16, F, n, Y, st);
+        launch_f32_to_f64(Y, Lc + (long)nnew * n, n, st);
+      }
       ++nnew;
     }
     if (kcur + nnew > kmax) {  // thick restart with the Ritz vectors
@@ -596,8 +682,16 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
       kcur = nr;
     }
     int added = 0;
-    for (int j = 0; j < nnew; ++j)
+    for (int j = 0; j < nnew; ++j) {
+      if (lrn_on) {  // rejected: non-finite, or (almost) inside the current subspace
+        if (append(Lc + (long)j * n, prec, 1e-6)) {
+          ++added;
+          continue;
+        }
+        st_.fallbacks++;
+      }
       if (append(Cc + (long)j * n, prec)) ++added;
+    }
     if (added == 0) {
       conv = rmax <= 1e3 * opt_.davidson_tol;
       break;
@@ -605,6 +699,16 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
   }
   st_.davidson_iters += iter;
   if (!conv) st_.converged = 0;
+  if (rec && conv && !rec_slots.empty()) {  // Delta = P_perp psi*, psi* oriented along psi_i
+    for (size_t j = 0; j < rec_slots.size(); ++j) {
+      const double* hj = rec_hist_.as<double>() + j * n;
+      launch_dots(hj, n, 1, X, n, part, sc + 210, st);
+      launch_triple_target(hj, X, sc + 210, rec_idx_.as<int64_t>(), rec_sample_,
+                           rec_T_.as<float>() + (size_t)rec_slots[j] * rec_sample_, st);
+    }
+    hip_check(hipStreamSynchronize(st), "triples");
+    rec_count_ += (int)rec_slots.size();
+  }
   // converged Ritz vectors are in X
   return matvecs;
 }

@@ -153,6 +153,8 @@ struct Stats {
   double grad_ms = 0, grad_flops = 0;  // integral-gradient passes
 };
 
+class MLP;
+
 class Solver {
  public:
   Solver(const Problem* p, const Options& o, hipStream_t s);
@@ -176,6 +178,18 @@ class Solver {
             std::vector<double>& energies);
   const Stats& stats() const { return st_; }
   int n_states() const { return opt_.n_states; }
+
+  // Davidson preconditioner: 0 diagonal, 1 learned (net borrowed, must outlive its use)
+  void set_precond(int mode, MLP* net);
+  // Record (features, projected target) training triples of root 0 in later
+  // Davidson solves: up to `capacity` triples of `sample` amplitudes each.
+  void record_triples(int capacity, int sample);
+  // Copies up to cap recorded triples to device arrays X[cap][sample][8],
+  // T[cap][sample] (stream-ordered) and clears the store; returns the count.
+  int take_triples(float* X, float* T, int cap);
+  int triple_sample() const { return rec_sample_; }
+  // Features of the prepared step k for device vectors r, d and a host theta.
+  void features_host_theta(int k, const double* r, const double* d, double theta, float* X);
   std::vector<double> env_host(int cut, int side);
   const Problem* prob() const { return prob_; }
 
@@ -235,6 +249,17 @@ class Solver {
   void gemm_once(int mode, std::vector<GemmItem>& items, std::vector<GemmUnit>& units);
   void grad_site(int k, std::vector<double>& g, double* norm);
   DevMem grad_P_, grad_Q_, grad_G_;
+
+  // learned preconditioner and training-triple store
+  int precond_ = 0;
+  MLP* net_ = nullptr;
+  std::vector<int64_t> fblocks_host_;  // feature blocks of the prepared step: off, ld, rows, cols
+  DevMem d_fblocks_, fstats_, feat_, nety_, dv_L_, feat_t_;
+  int nfb_ = 0;
+  int rec_cap_ = 0, rec_sample_ = 0, rec_count_ = 0;
+  unsigned long long rec_seed_ = 0;
+  DevMem rec_X_, rec_T_, rec_hist_, rec_idx_;
+  void features(const double* r, const double* d, const double* theta, const double* t, float* X);
 
   // Davidson workspace
   DevMem dv_V_, dv_AV_, dv_G_, dv_evals_, dv_evecs_, dv_X_, dv_R_, dv_C_, dv_t_, dv_diag_, dv_part_,

@@ -1,0 +1,150 @@
+"""Learned-preconditioner form on the GPU: network kernels against the fp64
+oracle (forward, cosine-loss gradient, Adam), features against the oracle's
+definition, the solver's training triples, and what a network trained on them
+gains over the diagonal preconditioner at the same tolerance."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import embed
+from oracle import mlp as omlp
+from oracle import precond as opre
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _pk():
+    import paper_2609_09990_amd as pk
+    return pk
+
+
+def _net_with_oracle_params(pk, F, W, seed):
+    rng = np.random.default_rng(seed)
+    P = omlp.init(F, W, seed=seed)
+    for k in ("b1", "b2", "b3"):
+        P[k] = rng.normal(0, 0.2, P[k].shape)
+    net = pk.MLP(F, W, seed=0)
+    net.set_params(net.pack(P))
+    Pd = {k: v.astype(np.float64) for k, v in net.unpack().items()}  # fp32-rounded, as the GPU holds them
+    return net, Pd
+
+
+@pytest.mark.parametrize("F,W,n", [(8, 256, 1000), (5, 64, 77), (8, 256, 1)])
+def test_mlp_forward_fp32_and_bf16(F, W, n):
+    pk = _pk()
+    net, Pd = _net_with_oracle_params(pk, F, W, 1)
+    X = np.random.default_rng(2).normal(size=(n, F)).astype(np.float32)
+    ref, _ = omlp.forward(Pd, X.astype(np.float64))
+    Xd = torch.from_numpy(X).cuda()
+    y = torch.empty(n, dtype=torch.float32, device="cuda")
+    net.forward(Xd, y, precision=1)
+    scale = np.abs(ref).max()
+    assert np.abs(y.cpu().numpy() - ref).max() <= 1e-5 * scale
+    net.forward(Xd, y, precision=2)
+    assert np.abs(y.cpu().numpy() - ref).max() <= 2e-2 * scale
+
+
+@pytest.mark.parametrize("F,W,nseg,L", [(8, 256, 5, 300), (3, 64, 2, 1100)])
+def test_mlp_loss_gradient_and_adam_match_oracle(F, W, nseg, L):
+    pk = _pk()
+    net, Pd = _net_with_oracle_params(pk, F, W, 3)
+    rng = np.random.default_rng(4)
+    X = rng.normal(size=(nseg * L, F)).astype(np.float32)
+    T = rng.normal(size=nseg * L).astype(np.float32)
+    loss, g = net.loss_grad(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), nseg, L, want_grad=True)
+    G = {k: np.zeros_like(v) for k, v in Pd.items()}
+    ref_loss = 0.0
+    for s in range(nseg):
+        sl = slice(s * L, (s + 1) * L)
+        ys, cache = omlp.forward(Pd, X[sl].astype(np.float64))
+        ls, dy = omlp.cosine_loss(ys, T[sl].astype(np.float64))
+        gs = omlp.backward(Pd, cache, dy / nseg)
+        ref_loss += ls / nseg
+        for k in G:
+            G[k] += gs[k]
+    assert abs(loss - ref_loss) <= 1e-5
+    gg = net.unpack(g)
+    for k in G:
+        assert np.abs(gg[k] - G[k]).max() <= 1e-4 * max(np.abs(G[k]).max(), 1e-6), k
+    # one Adam step from the same gradient
+    net.adam_step(3e-3)
+    st = {}
+    Pa = {k: v.copy() for k, v in Pd.items()}
+    omlp.adam_step(Pa, {k: gg[k].astype(np.float64) for k in G}, st, 3e-3)
+    assert np.abs(net.params() - net.pack(Pa)).max() <= 1e-6
+
+
+@pytest.mark.parametrize("n,na,nb,nq,M,k", [(6, 3, 3, 8, 12, 2), (8, 4, 4, 16, 40, 3), (5, 3, 2, 4, 10, 0)])
+def test_features_match_oracle(n, na, nb, nq, M, k):
+    pk = _pk()
+    h, B, e0 = synth.make_hamiltonian(n, nq, 0)
+    sol = pk.Solver(pk.Problem(h, B, na, nb, e0), M=M)
+    mps = synth.random_mps(n, na, nb, M, seed=5)
+    sol.set_mps(mps["bonds"], mps["sites"])
+    N = sol.prepare(k)
+    r = np.random.default_rng(6).normal(size=N)
+    d = torch.zeros(N, dtype=torch.float64, device="cuda")
+    sol.diag(k, d)
+    dh = d.cpu().numpy()
+    theta = float(np.sort(dh)[N // 3])  # inside the spectrum of the diagonal: signs mix
+    X = torch.zeros((N, 8), dtype=torch.float32, device="cuda")
+    sol.features(k, torch.from_numpy(r).cuda(), d, theta, X)
+    blocks = [np.array([st + i * rs + cs + j for i in range(ml) for j in range(mr)])
+              for (_, ml, _, _, mr, st, rs, cs) in embed._slab_blocks(mps["bonds"][k], mps["bonds"][k + 2],
+                                                                      embed.twosite_qn())]
+    ref = opre.features(r, dh, theta, blocks, k, n)
+    Xh = X.cpu().numpy()
+    for f in range(8):
+        tol = 1e-5 * max(1.0, np.abs(ref[:, f]).max())
+        assert np.abs(Xh[:, f] - ref[:, f]).max() <= tol, f
+
+
+def test_training_triples_are_recorded_and_deterministic():
+    pk = _pk()
+    h, B, e0 = synth.make_hamiltonian(8, 16, 2)
+    out = []
+    for _ in range(2):
+        sol = pk.Solver(pk.Problem(h, B, 4, 4, e0), M=64, tol=1e-9)
+        sol.record_triples(500, 128)
+        sol.sweep(1)
+        X = torch.zeros((500, 128, 8), dtype=torch.float32, device="cuda")
+        T = torch.zeros((500, 128), dtype=torch.float32, device="cuda")
+        c = sol.take_triples(X, T, 500)
+        assert c > 10
+        assert bool(torch.isfinite(X[:c]).all()) and bool(torch.isfinite(T[:c]).all())
+        assert float(T[:c].abs().sum()) > 0
+        kpos = X[:c, :, 7].cpu().numpy()
+        assert np.all((kpos >= 0) & (kpos < 1))
+        out.append((c, X[:c].cpu().numpy(), T[:c].cpu().numpy()))
+        assert sol.take_triples(X, T, 500) == 0  # the store was emptied
+    assert out[0][0] == out[1][0]
+    assert np.array_equal(out[0][1], out[1][1]) and np.array_equal(out[0][2], out[1][2])
+
+
+def test_learned_preconditioner_gain_and_same_answer():
+    """Train on triples of four Hamiltonians, then solve a fifth with the
+    diagonal and with the learned preconditioner: the energies agree (the exact
+    residual judges both), and the matvec counts show the gain (printed)."""
+    pk = _pk()
+    from paper_2609_09990_amd import precond as pc
+    train = [synth.make_hamiltonian(8, 32, s) for s in (11, 12, 13, 14)]
+    X, T = pc.collect_triples(train, 4, 4, M=64, sweeps=2, sample=512, capacity=2048, tol=1e-9)
+    assert X.shape[0] > 100
+    net = pk.MLP(8, 256, seed=0)
+    hist = pc.train(net, X, T, steps=400, batch=32, lr=1e-3)
+    base = pc.diag_baseline_loss(X, T)
+    print(f"triples={X.shape[0]} loss first={hist[:20].mean():.3f} last={hist[-20:].mean():.3f} diag={base:.3f}")
+    assert hist[-20:].mean() < hist[:20].mean()
+    h, B, e0 = synth.make_hamiltonian(8, 32, 0)
+    res = {}
+    for mode in (0, 1):
+        sol = pk.Solver(pk.Problem(h, B, 4, 4, e0), M=256, tol=1e-10)
+        sol.set_precond(mode, net if mode else None)
+        e, tau, ok = sol.sweep(2)
+        st = sol.stats()
+        res[mode] = (e[0], ok, st["matvecs"], st["fallbacks"])
+    print(f"diag: E={res[0][0]:.12f} matvecs={res[0][2]:.0f}; learned: E={res[1][0]:.12f} "
+          f"matvecs={res[1][2]:.0f} fallbacks={res[1][3]:.0f}; gain={res[0][2] / res[1][2]:.3f}x")
+    assert res[0][1] and res[1][1]
+    assert abs(res[0][0] - res[1][0]) <= 1e-9
