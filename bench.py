@@ -8,7 +8,9 @@ up to the middle bond.  A step is one full two-site DMRG step at the middle bond
 update; steps alternate direction so every step re-solves the same bond.
 
 Prints one JSON line (rank 0).  `value` = algorithmic sigma + environment-update
-TFLOP/s over the timed steps' wall time.
+TFLOP/s over the timed steps' wall time.  After the steps, one full sweep
+(2(L-1) two-site steps from site 0) is timed end to end ("sweep"); step plans
+are rebuilt whenever a step's outer bonds changed since its last visit.
 """
 import argparse
 import json
@@ -72,6 +74,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the timed full sweep")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
@@ -134,16 +137,41 @@ def main():
                    "n_chol": N_CHOL, "M": M, "davidson_tol": 1e-8, "seed": SEED},
         "sigma_kernel_tflops": sig_flops / ((d["sigma_a_ms"] + d["sigma_b_ms"]) * 1e-3) / 1e12,
         "matvecs_per_step": nmv / args.steps,
-        "sweep_s_estimate": ms_per_step * 2 * (N_ORB - 1) / 1e3,
+
         "breakdown_ms_per_step": {"sigma": (d["sigma_a_ms"] + d["sigma_b_ms"]) / args.steps,
-                                  "env": d["env_ms"] / args.steps, "svd": d["svd_ms"] / args.steps},
+                                  "env": d["env_ms"] / args.steps, "svd": d["svd_ms"] / args.steps,
+                                  "prepare_wall": d["prepare_ms"] / args.steps,
+                                  "plan_resolve_wall": d["resolve_ms"] / args.steps,
+                                  "davidson_wall": d["davidson_ms"] / args.steps},
         "setup_s": t_setup,
         "energy_last": energies[-1] if energies else None,
+        "plan_reuse_per_step": (d["plan_hits"]) / args.steps,
         "roofline": {"bound": "mfma", "kernel": "gemm_f64_w32<1, 4> (sigma phase B, timed launches)",
                      "achieved": b_achieved, "peak": PEAK_FP64, "unit": "TFLOP/s",
                      "frac": b_achieved / PEAK_FP64, "traffic": TRAFFIC,
                      "launch_ms": b_launch_ms, "flops_per_launch": d["sigma_b_flops"] / nmv},
     }
+    if not args.no_sweep:
+        # one full sweep (2(L-1) two-site steps) timed end to end; the centre first
+        # walks back to site 0 with right-to-left steps (untimed)
+        centre = MID + 1 if direction == 1 else MID
+        for k in range(centre - 1, -1, -1):
+            sol.step(k, 1)
+        print("# centre at site 0", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        s2 = sol.stats()
+        t0 = time.time()
+        e, tau, ok = sol.sweep(1)
+        torch.cuda.synchronize()
+        sweep_s = time.time() - t0
+        s3 = sol.stats()
+        out["sweep"] = {"seconds": sweep_s, "steps": 2 * (N_ORB - 1), "energy": float(e[0]), "tau_max": tau,
+                        "converged": bool(ok), "matvecs": s3["matvecs"] - s2["matvecs"],
+                        "plan_reuse": s3["plan_hits"] - s2["plan_hits"],
+                        "sigma_s": (s3["sigma_a_ms"] + s3["sigma_b_ms"] - s2["sigma_a_ms"] - s2["sigma_b_ms"]) / 1e3,
+                        "tflops": (s3["sigma_a_flops"] + s3["sigma_b_flops"] + s3["env_flops"] - s2["sigma_a_flops"]
+                                   - s2["sigma_b_flops"] - s2["env_flops"]) / sweep_s / 1e12}
+        print(f"# sweep {sweep_s:.1f} s E={e[0]:.10f}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pk, torch)
     print(json.dumps(out), flush=True)

@@ -136,6 +136,9 @@ dmrg_status dmrg_sweep(dmrg_solver* s, int n_sweeps, double* energies, double* t
 /* One two-site step on sites (k, k+1): Davidson on H_eff, SVD truncation to M,
  * environment update; direction 0 moves the center right (k -> k+1), 1 moves
  * it left.  A sweep is steps 0..n_orb-2 in direction 0 then n_orb-2..0 in 1.
+ * The orthogonality centre must be on site k or k+1 (after solver creation it
+ * is site 0; each step leaves it on the site it moved to; after dmrg_set_mps
+ * the gauge is the caller's): else DMRG_ESTATE.
  * energies[n_states]: Ritz values + e_core; tau: discarded weight. */
 dmrg_status dmrg_step(dmrg_solver* s, int k, int direction, double* energies, double* tau);
 
@@ -244,7 +247,11 @@ dmrg_status dmrg_set_kernel_tag(dmrg_solver* s, int tag);
  * [12] phase-A flops, [13] phase-B flops, [14] environment-update flops,
  * [15] fp64 refinements, [16] phase-B GEMM kernel ms alone (fp64; without the
  * split-K reduction), [17] dmrg_grad wall ms, [18] dmrg_grad flops (without
- * the environment updates it triggers).  Times of [2]-[4], [10], [11], [16] are
+ * the environment updates it triggers), [19] step-preparation wall ms
+ * (environments, factors, plans), [20] plan resolution and upload wall ms,
+ * [21] Davidson wall ms, [22] step plans reused (a step's plan depends only on
+ * its outer bonds and is kept per step; it is rebuilt when they change).
+ * Times of [2]-[4], [10], [11], [16] are
  * HIP-event times on the solver stream and flops count unpadded block
  * products.  n: capacity of out. */
 dmrg_status dmrg_get_stats(const dmrg_solver* s, double* out, int n);

@@ -13,6 +13,7 @@
 // and the left (right) environment update reuses the same factors with the site
 // tensor in place of psi.
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 
 #include "solver.hpp"
@@ -193,6 +194,7 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
     launch_resolved(ph, prec, slot);
     return;
   }
+  const auto tr0 = std::chrono::steady_clock::now();
   validate_phase(ph, sizes);
   for (int b = 0; b < B_NBUF; ++b) ph.last_bases[slot][b] = bases[b];
   ph.uploaded[slot] = true;
@@ -261,6 +263,7 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
   hip_check(hipMemcpyAsync(ph.d_units[slot].p, units.data(), units.size() * sizeof(GemmUnit), hipMemcpyHostToDevice, st), "units");
   if (!tiles.empty())
     hip_check(hipMemcpyAsync(ph.d_tiles[slot].p, tiles.data(), tiles.size() * sizeof(SplitTile), hipMemcpyHostToDevice, st), "tiles");
+  st_.resolve_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tr0).count();
   launch_resolved(ph, prec, slot);
 }
 
@@ -357,12 +360,12 @@ void Solver::env_update_left(int k, const FactorSide& fs) {
       add_units(pb.units, B_OUT, cbase + eb.off, eb.mc, eb.mr, eb.mc, ib, (int)pb.items.size(), 0);
     }
   }
-  t_buf_.reserve(std::max<long>(zsize, 1) * sizeof(double));
+  env_t_buf_.reserve(std::max<long>(zsize, 1) * sizeof(double));
   launch_fill(out.buf.as<double>(), out.size, 0.0, st);
   void* bases[B_NBUF] = {};
   bases[B_PSI] = A.buf.p;
   bases[B_OUT] = out.buf.p;
-  bases[B_T] = t_buf_.p;
+  bases[B_T] = env_t_buf_.p;
   bases[B_XMIX] = fs.mix.p;
   bases[B_ENVL] = envk.buf.p;
   size_t esz[B_NBUF] = {8, 8, 8, 8, 8, 8, 8, 8};
@@ -476,11 +479,11 @@ void Solver::env_update_right(int j, const FactorSide& fs) {
       add_units(pb.units, B_OUT, cbase + eb.off, eb.mc, eb.mr, eb.mc, ib, (int)pb.items.size(), 0);
     }
   }
-  t_buf_.reserve(std::max<long>(usize, 1) * sizeof(double));
+  env_t_buf_.reserve(std::max<long>(usize, 1) * sizeof(double));
   launch_fill(out.buf.as<double>(), out.size, 0.0, st);
   void* bases[B_NBUF] = {};
   bases[B_OUT] = out.buf.p;
-  bases[B_T] = t_buf_.p;
+  bases[B_T] = env_t_buf_.p;
   bases[B_YMIX] = fs.mix.p;
   bases[B_ENVR] = envr.buf.p;
   bases[B_SITE2] = Bt.buf.p;

@@ -181,7 +181,8 @@ void Solver::init_random_mps() {
   for (auto& e : left_) e.valid = false;
   for (auto& e : right_) e.valid = false;
   plan_k_ = -1;
-  center_site_ = -1;
+  centers_.clear();
+  center_site_ = 0;  // every site right-canonical: the orthogonality centre is site 0
 }
 
 void Solver::set_mps(const std::vector<Bond>& bonds, const std::vector<const double*>& sites) {
@@ -205,7 +206,8 @@ void Solver::set_mps(const std::vector<Bond>& bonds, const std::vector<const dou
   for (auto& e : left_) e.valid = false;
   for (auto& e : right_) e.valid = false;
   plan_k_ = -1;
-  center_site_ = -1;
+  centers_.clear();
+  center_site_ = -1;  // gauge unknown
 }
 
 void Solver::ensure_left(int c) {
@@ -254,19 +256,64 @@ void Solver::ensure_right(int c) {
 
 void Solver::prepare(int k) {
   DMRG_REQUIRE(k >= 0 && k + 1 < L_, ST_EINVAL, "two-site step out of range");
+  const auto tp0 = std::chrono::steady_clock::now();
   ensure_left(k);
   ensure_right(k + 2);
-  build_factor_side(lf_, true, k);
-  run_premix(lf_, left_[k]);
-  build_factor_side(rf_, false, k + 1);
-  run_premix(rf_, right_[k + 2]);
-  build_sigma_plan(k);
+  // park the current plan, then reuse the cached one of step k if its outer bonds match
+  hip_check(hipStreamSynchronize(st), "prepare");  // host staging of the parked plan is no longer read
+  if (plan_built_k_ >= 0) {
+    StepPlan& c = plan_cache_[plan_built_k_];
+    c.key_l = bonds_at_build_l_;
+    c.key_r = bonds_at_build_r_;
+    c.lf = std::move(lf_);
+    c.rf = std::move(rf_);
+    c.psi_lay = std::move(psi_lay_);
+    c.phA = std::move(phA_);
+    c.phB = std::move(phB_);
+    c.t_size = t_size_;
+    for (Phase* ph : {&c.phA, &c.phB})
+      for (int i = 0; i < 3; ++i) {
+        std::vector<GemmItem>().swap(ph->h_items[i]);
+        std::vector<GemmUnit>().swap(ph->h_units[i]);
+        std::vector<SplitTile>().swap(ph->h_tiles[i]);
+      }
+    plan_built_k_ = -1;
+  }
+  auto same_bond = [](const std::vector<Sector>& a, const std::vector<Sector>& b) {
+    if (a.size() != b.size()) return false;
+    for (size_t i = 0; i < a.size(); ++i)
+      if (a[i].q != b[i].q || a[i].dim != b[i].dim) return false;
+    return true;
+  };
+  auto hit = plan_cache_.find(k);
+  if (hit != plan_cache_.end() && same_bond(hit->second.key_l, bonds_[k].sec) &&
+      same_bond(hit->second.key_r, bonds_[k + 2].sec)) {
+    StepPlan& c = hit->second;
+    lf_ = std::move(c.lf);
+    rf_ = std::move(c.rf);
+    psi_lay_ = std::move(c.psi_lay);
+    phA_ = std::move(c.phA);
+    phB_ = std::move(c.phB);
+    t_size_ = c.t_size;
+    plan_cache_.erase(hit);
+    run_premix(lf_, left_[k]);
+    run_premix(rf_, right_[k + 2]);
+    st_.plan_hits++;
+  } else {
+    if (hit != plan_cache_.end()) plan_cache_.erase(hit);
+    build_factor_side(lf_, true, k);
+    run_premix(lf_, left_[k]);
+    build_factor_side(rf_, false, k + 1);
+    run_premix(rf_, right_[k + 2]);
+    build_sigma_plan(k);
+    for (int i = 0; i < 3; ++i) phA_.uploaded[i] = phB_.uploaded[i] = false;
+  }
+  plan_built_k_ = k;
+  bonds_at_build_l_ = bonds_[k].sec;
+  bonds_at_build_r_ = bonds_[k + 2].sec;
   t_buf_.reserve(std::max<long>(t_size_, 1) * sizeof(double));
   psi_in_.reserve(std::max<long>(psi_lay_.size, 1) * sizeof(double));
   out_buf_.reserve(std::max<long>(psi_lay_.size, 1) * sizeof(double));
-  for (int i = 0; i < 3; ++i) {
-    phA_.uploaded[i] = phB_.uploaded[i] = false;
-  }
   lowp_prec_ = -1;
   diag_ready_ = false;
   // dense blocks of the two-site vector, for the preconditioner features
@@ -282,6 +329,7 @@ void Solver::prepare(int k) {
               "feature blocks");
   plan_k_ = k;
   hip_check(hipStreamSynchronize(st), "prepare");
+  st_.prepare_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tp0).count();
 }
 
 std::vector<double> Solver::env_host(int cut, int side) {
@@ -318,8 +366,7 @@ void Solver::ensure_lowp(int prec) {
   lowp_[B_PSI].reserve(std::max<long>(psi_lay_.size, 1) * esz);
   lowp_[B_T].reserve(std::max<long>(t_size_, 1) * 4);
   lowp_[B_OUT].reserve(std::max<long>(psi_lay_.size, 1) * 4);
-  lowp_prec_ = prec;
-  phA_.uploaded[1] = phA_.uploaded[2] = phB_.uploaded[1] = phB_.uploaded[2] = false;
+  lowp_prec_ = prec;  // resolved low-precision plans stay valid while their buffers do (bases are compared)
 }
 
 void Solver::sigma(int k, int prec, const double* psi, double* out) {
@@ -461,6 +508,12 @@ void Solver::form_twosite(int k, const SiteTensor& a, const SiteTensor& b, doubl
 // precision convergence the Ritz vectors' fp64 sigma replaces the subspace).
 int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& evals) {
   if (plan_k_ != k) prepare(k);
+  const auto td0 = std::chrono::steady_clock::now();
+  struct WallTimer {
+    std::chrono::steady_clock::time_point t0;
+    double* acc;
+    ~WallTimer() { *acc += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count(); }
+  } wall_timer{td0, &st_.davidson_ms};
   const long n = psi_lay_.size;
   const int nr = opt_.n_states;
   const int kmax = std::min<long>(opt_.max_subspace, std::max<long>(n, 1));
@@ -1081,6 +1134,9 @@ void Solver::make_guess(int k, bool l2r) {
 // Davidson, decimate with the SVD, move the center, update the environment.
 double Solver::step(int k, bool l2r, std::vector<double>& energies) {
   DMRG_REQUIRE(k >= 0 && k + 1 < L_, ST_EINVAL, "two-site step out of range");
+  // the environments are orthonormal bases only when the orthogonality centre is on the two sites
+  DMRG_REQUIRE(center_site_ < 0 || center_site_ == k || center_site_ == k + 1, ST_ESTATE,
+               "two-site step away from the orthogonality centre (site " + std::to_string(center_site_) + ")");
   make_guess(k, l2r);
   prepare(k);
   std::vector<double> ev;

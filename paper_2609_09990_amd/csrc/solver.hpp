@@ -151,6 +151,8 @@ struct Stats {
   int converged = 1;
   int refinements = 0;
   double grad_ms = 0, grad_flops = 0;  // integral-gradient passes
+  double prepare_ms = 0, resolve_ms = 0, davidson_ms = 0;  // host wall times
+  int plan_hits = 0;  // step plans reused from the cache
 };
 
 class MLP;
@@ -219,6 +221,19 @@ class Solver {
   Phase phA_, phB_;
   long t_size_ = 0;
   DevMem psi_in_, out_buf_, t_buf_;
+  DevMem env_t_buf_;  // intermediates of environment updates (kept apart so t_buf_ stays put)
+  // Step plans by step k, reused when the outer bonds k and k+2 are unchanged
+  // (the plan depends on them and the MPO only; values come from the buffers).
+  struct StepPlan {
+    std::vector<Sector> key_l, key_r;
+    FactorSide lf, rf;
+    TensorLayout psi_lay;
+    Phase phA, phB;
+    long t_size = 0;
+  };
+  std::map<int, StepPlan> plan_cache_;
+  int plan_built_k_ = -1;  // step whose plan is in lf_, rf_, psi_lay_, phA_, phB_
+  std::vector<Sector> bonds_at_build_l_, bonds_at_build_r_;
   DevMem lowp_[B_NBUF];  // low-precision copies per buffer id
   int lowp_prec_ = -1;
   long lowp_size_[B_NBUF] = {0};
