@@ -297,6 +297,22 @@ __device__ inline double ld_b(const double* B, int ldb, int k, int n) {
   return MODE == GEMM_NT ? B[(long)n * ldb + k] : B[(long)k * ldb + n];
 }
 
+// Two consecutive doubles p[k], p[k+1] of a row (zero past K or for a masked
+// row); a full pair is one 16-byte load (8-byte aligned).
+typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
+typedef __attribute__((address_space(1))) const d2u gd2u;      // global memory
+typedef __attribute__((address_space(1))) const double gdbl;
+__device__ inline void ld_pair(const double* p, int k, int K, bool rowv, double* x) {
+  if (rowv && k + 1 < K) {
+    const d2u v = *(gd2u*)(p + k);
+    x[0] = v.x;
+    x[1] = v.y;
+  } else {
+    x[0] = (rowv && k < K) ? *(gdbl*)(p + k) : 0.0;
+    x[1] = 0.0;
+  }
+}
+
 // TAG only names otherwise identical instantiations, so a profiler can tell
 // launches apart (e.g. sigma phases, timed and untimed work).
 template <int MODE, int TAG>
@@ -314,6 +330,69 @@ __global__ __launch_bounds__(256) void gemm_f64_w32(const GemmUnit* __restrict__
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+  if constexpr (MODE == GEMM_NT) {
+    // Both operands run along k in memory: lane (r, kq) loads the pair k0+2kq,
+    // k0+2kq+1 of its rows with one 16-byte load, and the two MFMA steps of an
+    // 8-deep block take the even and the odd k of the pairs (the same k order
+    // for A and B, so the product is unchanged).
+    for (int it = u.ib; it < u.ie; ++it) {
+      const GemmItem g = items[it];
+      const double* A = (const double*)g.A;
+      const double* B = (const double*)g.B;
+      const double c = g.coef;
+      const double* pa0 = A + (long)(av0 ? am0 : 0) * g.lda;
+      const double* pa1 = A + (long)(av1 ? am1 : 0) * g.lda;
+      const double* pb0 = B + (long)(bv0 ? bn0 : 0) * g.ldb;
+      const double* pb1 = B + (long)(bv1 ? bn1 : 0) * g.ldb;
+      for (int k0 = 0; k0 < g.K; k0 += 8) {
+        const int kk = k0 + 2 * kq;
+        double a0[2], a1[2], b0[2], b1[2];
+        ld_pair(pa0, kk, g.K, av0, a0);
+        ld_pair(pa1, kk, g.K, av1, a1);
+        ld_pair(pb0, kk, g.K, bv0, b0);
+        ld_pair(pb1, kk, g.K, bv1, b1);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const double x0 = a0[h] * c, x1 = a1[h] * c;
+          acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, b0[h], acc[0][0], 0, 0, 0);
+          acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, b1[h], acc[0][1], 0, 0, 0);
+          acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, b0[h], acc[1][0], 0, 0, 0);
+          acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, b1[h], acc[1][1], 0, 0, 0);
+        }
+      }
+    }
+  } else if constexpr (MODE == GEMM_NN) {
+    // A runs along k: pair loads as above; B rows kk and kk+1 are contiguous in n.
+    for (int it = u.ib; it < u.ie; ++it) {
+      const GemmItem g = items[it];
+      const double* A = (const double*)g.A;
+      const double* B = (const double*)g.B;
+      const double c = g.coef;
+      const double* pa0 = A + (long)(av0 ? am0 : 0) * g.lda;
+      const double* pa1 = A + (long)(av1 ? am1 : 0) * g.lda;
+      for (int k0 = 0; k0 < g.K; k0 += 8) {
+        const int kk = k0 + 2 * kq;
+        double a0[2], a1[2], b0[2], b1[2];
+        ld_pair(pa0, kk, g.K, av0, a0);
+        ld_pair(pa1, kk, g.K, av1, a1);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const bool kv = kk + h < g.K;
+          const gdbl* brow = (const gdbl*)(B + (long)(kv ? kk + h : 0) * g.ldb);
+          b0[h] = (bv0 && kv) ? brow[bn0] : 0.0;
+          b1[h] = (bv1 && kv) ? brow[bn1] : 0.0;
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const double x0 = a0[h] * c, x1 = a1[h] * c;
+          acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, b0[h], acc[0][0], 0, 0, 0);
+          acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, b1[h], acc[0][1], 0, 0, 0);
+          acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, b0[h], acc[1][0], 0, 0, 0);
+          acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, b1[h], acc[1][1], 0, 0, 0);
+        }
+      }
+    }
+  } else
   for (int it = u.ib; it < u.ie; ++it) {
     const GemmItem g = items[it];
     const double* A = (const double*)g.A;
