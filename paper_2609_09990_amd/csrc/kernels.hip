@@ -313,141 +313,174 @@ __device__ inline void ld_pair(const double* p, int k, int K, bool rowv, double*
   }
 }
 
-// TAG only names otherwise identical instantiations, so a profiler can tell
-// launches apart (e.g. sigma phases, timed and untimed work).
-template <int MODE, int TAG>
-__global__ __launch_bounds__(256) void gemm_f64_w32(const GemmUnit* __restrict__ units,
-                                                    const GemmItem* __restrict__ items, int n_units) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int ui = blockIdx.x * 4 + wave;
-  if (ui >= n_units) return;  // whole wave exits; the kernel has no barriers
-  const GemmUnit u = units[ui];
+// Raw buffer loads: a resource covers one operand's extent, loads past it return
+// zeros (no fault), so masked lanes need no branches.  Word 3 is the gfx9 raw
+// buffer format.
+typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
+typedef unsigned int v2u32 __attribute__((ext_vector_type(2)));
+constexpr int kBufWord3 = 0x00020000;
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, long bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, kBufWord3);
+}
+__device__ inline void buf_pair(__amdgpu_buffer_rsrc_t r, int e, double* x) {
+  const v4u32 v = __builtin_amdgcn_raw_buffer_load_b128(r, e * 8, 0, 0);
+  __builtin_memcpy(&x[0], &v, 8);
+  __builtin_memcpy(&x[1], reinterpret_cast<const char*>(&v) + 8, 8);
+}
+__device__ inline double buf_one(__amdgpu_buffer_rsrc_t r, int e) {
+  const v2u32 v = __builtin_amdgcn_raw_buffer_load_b64(r, e * 8, 0, 0);
+  double x;
+  __builtin_memcpy(&x, &v, 8);
+  return x;
+}
+
+// One wave computes a (16 RB) x (16 CB) tile: RB x CB fp64 16x16x4 MFMA blocks.
+template <int MODE, int RB, int CB>
+__device__ inline void w32_tile(const GemmUnit& u, const GemmItem* __restrict__ items, int lane) {
   const int r = lane & 15, kq = lane >> 4;
-  const int am0 = u.m0 + r, am1 = u.m0 + 16 + r, bn0 = u.n0 + r, bn1 = u.n0 + 16 + r;
-  const bool av0 = am0 < u.M, av1 = am1 < u.M, bv0 = bn0 < u.N, bv1 = bn1 < u.N;
-  v4d acc[2][2];
+  int am[RB], bn[CB];
+  bool av[RB], bv[CB];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < RB; ++i) {
+    am[i] = u.m0 + 16 * i + r;
+    av[i] = am[i] < u.M;
+  }
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
-  if constexpr (MODE == GEMM_NT) {
-    // Both operands run along k in memory: lane (r, kq) loads the pair k0+2kq,
-    // k0+2kq+1 of its rows with one 16-byte load, and the two MFMA steps of an
-    // 8-deep block take the even and the odd k of the pairs (the same k order
-    // for A and B, so the product is unchanged).
-    for (int it = u.ib; it < u.ie; ++it) {
-      const GemmItem g = items[it];
-      const double* A = (const double*)g.A;
-      const double* B = (const double*)g.B;
-      const double c = g.coef;
-      const double* pa0 = A + (long)(av0 ? am0 : 0) * g.lda;
-      const double* pa1 = A + (long)(av1 ? am1 : 0) * g.lda;
-      const double* pb0 = B + (long)(bv0 ? bn0 : 0) * g.ldb;
-      const double* pb1 = B + (long)(bv1 ? bn1 : 0) * g.ldb;
-      for (int k0 = 0; k0 < g.K; k0 += 8) {
-        const int kk = k0 + 2 * kq;
-        double a0[2], a1[2], b0[2], b1[2];
-        ld_pair(pa0, kk, g.K, av0, a0);
-        ld_pair(pa1, kk, g.K, av1, a1);
-        ld_pair(pb0, kk, g.K, bv0, b0);
-        ld_pair(pb1, kk, g.K, bv1, b1);
+  for (int j = 0; j < CB; ++j) {
+    bn[j] = u.n0 + 16 * j + r;
+    bv[j] = bn[j] < u.N;
+  }
+  v4d acc[RB][CB];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const double x0 = a0[h] * c, x1 = a1[h] * c;
-          acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, b0[h], acc[0][0], 0, 0, 0);
-          acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, b1[h], acc[0][1], 0, 0, 0);
-          acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, b0[h], acc[1][0], 0, 0, 0);
-          acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, b1[h], acc[1][1], 0, 0, 0);
-        }
-      }
-    }
-  } else if constexpr (MODE == GEMM_NN) {
-    // A runs along k: pair loads as above; B rows kk and kk+1 are contiguous in n.
-    for (int it = u.ib; it < u.ie; ++it) {
-      const GemmItem g = items[it];
-      const double* A = (const double*)g.A;
-      const double* B = (const double*)g.B;
-      const double c = g.coef;
-      const double* pa0 = A + (long)(av0 ? am0 : 0) * g.lda;
-      const double* pa1 = A + (long)(av1 ? am1 : 0) * g.lda;
-      for (int k0 = 0; k0 < g.K; k0 += 8) {
-        const int kk = k0 + 2 * kq;
-        double a0[2], a1[2], b0[2], b1[2];
-        ld_pair(pa0, kk, g.K, av0, a0);
-        ld_pair(pa1, kk, g.K, av1, a1);
+  for (int i = 0; i < RB; ++i)
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const bool kv = kk + h < g.K;
-          const gdbl* brow = (const gdbl*)(B + (long)(kv ? kk + h : 0) * g.ldb);
-          b0[h] = (bv0 && kv) ? brow[bn0] : 0.0;
-          b1[h] = (bv1 && kv) ? brow[bn1] : 0.0;
-        }
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const double x0 = a0[h] * c, x1 = a1[h] * c;
-          acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, b0[h], acc[0][0], 0, 0, 0);
-          acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, b1[h], acc[0][1], 0, 0, 0);
-          acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, b0[h], acc[1][0], 0, 0, 0);
-          acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, b1[h], acc[1][1], 0, 0, 0);
-        }
-      }
-    }
-  } else
+    for (int j = 0; j < CB; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+  // the next item's descriptor is fetched while the current item computes
+  GemmItem gnext;
+  if (u.ib < u.ie) gnext = items[u.ib];
   for (int it = u.ib; it < u.ie; ++it) {
-    const GemmItem g = items[it];
+    const GemmItem g = gnext;
+    if (it + 1 < u.ie) gnext = items[it + 1];
     const double* A = (const double*)g.A;
     const double* B = (const double*)g.B;
     const double c = g.coef;
-    int k0 = 0;
-    for (; k0 + 8 <= g.K; k0 += 8) {  // two k steps in flight
-      const int ka = k0 + kq, kb = k0 + 4 + kq;
-      double a0 = av0 ? ld_a<MODE>(A, g.lda, am0, ka) : 0.0;
-      double a1 = av1 ? ld_a<MODE>(A, g.lda, am1, ka) : 0.0;
-      double b0 = bv0 ? ld_b<MODE>(B, g.ldb, ka, bn0) : 0.0;
-      double b1 = bv1 ? ld_b<MODE>(B, g.ldb, ka, bn1) : 0.0;
-      double a2 = av0 ? ld_a<MODE>(A, g.lda, am0, kb) : 0.0;
-      double a3 = av1 ? ld_a<MODE>(A, g.lda, am1, kb) : 0.0;
-      double b2 = bv0 ? ld_b<MODE>(B, g.ldb, kb, bn0) : 0.0;
-      double b3 = bv1 ? ld_b<MODE>(B, g.ldb, kb, bn1) : 0.0;
-      a0 *= c;
-      a1 *= c;
-      a2 *= c;
-      a3 *= c;
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b2, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b3, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, b2, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, b3, acc[1][1], 0, 0, 0);
-    }
-    for (; k0 < g.K; k0 += 4) {
-      const int ka = k0 + kq;
-      const bool kv = ka < g.K;
-      double a0 = (av0 && kv) ? ld_a<MODE>(A, g.lda, am0, ka) * c : 0.0;
-      double a1 = (av1 && kv) ? ld_a<MODE>(A, g.lda, am1, ka) * c : 0.0;
-      double b0 = (bv0 && kv) ? ld_b<MODE>(B, g.ldb, ka, bn0) : 0.0;
-      double b1 = (bv1 && kv) ? ld_b<MODE>(B, g.ldb, ka, bn1) : 0.0;
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    // elements of A and B the unit can touch (row-major, leading dims lda, ldb)
+    const long ea = (long)(u.M - 1) * g.lda + g.K;
+    const long eb = MODE == GEMM_NT ? (long)(u.N - 1) * g.ldb + g.K : (long)(g.K - 1) * g.ldb + u.N;
+    if ((MODE == GEMM_NT || MODE == GEMM_NN) && ea < (1L << 27) && eb < (1L << 27)) {
+      // Same k pairing as below, through buffer loads: a masked row starts past
+      // the extent (its loads read zeros), a k past K is zeroed by a select.
+      const __amdgpu_buffer_rsrc_t ra = buf_rsrc(A, ea * 8), rb = buf_rsrc(B, eb * 8);
+      int ao[RB], bo[CB];
+#pragma unroll
+      for (int i = 0; i < RB; ++i) ao[i] = av[i] ? am[i] * g.lda : (int)ea;
+#pragma unroll
+      for (int j = 0; j < CB; ++j) bo[j] = MODE == GEMM_NT ? (bv[j] ? bn[j] * g.ldb : (int)eb) : bn[j];
+      for (int k0 = 0; k0 < g.K; k0 += 8) {
+        const int kk = k0 + 2 * kq;
+        const bool k0v = kk < g.K, k1v = kk + 1 < g.K;
+        double a[RB][2], b[CB][2];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          double t[2];
+          buf_pair(ra, ao[i] + kk, t);
+          a[i][0] = k0v ? t[0] * c : 0.0;
+          a[i][1] = k1v ? t[1] * c : 0.0;
+        }
+        if constexpr (MODE == GEMM_NT) {
+#pragma unroll
+          for (int j = 0; j < CB; ++j) {
+            double t[2];
+            buf_pair(rb, bo[j] + kk, t);
+            b[j][0] = k0v ? t[0] : 0.0;
+            b[j][1] = k1v ? t[1] : 0.0;
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < CB; ++j) {
+            const double t0 = buf_one(rb, kk * g.ldb + bo[j]);
+            const double t1 = buf_one(rb, (kk + 1) * g.ldb + bo[j]);
+            b[j][0] = (bv[j] && k0v) ? t0 : 0.0;
+            b[j][1] = (bv[j] && k1v) ? t1 : 0.0;
+          }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int i = 0; i < RB; ++i)
+#pragma unroll
+            for (int j = 0; j < CB; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][h], b[j][h], acc[i][j], 0, 0, 0);
+      }
+    } else if constexpr (MODE == GEMM_NT || MODE == GEMM_NN) {
+      // A runs along k in memory: lane (r, kq) loads the pair k0+2kq, k0+2kq+1 of
+      // its rows with one 16-byte load, and the two MFMA steps of an 8-deep block
+      // take the even and the odd k of the pairs (the same k order for B, so the
+      // product is unchanged).  In NT mode B runs along k too; in NN mode its rows
+      // kk and kk+1 are contiguous in n.
+      const double* pa[RB];
+      const double* pb[CB];
+#pragma unroll
+      for (int i = 0; i < RB; ++i) pa[i] = A + (long)(av[i] ? am[i] : 0) * g.lda;
+#pragma unroll
+      for (int j = 0; j < CB; ++j) pb[j] = B + (long)(bv[j] ? bn[j] : 0) * g.ldb;
+      for (int k0 = 0; k0 < g.K; k0 += 8) {
+        const int kk = k0 + 2 * kq;
+        double a[RB][2], b[CB][2];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) ld_pair(pa[i], kk, g.K, av[i], a[i]);
+        if constexpr (MODE == GEMM_NT) {
+#pragma unroll
+          for (int j = 0; j < CB; ++j) ld_pair(pb[j], kk, g.K, bv[j], b[j]);
+        } else {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const bool kv = kk + h < g.K;
+            const gdbl* brow = (const gdbl*)(B + (long)(kv ? kk + h : 0) * g.ldb);
+#pragma unroll
+            for (int j = 0; j < CB; ++j) b[j][h] = (bv[j] && kv) ? brow[bn[j]] : 0.0;
+          }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int i = 0; i < RB; ++i) {
+            const double x = a[i][h] * c;
+#pragma unroll
+            for (int j = 0; j < CB; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, b[j][h], acc[i][j], 0, 0, 0);
+          }
+      }
+    } else {
+      for (int k0 = 0; k0 < g.K; k0 += 4) {
+        const int ka = k0 + kq;
+        const bool kv = ka < g.K;
+        double a[RB], b[CB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) a[i] = (av[i] && kv) ? ld_a<MODE>(A, g.lda, am[i], ka) * c : 0.0;
+#pragma unroll
+        for (int j = 0; j < CB; ++j) b[j] = (bv[j] && kv) ? ld_b<MODE>(B, g.ldb, ka, bn[j]) : 0.0;
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+#pragma unroll
+          for (int j = 0; j < CB; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
     }
   }
   double* C = (double*)u.C;
   // accumulator element q of lane l: row l/16 + 4q, column l%16 (fp64 16x16x4 layout)
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < RB; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < CB; ++j)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         int tr = 16 * i + kq + 4 * q, tc = 16 * j + r;
         int gm = u.m0 + tr, gn = u.n0 + tc;
         double v = acc[i][j][q];
         if (u.accumulate == 2) {
-          C[tr * 32 + tc] = v;  // partial slot, full 32x32 (masked entries are zero)
+          C[tr * (16 * CB) + tc] = v;  // partial slot, full tile (masked entries are zero)
         } else if (gm < u.M && gn < u.N) {
           long idx = (long)gm * u.ldc + gn;
           C[idx] = u.accumulate ? C[idx] + v : v;
@@ -455,16 +488,32 @@ __global__ __launch_bounds__(256) void gemm_f64_w32(const GemmUnit* __restrict__
       }
 }
 
+// TAG only names otherwise identical instantiations, so a profiler can tell
+// launches apart (e.g. sigma phases, timed and untimed work).
+template <int MODE, int TAG>
+__global__ __launch_bounds__(256) void gemm_f64_w32(const GemmUnit* __restrict__ units,
+                                                    const GemmItem* __restrict__ items, int n_units) {
+  // the wave index is uniform across the wave; saying so keeps the unit and item
+  // descriptors (and the buffer resources built from them) in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int ui = blockIdx.x * 4 + wave;
+  if (ui >= n_units) return;  // whole wave exits; the kernel has no barriers
+  const GemmUnit u = units[ui];
+  if (u.shape == 1) w32_tile<MODE, 4, 2>(u, items, lane);
+  else if (u.shape == 2) w32_tile<MODE, 2, 4>(u, items, lane);
+  else w32_tile<MODE, 2, 2>(u, items, lane);
+}
+
 // Split-K reduction: out tile += nothing; out tile = sum of its partial slots in order.
 __global__ void splitk_reduce(const SplitTile* __restrict__ tiles, const double* __restrict__ slots) {
   const SplitTile t = tiles[blockIdx.x];
   double* C = (double*)t.C;
-  for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
-    int tr = e >> 5, tc = e & 31;
+  for (int e = threadIdx.x; e < t.tm * t.tn; e += blockDim.x) {
+    int tr = e / t.tn, tc = e - tr * t.tn;
     int gm = t.m0 + tr, gn = t.n0 + tc;
     if (gm >= t.M || gn >= t.N) continue;
     double acc = 0.0;
-    for (int s = 0; s < t.ns; ++s) acc += slots[(long)(t.s0 + s) * 1024 + e];
+    for (int s = 0; s < t.ns; ++s) acc += slots[(long)(t.s0 + s) * kSlotElems + e];
     C[(long)gm * t.ldc + gn] = acc;
   }
 }

@@ -17,9 +17,11 @@ struct GemmItem {
 
 // One output tile (rows m0.., cols n0.., at most 64 x 64) of an M x N output
 // block; it accumulates items [ib, ie) in order (no atomics: deterministic).
+// shape (fp64 one-wave kernel only): 0 = 32 x 32, 1 = 64 x 32, 2 = 32 x 64.
 struct GemmUnit {
   void* C;
   int ldc, M, N, m0, n0, ib, ie, accumulate;
+  int shape;
 };
 
 enum GemmMode : int {
@@ -34,16 +36,19 @@ enum GemmPrec : int { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2 };
 void launch_gemm(int prec, int mode, const GemmUnit* units, int n_units, const GemmItem* items,
                  hipStream_t s);
 
-// fp64 32x32-tile variant (one wave per unit, operands from global memory).
-// Units with accumulate == 2 write a full 32x32 partial tile to C (split-K).
+// fp64 one-wave variant (one wave per unit, tile 32x32, 64x32 or 32x64 by the
+// unit's shape, operands from global memory).  Units with accumulate == 2 write
+// the full tile, row-major (tile rows x tile cols), to a partial slot (split-K).
 void launch_gemm_w32(int mode, int tag, const GemmUnit* units, int n_units, const GemmItem* items,
                      hipStream_t s);
 
-// Output tile (rows m0.., cols n0.. of an M x N block) = sum of ns partial slots
-// s0..s0+ns-1 (each 32x32, row-major), summed in slot order.
+// Output tile (rows m0.., cols n0.. of an M x N block, tm x tn) = sum of ns
+// partial slots s0..s0+ns-1 (slot stride kSlotElems, tile row-major), summed in
+// slot order.
+constexpr int kSlotElems = 2048;
 struct SplitTile {
   void* C;
-  int ldc, M, N, m0, n0, s0, ns;
+  int ldc, M, N, m0, n0, s0, ns, tm, tn;
 };
 void launch_splitk_reduce(const SplitTile* tiles, int n, const double* slots, hipStream_t s);
 

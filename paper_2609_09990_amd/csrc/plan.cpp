@@ -216,35 +216,79 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
   tiles.clear();
   long n_slots = 0;
   if (prec == PREC_F64) {
-    // 32x32 tiles; long item lists are cut into chunks of about `chunk` MFMA
-    // k-steps, each writing a partial tile that splitk_reduce sums in order.
+    // One-wave tiles of 32x32, 64x32 or 32x64 (block rows and columns are covered
+    // by 64-wide strips while more than 32 remain, then by a 32-wide one); long
+    // item lists are cut into chunks of about `chunk` MFMA k-steps, each writing
+    // a partial tile that splitk_reduce sums in order.
+    auto strips = [](int n, std::vector<std::pair<int, int>>& v) {
+      v.clear();
+      int x = 0;
+      while (n - x > 32) {
+        v.push_back({x, 64});
+        x += 64;
+      }
+      if (x < n) v.push_back({x, 32});
+    };
+    struct TileShape { int m0, n0, tm, tn, shape; };
+    std::vector<std::pair<int, int>> rs, cs;
+    std::vector<TileShape> ts;
+    auto tiles_of = [&](const PUnit& u) {
+      strips(u.M, rs);
+      strips(u.N, cs);
+      ts.clear();
+      for (auto& r : rs)
+        for (auto& c : cs) {
+          if (r.second == 64 && c.second == 64) {  // no 64x64 wave tile: two 64x32
+            ts.push_back({r.first, c.first, 64, 32, 1});
+            ts.push_back({r.first, c.first + 32, 64, 32, 1});
+          } else if (r.second == 64) {
+            ts.push_back({r.first, c.first, 64, 32, 1});
+          } else if (c.second == 64) {
+            ts.push_back({r.first, c.first, 32, 64, 2});
+          } else {
+            ts.push_back({r.first, c.first, 32, 32, 0});
+          }
+        }
+    };
     double work = 0;
     for (const PUnit& u : ph.units)
       for (int i = u.ib; i < u.ie; ++i) work += ((u.M + 31) / 32) * ((u.N + 31) / 32) * ((ph.items[i].K + 3) / 4);
     const double chunk = std::max(DMRG_SPLIT_MIN, work / 16384.0);
+    std::vector<std::pair<int, int>> cuts;
     for (const PUnit& u : ph.units) {
       char* C = (char*)bases[u.cbuf] + u.coff * esz[u.cbuf];
-      for (int m0 = 0; m0 < u.M; m0 += 32)
-        for (int n0 = 0; n0 < u.N; n0 += 32) {
-          double w = 0;
-          for (int i = u.ib; i < u.ie; ++i) w += (ph.items[i].K + 3) / 4;
-          if (w <= chunk || u.ie - u.ib <= 1) {
-            units.push_back({C, u.ldc, u.M, u.N, m0, n0, u.ib, u.ie, u.acc});
-            continue;
-          }
-          int s0 = (int)n_slots, b = u.ib;
-          while (b < u.ie) {
-            int e = b;
-            double cw = 0;
-            while (e < u.ie && (cw < chunk || e == b)) cw += (ph.items[e++].K + 3) / 4;
-            units.push_back({(void*)(intptr_t)(n_slots * 1024), 32, u.M, u.N, m0, n0, b, e, 2});
-            ++n_slots;
-            b = e;
-          }
-          tiles.push_back({C, u.ldc, u.M, u.N, m0, n0, s0, (int)(n_slots - s0)});
+      tiles_of(u);
+      double w = 0;
+      for (int i = u.ib; i < u.ie; ++i) w += (ph.items[i].K + 3) / 4;
+      if (w <= chunk || u.ie - u.ib <= 1) {
+        for (const TileShape& t : ts) units.push_back({C, u.ldc, u.M, u.N, t.m0, t.n0, u.ib, u.ie, u.acc, t.shape});
+        continue;
+      }
+      // the same item chunks for every tile of the block; units chunk-major, so the
+      // waves of one workgroup run one chunk on neighbouring tiles (shared rows of A
+      // or columns of B)
+      cuts.clear();
+      for (int b = u.ib; b < u.ie;) {
+        int e = b;
+        double cw = 0;
+        while (e < u.ie && (cw < chunk || e == b)) cw += (ph.items[e++].K + 3) / 4;
+        cuts.push_back({b, e});
+        b = e;
+      }
+      const int nc = (int)cuts.size();
+      const long first_tile = (long)tiles.size();
+      for (const TileShape& t : ts) {
+        tiles.push_back({C, u.ldc, u.M, u.N, t.m0, t.n0, (int)n_slots, nc, t.tm, t.tn});
+        n_slots += nc;
+      }
+      for (int c = 0; c < nc; ++c)
+        for (size_t t = 0; t < ts.size(); ++t) {
+          const SplitTile& st_ = tiles[first_tile + t];
+          units.push_back({(void*)(intptr_t)((long)(st_.s0 + c) * kSlotElems), st_.tn, u.M, u.N, st_.m0, st_.n0,
+                           cuts[c].first, cuts[c].second, 2, ts[t].shape});
         }
     }
-    ph.slots.reserve(std::max<long>(n_slots, 1) * 1024 * sizeof(double));
+    ph.slots.reserve(std::max<long>(n_slots, 1) * kSlotElems * sizeof(double));
     for (auto& un : units)
       if (un.accumulate == 2) un.C = ph.slots.as<double>() + (intptr_t)un.C;
   } else {
@@ -592,6 +636,11 @@ void Solver::build_sigma_plan(int k) {
   for (size_t so = 0; so < P.slabs.size(); ++so)
     for (size_t ob = 0; ob < per[so].size(); ++ob) {
       auto& v = per[so][ob];  // blocks without items still get (zero-writing) tiles
+      // operand order: consecutive items read neighbouring stretches of T rows
+      std::stable_sort(v.begin(), v.end(), [](const PItem& x, const PItem& y) {
+        if (x.aoff != y.aoff) return x.aoff < y.aoff;
+        return x.boff < y.boff;
+      });
       int ib = (int)phB_.items.size();
       phB_.items.insert(phB_.items.end(), v.begin(), v.end());
       const Slab& dst = P.slabs[so];
