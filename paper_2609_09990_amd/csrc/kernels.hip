@@ -376,7 +376,8 @@ __device__ inline void w32_tile(const GemmUnit& u, const GemmItem* __restrict__ 
       for (int i = 0; i < RB; ++i) ao[i] = av[i] ? am[i] * g.lda : (int)ea;
 #pragma unroll
       for (int j = 0; j < CB; ++j) bo[j] = MODE == GEMM_NT ? (bv[j] ? bn[j] * g.ldb : (int)eb) : bn[j];
-      for (int k0 = 0; k0 < g.K; k0 += 8) {
+      const int kfull = g.K - (g.K & 7) + ((g.K & 7) > 4 ? 8 : 0);  // paired blocks; a tail of <= 4 goes alone
+      for (int k0 = 0; k0 < kfull; k0 += 8) {
         const int kk = k0 + 2 * kq;
         const bool k0v = kk < g.K, k1v = kk + 1 < g.K;
         double a[RB][2], b[CB][2];
@@ -411,6 +412,26 @@ __device__ inline void w32_tile(const GemmUnit& u, const GemmItem* __restrict__ 
 #pragma unroll
             for (int j = 0; j < CB; ++j)
               acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][h], b[j][h], acc[i][j], 0, 0, 0);
+      }
+      if (kfull < g.K) {  // last 1..4 k: one MFMA step, lane kq takes k = kfull + kq
+        const int kk = kfull + kq;
+        const bool kv = kk < g.K;
+        double a[RB], b[CB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          const double t = buf_one(ra, ao[i] + kk);
+          a[i] = kv ? t * c : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < CB; ++j) {
+          const double t = MODE == GEMM_NT ? buf_one(rb, bo[j] + kk) : buf_one(rb, kk * g.ldb + bo[j]);
+          b[j] = (kv && (MODE == GEMM_NT || bv[j])) ? t : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+#pragma unroll
+          for (int j = 0; j < CB; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
       }
     } else if constexpr (MODE == GEMM_NT || MODE == GEMM_NN) {
       // A runs along k in memory: lane (r, kq) loads the pair k0+2kq, k0+2kq+1 of
@@ -499,9 +520,16 @@ __global__ __launch_bounds__(256) void gemm_f64_w32(const GemmUnit* __restrict__
   const int ui = blockIdx.x * 4 + wave;
   if (ui >= n_units) return;  // whole wave exits; the kernel has no barriers
   const GemmUnit u = units[ui];
-  if (u.shape == 1) w32_tile<MODE, 4, 2>(u, items, lane);
-  else if (u.shape == 2) w32_tile<MODE, 2, 4>(u, items, lane);
-  else w32_tile<MODE, 2, 2>(u, items, lane);
+  switch (u.shape) {  // 8 * RB + CB: tile (16 RB) x (16 CB)
+    case 9: w32_tile<MODE, 1, 1>(u, items, lane); break;
+    case 10: w32_tile<MODE, 1, 2>(u, items, lane); break;
+    case 17: w32_tile<MODE, 2, 1>(u, items, lane); break;
+    case 25: w32_tile<MODE, 3, 1>(u, items, lane); break;
+    case 26: w32_tile<MODE, 3, 2>(u, items, lane); break;
+    case 33: w32_tile<MODE, 4, 1>(u, items, lane); break;
+    case 34: w32_tile<MODE, 4, 2>(u, items, lane); break;
+    default: w32_tile<MODE, 2, 2>(u, items, lane); break;
+  }
 }
 
 // Split-K reduction: out tile += nothing; out tile = sum of its partial slots in order.

@@ -17,7 +17,8 @@ struct GemmItem {
 
 // One output tile (rows m0.., cols n0.., at most 64 x 64) of an M x N output
 // block; it accumulates items [ib, ie) in order (no atomics: deterministic).
-// shape (fp64 one-wave kernel only): 0 = 32 x 32, 1 = 64 x 32, 2 = 32 x 64.
+// shape (fp64 one-wave kernel only): 8 RB + CB for a (16 RB) x (16 CB) tile,
+// RB in 1..4, CB in 1..2 (0 = 32 x 32).
 struct GemmUnit {
   void* C;
   int ldc, M, N, m0, n0, ib, ie, accumulate;
@@ -36,8 +37,8 @@ enum GemmPrec : int { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2 };
 void launch_gemm(int prec, int mode, const GemmUnit* units, int n_units, const GemmItem* items,
                  hipStream_t s);
 
-// fp64 one-wave variant (one wave per unit, tile 32x32, 64x32 or 32x64 by the
-// unit's shape, operands from global memory).  Units with accumulate == 2 write
+// fp64 one-wave variant (one wave per unit, tile of 16..64 rows by 16 or 32
+// columns from the unit's shape, operands from global memory).  Units with accumulate == 2 write
 // the full tile, row-major (tile rows x tile cols), to a partial slot (split-K).
 void launch_gemm_w32(int mode, int tag, const GemmUnit* units, int n_units, const GemmItem* items,
                      hipStream_t s);

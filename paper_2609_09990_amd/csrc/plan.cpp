@@ -216,39 +216,29 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
   tiles.clear();
   long n_slots = 0;
   if (prec == PREC_F64) {
-    // One-wave tiles of 32x32, 64x32 or 32x64 (block rows and columns are covered
-    // by 64-wide strips while more than 32 remain, then by a 32-wide one); long
-    // item lists are cut into chunks of about `chunk` MFMA k-steps, each writing
-    // a partial tile that splitk_reduce sums in order.
-    auto strips = [](int n, std::vector<std::pair<int, int>>& v) {
+    // One-wave tiles of (16 RB) x (16 CB), RB <= 4, CB <= 2: block rows are cut
+    // into strips of 64 while more than 64 remain, columns into strips of 32, and
+    // the last strip is rounded up to a multiple of 16 (MFMA blocks are 16 x 16).
+    // Long item lists are cut into chunks of about `chunk` MFMA k-steps, each
+    // writing a partial tile that splitk_reduce sums in order.
+    auto strips = [](int n, int wmax, std::vector<std::pair<int, int>>& v) {
       v.clear();
       int x = 0;
-      while (n - x > 32) {
-        v.push_back({x, 64});
-        x += 64;
+      while (n - x > wmax) {
+        v.push_back({x, wmax});
+        x += wmax;
       }
-      if (x < n) v.push_back({x, 32});
+      if (x < n) v.push_back({x, (n - x + 15) / 16 * 16});
     };
     struct TileShape { int m0, n0, tm, tn, shape; };
     std::vector<std::pair<int, int>> rs, cs;
     std::vector<TileShape> ts;
     auto tiles_of = [&](const PUnit& u) {
-      strips(u.M, rs);
-      strips(u.N, cs);
+      strips(u.M, 64, rs);
+      strips(u.N, 32, cs);
       ts.clear();
       for (auto& r : rs)
-        for (auto& c : cs) {
-          if (r.second == 64 && c.second == 64) {  // no 64x64 wave tile: two 64x32
-            ts.push_back({r.first, c.first, 64, 32, 1});
-            ts.push_back({r.first, c.first + 32, 64, 32, 1});
-          } else if (r.second == 64) {
-            ts.push_back({r.first, c.first, 64, 32, 1});
-          } else if (c.second == 64) {
-            ts.push_back({r.first, c.first, 32, 64, 2});
-          } else {
-            ts.push_back({r.first, c.first, 32, 32, 0});
-          }
-        }
+        for (auto& c : cs) ts.push_back({r.first, c.first, r.second, c.second, 8 * (r.second / 16) + c.second / 16});
     };
     double work = 0;
     for (const PUnit& u : ph.units)
