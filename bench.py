@@ -67,6 +67,100 @@ def cpu_baseline(pk, torch):
                       f"{reps} calls, {dt:.2f} s each; flops = GPU-plan algorithmic count {flops:.3e}"}
 
 
+def precision_form(sol, torch, direction, e_ref, fp64_ms, out):
+    """Precision form at the bench bond: sigma in FP32 / BF16 on the matrix cores
+    (fp32 accumulation), converged on an fp64 residual; energy against the FP64
+    step's Ritz value, time against the FP64 step."""
+    res = {}
+    for name, prec in (("fp32", 1), ("bf16", 2)):
+        sol.set_precision(prec)
+        s0 = sol.stats()
+        torch.cuda.synchronize()
+        t0 = time.time()
+        err, ok_all = 0.0, True
+        for _ in range(2):
+            e, tau, ok = sol.step(MID, direction)
+            direction ^= 1
+            err = max(err, abs(float(e[0]) - e_ref))
+            ok_all = ok_all and ok
+        torch.cuda.synchronize()
+        ms = (time.time() - t0) / 2 * 1e3
+        s1 = sol.stats()
+        res[name] = {"ms_per_step": ms, "speedup_vs_fp64": fp64_ms / ms, "energy_err_vs_fp64": err,
+                     "converged": ok_all, "matvecs_per_step": (s1["matvecs"] - s0["matvecs"]) / 2,
+                     "fp64_refinements": s1["refinements"] - s0["refinements"],
+                     "sigma_ms_per_step": (s1["sigma_a_ms"] + s1["sigma_b_ms"] - s0["sigma_a_ms"] - s0["sigma_b_ms"]) / 2}
+        print(f"# precision {name}: {ms:.0f} ms/step dE={err:.2e}", file=sys.stderr, flush=True)
+    sol.set_precision(0)
+    out["precision_form"] = res
+    return direction
+
+
+def learned_form(pk, sol, torch, direction, e_ref, out):
+    """Learned preconditioner: trained on the GPU (the library's forward, backward
+    and Adam kernels) on triples the solver records from diagonal-preconditioned
+    sweeps of CAS(12,12) and CAS(14,14) Hamiltonians (seeds 1-4); then the bench
+    bond's step (Davidson to a residual of 1e-8: energy within 1e-8 Ha of the
+    FP64 reference) with each preconditioner and sigma precision."""
+    import synth
+    from paper_2609_09990_amd import precond as pc
+    t0 = time.time()
+    train = [synth.make_hamiltonian(n, 5 * n, seed) for n, seed in ((12, 1), (12, 2), (14, 3), (14, 4))]
+    Xs, Ts = [], []
+    for (hh, BB, ee), n in zip(train, (12, 12, 14, 14)):
+        X, T = pc.collect_triples([(hh, BB, ee)], n // 2, n // 2, M=256, sweeps=1, sample=1024, capacity=1024,
+                                  tol=1e-8)
+        Xs.append(X)
+        Ts.append(T)
+    X, T = torch.cat(Xs), torch.cat(Ts)
+    net = pk.MLP(8, 256, seed=0)
+    hist = pc.train(net, X, T, steps=400, batch=32, lr=1e-3)
+    torch.cuda.synchronize()
+    train_s = time.time() - t0
+    res = {"training": {"seconds": train_s, "triples": int(X.shape[0]), "sample": int(X.shape[1]),
+                        "loss_first": float(hist[:20].mean()), "loss_last": float(hist[-20:].mean()),
+                        "diag_candidate_loss": pc.diag_baseline_loss(X, T)}}
+    print(f"# learned: trained on {X.shape[0]} triples in {train_s:.0f} s, loss {hist[-20:].mean():.3f}",
+          file=sys.stderr, flush=True)
+    for name, prec, mode in (("fp64_diag", 0, 0), ("fp64_learned", 0, 1), ("fp32_diag", 1, 0),
+                             ("fp32_learned", 1, 1)):
+        sol.set_precision(prec)
+        sol.set_precond(mode, net if mode else None)
+        s0 = sol.stats()
+        torch.cuda.synchronize()
+        t1 = time.time()
+        e, tau, ok = sol.step(MID, direction)
+        direction ^= 1
+        torch.cuda.synchronize()
+        s1 = sol.stats()
+        res[name] = {"ms": (time.time() - t1) * 1e3, "matvecs": s1["matvecs"] - s0["matvecs"],
+                     "energy_err_vs_fp64": abs(float(e[0]) - e_ref), "converged": bool(ok),
+                     "fallbacks": s1["fallbacks"] - s0["fallbacks"]}
+        print(f"# {name}: {res[name]['ms']:.0f} ms, {res[name]['matvecs']:.0f} matvecs", file=sys.stderr, flush=True)
+    sol.set_precision(0)
+    sol.set_precond(0, None)
+    out["learned_form"] = res
+    return direction
+
+
+def adjoint_form(sol, torch, h, B, e_core, out):
+    """Adjoint form: dE/dh and dE/dB^Q of the current MPS (dmrg_grad) at the bench
+    size, with the properties that hold for any state as checks."""
+    import numpy as np
+    s0 = sol.stats()
+    torch.cuda.synchronize()
+    t0 = time.time()
+    dh, dB, e = sol.grad()
+    dt = time.time() - t0
+    s1 = sol.stats()
+    euler = float(np.sum(h * dh) + 0.5 * np.sum(B * dB))
+    out["adjoint_form"] = {"seconds": dt, "tflops": (s1["grad_flops"] - s0["grad_flops"]) / dt / 1e12,
+                           "energy": float(e[0]), "trace_dE_dh": float(np.trace(dh)),
+                           "euler_residual": abs(euler - (float(e[0]) - e_core)),
+                           "dE_dh_asymmetry": float(np.abs(dh - dh.T).max())}
+    print(f"# adjoint: {dt:.1f} s", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +169,7 @@ def main():
     ap.add_argument("--precision", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the timed full sweep")
+    ap.add_argument("--no-forms", action="store_true", help="skip the precision, learned and adjoint forms")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
@@ -111,6 +206,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.time() - t0
     s1 = sol.stats()
+    sol.set_kernel_tag(0)  # only the timed steps above use the tagged kernel names
     d = {k: s1[k] - s0[k] for k in s1}
     sig_flops = d["sigma_a_flops"] + d["sigma_b_flops"]
     tot_flops = sig_flops + d["env_flops"]
@@ -151,6 +247,9 @@ def main():
                      "frac": b_achieved / PEAK_FP64, "traffic": TRAFFIC,
                      "launch_ms": b_launch_ms, "flops_per_launch": d["sigma_b_flops"] / nmv},
     }
+    if not args.no_forms:
+        direction = precision_form(sol, torch, direction, energies[-1], ms_per_step, out)
+        direction = learned_form(pk, sol, torch, direction, energies[-1], out)
     if not args.no_sweep:
         # one full sweep (2(L-1) two-site steps) timed end to end; the centre first
         # walks back to site 0 with right-to-left steps (untimed)
@@ -172,6 +271,8 @@ def main():
                         "tflops": (s3["sigma_a_flops"] + s3["sigma_b_flops"] + s3["env_flops"] - s2["sigma_a_flops"]
                                    - s2["sigma_b_flops"] - s2["env_flops"]) / sweep_s / 1e12}
         print(f"# sweep {sweep_s:.1f} s E={e[0]:.10f}", file=sys.stderr, flush=True)
+        if not args.no_forms:
+            adjoint_form(sol, torch, h, B, e0, out)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pk, torch)
     print(json.dumps(out), flush=True)

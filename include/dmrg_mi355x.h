@@ -234,6 +234,12 @@ dmrg_status dmrg_get_env(dmrg_solver* s, int cut, int side, double* host, int64_
 dmrg_status dmrg_block_gemm(int precision, int mode, int M, int N, int K, const void* A, int lda,
                             const void* B, int ldb, void* C, int ldc, double coef, void* hip_stream);
 
+/* Precision of the sigma products in later Davidson solves (dmrg_precision; the
+ * option of the same name at creation).  fp64 is kept for the basis, the
+ * subspace eigenproblem, the residual, the truncation and the environments; the
+ * low-precision forms converge on an fp64 residual (defect correction). */
+dmrg_status dmrg_set_precision(dmrg_solver* s, int precision);
+
 /* Profiling aid: the fp64 sigma kernels exist as two identical instantiations
  * (names gemm_f64_w32<mode, 1|2> and <mode, 3|4>); tag 0 (default) launches the
  * first pair, tag 1 the second, so a profiler can separate e.g. timed from
@@ -242,7 +248,8 @@ dmrg_status dmrg_set_kernel_tag(dmrg_solver* s, int tag);
 
 /* Run statistics (host doubles): [0] matvecs, [1] Davidson iterations,
  * [2] sigma ms, [3] env-update ms, [4] SVD ms, [5] sigma flops, [6] tau,
- * [7] max bond dimension, [8] preconditioner fallbacks, [9] converged (0/1),
+ * [7] max bond dimension, [8] preconditioner fallbacks, [9] 1 while every
+ * Davidson solve so far reached the tolerance (0 after the first that did not),
  * [10] sigma phase-A ms (T = X psi), [11] sigma phase-B ms (long-K products),
  * [12] phase-A flops, [13] phase-B flops, [14] environment-update flops,
  * [15] fp64 refinements, [16] phase-B GEMM kernel ms alone (fp64; without the

@@ -64,6 +64,7 @@ dmrg_mlp_forward = _decl("dmrg_mlp_forward", [_p, _i, _p, _i64, _p])
 dmrg_mlp_loss_grad = _decl("dmrg_mlp_loss_grad", [_p, _p, _p, _i, _i, C.POINTER(_d), _p])
 dmrg_mlp_adam_step = _decl("dmrg_mlp_adam_step", [_p, _d])
 dmrg_set_precond = _decl("dmrg_set_precond", [_p, _i, _p])
+dmrg_set_precision = _decl("dmrg_set_precision", [_p, _i])
 dmrg_record_triples = _decl("dmrg_record_triples", [_p, _i, _i])
 dmrg_take_triples = _decl("dmrg_take_triples", [_p, _p, _p, _i, C.POINTER(_i)])
 dmrg_precond_features = _decl("dmrg_precond_features", [_p, _i, _p, _p, _d, _p])
@@ -250,6 +251,9 @@ class Solver:
         if code not in (0, -4):
             _check(code)
         return e, tau.value, code == 0
+
+    def set_precision(self, precision):
+        _check(dmrg_set_precision(self.h, precision))
 
     def set_precond(self, precond, net=None):
         """0: diagonal, 1: learned with the MLP `net` (kept alive by this object)."""

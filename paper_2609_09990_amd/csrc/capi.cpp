@@ -251,7 +251,7 @@ dmrg_status dmrg_sweep(dmrg_solver* s, int n_sweeps, double* energies, double* t
     for (size_t i = 0; i < e.size(); ++i) energies[i] = e[i];
     if (tau) *tau = t;
   });
-  if (st == DMRG_OK && s && !s->s->stats().converged) {
+  if (st == DMRG_OK && s && !s->s->last_converged()) {
     g_err = "Davidson did not reach the tolerance in at least one step";
     return DMRG_ENOCONV;
   }
@@ -267,7 +267,7 @@ dmrg_status dmrg_step(dmrg_solver* s, int k, int direction, double* energies, do
     for (size_t i = 0; i < e.size(); ++i) energies[i] = e[i];
     if (tau) *tau = t;
   });
-  if (st == DMRG_OK && s && !s->s->stats().converged) {
+  if (st == DMRG_OK && s && !s->s->last_converged()) {
     g_err = "Davidson did not reach the tolerance";
     return DMRG_ENOCONV;
   }
@@ -370,6 +370,13 @@ dmrg_status dmrg_mlp_adam_step(dmrg_mlp* m, double lr) {
     DMRG_REQUIRE(m, ST_EINVAL, "NULL argument");
     DMRG_REQUIRE(lr > 0 && std::isfinite(lr), ST_EINVAL, "learning rate must be positive");
     m->m->adam((float)lr);
+  });
+}
+
+dmrg_status dmrg_set_precision(dmrg_solver* s, int precision) {
+  return guard([&] {
+    DMRG_REQUIRE(s, ST_EINVAL, "NULL argument");
+    s->s->set_precision(precision);
   });
 }
 

@@ -532,6 +532,189 @@ __global__ __launch_bounds__(256) void gemm_f64_w32(const GemmUnit* __restrict__
   }
 }
 
+// fp32 operands, fp32 accumulation (the precision form): the same one-wave tiles,
+// k pairing and buffer loads as the fp64 kernel, on v_mfma_f32_16x16x4f32, whose
+// accumulator element q of lane l is row 4 (l/16) + q, column l%16.
+__device__ inline void buf_pair_f32(__amdgpu_buffer_rsrc_t r, int e, float* x) {
+  const v2u32 v = __builtin_amdgcn_raw_buffer_load_b64(r, e * 4, 0, 0);
+  __builtin_memcpy(&x[0], &v, 4);
+  __builtin_memcpy(&x[1], reinterpret_cast<const char*>(&v) + 4, 4);
+}
+__device__ inline float buf_one_f32(__amdgpu_buffer_rsrc_t r, int e) {
+  const unsigned int v = __builtin_amdgcn_raw_buffer_load_b32(r, e * 4, 0, 0);
+  float x;
+  __builtin_memcpy(&x, &v, 4);
+  return x;
+}
+
+template <int MODE, int RB, int CB>
+__device__ inline void w32_tile_f32(const GemmUnit& u, const GemmItem* __restrict__ items, int lane) {
+  const int r = lane & 15, kq = lane >> 4;
+  int am[RB], bn[CB];
+  bool av[RB], bv[CB];
+#pragma unroll
+  for (int i = 0; i < RB; ++i) {
+    am[i] = u.m0 + 16 * i + r;
+    av[i] = am[i] < u.M;
+  }
+#pragma unroll
+  for (int j = 0; j < CB; ++j) {
+    bn[j] = u.n0 + 16 * j + r;
+    bv[j] = bn[j] < u.N;
+  }
+  v4f acc[RB][CB];
+#pragma unroll
+  for (int i = 0; i < RB; ++i)
+#pragma unroll
+    for (int j = 0; j < CB; ++j) acc[i][j] = (v4f){0.f, 0.f, 0.f, 0.f};
+  GemmItem gnext;
+  if (u.ib < u.ie) gnext = items[u.ib];
+  for (int it = u.ib; it < u.ie; ++it) {
+    const GemmItem g = gnext;
+    if (it + 1 < u.ie) gnext = items[it + 1];
+    const float* A = (const float*)g.A;
+    const float* B = (const float*)g.B;
+    const float c = (float)g.coef;
+    const long ea = MODE == GEMM_TN ? (long)(g.K - 1) * g.lda + u.M : (long)(u.M - 1) * g.lda + g.K;
+    const long eb = MODE == GEMM_NT ? (long)(u.N - 1) * g.ldb + g.K : (long)(g.K - 1) * g.ldb + u.N;
+    if ((MODE == GEMM_NT || MODE == GEMM_NN) && ea < (1L << 28) && eb < (1L << 28)) {
+      const __amdgpu_buffer_rsrc_t ra = buf_rsrc(A, ea * 4), rb = buf_rsrc(B, eb * 4);
+      int ao[RB], bo[CB];
+#pragma unroll
+      for (int i = 0; i < RB; ++i) ao[i] = av[i] ? am[i] * g.lda : (int)ea;
+#pragma unroll
+      for (int j = 0; j < CB; ++j) bo[j] = MODE == GEMM_NT ? (bv[j] ? bn[j] * g.ldb : (int)eb) : bn[j];
+      const int kfull = g.K - (g.K & 7) + ((g.K & 7) > 4 ? 8 : 0);
+      for (int k0 = 0; k0 < kfull; k0 += 8) {
+        const int kk = k0 + 2 * kq;
+        const bool k0v = kk < g.K, k1v = kk + 1 < g.K;
+        float a[RB][2], b[CB][2];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          float t[2];
+          buf_pair_f32(ra, ao[i] + kk, t);
+          a[i][0] = k0v ? t[0] * c : 0.f;
+          a[i][1] = k1v ? t[1] * c : 0.f;
+        }
+        if constexpr (MODE == GEMM_NT) {
+#pragma unroll
+          for (int j = 0; j < CB; ++j) {
+            float t[2];
+            buf_pair_f32(rb, bo[j] + kk, t);
+            b[j][0] = k0v ? t[0] : 0.f;
+            b[j][1] = k1v ? t[1] : 0.f;
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < CB; ++j) {
+            const float t0 = buf_one_f32(rb, kk * g.ldb + bo[j]);
+            const float t1 = buf_one_f32(rb, (kk + 1) * g.ldb + bo[j]);
+            b[j][0] = (bv[j] && k0v) ? t0 : 0.f;
+            b[j][1] = (bv[j] && k1v) ? t1 : 0.f;
+          }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int i = 0; i < RB; ++i)
+#pragma unroll
+            for (int j = 0; j < CB; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][h], b[j][h], acc[i][j], 0, 0, 0);
+      }
+      if (kfull < g.K) {
+        const int kk = kfull + kq;
+        const bool kv = kk < g.K;
+        float a[RB], b[CB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          const float t = buf_one_f32(ra, ao[i] + kk);
+          a[i] = kv ? t * c : 0.f;
+        }
+#pragma unroll
+        for (int j = 0; j < CB; ++j) {
+          const float t = MODE == GEMM_NT ? buf_one_f32(rb, bo[j] + kk) : buf_one_f32(rb, kk * g.ldb + bo[j]);
+          b[j] = (kv && (MODE == GEMM_NT || bv[j])) ? t : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+#pragma unroll
+          for (int j = 0; j < CB; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+    } else {
+      // any mode, any extent: element loads behind lane masks
+      for (int k0 = 0; k0 < g.K; k0 += 4) {
+        const int ka = k0 + kq;
+        const bool kv = ka < g.K;
+        float a[RB], b[CB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+          a[i] = (av[i] && kv)
+                     ? (MODE == GEMM_TN ? A[(long)ka * g.lda + am[i]] : A[(long)am[i] * g.lda + ka]) * c
+                     : 0.f;
+#pragma unroll
+        for (int j = 0; j < CB; ++j)
+          b[j] = (bv[j] && kv) ? (MODE == GEMM_NT ? B[(long)bn[j] * g.ldb + ka] : B[(long)ka * g.ldb + bn[j]])
+                               : 0.f;
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+#pragma unroll
+          for (int j = 0; j < CB; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+    }
+  }
+  float* C = (float*)u.C;
+#pragma unroll
+  for (int i = 0; i < RB; ++i)
+#pragma unroll
+    for (int j = 0; j < CB; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        int tr = 16 * i + 4 * kq + q, tc = 16 * j + r;
+        int gm = u.m0 + tr, gn = u.n0 + tc;
+        float v = acc[i][j][q];
+        if (u.accumulate == 2) {
+          C[tr * (16 * CB) + tc] = v;
+        } else if (gm < u.M && gn < u.N) {
+          long idx = (long)gm * u.ldc + gn;
+          C[idx] = u.accumulate ? C[idx] + v : v;
+        }
+      }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void gemm_f32_w32(const GemmUnit* __restrict__ units,
+                                                    const GemmItem* __restrict__ items, int n_units) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int ui = blockIdx.x * 4 + wave;
+  if (ui >= n_units) return;
+  const GemmUnit u = units[ui];
+  switch (u.shape) {
+    case 9: w32_tile_f32<MODE, 1, 1>(u, items, lane); break;
+    case 10: w32_tile_f32<MODE, 1, 2>(u, items, lane); break;
+    case 17: w32_tile_f32<MODE, 2, 1>(u, items, lane); break;
+    case 25: w32_tile_f32<MODE, 3, 1>(u, items, lane); break;
+    case 26: w32_tile_f32<MODE, 3, 2>(u, items, lane); break;
+    case 33: w32_tile_f32<MODE, 4, 1>(u, items, lane); break;
+    case 34: w32_tile_f32<MODE, 4, 2>(u, items, lane); break;
+    default: w32_tile_f32<MODE, 2, 2>(u, items, lane); break;
+  }
+}
+
+__global__ void splitk_reduce_f32(const SplitTile* __restrict__ tiles, const float* __restrict__ slots) {
+  const SplitTile t = tiles[blockIdx.x];
+  float* C = (float*)t.C;
+  for (int e = threadIdx.x; e < t.tm * t.tn; e += blockDim.x) {
+    int tr = e / t.tn, tc = e - tr * t.tn;
+    int gm = t.m0 + tr, gn = t.n0 + tc;
+    if (gm >= t.M || gn >= t.N) continue;
+    float acc = 0.f;
+    for (int s = 0; s < t.ns; ++s) acc += slots[(long)(t.s0 + s) * kSlotElems + e];
+    C[(long)gm * t.ldc + gn] = acc;
+  }
+}
+
 // Split-K reduction: out tile += nothing; out tile = sum of its partial slots in order.
 __global__ void splitk_reduce(const SplitTile* __restrict__ tiles, const double* __restrict__ slots) {
   const SplitTile t = tiles[blockIdx.x];
@@ -833,6 +1016,18 @@ void launch_gemm_w32(int mode, int tag, const GemmUnit* units, int n_units, cons
 
 void launch_splitk_reduce(const SplitTile* tiles, int n, const double* slots, hipStream_t s) {
   if (n > 0) splitk_reduce<<<n, 256, 0, s>>>(tiles, slots);
+}
+
+void launch_gemm_w32_f32(int mode, const GemmUnit* units, int n_units, const GemmItem* items, hipStream_t s) {
+  if (n_units <= 0) return;
+  dim3 grid((n_units + 3) / 4), block(256);
+  if (mode == GEMM_NN) gemm_f32_w32<GEMM_NN><<<grid, block, 0, s>>>(units, items, n_units);
+  else if (mode == GEMM_NT) gemm_f32_w32<GEMM_NT><<<grid, block, 0, s>>>(units, items, n_units);
+  else gemm_f32_w32<GEMM_TN><<<grid, block, 0, s>>>(units, items, n_units);
+}
+
+void launch_splitk_reduce_f32(const SplitTile* tiles, int n, const float* slots, hipStream_t s) {
+  if (n > 0) splitk_reduce_f32<<<n, 256, 0, s>>>(tiles, slots);
 }
 
 void launch_gemm(int prec, int mode, const GemmUnit* units, int n_units, const GemmItem* items,

@@ -52,6 +52,9 @@ struct SplitTile {
   int ldc, M, N, m0, n0, s0, ns, tm, tn;
 };
 void launch_splitk_reduce(const SplitTile* tiles, int n, const double* slots, hipStream_t s);
+// The same for fp32 operands, fp32 accumulation and fp32 outputs and slots.
+void launch_gemm_w32_f32(int mode, const GemmUnit* units, int n_units, const GemmItem* items, hipStream_t s);
+void launch_splitk_reduce_f32(const SplitTile* tiles, int n, const float* slots, hipStream_t s);
 
 // out[f][j] = sum_{i in [ptr[f], ptr[f+1])} coef[i] * src[idx[i]][j], j < nnz.
 void launch_premix(double* out, const double* const* srcs, const int* ptr, const double* coef,

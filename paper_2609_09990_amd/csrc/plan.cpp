@@ -215,7 +215,7 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
   std::vector<SplitTile>& tiles = ph.h_tiles[slot];
   tiles.clear();
   long n_slots = 0;
-  if (prec == PREC_F64) {
+  if (prec == PREC_F64 || prec == PREC_F32) {
     // One-wave tiles of (16 RB) x (16 CB), RB <= 4, CB <= 2: block rows are cut
     // into strips of 64 while more than 64 remain, columns into strips of 32, and
     // the last strip is rounded up to a multiple of 16 (MFMA blocks are 16 x 16).
@@ -278,9 +278,10 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
                            cuts[c].first, cuts[c].second, 2, ts[t].shape});
         }
     }
-    ph.slots.reserve(std::max<long>(n_slots, 1) * kSlotElems * sizeof(double));
+    const size_t slot_esz = prec == PREC_F64 ? sizeof(double) : sizeof(float);
+    ph.slots_f[slot].reserve(std::max<long>(n_slots, 1) * kSlotElems * slot_esz);
     for (auto& un : units)
-      if (un.accumulate == 2) un.C = ph.slots.as<double>() + (intptr_t)un.C;
+      if (un.accumulate == 2) un.C = (char*)ph.slots_f[slot].p + (intptr_t)un.C * slot_esz;
   } else {
     for (const PUnit& u : ph.units) {
       char* C = (char*)bases[u.cbuf] + u.coff * esz[u.cbuf];
@@ -306,7 +307,10 @@ void Solver::launch_resolved(Phase& ph, int prec, int slot) {
     launch_gemm_w32(ph.mode, ph.tag, ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot],
                     ph.d_items[slot].as<GemmItem>(), st);
     if (ph.gemm_done) (void)hipEventRecord(ph.gemm_done, st);  // GEMM-only timing
-    launch_splitk_reduce(ph.d_tiles[slot].as<SplitTile>(), ph.n_tiles[slot], ph.slots.as<double>(), st);
+    launch_splitk_reduce(ph.d_tiles[slot].as<SplitTile>(), ph.n_tiles[slot], ph.slots_f[slot].as<double>(), st);
+  } else if (prec == PREC_F32) {
+    launch_gemm_w32_f32(ph.mode, ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot], ph.d_items[slot].as<GemmItem>(), st);
+    launch_splitk_reduce_f32(ph.d_tiles[slot].as<SplitTile>(), ph.n_tiles[slot], ph.slots_f[slot].as<float>(), st);
   } else {
     launch_gemm(prec, ph.mode, ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot], ph.d_items[slot].as<GemmItem>(), st);
   }

@@ -635,6 +635,7 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
   std::vector<double> rn(nr, 0.0), hv(2 * nr);
   int iter = 0;
   bool exact_basis = (prec == PREC_F64);
+  int sprec = prec;  // precision of new sigma products (fp64 after the switch)
   double best_lo = 1e300;
   int stall = 0;
   int conv = 0;
@@ -668,7 +669,10 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
         ++stall;
       }
       if (lo_done || stall >= 3) {
-        // fp64 refinement: exact sigma of the Ritz vectors, restart from them
+        // switch to fp64 for the rest of the step: exact sigma of the Ritz vectors,
+        // restart from them; every later product is fp64, so the step converges on
+        // an exact residual like the plain form (defect correction of the
+        // low-precision solution)
         for (int i = 0; i < nr; ++i) launch_copy(V + (long)i * n, X + (long)i * n, n, st);
         for (int i = 0; i < nr; ++i) {
           sigma(k, PREC_F64, V + (long)i * n, AV + (long)i * n);
@@ -676,17 +680,15 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
         }
         for (int i = 0; i < nr; ++i) launch_dots(V, n, i + 1, AV + (long)i * n, n, part, G + (long)i * ldg, st);
         kcur = nr;
-        exact_basis = true;  // residual of the next RR is exact
+        exact_basis = true;
+        sprec = PREC_F64;
         st_.refinements++;
-        best_lo = 1e300;
-        stall = 0;
         continue;
       }
     } else if (lo_done) {
       conv = 1;
       break;
     }
-    exact_basis = (prec == PREC_F64);
     // training triple of root 0: features now, target once the step has converged
     if (rec && rn[0] > opt_.davidson_tol && (int)rec_slots.size() < kRecHist &&
         rec_count_ + (int)rec_slots.size() < rec_cap_) {
@@ -737,13 +739,13 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
     int added = 0;
     for (int j = 0; j < nnew; ++j) {
       if (lrn_on) {  // rejected: non-finite, or (almost) inside the current subspace
-        if (append(Lc + (long)j * n, prec, 1e-6)) {
+        if (append(Lc + (long)j * n, sprec, 1e-6)) {
           ++added;
           continue;
         }
         st_.fallbacks++;
       }
-      if (append(Cc + (long)j * n, prec)) ++added;
+      if (append(Cc + (long)j * n, sprec)) ++added;
     }
     if (added == 0) {
       conv = rmax <= 1e3 * opt_.davidson_tol;
@@ -752,6 +754,7 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
   }
   st_.davidson_iters += iter;
   if (!conv) st_.converged = 0;
+  last_converged_ = conv != 0;
   if (rec && conv && !rec_slots.empty()) {  // Delta = P_perp psi*, psi* oriented along psi_i
     for (size_t j = 0; j < rec_slots.size(); ++j) {
       const double* hj = rec_hist_.as<double>() + j * n;
@@ -1173,11 +1176,19 @@ double Solver::step(int k, bool l2r, std::vector<double>& energies) {
 
 double Solver::sweep(int n_sweeps, std::vector<double>& energies) {
   double tau_max = 0;
+  bool all_ok = true;
   for (int sw = 0; sw < n_sweeps; ++sw) {
     tau_max = 0;
-    for (int k = 0; k + 1 < L_; ++k) tau_max = std::max(tau_max, step(k, true, energies));
-    for (int k = L_ - 2; k >= 0; --k) tau_max = std::max(tau_max, step(k, false, energies));
+    for (int k = 0; k + 1 < L_; ++k) {
+      tau_max = std::max(tau_max, step(k, true, energies));
+      all_ok = all_ok && last_converged_;
+    }
+    for (int k = L_ - 2; k >= 0; --k) {
+      tau_max = std::max(tau_max, step(k, false, energies));
+      all_ok = all_ok && last_converged_;
+    }
   }
+  last_converged_ = all_ok;
   st_.tau = tau_max;
   return tau_max;
 }

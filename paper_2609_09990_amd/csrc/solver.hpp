@@ -104,7 +104,7 @@ struct Phase {
   std::vector<GemmItem> h_items[3];  // host staging kept alive for async copies
   std::vector<GemmUnit> h_units[3];
   std::vector<SplitTile> h_tiles[3];
-  DevMem d_tiles[3], slots;          // split-K tile table and partial slots (fp64)
+  DevMem d_tiles[3], slots_f[3];     // split-K tile table and partial slots per precision slot
   int n_units[3] = {0, 0, 0}, n_tiles[3] = {0, 0, 0};
   const void* last_bases[3][B_NBUF] = {};
   bool uploaded[3] = {false, false, false};
@@ -180,6 +180,11 @@ class Solver {
             std::vector<double>& energies);
   const Stats& stats() const { return st_; }
   int n_states() const { return opt_.n_states; }
+  bool last_converged() const { return last_converged_; }  // the last step / sweep call
+  void set_precision(int prec) {
+    DMRG_REQUIRE(prec == PREC_F64 || prec == PREC_F32 || prec == PREC_BF16, ST_EINVAL, "unknown precision");
+    opt_.precision = prec;
+  }
 
   // Davidson preconditioner: 0 diagonal, 1 learned (net borrowed, must outlive its use)
   void set_precond(int mode, MLP* net);
@@ -266,6 +271,7 @@ class Solver {
   DevMem grad_P_, grad_Q_, grad_G_;
 
   // learned preconditioner and training-triple store
+  bool last_converged_ = true;
   int precond_ = 0;
   MLP* net_ = nullptr;
   std::vector<int64_t> fblocks_host_;  // feature blocks of the prepared step: off, ld, rows, cols

@@ -136,3 +136,21 @@ def test_state_averaged_full_bond_cas6():
     print("cas6 SA", e, g["energies"], flush=True)
     assert ok
     assert np.max(np.abs(np.array(e) - np.array(g["energies"]))) <= 1e-10
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_precision_form_full_bond_equals_fci_cas8(prec):
+    """FP32 / BF16 sigma with the switch to fp64 (defect correction): every step
+    converges on an fp64 residual, so at full bond the energy is FCI's."""
+    _torch()
+    import paper_2609_09990_amd as pk
+    h, B, e0 = synth.make_hamiltonian(8, 32, 0)
+    sol = pk.Solver(pk.Problem(h, B, 4, 4, e0), M=256, tol=1e-10, precision=prec)
+    e, tau, ok = sol.sweep(2)
+    ref = json.load(open(GOLD))["cas8_nq32_s0"]["energies"][0]
+    st = sol.stats()
+    print(f"prec={prec} E-E_fci={e[0] - ref:.2e} matvecs={st['matvecs']:.0f} switches={st['refinements']:.0f}")
+    assert ok
+    assert abs(e[0] - ref) <= 1e-10
+    assert abs(sol.energy()[0] - ref) <= 1e-10
+    assert st["refinements"] > 0
