@@ -99,17 +99,16 @@ def precision_form(sol, torch, direction, e_ref, fp64_ms, out):
 def learned_form(pk, sol, torch, direction, e_ref, out):
     """Learned preconditioner: trained on the GPU (the library's forward, backward
     and Adam kernels) on triples the solver records from diagonal-preconditioned
-    sweeps of CAS(12,12) and CAS(14,14) Hamiltonians (seeds 1-4); then the bench
-    bond's step (Davidson to a residual of 1e-8: energy within 1e-8 Ha of the
-    FP64 reference) with each preconditioner and sigma precision."""
+    sweeps of CAS(16,16) Hamiltonians (N_Q = 96, M = 512, seeds 1-3); then the
+    bench bond's step (Davidson to a residual of 1e-8: energy within 1e-8 Ha of
+    the FP64 reference) with each preconditioner and sigma precision."""
     import synth
     from paper_2609_09990_amd import precond as pc
     t0 = time.time()
-    train = [synth.make_hamiltonian(n, 5 * n, seed) for n, seed in ((12, 1), (12, 2), (14, 3), (14, 4))]
     Xs, Ts = [], []
-    for (hh, BB, ee), n in zip(train, (12, 12, 14, 14)):
-        X, T = pc.collect_triples([(hh, BB, ee)], n // 2, n // 2, M=256, sweeps=1, sample=1024, capacity=1024,
-                                  tol=1e-8)
+    for seed in (1, 2, 3):
+        hh, BB, ee = synth.make_hamiltonian(16, 96, seed)
+        X, T = pc.collect_triples([(hh, BB, ee)], 8, 8, M=512, sweeps=1, sample=1024, capacity=1024, tol=1e-8)
         Xs.append(X)
         Ts.append(T)
     X, T = torch.cat(Xs), torch.cat(Ts)

@@ -517,7 +517,16 @@ __global__ __launch_bounds__(256) void gemm_f64_w32(const GemmUnit* __restrict__
   // the wave index is uniform across the wave; saying so keeps the unit and item
   // descriptors (and the buffer resources built from them) in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int ui = blockIdx.x * 4 + wave;
+  // NN launches (sigma phase A: a factor block feeds every column tile of its
+  // unit) give each XCD a contiguous range of units, so a block is fetched into
+  // one XCD's L2; workgroups are dispatched to the 8 XCDs round-robin.  The NT
+  // launch (phase B) keeps the plain order, which measured faster.
+  int wg = blockIdx.x;
+  if constexpr (MODE == GEMM_NN) {
+    const int nb = gridDim.x, q = nb >> 3, rem = nb & 7, x = wg & 7;
+    wg = x * q + min(x, rem) + (wg >> 3);
+  }
+  const int ui = wg * 4 + wave;
   if (ui >= n_units) return;  // whole wave exits; the kernel has no barriers
   const GemmUnit u = units[ui];
   switch (u.shape) {  // 8 * RB + CB: tile (16 RB) x (16 CB)
@@ -847,6 +856,7 @@ __global__ __launch_bounds__(256) void jacobi_eig_kernel(const double* __restric
   __shared__ int P[32], Q[32];
   __shared__ double red[256];
   __shared__ int order[64];
+  __shared__ int rotated;
   const int t = threadIdx.x;
   for (int e = t; e < k * k; e += blockDim.x) {  // lower triangle holds the matrix
     int i = e / k, j = e % k;
@@ -880,6 +890,8 @@ __global__ __launch_bounds__(256) void jacobi_eig_kernel(const double* __restric
     double dgsum = red[0];
     __syncthreads();
     if (offsum <= 1e-32 * (dgsum > 1e-300 ? dgsum : 1e-300)) break;
+    if (t == 0) rotated = 0;
+    __syncthreads();
     for (int round = 0; round < n - 1; ++round) {
       if (t < half) {
         int p, q;
@@ -897,12 +909,16 @@ __global__ __launch_bounds__(256) void jacobi_eig_kernel(const double* __restric
         }
         double c = 1.0, s = 0.0;
         if (q < k) {
+          // rotate only pairs whose coupling is significant against their diagonal
+          // entries; a sweep without rotations ends the iteration (the off-diagonal
+          // part is then at the rounding level)
           double apq = A[p][q];
-          if (fabs(apq) > 1e-300) {
+          if (fabs(apq) > 1e-300 && fabs(apq) > 1e-15 * sqrt(fabs(A[p][p] * A[q][q]))) {
             double theta = (A[q][q] - A[p][p]) / (2.0 * apq);
             double tt = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
             c = 1.0 / sqrt(tt * tt + 1.0);
             s = tt * c;
+            rotated = 1;
           }
         }
         P[t] = p;
@@ -935,6 +951,8 @@ __global__ __launch_bounds__(256) void jacobi_eig_kernel(const double* __restric
       }
       __syncthreads();
     }
+    if (!rotated) break;  // uniform: read after the last barrier of the sweep
+    __syncthreads();
   }
   if (t == 0) {
     for (int i = 0; i < k; ++i) order[i] = i;
