@@ -25,6 +25,13 @@
 
 namespace dmrg {
 
+bool same_sectors(const std::vector<Sector>& a, const std::vector<Sector>& b) {
+  if (a.size() != b.size()) return false;
+  for (size_t i = 0; i < a.size(); ++i)
+    if (a[i].q != b[i].q || a[i].dim != b[i].dim) return false;
+  return true;
+}
+
 void Solver::make_env_layout(Env& e, int cut, const Bond& b) {
   const auto& ch = prob_->mpo.chans[cut];
   std::vector<QN> dqs;
@@ -324,11 +331,18 @@ void Solver::env_update_left(int k, const FactorSide& fs) {
   const SiteTensor& A = mps_[k];
   Env& out = left_[k + 1];
   make_env_layout(out, k + 1, bonds_[k + 1]);
+  // the plan depends on bonds k, k+1 and the MPO only: reuse it while they hold
+  EnvPlan& ep = env_plans_[{k, 0}];
+  const bool hit = same_sectors(ep.key_a, bonds_[k].sec) && same_sectors(ep.key_b, bonds_[k + 1].sec);
+  if (!hit) {
+  ep.pa = Phase();
+  ep.pb = Phase();
+  Phase& pa = ep.pa;
+  Phase& pb = ep.pb;
   // phase A: Z_X = X A for every factor used
   std::vector<char> used(fs.fac.size(), 0);
   for (auto& v : fs.by_mid)
     for (auto& u : v) used[u.f] = 1;
-  Phase pa;
   pa.mode = GEMM_NN;
   std::vector<std::vector<long>> zoff(fs.fac.size());  // per factor, per A slab: offset or -1
   long zsize = 0;
@@ -351,7 +365,6 @@ void Solver::env_update_left(int k, const FactorSide& fs) {
     }
   }
   // phase B
-  Phase pb;
   pb.mode = GEMM_TN;
   const auto& mids = mpo.chans[k + 1];
   for (size_t beta = 0; beta < mids.size(); ++beta) {
@@ -398,6 +411,13 @@ void Solver::env_update_left(int k, const FactorSide& fs) {
       add_units(pb.units, B_OUT, cbase + eb.off, eb.mc, eb.mr, eb.mc, ib, (int)pb.items.size(), 0);
     }
   }
+  ep.zsize = zsize;
+  ep.key_a = bonds_[k].sec;
+  ep.key_b = bonds_[k + 1].sec;
+  }
+  Phase& pa = ep.pa;
+  Phase& pb = ep.pb;
+  const long zsize = ep.zsize;
   env_t_buf_.reserve(std::max<long>(zsize, 1) * sizeof(double));
   launch_fill(out.buf.as<double>(), out.size, 0.0, st);
   void* bases[B_NBUF] = {};
@@ -416,7 +436,7 @@ void Solver::env_update_left(int k, const FactorSide& fs) {
   run_phase(pa, PREC_F64, bases, esz, sizes);
   run_phase(pb, PREC_F64, bases, esz, sizes);
   st_.env_flops += pa.flops + pb.flops;
-  hip_check(hipStreamSynchronize(st), "env update");  // local plan buffers die here
+  hip_check(hipStreamSynchronize(st), "env update");
   out.valid = true;
 }
 
@@ -428,6 +448,13 @@ void Solver::env_update_right(int j, const FactorSide& fs) {
   const SiteTensor& Bt = mps_[j];
   Env& out = right_[j];
   make_env_layout(out, j, bonds_[j]);
+  EnvPlan& ep = env_plans_[{j, 1}];
+  const bool hit = same_sectors(ep.key_a, bonds_[j].sec) && same_sectors(ep.key_b, bonds_[j + 1].sec);
+  if (!hit) {
+  ep.pa = Phase();
+  ep.pb = Phase();
+  Phase& pa = ep.pa;
+  Phase& pb = ep.pb;
   std::vector<char> used(fs.fac.size(), 0);
   for (auto& v : fs.by_mid)
     for (auto& u : v) used[u.f] = 1;
@@ -438,7 +465,6 @@ void Solver::env_update_right(int j, const FactorSide& fs) {
     std::vector<std::array<int, 3>> blocks;  // s, c (bond j+1 sector), col0
   };
   std::vector<std::vector<USlab>> U(fs.fac.size());
-  Phase pa;
   pa.mode = GEMM_NN;
   long usize = 0;
   for (size_t f = 0; f < fs.fac.size(); ++f) {
@@ -472,7 +498,6 @@ void Solver::env_update_right(int j, const FactorSide& fs) {
       usize += (long)sl.ml * us.width;
     }
   }
-  Phase pb;
   pb.mode = GEMM_NT;
   const Bond& bj = bonds_[j];
   const auto& mids = mpo.chans[j];
@@ -517,6 +542,13 @@ void Solver::env_update_right(int j, const FactorSide& fs) {
       add_units(pb.units, B_OUT, cbase + eb.off, eb.mc, eb.mr, eb.mc, ib, (int)pb.items.size(), 0);
     }
   }
+  ep.zsize = usize;
+  ep.key_a = bonds_[j].sec;
+  ep.key_b = bonds_[j + 1].sec;
+  }
+  Phase& pa = ep.pa;
+  Phase& pb = ep.pb;
+  const long usize = ep.zsize;
   env_t_buf_.reserve(std::max<long>(usize, 1) * sizeof(double));
   launch_fill(out.buf.as<double>(), out.size, 0.0, st);
   void* bases[B_NBUF] = {};
@@ -535,7 +567,7 @@ void Solver::env_update_right(int j, const FactorSide& fs) {
   run_phase(pa, PREC_F64, bases, esz, sizes);
   run_phase(pb, PREC_F64, bases, esz, sizes);
   st_.env_flops += pa.flops + pb.flops;
-  hip_check(hipStreamSynchronize(st), "env update");  // local plan buffers die here
+  hip_check(hipStreamSynchronize(st), "env update");
   out.valid = true;
 }
 

@@ -49,6 +49,7 @@ struct DevMem {
 };
 
 void hip_check(hipError_t e, const char* what);
+bool same_sectors(const std::vector<Sector>& a, const std::vector<Sector>& b);
 
 // Environment at one cut: channels grouped by quantum-number shift.
 struct Env {
@@ -237,6 +238,13 @@ class Solver {
     long t_size = 0;
   };
   std::map<int, StepPlan> plan_cache_;
+  // environment-update plans by (site, side), reused while bonds site, site+1 hold
+  struct EnvPlan {
+    std::vector<Sector> key_a, key_b;
+    Phase pa, pb;
+    long zsize = 0;
+  };
+  std::map<std::pair<int, int>, EnvPlan> env_plans_;
   int plan_built_k_ = -1;  // step whose plan is in lf_, rf_, psi_lay_, phA_, phB_
   std::vector<Sector> bonds_at_build_l_, bonds_at_build_r_;
   DevMem lowp_[B_NBUF];  // low-precision copies per buffer id
