@@ -160,6 +160,50 @@ def adjoint_form(sol, torch, h, B, e_core, out):
     print(f"# adjoint: {dt:.1f} s", file=sys.stderr, flush=True)
 
 
+def diff_form(pk, torch):
+    """Differentiation form: CAS(16,16), N_Q = 96, M = 512, 2 state-averaged roots
+    (seed 0), 4 sweeps.  Per-state gradients of the final MPS (time), and the
+    central finite difference (step 1e-5) of each root's energy along a random
+    symmetric direction of (h, B), each side a full DMRG run from the same
+    start: at truncated bond the two differ by an amount that tracks the
+    discarded weight (the MPS is not stationary in the full tangent space)."""
+    import numpy as np
+    import synth
+    n, nq, Mb, eps = 16, 96, 512, 1e-5
+    h, B, e0 = synth.make_hamiltonian(n, nq, 0)
+    rng = np.random.default_rng(7)
+    Dh = rng.normal(size=(n, n))
+    Dh = Dh + Dh.T
+    DB = rng.normal(size=(nq, n, n))
+    DB = DB + DB.transpose(0, 2, 1)
+
+    def run(hh, BB):
+        s = pk.Solver(pk.Problem(hh, BB, n // 2, n // 2, e0), M=Mb, n_states=2, tol=1e-9)
+        e, tau, ok = s.sweep(4)
+        return s, s.energy(), tau, ok
+
+    t0 = time.time()
+    sol, e, tau, ok = run(h, B)
+    run_s = time.time() - t0
+    res = {"config": "CAS(16,16) N_Q=96 M=512 2 states, 4 sweeps", "dmrg_s": run_s, "energies": e.tolist(),
+           "tau_last_sweep": tau, "converged": bool(ok), "states": []}
+    ep = run(h + eps * Dh, B + eps * DB)[1]
+    em = run(h - eps * Dh, B - eps * DB)[1]
+    for r in range(2):
+        w = np.zeros(2)
+        w[r] = 1.0
+        torch.cuda.synchronize()
+        t1 = time.time()
+        dh, dB, _ = sol.grad(w)
+        gs = time.time() - t1
+        analytic = float(np.sum(dh * Dh) + np.sum(dB * DB))
+        fd = float((ep[r] - em[r]) / (2 * eps))
+        res["states"].append({"grad_s": gs, "analytic": analytic, "finite_difference": fd,
+                              "gap": abs(analytic - fd), "trace_dE_dh": float(np.trace(dh))})
+    print(f"# diff form: {res}", file=sys.stderr, flush=True)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,6 +213,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the timed full sweep")
     ap.add_argument("--no-forms", action="store_true", help="skip the precision, learned and adjoint forms")
+    ap.add_argument("--diff-form", action="store_true",
+                    help="also run the differentiation-form configuration (CAS(16,16), M=512, 2 states)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
@@ -272,6 +318,8 @@ def main():
         print(f"# sweep {sweep_s:.1f} s E={e[0]:.10f}", file=sys.stderr, flush=True)
         if not args.no_forms:
             adjoint_form(sol, torch, h, B, e0, out)
+    if args.diff_form:
+        out["diff_form"] = diff_form(pk, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pk, torch)
     print(json.dumps(out), flush=True)
