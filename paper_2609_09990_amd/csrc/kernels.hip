@@ -318,6 +318,7 @@ __device__ inline void ld_pair(const double* p, int k, int K, bool rowv, double*
 // buffer format.
 typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
 typedef unsigned int v2u32 __attribute__((ext_vector_type(2)));
+typedef unsigned int v3u32 __attribute__((ext_vector_type(3)));
 constexpr int kBufWord3 = 0x00020000;
 __device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, long bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, kBufWord3);
@@ -377,33 +378,40 @@ __device__ inline void w32_tile(const GemmUnit& u, const GemmItem* __restrict__ 
 #pragma unroll
       for (int j = 0; j < CB; ++j) bo[j] = MODE == GEMM_NT ? (bv[j] ? bn[j] * g.ldb : (int)eb) : bn[j];
       const int kfull = g.K - (g.K & 7) + ((g.K & 7) > 4 ? 8 : 0);  // paired blocks; a tail of <= 4 goes alone
+      // raw loads of block k0 (masking applied at use), so block k0+8 can be in
+      // flight while block k0 is multiplied
+      double ta[RB][2], tb[CB][2];
+      auto raw = [&](int k0, double (&xa)[RB][2], double (&xb)[CB][2]) {
+        const int kk = k0 + 2 * kq;
+#pragma unroll
+        for (int i = 0; i < RB; ++i) buf_pair(ra, ao[i] + kk, xa[i]);
+        if constexpr (MODE == GEMM_NT) {
+#pragma unroll
+          for (int j = 0; j < CB; ++j) buf_pair(rb, bo[j] + kk, xb[j]);
+        } else {
+#pragma unroll
+          for (int j = 0; j < CB; ++j) {
+            xb[j][0] = buf_one(rb, kk * g.ldb + bo[j]);
+            xb[j][1] = buf_one(rb, (kk + 1) * g.ldb + bo[j]);
+          }
+        }
+      };
+      if (kfull > 0) raw(0, ta, tb);
       for (int k0 = 0; k0 < kfull; k0 += 8) {
+        double na[RB][2], nb[CB][2];
+        if (k0 + 8 < kfull) raw(k0 + 8, na, nb);
         const int kk = k0 + 2 * kq;
         const bool k0v = kk < g.K, k1v = kk + 1 < g.K;
         double a[RB][2], b[CB][2];
 #pragma unroll
         for (int i = 0; i < RB; ++i) {
-          double t[2];
-          buf_pair(ra, ao[i] + kk, t);
-          a[i][0] = k0v ? t[0] * c : 0.0;
-          a[i][1] = k1v ? t[1] * c : 0.0;
+          a[i][0] = k0v ? ta[i][0] * c : 0.0;
+          a[i][1] = k1v ? ta[i][1] * c : 0.0;
         }
-        if constexpr (MODE == GEMM_NT) {
 #pragma unroll
-          for (int j = 0; j < CB; ++j) {
-            double t[2];
-            buf_pair(rb, bo[j] + kk, t);
-            b[j][0] = k0v ? t[0] : 0.0;
-            b[j][1] = k1v ? t[1] : 0.0;
-          }
-        } else {
-#pragma unroll
-          for (int j = 0; j < CB; ++j) {
-            const double t0 = buf_one(rb, kk * g.ldb + bo[j]);
-            const double t1 = buf_one(rb, (kk + 1) * g.ldb + bo[j]);
-            b[j][0] = (bv[j] && k0v) ? t0 : 0.0;
-            b[j][1] = (bv[j] && k1v) ? t1 : 0.0;
-          }
+        for (int j = 0; j < CB; ++j) {
+          b[j][0] = ((MODE == GEMM_NT || bv[j]) && k0v) ? tb[j][0] : 0.0;
+          b[j][1] = ((MODE == GEMM_NT || bv[j]) && k1v) ? tb[j][1] : 0.0;
         }
 #pragma unroll
         for (int h = 0; h < 2; ++h)
@@ -412,6 +420,18 @@ __device__ inline void w32_tile(const GemmUnit& u, const GemmItem* __restrict__ 
 #pragma unroll
             for (int j = 0; j < CB; ++j)
               acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][h], b[j][h], acc[i][j], 0, 0, 0);
+        if (k0 + 8 < kfull) {
+#pragma unroll
+          for (int i = 0; i < RB; ++i) {
+            ta[i][0] = na[i][0];
+            ta[i][1] = na[i][1];
+          }
+#pragma unroll
+          for (int j = 0; j < CB; ++j) {
+            tb[j][0] = nb[j][0];
+            tb[j][1] = nb[j][1];
+          }
+        }
       }
       if (kfull < g.K) {  // last 1..4 k: one MFMA step, lane kq takes k = kfull + kq
         const int kk = kfull + kq;
@@ -708,6 +728,192 @@ __global__ __launch_bounds__(256) void gemm_f32_w32(const GemmUnit* __restrict__
     case 33: w32_tile_f32<MODE, 4, 1>(u, items, lane); break;
     case 34: w32_tile_f32<MODE, 4, 2>(u, items, lane); break;
     default: w32_tile_f32<MODE, 2, 2>(u, items, lane); break;
+  }
+}
+
+// bf16 operands, fp32 accumulation on v_mfma_f32_16x16x16bf16_1k: lane (r, kq)
+// supplies A[row r][4 kq .. 4 kq + 3] and B[4 kq .. 4 kq + 3][col r] of each
+// 16-deep k step; its accumulator layout is the fp32 one.  A is bf16 bits
+// (AF32 = false) or fp32 rounded to bf16 after the item coefficient (AF32 =
+// true); B is bf16 bits.  Same one-wave tiles and buffer loads as above.
+// Four consecutive bf16 elements from element offset e, which may be odd.  Wide
+// buffer loads need dword-aligned addresses, so three dwords are read from the
+// even element at or below e and shifted down by 16 bits when e is odd.
+__device__ inline void bf16_quad(__amdgpu_buffer_rsrc_t r, int e, uint16_t (&hb)[4]) {
+  const v3u32 v = __builtin_amdgcn_raw_buffer_load_b96(r, (e & ~1) * 2, 0, 0);
+  const uint32_t sh = (e & 1) * 16;
+  const uint32_t w0 = __builtin_amdgcn_alignbit(v[1], v[0], sh), w1 = __builtin_amdgcn_alignbit(v[2], v[1], sh);
+  hb[0] = (uint16_t)w0;
+  hb[1] = (uint16_t)(w0 >> 16);
+  hb[2] = (uint16_t)w1;
+  hb[3] = (uint16_t)(w1 >> 16);
+}
+
+template <bool AF32>
+__device__ inline void a_quad(__amdgpu_buffer_rsrc_t r, int e, float c, int kk, int K, v4s& out) {
+  float x[4];
+  if constexpr (AF32) {
+    const v4u32 v = __builtin_amdgcn_raw_buffer_load_b128(r, e * 4, 0, 0);
+    __builtin_memcpy(x, &v, 16);
+  } else {
+    uint16_t hb[4];
+    bf16_quad(r, e, hb);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) x[q] = __uint_as_float(((uint32_t)hb[q]) << 16);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) out[q] = (short)(kk + q < K ? f2bf(x[q] * c) : 0);
+}
+__device__ inline void b_quad_rows(__amdgpu_buffer_rsrc_t r, int e, int kk, int K, v4s& out) {
+  uint16_t hb[4];
+  bf16_quad(r, e, hb);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) out[q] = (short)(kk + q < K ? hb[q] : 0);
+}
+__device__ inline uint16_t buf_bf16(__amdgpu_buffer_rsrc_t r, int e) {
+  const unsigned short v = __builtin_amdgcn_raw_buffer_load_b16(r, e * 2, 0, 0);
+  return (uint16_t)v;
+}
+
+template <int MODE, bool AF32, int RB, int CB>
+__device__ inline void w32_tile_bf16(const GemmUnit& u, const GemmItem* __restrict__ items, int lane) {
+  const int r = lane & 15, kq = lane >> 4;
+  int am[RB], bn[CB];
+  bool av[RB], bv[CB];
+#pragma unroll
+  for (int i = 0; i < RB; ++i) {
+    am[i] = u.m0 + 16 * i + r;
+    av[i] = am[i] < u.M;
+  }
+#pragma unroll
+  for (int j = 0; j < CB; ++j) {
+    bn[j] = u.n0 + 16 * j + r;
+    bv[j] = bn[j] < u.N;
+  }
+  v4f acc[RB][CB];
+#pragma unroll
+  for (int i = 0; i < RB; ++i)
+#pragma unroll
+    for (int j = 0; j < CB; ++j) acc[i][j] = (v4f){0.f, 0.f, 0.f, 0.f};
+  constexpr int ea_sz = AF32 ? 4 : 2;
+  GemmItem gnext;
+  if (u.ib < u.ie) gnext = items[u.ib];
+  for (int it = u.ib; it < u.ie; ++it) {
+    const GemmItem g = gnext;
+    if (it + 1 < u.ie) gnext = items[it + 1];
+    const float c = (float)g.coef;
+    const long ea = MODE == GEMM_TN ? (long)(g.K - 1) * g.lda + u.M : (long)(u.M - 1) * g.lda + g.K;
+    const long eb = MODE == GEMM_NT ? (long)(u.N - 1) * g.ldb + g.K : (long)(g.K - 1) * g.ldb + u.N;
+    // NN reads B rows up to K + 15: their element offsets must fit in 31 bits too
+    const long eb_reach = MODE == GEMM_NT ? eb + 16 : (long)(g.K + 15) * g.ldb + u.N;
+    if ((MODE == GEMM_NT || MODE == GEMM_NN) && ea < (1L << 28) && eb_reach < (1L << 29)) {
+      // bf16 operands may start at an odd element: the descriptors start at the
+      // dword boundary below, and element offsets count from there, so that the
+      // parity test in bf16_quad sees the true address parity.  The range check
+      // of buffer loads works on whole dwords, so the extents are rounded up to
+      // the dword holding the last element (same dword, no wider access).
+      const int a_sh = AF32 ? 0 : (int)(((uintptr_t)g.A >> 1) & 1), b_sh = (int)(((uintptr_t)g.B >> 1) & 1);
+      const __amdgpu_buffer_rsrc_t ra =
+          buf_rsrc((const char*)g.A - 2 * a_sh, ((ea + a_sh) * ea_sz + 3) & ~3L);
+      const __amdgpu_buffer_rsrc_t rb = buf_rsrc((const char*)g.B - 2 * b_sh, ((eb + b_sh) * 2 + 3) & ~3L);
+      int ao[RB], bo[CB];
+#pragma unroll
+      for (int i = 0; i < RB; ++i) ao[i] = (av[i] ? am[i] * g.lda : (int)ea) + a_sh;
+#pragma unroll
+      for (int j = 0; j < CB; ++j) bo[j] = (MODE == GEMM_NT ? (bv[j] ? bn[j] * g.ldb : (int)eb) : bn[j]) + b_sh;
+      for (int k0 = 0; k0 < g.K; k0 += 16) {
+        const int kk = k0 + 4 * kq;
+        v4s a[RB], b[CB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) a_quad<AF32>(ra, ao[i] + kk, c, kk, g.K, a[i]);
+        if constexpr (MODE == GEMM_NT) {
+#pragma unroll
+          for (int j = 0; j < CB; ++j) b_quad_rows(rb, bo[j] + kk, kk, g.K, b[j]);
+        } else {
+#pragma unroll
+          for (int j = 0; j < CB; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const uint16_t v = buf_bf16(rb, (kk + q) * g.ldb + bo[j]);
+              b[j][q] = (short)((bv[j] && kk + q < g.K) ? v : 0);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+#pragma unroll
+          for (int j = 0; j < CB; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+    } else {
+      // any mode, any extent: element loads behind lane masks
+      for (int k0 = 0; k0 < g.K; k0 += 16) {
+        const int kk = k0 + 4 * kq;
+        v4s a[RB], b[CB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int k = kk + q;
+            float x = 0.f;
+            if (av[i] && k < g.K) {
+              const long e = MODE == GEMM_TN ? (long)k * g.lda + am[i] : (long)am[i] * g.lda + k;
+              x = AF32 ? ((const float*)g.A)[e] : to_f(((const uint16_t*)g.A)[e]);
+            }
+            a[i][q] = (short)f2bf(x * c);
+          }
+#pragma unroll
+        for (int j = 0; j < CB; ++j)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int k = kk + q;
+            uint16_t v = 0;
+            if (bv[j] && k < g.K)
+              v = ((const uint16_t*)g.B)[MODE == GEMM_NT ? (long)bn[j] * g.ldb + k : (long)k * g.ldb + bn[j]];
+            b[j][q] = (short)v;
+          }
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+#pragma unroll
+          for (int j = 0; j < CB; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+    }
+  }
+  float* C = (float*)u.C;
+#pragma unroll
+  for (int i = 0; i < RB; ++i)
+#pragma unroll
+    for (int j = 0; j < CB; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        int tr = 16 * i + 4 * kq + q, tc = 16 * j + r;
+        int gm = u.m0 + tr, gn = u.n0 + tc;
+        float v = acc[i][j][q];
+        if (u.accumulate == 2) {
+          C[tr * (16 * CB) + tc] = v;
+        } else if (gm < u.M && gn < u.N) {
+          long idx = (long)gm * u.ldc + gn;
+          C[idx] = u.accumulate ? C[idx] + v : v;
+        }
+      }
+}
+
+template <int MODE, bool AF32>
+__global__ __launch_bounds__(256) void gemm_bf16_w32(const GemmUnit* __restrict__ units,
+                                                     const GemmItem* __restrict__ items, int n_units) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int ui = blockIdx.x * 4 + wave;
+  if (ui >= n_units) return;
+  const GemmUnit u = units[ui];
+  switch (u.shape) {
+    case 9: w32_tile_bf16<MODE, AF32, 1, 1>(u, items, lane); break;
+    case 10: w32_tile_bf16<MODE, AF32, 1, 2>(u, items, lane); break;
+    case 17: w32_tile_bf16<MODE, AF32, 2, 1>(u, items, lane); break;
+    case 25: w32_tile_bf16<MODE, AF32, 3, 1>(u, items, lane); break;
+    case 26: w32_tile_bf16<MODE, AF32, 3, 2>(u, items, lane); break;
+    case 33: w32_tile_bf16<MODE, AF32, 4, 1>(u, items, lane); break;
+    case 34: w32_tile_bf16<MODE, AF32, 4, 2>(u, items, lane); break;
+    default: w32_tile_bf16<MODE, AF32, 2, 2>(u, items, lane); break;
   }
 }
 
@@ -1042,6 +1248,21 @@ void launch_gemm_w32_f32(int mode, const GemmUnit* units, int n_units, const Gem
   if (mode == GEMM_NN) gemm_f32_w32<GEMM_NN><<<grid, block, 0, s>>>(units, items, n_units);
   else if (mode == GEMM_NT) gemm_f32_w32<GEMM_NT><<<grid, block, 0, s>>>(units, items, n_units);
   else gemm_f32_w32<GEMM_TN><<<grid, block, 0, s>>>(units, items, n_units);
+}
+
+void launch_gemm_w32_bf16(int mode, bool a_f32, const GemmUnit* units, int n_units, const GemmItem* items,
+                          hipStream_t s) {
+  if (n_units <= 0) return;
+  dim3 grid((n_units + 3) / 4), block(256);
+  if (a_f32) {
+    if (mode == GEMM_NN) gemm_bf16_w32<GEMM_NN, true><<<grid, block, 0, s>>>(units, items, n_units);
+    else if (mode == GEMM_NT) gemm_bf16_w32<GEMM_NT, true><<<grid, block, 0, s>>>(units, items, n_units);
+    else gemm_bf16_w32<GEMM_TN, true><<<grid, block, 0, s>>>(units, items, n_units);
+  } else {
+    if (mode == GEMM_NN) gemm_bf16_w32<GEMM_NN, false><<<grid, block, 0, s>>>(units, items, n_units);
+    else if (mode == GEMM_NT) gemm_bf16_w32<GEMM_NT, false><<<grid, block, 0, s>>>(units, items, n_units);
+    else gemm_bf16_w32<GEMM_TN, false><<<grid, block, 0, s>>>(units, items, n_units);
+  }
 }
 
 void launch_splitk_reduce_f32(const SplitTile* tiles, int n, const float* slots, hipStream_t s) {

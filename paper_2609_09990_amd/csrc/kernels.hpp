@@ -55,6 +55,10 @@ void launch_splitk_reduce(const SplitTile* tiles, int n, const double* slots, hi
 // The same for fp32 operands, fp32 accumulation and fp32 outputs and slots.
 void launch_gemm_w32_f32(int mode, const GemmUnit* units, int n_units, const GemmItem* items, hipStream_t s);
 void launch_splitk_reduce_f32(const SplitTile* tiles, int n, const float* slots, hipStream_t s);
+// bf16 one-wave variant: A bf16 bits (a_f32 = false) or fp32 rounded to bf16,
+// B bf16 bits, fp32 accumulation and fp32 outputs / slots.
+void launch_gemm_w32_bf16(int mode, bool a_f32, const GemmUnit* units, int n_units, const GemmItem* items,
+                          hipStream_t s);
 
 // out[f][j] = sum_{i in [ptr[f], ptr[f+1])} coef[i] * src[idx[i]][j], j < nnz.
 void launch_premix(double* out, const double* const* srcs, const int* ptr, const double* coef,

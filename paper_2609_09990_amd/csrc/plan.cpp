@@ -222,7 +222,7 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
   std::vector<SplitTile>& tiles = ph.h_tiles[slot];
   tiles.clear();
   long n_slots = 0;
-  if (prec == PREC_F64 || prec == PREC_F32) {
+  if (prec == PREC_F64 || prec == PREC_F32 || prec == PREC_BF16 || prec == 3) {
     // One-wave tiles of (16 RB) x (16 CB), RB <= 4, CB <= 2: block rows are cut
     // into strips of 64 while more than 64 remain, columns into strips of 32, and
     // the last strip is rounded up to a multiple of 16 (MFMA blocks are 16 x 16).
@@ -317,6 +317,10 @@ void Solver::launch_resolved(Phase& ph, int prec, int slot) {
     launch_splitk_reduce(ph.d_tiles[slot].as<SplitTile>(), ph.n_tiles[slot], ph.slots_f[slot].as<double>(), st);
   } else if (prec == PREC_F32) {
     launch_gemm_w32_f32(ph.mode, ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot], ph.d_items[slot].as<GemmItem>(), st);
+    launch_splitk_reduce_f32(ph.d_tiles[slot].as<SplitTile>(), ph.n_tiles[slot], ph.slots_f[slot].as<float>(), st);
+  } else if (prec == PREC_BF16 || prec == 3) {
+    launch_gemm_w32_bf16(ph.mode, prec == 3, ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot],
+                         ph.d_items[slot].as<GemmItem>(), st);
     launch_splitk_reduce_f32(ph.d_tiles[slot].as<SplitTile>(), ph.n_tiles[slot], ph.slots_f[slot].as<float>(), st);
   } else {
     launch_gemm(prec, ph.mode, ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot], ph.d_items[slot].as<GemmItem>(), st);

@@ -91,7 +91,10 @@ def test_diag_matches_sigma_on_unit_vectors():
         assert abs(float(out[int(i)]) - float(d[int(i)])) <= 1e-12 * max(1.0, abs(float(d[int(i)])))
 
 
-@pytest.mark.parametrize("prec,tol", [(1, 1e-5), (2, 3e-2)])
+# Rounding the operands once (fp32 unit roundoff 6e-8, bf16 3.9e-3) with fp32
+# accumulation gives relative errors of a few units of the operand roundoff
+# here (2e-7 and 4e-3 with exact rounding on the CPU).
+@pytest.mark.parametrize("prec,tol", [(1, 2e-6), (2, 1e-2)])
 def test_low_precision_sigma_close_to_fp64(prec, tol):
     torch, pk, h, B, prob, sol, mps = _setup(8, 4, 4, 16, 60)
     k = 3
