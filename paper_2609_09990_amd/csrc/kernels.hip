@@ -336,7 +336,10 @@ __device__ inline double buf_one(__amdgpu_buffer_rsrc_t r, int e) {
 }
 
 // One wave computes a (16 RB) x (16 CB) tile: RB x CB fp64 16x16x4 MFMA blocks.
-template <int MODE, int RB, int CB>
+// BUF: every item is known (checked on the host) to fit the buffer-load path, so
+// the kernel holds that path alone; otherwise the plain-load paths.  Keeping the
+// two apart lets one set of accumulators serve the whole kernel.
+template <int MODE, int RB, int CB, bool BUF>
 __device__ inline void w32_tile(const GemmUnit& u, const GemmItem* __restrict__ items, int lane) {
   const int r = lane & 15, kq = lane >> 4;
   int am[RB], bn[CB];
@@ -368,7 +371,7 @@ __device__ inline void w32_tile(const GemmUnit& u, const GemmItem* __restrict__ 
     // elements of A and B the unit can touch (row-major, leading dims lda, ldb)
     const long ea = (long)(u.M - 1) * g.lda + g.K;
     const long eb = MODE == GEMM_NT ? (long)(u.N - 1) * g.ldb + g.K : (long)(g.K - 1) * g.ldb + u.N;
-    if ((MODE == GEMM_NT || MODE == GEMM_NN) && ea < (1L << 27) && eb < (1L << 27)) {
+    if constexpr (BUF) {
       // Same k pairing as below, through buffer loads: a masked row starts past
       // the extent (its loads read zeros), a k past K is zeroed by a select.
       const __amdgpu_buffer_rsrc_t ra = buf_rsrc(A, ea * 8), rb = buf_rsrc(B, eb * 8);
@@ -454,6 +457,8 @@ __device__ inline void w32_tile(const GemmUnit& u, const GemmItem* __restrict__ 
             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
       }
     } else if constexpr (MODE == GEMM_NT || MODE == GEMM_NN) {
+      (void)ea;
+      (void)eb;
       // A runs along k in memory: lane (r, kq) loads the pair k0+2kq, k0+2kq+1 of
       // its rows with one 16-byte load, and the two MFMA steps of an 8-deep block
       // take the even and the odd k of the pairs (the same k order for B, so the
@@ -531,7 +536,7 @@ __device__ inline void w32_tile(const GemmUnit& u, const GemmItem* __restrict__ 
 
 // TAG only names otherwise identical instantiations, so a profiler can tell
 // launches apart (e.g. sigma phases, timed and untimed work).
-template <int MODE, int TAG>
+template <int MODE, int TAG, bool BUF>
 __global__ __launch_bounds__(256) void gemm_f64_w32(const GemmUnit* __restrict__ units,
                                                     const GemmItem* __restrict__ items, int n_units) {
   // the wave index is uniform across the wave; saying so keeps the unit and item
@@ -550,14 +555,14 @@ __global__ __launch_bounds__(256) void gemm_f64_w32(const GemmUnit* __restrict__
   if (ui >= n_units) return;  // whole wave exits; the kernel has no barriers
   const GemmUnit u = units[ui];
   switch (u.shape) {  // 8 * RB + CB: tile (16 RB) x (16 CB)
-    case 9: w32_tile<MODE, 1, 1>(u, items, lane); break;
-    case 10: w32_tile<MODE, 1, 2>(u, items, lane); break;
-    case 17: w32_tile<MODE, 2, 1>(u, items, lane); break;
-    case 25: w32_tile<MODE, 3, 1>(u, items, lane); break;
-    case 26: w32_tile<MODE, 3, 2>(u, items, lane); break;
-    case 33: w32_tile<MODE, 4, 1>(u, items, lane); break;
-    case 34: w32_tile<MODE, 4, 2>(u, items, lane); break;
-    default: w32_tile<MODE, 2, 2>(u, items, lane); break;
+    case 9: w32_tile<MODE, 1, 1, BUF>(u, items, lane); break;
+    case 10: w32_tile<MODE, 1, 2, BUF>(u, items, lane); break;
+    case 17: w32_tile<MODE, 2, 1, BUF>(u, items, lane); break;
+    case 25: w32_tile<MODE, 3, 1, BUF>(u, items, lane); break;
+    case 26: w32_tile<MODE, 3, 2, BUF>(u, items, lane); break;
+    case 33: w32_tile<MODE, 4, 1, BUF>(u, items, lane); break;
+    case 34: w32_tile<MODE, 4, 2, BUF>(u, items, lane); break;
+    default: w32_tile<MODE, 2, 2, BUF>(u, items, lane); break;
   }
 }
 
@@ -576,7 +581,7 @@ __device__ inline float buf_one_f32(__amdgpu_buffer_rsrc_t r, int e) {
   return x;
 }
 
-template <int MODE, int RB, int CB>
+template <int MODE, int RB, int CB, bool BUF>
 __device__ inline void w32_tile_f32(const GemmUnit& u, const GemmItem* __restrict__ items, int lane) {
   const int r = lane & 15, kq = lane >> 4;
   int am[RB], bn[CB];
@@ -606,7 +611,7 @@ __device__ inline void w32_tile_f32(const GemmUnit& u, const GemmItem* __restric
     const float c = (float)g.coef;
     const long ea = MODE == GEMM_TN ? (long)(g.K - 1) * g.lda + u.M : (long)(u.M - 1) * g.lda + g.K;
     const long eb = MODE == GEMM_NT ? (long)(u.N - 1) * g.ldb + g.K : (long)(g.K - 1) * g.ldb + u.N;
-    if ((MODE == GEMM_NT || MODE == GEMM_NN) && ea < (1L << 28) && eb < (1L << 28)) {
+    if constexpr (BUF) {
       const __amdgpu_buffer_rsrc_t ra = buf_rsrc(A, ea * 4), rb = buf_rsrc(B, eb * 4);
       int ao[RB], bo[CB];
 #pragma unroll
@@ -712,7 +717,7 @@ __device__ inline void w32_tile_f32(const GemmUnit& u, const GemmItem* __restric
       }
 }
 
-template <int MODE>
+template <int MODE, bool BUF>
 __global__ __launch_bounds__(256) void gemm_f32_w32(const GemmUnit* __restrict__ units,
                                                     const GemmItem* __restrict__ items, int n_units) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -720,14 +725,14 @@ __global__ __launch_bounds__(256) void gemm_f32_w32(const GemmUnit* __restrict__
   if (ui >= n_units) return;
   const GemmUnit u = units[ui];
   switch (u.shape) {
-    case 9: w32_tile_f32<MODE, 1, 1>(u, items, lane); break;
-    case 10: w32_tile_f32<MODE, 1, 2>(u, items, lane); break;
-    case 17: w32_tile_f32<MODE, 2, 1>(u, items, lane); break;
-    case 25: w32_tile_f32<MODE, 3, 1>(u, items, lane); break;
-    case 26: w32_tile_f32<MODE, 3, 2>(u, items, lane); break;
-    case 33: w32_tile_f32<MODE, 4, 1>(u, items, lane); break;
-    case 34: w32_tile_f32<MODE, 4, 2>(u, items, lane); break;
-    default: w32_tile_f32<MODE, 2, 2>(u, items, lane); break;
+    case 9: w32_tile_f32<MODE, 1, 1, BUF>(u, items, lane); break;
+    case 10: w32_tile_f32<MODE, 1, 2, BUF>(u, items, lane); break;
+    case 17: w32_tile_f32<MODE, 2, 1, BUF>(u, items, lane); break;
+    case 25: w32_tile_f32<MODE, 3, 1, BUF>(u, items, lane); break;
+    case 26: w32_tile_f32<MODE, 3, 2, BUF>(u, items, lane); break;
+    case 33: w32_tile_f32<MODE, 4, 1, BUF>(u, items, lane); break;
+    case 34: w32_tile_f32<MODE, 4, 2, BUF>(u, items, lane); break;
+    default: w32_tile_f32<MODE, 2, 2, BUF>(u, items, lane); break;
   }
 }
 
@@ -775,7 +780,7 @@ __device__ inline uint16_t buf_bf16(__amdgpu_buffer_rsrc_t r, int e) {
   return (uint16_t)v;
 }
 
-template <int MODE, bool AF32, int RB, int CB>
+template <int MODE, bool AF32, int RB, int CB, bool BUF>
 __device__ inline void w32_tile_bf16(const GemmUnit& u, const GemmItem* __restrict__ items, int lane) {
   const int r = lane & 15, kq = lane >> 4;
   int am[RB], bn[CB];
@@ -804,9 +809,7 @@ __device__ inline void w32_tile_bf16(const GemmUnit& u, const GemmItem* __restri
     const float c = (float)g.coef;
     const long ea = MODE == GEMM_TN ? (long)(g.K - 1) * g.lda + u.M : (long)(u.M - 1) * g.lda + g.K;
     const long eb = MODE == GEMM_NT ? (long)(u.N - 1) * g.ldb + g.K : (long)(g.K - 1) * g.ldb + u.N;
-    // NN reads B rows up to K + 15: their element offsets must fit in 31 bits too
-    const long eb_reach = MODE == GEMM_NT ? eb + 16 : (long)(g.K + 15) * g.ldb + u.N;
-    if ((MODE == GEMM_NT || MODE == GEMM_NN) && ea < (1L << 28) && eb_reach < (1L << 29)) {
+    if constexpr (BUF) {
       // bf16 operands may start at an odd element: the descriptors start at the
       // dword boundary below, and element offsets count from there, so that the
       // parity test in bf16_quad sees the true address parity.  The range check
@@ -898,7 +901,7 @@ __device__ inline void w32_tile_bf16(const GemmUnit& u, const GemmItem* __restri
       }
 }
 
-template <int MODE, bool AF32>
+template <int MODE, bool AF32, bool BUF>
 __global__ __launch_bounds__(256) void gemm_bf16_w32(const GemmUnit* __restrict__ units,
                                                      const GemmItem* __restrict__ items, int n_units) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -906,14 +909,14 @@ __global__ __launch_bounds__(256) void gemm_bf16_w32(const GemmUnit* __restrict_
   if (ui >= n_units) return;
   const GemmUnit u = units[ui];
   switch (u.shape) {
-    case 9: w32_tile_bf16<MODE, AF32, 1, 1>(u, items, lane); break;
-    case 10: w32_tile_bf16<MODE, AF32, 1, 2>(u, items, lane); break;
-    case 17: w32_tile_bf16<MODE, AF32, 2, 1>(u, items, lane); break;
-    case 25: w32_tile_bf16<MODE, AF32, 3, 1>(u, items, lane); break;
-    case 26: w32_tile_bf16<MODE, AF32, 3, 2>(u, items, lane); break;
-    case 33: w32_tile_bf16<MODE, AF32, 4, 1>(u, items, lane); break;
-    case 34: w32_tile_bf16<MODE, AF32, 4, 2>(u, items, lane); break;
-    default: w32_tile_bf16<MODE, AF32, 2, 2>(u, items, lane); break;
+    case 9: w32_tile_bf16<MODE, AF32, 1, 1, BUF>(u, items, lane); break;
+    case 10: w32_tile_bf16<MODE, AF32, 1, 2, BUF>(u, items, lane); break;
+    case 17: w32_tile_bf16<MODE, AF32, 2, 1, BUF>(u, items, lane); break;
+    case 25: w32_tile_bf16<MODE, AF32, 3, 1, BUF>(u, items, lane); break;
+    case 26: w32_tile_bf16<MODE, AF32, 3, 2, BUF>(u, items, lane); break;
+    case 33: w32_tile_bf16<MODE, AF32, 4, 1, BUF>(u, items, lane); break;
+    case 34: w32_tile_bf16<MODE, AF32, 4, 2, BUF>(u, items, lane); break;
+    default: w32_tile_bf16<MODE, AF32, 2, 2, BUF>(u, items, lane); break;
   }
 }
 
@@ -1220,14 +1223,19 @@ inline int grid_for(long n, int bs = 256, int cap = 4096) {
 
 }  // namespace
 
-void launch_gemm_w32(int mode, int tag, const GemmUnit* units, int n_units, const GemmItem* items,
+void launch_gemm_w32(int mode, int tag, bool buf, const GemmUnit* units, int n_units, const GemmItem* items,
                      hipStream_t s) {
   if (n_units <= 0) return;
   dim3 grid((n_units + 3) / 4), block(256);
-#define DMRG_W32_LAUNCH(T)                                                                      \
-  if (mode == GEMM_NN) gemm_f64_w32<GEMM_NN, T><<<grid, block, 0, s>>>(units, items, n_units); \
-  else if (mode == GEMM_NT) gemm_f64_w32<GEMM_NT, T><<<grid, block, 0, s>>>(units, items, n_units); \
-  else gemm_f64_w32<GEMM_TN, T><<<grid, block, 0, s>>>(units, items, n_units);
+  if (!buf || mode == GEMM_TN) {
+    if (mode == GEMM_NN) gemm_f64_w32<GEMM_NN, 0, false><<<grid, block, 0, s>>>(units, items, n_units);
+    else if (mode == GEMM_NT) gemm_f64_w32<GEMM_NT, 0, false><<<grid, block, 0, s>>>(units, items, n_units);
+    else gemm_f64_w32<GEMM_TN, 0, false><<<grid, block, 0, s>>>(units, items, n_units);
+    return;
+  }
+#define DMRG_W32_LAUNCH(T)                                                                            \
+  if (mode == GEMM_NN) gemm_f64_w32<GEMM_NN, T, true><<<grid, block, 0, s>>>(units, items, n_units); \
+  else gemm_f64_w32<GEMM_NT, T, true><<<grid, block, 0, s>>>(units, items, n_units);
   switch (tag) {
     case 1: DMRG_W32_LAUNCH(1) break;
     case 2: DMRG_W32_LAUNCH(2) break;
@@ -1242,27 +1250,33 @@ void launch_splitk_reduce(const SplitTile* tiles, int n, const double* slots, hi
   if (n > 0) splitk_reduce<<<n, 256, 0, s>>>(tiles, slots);
 }
 
-void launch_gemm_w32_f32(int mode, const GemmUnit* units, int n_units, const GemmItem* items, hipStream_t s) {
+void launch_gemm_w32_f32(int mode, bool buf, const GemmUnit* units, int n_units, const GemmItem* items,
+                         hipStream_t s) {
   if (n_units <= 0) return;
   dim3 grid((n_units + 3) / 4), block(256);
-  if (mode == GEMM_NN) gemm_f32_w32<GEMM_NN><<<grid, block, 0, s>>>(units, items, n_units);
-  else if (mode == GEMM_NT) gemm_f32_w32<GEMM_NT><<<grid, block, 0, s>>>(units, items, n_units);
-  else gemm_f32_w32<GEMM_TN><<<grid, block, 0, s>>>(units, items, n_units);
+  if (buf && mode == GEMM_NN) gemm_f32_w32<GEMM_NN, true><<<grid, block, 0, s>>>(units, items, n_units);
+  else if (buf && mode == GEMM_NT) gemm_f32_w32<GEMM_NT, true><<<grid, block, 0, s>>>(units, items, n_units);
+  else if (mode == GEMM_NN) gemm_f32_w32<GEMM_NN, false><<<grid, block, 0, s>>>(units, items, n_units);
+  else if (mode == GEMM_NT) gemm_f32_w32<GEMM_NT, false><<<grid, block, 0, s>>>(units, items, n_units);
+  else gemm_f32_w32<GEMM_TN, false><<<grid, block, 0, s>>>(units, items, n_units);
 }
 
-void launch_gemm_w32_bf16(int mode, bool a_f32, const GemmUnit* units, int n_units, const GemmItem* items,
+void launch_gemm_w32_bf16(int mode, bool a_f32, bool buf, const GemmUnit* units, int n_units, const GemmItem* items,
                           hipStream_t s) {
   if (n_units <= 0) return;
   dim3 grid((n_units + 3) / 4), block(256);
+#define DMRG_BF_LAUNCH(AF)                                                                                 \
+  if (buf && mode == GEMM_NN) gemm_bf16_w32<GEMM_NN, AF, true><<<grid, block, 0, s>>>(units, items, n_units);      \
+  else if (buf && mode == GEMM_NT) gemm_bf16_w32<GEMM_NT, AF, true><<<grid, block, 0, s>>>(units, items, n_units); \
+  else if (mode == GEMM_NN) gemm_bf16_w32<GEMM_NN, AF, false><<<grid, block, 0, s>>>(units, items, n_units);       \
+  else if (mode == GEMM_NT) gemm_bf16_w32<GEMM_NT, AF, false><<<grid, block, 0, s>>>(units, items, n_units);       \
+  else gemm_bf16_w32<GEMM_TN, AF, false><<<grid, block, 0, s>>>(units, items, n_units);
   if (a_f32) {
-    if (mode == GEMM_NN) gemm_bf16_w32<GEMM_NN, true><<<grid, block, 0, s>>>(units, items, n_units);
-    else if (mode == GEMM_NT) gemm_bf16_w32<GEMM_NT, true><<<grid, block, 0, s>>>(units, items, n_units);
-    else gemm_bf16_w32<GEMM_TN, true><<<grid, block, 0, s>>>(units, items, n_units);
+    DMRG_BF_LAUNCH(true)
   } else {
-    if (mode == GEMM_NN) gemm_bf16_w32<GEMM_NN, false><<<grid, block, 0, s>>>(units, items, n_units);
-    else if (mode == GEMM_NT) gemm_bf16_w32<GEMM_NT, false><<<grid, block, 0, s>>>(units, items, n_units);
-    else gemm_bf16_w32<GEMM_TN, false><<<grid, block, 0, s>>>(units, items, n_units);
+    DMRG_BF_LAUNCH(false)
   }
+#undef DMRG_BF_LAUNCH
 }
 
 void launch_splitk_reduce_f32(const SplitTile* tiles, int n, const float* slots, hipStream_t s) {

@@ -40,8 +40,20 @@ void launch_gemm(int prec, int mode, const GemmUnit* units, int n_units, const G
 // fp64 one-wave variant (one wave per unit, tile of 16..64 rows by 16 or 32
 // columns from the unit's shape, operands from global memory).  Units with accumulate == 2 write
 // the full tile, row-major (tile rows x tile cols), to a partial slot (split-K).
-void launch_gemm_w32(int mode, int tag, const GemmUnit* units, int n_units, const GemmItem* items,
+// buf: NN / NT launch whose items all pass buffer_reach_ok (raw buffer loads);
+// otherwise plain loads (and any mode).
+void launch_gemm_w32(int mode, int tag, bool buf, const GemmUnit* units, int n_units, const GemmItem* items,
                      hipStream_t s);
+// Whether one item may take the buffer-load path: every element offset a tile
+// forms from the operand starts (up to 16 past the last row's K, NN rows of B up
+// to K + 16) stays below 1 GiB in bytes, so offsets fit 32-bit arithmetic.
+inline bool buffer_reach_ok(int mode, int M, int N, int K, int lda, int ldb, size_t esz_a, size_t esz_b) {
+  if (mode != GEMM_NN && mode != GEMM_NT) return false;
+  const long lim = 1L << 30;
+  const long ra = ((long)(M - 1) * lda + K + 16) * (long)esz_a;
+  const long rb = (mode == GEMM_NT ? (long)(N - 1) * ldb + K + 16 : (long)(K + 16) * ldb + N) * (long)esz_b;
+  return ra < lim && rb < lim;
+}
 
 // Output tile (rows m0.., cols n0.. of an M x N block, tm x tn) = sum of ns
 // partial slots s0..s0+ns-1 (slot stride kSlotElems, tile row-major), summed in
@@ -53,11 +65,12 @@ struct SplitTile {
 };
 void launch_splitk_reduce(const SplitTile* tiles, int n, const double* slots, hipStream_t s);
 // The same for fp32 operands, fp32 accumulation and fp32 outputs and slots.
-void launch_gemm_w32_f32(int mode, const GemmUnit* units, int n_units, const GemmItem* items, hipStream_t s);
+void launch_gemm_w32_f32(int mode, bool buf, const GemmUnit* units, int n_units, const GemmItem* items,
+                         hipStream_t s);
 void launch_splitk_reduce_f32(const SplitTile* tiles, int n, const float* slots, hipStream_t s);
 // bf16 one-wave variant: A bf16 bits (a_f32 = false) or fp32 rounded to bf16,
 // B bf16 bits, fp32 accumulation and fp32 outputs / slots.
-void launch_gemm_w32_bf16(int mode, bool a_f32, const GemmUnit* units, int n_units, const GemmItem* items,
+void launch_gemm_w32_bf16(int mode, bool a_f32, bool buf, const GemmUnit* units, int n_units, const GemmItem* items,
                           hipStream_t s);
 
 // out[f][j] = sum_{i in [ptr[f], ptr[f+1])} coef[i] * src[idx[i]][j], j < nnz.

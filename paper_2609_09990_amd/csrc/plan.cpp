@@ -217,6 +217,13 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
     items[i].pad = 0;
     items[i].coef = p.coef;
   }
+  bool buf_ok = true;
+  for (const PUnit& u : ph.units)
+    for (int i = u.ib; i < u.ie && buf_ok; ++i) {
+      const PItem& p = ph.items[i];
+      buf_ok = buffer_reach_ok(ph.mode, u.M, u.N, p.K, p.lda, p.ldb, esz[p.abuf], esz[p.bbuf]);
+    }
+  ph.buf_ok[slot] = buf_ok;
   std::vector<GemmUnit>& units = ph.h_units[slot];
   units.clear();
   std::vector<SplitTile>& tiles = ph.h_tiles[slot];
@@ -311,15 +318,15 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
 
 void Solver::launch_resolved(Phase& ph, int prec, int slot) {
   if (prec == PREC_F64) {
-    launch_gemm_w32(ph.mode, ph.tag, ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot],
+    launch_gemm_w32(ph.mode, ph.tag, ph.buf_ok[slot], ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot],
                     ph.d_items[slot].as<GemmItem>(), st);
     if (ph.gemm_done) (void)hipEventRecord(ph.gemm_done, st);  // GEMM-only timing
     launch_splitk_reduce(ph.d_tiles[slot].as<SplitTile>(), ph.n_tiles[slot], ph.slots_f[slot].as<double>(), st);
   } else if (prec == PREC_F32) {
-    launch_gemm_w32_f32(ph.mode, ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot], ph.d_items[slot].as<GemmItem>(), st);
+    launch_gemm_w32_f32(ph.mode, ph.buf_ok[slot], ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot], ph.d_items[slot].as<GemmItem>(), st);
     launch_splitk_reduce_f32(ph.d_tiles[slot].as<SplitTile>(), ph.n_tiles[slot], ph.slots_f[slot].as<float>(), st);
   } else if (prec == PREC_BF16 || prec == 3) {
-    launch_gemm_w32_bf16(ph.mode, prec == 3, ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot],
+    launch_gemm_w32_bf16(ph.mode, prec == 3, ph.buf_ok[slot], ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot],
                          ph.d_items[slot].as<GemmItem>(), st);
     launch_splitk_reduce_f32(ph.d_tiles[slot].as<SplitTile>(), ph.n_tiles[slot], ph.slots_f[slot].as<float>(), st);
   } else {
@@ -693,6 +700,28 @@ void Solver::build_sigma_plan(int k) {
       fprintf(stderr, "plan k=%d phase %s: units %zu items %zu (unit-items %ld) useful %.3e padded %.3e (x%.1f) "
               "mean K %.1f (padded %.1f)\n", k, ph == &phA_ ? "A" : "B", ph->units.size(), ph->items.size(), nit,
               ph->flops, padded, padded / std::max(ph->flops, 1.0), ksum / std::max(nit, 1L), kpad / std::max(nit, 1L));
+    }
+    {
+      // operand sharing inside phase-B output blocks: items with one A slice
+      // (or one B block) in common, and the operand bytes items read
+      long ga = 0, gb = 0;
+      double abytes = 0, bbytes = 0;
+      for (const PUnit& u : phB_.units) {
+        std::vector<long> ka, kb;
+        for (int i = u.ib; i < u.ie; ++i) {
+          const PItem& p = phB_.items[i];
+          ka.push_back(p.aoff * 16 + p.abuf);
+          kb.push_back(p.boff * 16 + p.bbuf);
+          abytes += 8.0 * u.M * p.K;
+          bbytes += 8.0 * u.N * p.K;
+        }
+        std::sort(ka.begin(), ka.end());
+        std::sort(kb.begin(), kb.end());
+        ga += std::unique(ka.begin(), ka.end()) - ka.begin();
+        gb += std::unique(kb.begin(), kb.end()) - kb.begin();
+      }
+      fprintf(stderr, "phase B sharing: items %zu, distinct (block, A slice) %ld, distinct (block, B block) %ld, "
+              "item A bytes %.3e, item B bytes %.3e\n", phB_.items.size(), ga, gb, abytes, bbytes);
     }
     std::string dims;
     for (auto& s : bonds_[k].sec) dims += std::to_string(s.dim) + " ";

@@ -109,6 +109,7 @@ struct Phase {
   int n_units[3] = {0, 0, 0}, n_tiles[3] = {0, 0, 0};
   const void* last_bases[3][B_NBUF] = {};
   bool uploaded[3] = {false, false, false};
+  bool buf_ok[3] = {false, false, false};  // every item fits the buffer-load kernels
 };
 
 // One side's factors for a middle cut: X_{beta,op} = sum_alpha c L[alpha] (left)
