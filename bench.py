@@ -28,7 +28,7 @@ PEAK_FP64 = 78.6  # TFLOP/s, MI355X dense FP64 matrix
 # HBM bytes per launch of the dominant kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
 # runs (profiles/sigma_phaseB_w32_cas20_m1024_fp64.md), scaled by the same counters on a
 # plain copy (fetch x2.0, write x1.0); set to None whenever that kernel changes.
-TRAFFIC = 4.291e10
+TRAFFIC = 6.04e10
 
 
 def cpu_baseline(pk, torch):
@@ -287,11 +287,16 @@ def main():
         "setup_s": t_setup,
         "energy_last": energies[-1] if energies else None,
         "plan_reuse_per_step": (d["plan_hits"]) / args.steps,
-        "roofline": {"bound": "mfma", "kernel": "gemm_f64_w32<1, 4> (sigma phase B, timed launches)",
+        "roofline": {"bound": "mfma", "kernel": "gemm_f64_w32<1, 4, true> (sigma phase B, timed launches)",
                      "achieved": b_achieved, "peak": PEAK_FP64, "unit": "TFLOP/s",
                      "frac": b_achieved / PEAK_FP64, "traffic": TRAFFIC,
                      "launch_ms": b_launch_ms, "flops_per_launch": d["sigma_b_flops"] / nmv},
     }
+    # measured device ceilings (register-only fp64 MFMA loop, 2 GiB streaming copy)
+    mf, cp = pk.measure_peaks(1 << 31)
+    out["measured_peaks"] = {"fp64_mfma_tflops": mf, "copy_gbs": cp,
+                             "phase_b_frac_of_measured_mfma": b_achieved / mf if mf > 0 else None}
+    print(f"# measured fp64 MFMA {mf:.1f} TFLOP/s, copy {cp:.0f} GB/s", file=sys.stderr, flush=True)
     if not args.no_forms:
         direction = precision_form(sol, torch, direction, energies[-1], ms_per_step, out)
         direction = learned_form(pk, sol, torch, direction, energies[-1], out)

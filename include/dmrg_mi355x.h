@@ -234,6 +234,18 @@ dmrg_status dmrg_get_env(dmrg_solver* s, int cut, int side, double* host, int64_
 dmrg_status dmrg_block_gemm(int precision, int mode, int M, int N, int K, const void* A, int lda,
                             const void* B, int ldb, void* C, int ldc, double coef, void* hip_stream);
 
+/* Device ceilings for roofline reports, measured on the current device: the
+ * fp64 MFMA rate of a register-only loop of v_mfma_f64_16x16x4 (four
+ * independent accumulators per wave, 8 waves per SIMD) and the bandwidth of a
+ * streaming copy of `bytes` from src to dst (read + write bytes per second).
+ * src and dst are caller-owned device buffers on the current device, 16-byte
+ * aligned, bytes a multiple of 16 and >= 4 MiB (dst's first 4 MiB also take
+ * the MFMA loop's results; both buffers' contents are overwritten / read).
+ * Best of three timed runs after a warm-up, on hip_stream; blocks the calling
+ * thread.  Outputs: *fp64_tflops in TFLOP/s, *copy_gbs in GB/s (1e9 B/s). */
+dmrg_status dmrg_measure_peaks(void* hip_stream, const void* src, void* dst, size_t bytes, double* fp64_tflops,
+                               double* copy_gbs);
+
 /* Precision of the sigma products in later Davidson solves (dmrg_precision; the
  * option of the same name at creation).  fp64 is kept for the basis, the
  * subspace eigenproblem, the residual, the truncation and the environments; the

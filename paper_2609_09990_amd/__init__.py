@@ -12,6 +12,8 @@ from ._lib import (  # noqa: F401
     Problem,
     Solver,
     dmrg_block_gemm,
+    dmrg_measure_peaks,
+    measure_peaks,
     dmrg_diag,
     dmrg_energy,
     dmrg_get_bonds,

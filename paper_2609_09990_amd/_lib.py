@@ -53,6 +53,7 @@ dmrg_step = _decl("dmrg_step", [_p, _i, _i, _p, C.POINTER(_d)])
 dmrg_set_kernel_tag = _decl("dmrg_set_kernel_tag", [_p, _i])
 dmrg_get_stats = _decl("dmrg_get_stats", [_p, _p, _i])
 dmrg_block_gemm = _decl("dmrg_block_gemm", [_i, _i, _i, _i, _i, _p, _i, _p, _i, _p, _i, _d, _p])
+dmrg_measure_peaks = _decl("dmrg_measure_peaks", [_p, _p, _p, C.c_size_t, _p, _p])
 dmrg_get_env = _decl("dmrg_get_env", [_p, _i, _i, _p, _i64, C.POINTER(_i64)])
 dmrg_grad = _decl("dmrg_grad", [_p, _p, _p, _p, _p])
 dmrg_mlp_create = _decl("dmrg_mlp_create", [_i, _i, C.c_ulonglong, _p, C.POINTER(_p)])
@@ -316,3 +317,17 @@ class Solver:
         if getattr(self, "h", None):
             dmrg_solver_destroy(self.h)
             self.h = None
+
+
+def measure_peaks(nbytes=1 << 31, stream=None):
+    """dmrg_measure_peaks on two torch device buffers of nbytes each:
+    (fp64 MFMA TFLOP/s of a register-only loop, streaming-copy GB/s)."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    st = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    f, c = C.c_double(), C.c_double()
+    _check(dmrg_measure_peaks(C.c_void_p(st), C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
+                              nbytes, C.byref(f), C.byref(c)))
+    del src, dst
+    return f.value, c.value

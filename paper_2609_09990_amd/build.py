@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdmrg_mi355x.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["kernels.hip", "mpo.cpp", "layout.cpp", "plan.cpp", "solver.cpp", "grad.cpp", "precond.cpp", "mlp.hip", "mlp_net.cpp", "capi.cpp"]
+SOURCES = ["kernels.hip", "mpo.cpp", "layout.cpp", "plan.cpp", "solver.cpp", "grad.cpp", "precond.cpp", "mlp.hip", "mlp_net.cpp", "capi.cpp", "peaks.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # packed fp32 arithmetic stays off (hand-written or compiler-made)
@@ -20,9 +20,13 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-I" + os.path.join(HERE, "..", "include")]
 
 
+# per-source extra flags: the ceiling microkernels keep MFMA accumulators in VGPRs
+EXTRA = {"peaks.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def _compile(src):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + FLAGS + EXTRA.get(src, []) + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in (r.stderr or "").splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:

@@ -1,4 +1,5 @@
 // C ABI over the solver: argument checks, exception-to-status translation.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -465,3 +466,42 @@ dmrg_status dmrg_get_stats(const dmrg_solver* s, double* out, int n) {
 }
 
 }  // extern "C"
+
+dmrg_status dmrg_measure_peaks(void* stream, const void* src, void* dst, size_t bytes, double* fp64_tflops,
+                               double* copy_gbs) {
+  return guard([&] {
+    DMRG_REQUIRE(src && dst && fp64_tflops && copy_gbs, ST_EINVAL, "NULL argument");
+    DMRG_REQUIRE(bytes >= (size_t(1) << 22) && bytes % 16 == 0, ST_EINVAL,
+                 "bytes must be a multiple of 16 and at least 4 MiB");
+    DMRG_REQUIRE(((uintptr_t)src | (uintptr_t)dst) % 16 == 0, ST_EINVAL, "buffers must be 16-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "event");
+    hip_check(hipEventCreate(&e1), "event");
+    // best of three timed runs after one warm-up, for each ceiling
+    const int n_blocks = 2048, iters = 2000;  // 8 waves per SIMD on 256 CUs; out = 4 MiB of dst
+    double best_f = 0.0, best_c = 0.0;
+    for (int rep = 0; rep < 4; ++rep) {
+      float ms = 0.f;
+      hip_check(hipEventRecord(e0, st), "event");
+      const long flops = launch_mfma_f64_peak((double*)dst, n_blocks, iters, st);
+      hip_check(hipEventRecord(e1, st), "event");
+      hip_check(hipEventSynchronize(e1), "mfma peak");
+      hip_check(hipEventElapsedTime(&ms, e0, e1), "event");
+      if (rep > 0 && ms > 0.f) best_f = std::max(best_f, flops / (ms * 1e-3) / 1e12);
+    }
+    for (int rep = 0; rep < 4; ++rep) {
+      float ms = 0.f;
+      hip_check(hipEventRecord(e0, st), "event");
+      launch_stream_copy(src, dst, (long)bytes, st);
+      hip_check(hipEventRecord(e1, st), "event");
+      hip_check(hipEventSynchronize(e1), "stream copy");
+      hip_check(hipEventElapsedTime(&ms, e0, e1), "event");
+      if (rep > 0 && ms > 0.f) best_c = std::max(best_c, 2.0 * (double)bytes / (ms * 1e-3) / 1e9);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *fp64_tflops = best_f;
+    *copy_gbs = best_c;
+  });
+}

@@ -77,6 +77,11 @@ void launch_gemm_w32_bf16(int mode, bool a_f32, bool buf, const GemmUnit* units,
 void launch_premix(double* out, const double* const* srcs, const int* ptr, const double* coef,
                    int n_out, long nnz, hipStream_t s);
 
+// Device ceilings: a register-only fp64 MFMA loop (out: n_blocks * 256 doubles;
+// returns the flops launched) and a streaming copy of bytes (multiple of 16,
+// 16-byte aligned buffers).
+long launch_mfma_f64_peak(double* out, int n_blocks, int iters, hipStream_t s);
+void launch_stream_copy(const void* src, void* dst, long bytes, hipStream_t s);
 void launch_fill(double* x, long n, double v, hipStream_t s);
 // desc per block (9 x int64): src_off, src_row_stride, src_col_stride, dst_off,
 // dst_row_stride, dst_col_stride, rows, cols, scale (bits of a double)
