@@ -28,7 +28,7 @@ PEAK_FP64 = 78.6  # TFLOP/s, MI355X dense FP64 matrix
 # HBM bytes per launch of the dominant kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
 # runs (profiles/sigma_phaseB_w32_cas20_m1024_fp64.md), scaled by the same counters on a
 # plain copy (fetch x2.0, write x1.0); set to None whenever that kernel changes.
-TRAFFIC = 6.04e10
+TRAFFIC = None
 
 
 def cpu_baseline(pk, torch):
@@ -287,7 +287,7 @@ def main():
         "setup_s": t_setup,
         "energy_last": energies[-1] if energies else None,
         "plan_reuse_per_step": (d["plan_hits"]) / args.steps,
-        "roofline": {"bound": "mfma", "kernel": "gemm_f64_w32<1, 4, true> (sigma phase B, timed launches)",
+        "roofline": {"bound": "mfma", "kernel": "gemm_f64_wg<4> (sigma phase B, timed launches)",
                      "achieved": b_achieved, "peak": PEAK_FP64, "unit": "TFLOP/s",
                      "frac": b_achieved / PEAK_FP64, "traffic": TRAFFIC,
                      "launch_ms": b_launch_ms, "flops_per_launch": d["sigma_b_flops"] / nmv},

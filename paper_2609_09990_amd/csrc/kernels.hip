@@ -566,6 +566,153 @@ __global__ __launch_bounds__(256) void gemm_f64_w32(const GemmUnit* __restrict__
   }
 }
 
+// Block kernel for long item lists in NT mode (fp64): one workgroup per unit,
+// whose tile ((16 RB) x (16 CB), up to 96 x 64) covers a whole output block of
+// the sizes a sigma meets, so every item's operands are read once per block
+// rather than once per one-wave tile.  Wave w computes columns 16w .. 16w + 15
+// of all RB row blocks.  A slices (c * A, rows m, k contiguous in memory) are
+// staged through LDS, transposed to As[k][m] and shared by the four waves; each
+// wave reads its own 16 rows of B straight from memory.  Items are walked in
+// k slices of 32 with one slice of lookahead: the next slice's loads are issued
+// before the current slice's MFMAs, and one barrier per slice hands the LDS
+// buffers over.  Requires the buffer-load reach of every item (host-checked).
+constexpr int kWgKs = 32;   // k slice
+constexpr int kWgTmp = 97;  // LDS row pitch (doubles) of As[k][m]
+
+struct WgStage {
+  int it;  // item index, or -1 past the end
+  int k0;  // first k of the slice
+};
+
+template <int RB>
+__device__ inline void wg_tile(const GemmUnit& u, const GemmItem* __restrict__ items, double (*As)[kWgKs][kWgTmp]) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int r = lane & 15, kq = lane >> 4;
+  const int CB = u.shape & 7;
+  const bool active = wave < CB;  // wave-uniform
+  const int bn = u.n0 + 16 * wave + r;
+  const bool bv = active && bn < u.N;
+  v4d acc[RB];
+#pragma unroll
+  for (int i = 0; i < RB; ++i) acc[i] = (v4d){0.0, 0.0, 0.0, 0.0};
+  // A staging: 16 RB rows x 16 k-pairs per slice, RB b128 loads per thread
+  double sa[RB][2];
+  double sb[4][2];  // this lane's B pairs of the slice: k = k0 + 8 pb + 2 kq (+1)
+  auto load = [&](const GemmItem& g, int k0, double (&xa)[RB][2], double (&xb)[4][2]) {
+    const long ea = (long)(u.M - 1) * g.lda + g.K;
+    const long eb = (long)(u.N - 1) * g.ldb + g.K;
+    const __amdgpu_buffer_rsrc_t ra = buf_rsrc(g.A, ea * 8), rb = buf_rsrc(g.B, eb * 8);
+    // pairs wholly past K are not fetched (their values are never used)
+#pragma unroll
+    for (int j = 0; j < RB; ++j) {
+      const int idx = tid + 256 * j, m = idx >> 4, kp = idx & 15;
+      const int gm = u.m0 + m;
+      const int off = gm < u.M ? gm * g.lda : (int)ea;
+      if (k0 + 2 * kp < g.K) buf_pair(ra, off + k0 + 2 * kp, xa[j]);
+    }
+    if (active) {
+      const int off = bv ? bn * g.ldb : (int)eb;
+#pragma unroll
+      for (int pb = 0; pb < 4; ++pb)
+        if (k0 + 8 * pb < g.K) buf_pair(rb, off + k0 + 8 * pb + 2 * kq, xb[pb]);
+    }
+  };
+  auto stash = [&](const GemmItem& g, int k0, const double (&xa)[RB][2], int buf) {
+    const double c = g.coef;
+#pragma unroll
+    for (int j = 0; j < RB; ++j) {
+      const int idx = tid + 256 * j, m = idx >> 4, kp = idx & 15;
+      const int k = k0 + 2 * kp;
+      As[buf][2 * kp][m] = k < g.K ? xa[j][0] * c : 0.0;
+      As[buf][2 * kp + 1][m] = k + 1 < g.K ? xa[j][1] * c : 0.0;
+    }
+  };
+  auto next = [&](WgStage s, int K) -> WgStage {
+    if (s.k0 + kWgKs < K) return {s.it, s.k0 + kWgKs};
+    return {s.it + 1 < u.ie ? s.it + 1 : -1, 0};
+  };
+  WgStage cur{u.ib < u.ie ? u.ib : -1, 0};
+  GemmItem g{}, gq{};  // current item; the next item's descriptor, fetched one item ahead
+  int buf = 0;
+  if (cur.it >= 0) {
+    g = items[cur.it];
+    if (cur.it + 1 < u.ie) gq = items[cur.it + 1];
+    load(g, 0, sa, sb);
+    stash(g, 0, sa, 0);
+  }
+  __syncthreads();
+  while (cur.it >= 0) {
+    const WgStage nx = next(cur, g.K);
+    GemmItem gn = g;
+    if (nx.it >= 0 && nx.it != cur.it) {
+      gn = gq;
+      if (nx.it + 1 < u.ie) gq = items[nx.it + 1];
+    }
+    double na[RB][2], nb[4][2];
+    if (nx.it >= 0) load(gn, nx.k0, na, nb);
+    if (active) {
+      // pair blocks of this slice: k = k0 + 8 pb + 2 kq + h, zeroed past K in A
+      const int np = (min(kWgKs, g.K - cur.k0) + 7) >> 3;
+#pragma unroll
+      for (int pb = 0; pb < 4; ++pb) {
+        if (pb < np) {
+          const int kk = 8 * pb + 2 * kq;
+          const bool k0v = cur.k0 + kk < g.K, k1v = cur.k0 + kk + 1 < g.K;
+          const double b0 = (bv && k0v) ? sb[pb][0] : 0.0, b1 = (bv && k1v) ? sb[pb][1] : 0.0;
+#pragma unroll
+          for (int i = 0; i < RB; ++i) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(As[buf][kk][16 * i + r], b0, acc[i], 0, 0, 0);
+#pragma unroll
+          for (int i = 0; i < RB; ++i)
+            acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(As[buf][kk + 1][16 * i + r], b1, acc[i], 0, 0, 0);
+        }
+      }
+    }
+    if (nx.it >= 0) stash(gn, nx.k0, na, buf ^ 1);
+#pragma unroll
+    for (int pb = 0; pb < 4; ++pb) {
+      sb[pb][0] = nb[pb][0];
+      sb[pb][1] = nb[pb][1];
+    }
+    __syncthreads();
+    buf ^= 1;
+    cur = nx;
+    g = gn;
+  }
+  if (!active) return;
+  double* C = (double*)u.C;
+  const int tn = 16 * CB;
+#pragma unroll
+  for (int i = 0; i < RB; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int tr = 16 * i + kq + 4 * q, tc = 16 * wave + r;
+      const int gm = u.m0 + tr, gn = u.n0 + tc;
+      const double v = acc[i][q];
+      if (u.accumulate == 2) {
+        C[tr * tn + tc] = v;  // partial slot, full tile
+      } else if (gm < u.M && gn < u.N) {
+        const long idx = (long)gm * u.ldc + gn;
+        C[idx] = u.accumulate ? C[idx] + v : v;
+      }
+    }
+}
+
+template <int TAG>
+__global__ __launch_bounds__(256) void gemm_f64_wg(const GemmUnit* __restrict__ units,
+                                                   const GemmItem* __restrict__ items) {
+  __shared__ double As[2][kWgKs][kWgTmp];
+  const GemmUnit u = units[blockIdx.x];
+  switch (u.shape >> 3) {  // RB; the tile is (16 RB) x (16 CB), CB = shape & 7
+    case 1: wg_tile<1>(u, items, As); break;
+    case 2: wg_tile<2>(u, items, As); break;
+    case 3: wg_tile<3>(u, items, As); break;
+    case 4: wg_tile<4>(u, items, As); break;
+    case 5: wg_tile<5>(u, items, As); break;
+    default: wg_tile<6>(u, items, As); break;
+  }
+}
+
 // fp32 operands, fp32 accumulation (the precision form): the same one-wave tiles,
 // k pairing and buffer loads as the fp64 kernel, on v_mfma_f32_16x16x4f32, whose
 // accumulator element q of lane l is row 4 (l/16) + q, column l%16.
@@ -928,7 +1075,7 @@ __global__ void splitk_reduce_f32(const SplitTile* __restrict__ tiles, const flo
     int gm = t.m0 + tr, gn = t.n0 + tc;
     if (gm >= t.M || gn >= t.N) continue;
     float acc = 0.f;
-    for (int s = 0; s < t.ns; ++s) acc += slots[(long)(t.s0 + s) * kSlotElems + e];
+    for (int s = 0; s < t.ns; ++s) acc += slots[t.s0 + (long)s * t.tm * t.tn + e];
     C[(long)gm * t.ldc + gn] = acc;
   }
 }
@@ -942,7 +1089,7 @@ __global__ void splitk_reduce(const SplitTile* __restrict__ tiles, const double*
     int gm = t.m0 + tr, gn = t.n0 + tc;
     if (gm >= t.M || gn >= t.N) continue;
     double acc = 0.0;
-    for (int s = 0; s < t.ns; ++s) acc += slots[(long)(t.s0 + s) * kSlotElems + e];
+    for (int s = 0; s < t.ns; ++s) acc += slots[t.s0 + (long)s * t.tm * t.tn + e];
     C[(long)gm * t.ldc + gn] = acc;
   }
 }
@@ -1244,6 +1391,17 @@ void launch_gemm_w32(int mode, int tag, bool buf, const GemmUnit* units, int n_u
     default: DMRG_W32_LAUNCH(0) break;
   }
 #undef DMRG_W32_LAUNCH
+}
+
+void launch_gemm_wg(int tag, const GemmUnit* units, int n_units, const GemmItem* items, hipStream_t s) {
+  if (n_units <= 0) return;
+  switch (tag) {
+    case 1: gemm_f64_wg<1><<<n_units, 256, 0, s>>>(units, items); break;
+    case 2: gemm_f64_wg<2><<<n_units, 256, 0, s>>>(units, items); break;
+    case 3: gemm_f64_wg<3><<<n_units, 256, 0, s>>>(units, items); break;
+    case 4: gemm_f64_wg<4><<<n_units, 256, 0, s>>>(units, items); break;
+    default: gemm_f64_wg<0><<<n_units, 256, 0, s>>>(units, items); break;
+  }
 }
 
 void launch_splitk_reduce(const SplitTile* tiles, int n, const double* slots, hipStream_t s) {

@@ -45,25 +45,29 @@ void launch_gemm(int prec, int mode, const GemmUnit* units, int n_units, const G
 void launch_gemm_w32(int mode, int tag, bool buf, const GemmUnit* units, int n_units, const GemmItem* items,
                      hipStream_t s);
 // Whether one item may take the buffer-load path: every element offset a tile
-// forms from the operand starts (up to 16 past the last row's K, NN rows of B up
-// to K + 16) stays below 1 GiB in bytes, so offsets fit 32-bit arithmetic.
+// forms from the operand starts (up to 32 past the last row's K, NN rows of B up
+// to K + 32) stays below 1 GiB in bytes, so offsets fit 32-bit arithmetic.
 inline bool buffer_reach_ok(int mode, int M, int N, int K, int lda, int ldb, size_t esz_a, size_t esz_b) {
   if (mode != GEMM_NN && mode != GEMM_NT) return false;
   const long lim = 1L << 30;
-  const long ra = ((long)(M - 1) * lda + K + 16) * (long)esz_a;
-  const long rb = (mode == GEMM_NT ? (long)(N - 1) * ldb + K + 16 : (long)(K + 16) * ldb + N) * (long)esz_b;
+  const long ra = ((long)(M - 1) * lda + K + 32) * (long)esz_a;
+  const long rb = (mode == GEMM_NT ? (long)(N - 1) * ldb + K + 32 : (long)(K + 32) * ldb + N) * (long)esz_b;
   return ra < lim && rb < lim;
 }
 
 // Output tile (rows m0.., cols n0.. of an M x N block, tm x tn) = sum of ns
-// partial slots s0..s0+ns-1 (slot stride kSlotElems, tile row-major), summed in
-// slot order.
-constexpr int kSlotElems = 2048;
+// partial tiles (row-major tm x tn each) stored one after another from element
+// s0 of the slot buffer, summed in order.
 struct SplitTile {
   void* C;
-  int ldc, M, N, m0, n0, s0, ns, tm, tn;
+  long s0;
+  int ldc, M, N, m0, n0, ns, tm, tn;
 };
 void launch_splitk_reduce(const SplitTile* tiles, int n, const double* slots, hipStream_t s);
+// fp64 NT block kernel: one 256-thread workgroup per unit, tile (16 RB) x
+// (16 CB) with RB = shape >> 3 in 1..6 and CB = shape & 7 in 1..4; every item
+// must pass buffer_reach_ok.  Partial tiles (accumulate == 2) are 16 CB wide.
+void launch_gemm_wg(int tag, const GemmUnit* units, int n_units, const GemmItem* items, hipStream_t s);
 // The same for fp32 operands, fp32 accumulation and fp32 outputs and slots.
 void launch_gemm_w32_f32(int mode, bool buf, const GemmUnit* units, int n_units, const GemmItem* items,
                          hipStream_t s);

@@ -224,11 +224,15 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
       buf_ok = buffer_reach_ok(ph.mode, u.M, u.N, p.K, p.lda, p.ldb, esz[p.abuf], esz[p.bbuf]);
     }
   ph.buf_ok[slot] = buf_ok;
+  // fp64 NT phases with long item lists (sigma phase B) take the workgroup block
+  // kernel: whole-block tiles up to 96 x 64, operands read once per block
+  const bool use_wg = ph.wg && prec == PREC_F64 && ph.mode == GEMM_NT && buf_ok;
+  ph.wg_used[slot] = use_wg;
   std::vector<GemmUnit>& units = ph.h_units[slot];
   units.clear();
   std::vector<SplitTile>& tiles = ph.h_tiles[slot];
   tiles.clear();
-  long n_slots = 0;
+  long n_slot_elems = 0;
   if (prec == PREC_F64 || prec == PREC_F32 || prec == PREC_BF16 || prec == 3) {
     // One-wave tiles of (16 RB) x (16 CB), RB <= 4, CB <= 2: block rows are cut
     // into strips of 64 while more than 64 remain, columns into strips of 32, and
@@ -247,9 +251,11 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
     struct TileShape { int m0, n0, tm, tn, shape; };
     std::vector<std::pair<int, int>> rs, cs;
     std::vector<TileShape> ts;
+    // one-wave tiles: up to 64 x 32; workgroup block tiles: up to 96 x 64
+    const int wm = use_wg ? 96 : 64, wn = use_wg ? 64 : 32;
     auto tiles_of = [&](const PUnit& u) {
-      strips(u.M, 64, rs);
-      strips(u.N, 32, cs);
+      strips(u.M, wm, rs);
+      strips(u.N, wn, cs);
       ts.clear();
       for (auto& r : rs)
         for (auto& c : cs) ts.push_back({r.first, c.first, r.second, c.second, 8 * (r.second / 16) + c.second / 16});
@@ -257,7 +263,10 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
     double work = 0;
     for (const PUnit& u : ph.units)
       for (int i = u.ib; i < u.ie; ++i) work += ((u.M + 31) / 32) * ((u.N + 31) / 32) * ((ph.items[i].K + 3) / 4);
-    const double chunk = std::max(DMRG_SPLIT_MIN, work / 16384.0);
+    // about 16384 one-wave units; workgroup units are cut finer (32768, measured
+    // best for sigma phase B at CAS(20,20), M = 1024: smaller pieces of the
+    // largest blocks spread over more CUs, against more split-K partial tiles)
+    const double chunk = std::max(DMRG_SPLIT_MIN, work / (use_wg ? 32768.0 : 16384.0));
     std::vector<std::pair<int, int>> cuts;
     for (const PUnit& u : ph.units) {
       char* C = (char*)bases[u.cbuf] + u.coff * esz[u.cbuf];
@@ -282,18 +291,18 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
       const int nc = (int)cuts.size();
       const long first_tile = (long)tiles.size();
       for (const TileShape& t : ts) {
-        tiles.push_back({C, u.ldc, u.M, u.N, t.m0, t.n0, (int)n_slots, nc, t.tm, t.tn});
-        n_slots += nc;
+        tiles.push_back({C, n_slot_elems, u.ldc, u.M, u.N, t.m0, t.n0, nc, t.tm, t.tn});
+        n_slot_elems += (long)nc * t.tm * t.tn;
       }
       for (int c = 0; c < nc; ++c)
         for (size_t t = 0; t < ts.size(); ++t) {
           const SplitTile& st_ = tiles[first_tile + t];
-          units.push_back({(void*)(intptr_t)((long)(st_.s0 + c) * kSlotElems), st_.tn, u.M, u.N, st_.m0, st_.n0,
+          units.push_back({(void*)(intptr_t)(st_.s0 + (long)c * st_.tm * st_.tn), st_.tn, u.M, u.N, st_.m0, st_.n0,
                            cuts[c].first, cuts[c].second, 2, ts[t].shape});
         }
     }
     const size_t slot_esz = prec == PREC_F64 ? sizeof(double) : sizeof(float);
-    ph.slots_f[slot].reserve(std::max<long>(n_slots, 1) * kSlotElems * slot_esz);
+    ph.slots_f[slot].reserve(std::max<long>(n_slot_elems, 1) * slot_esz);
     for (auto& un : units)
       if (un.accumulate == 2) un.C = (char*)ph.slots_f[slot].p + (intptr_t)un.C * slot_esz;
   } else {
@@ -318,8 +327,11 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
 
 void Solver::launch_resolved(Phase& ph, int prec, int slot) {
   if (prec == PREC_F64) {
-    launch_gemm_w32(ph.mode, ph.tag, ph.buf_ok[slot], ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot],
-                    ph.d_items[slot].as<GemmItem>(), st);
+    if (ph.wg_used[slot])
+      launch_gemm_wg(ph.tag, ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot], ph.d_items[slot].as<GemmItem>(), st);
+    else
+      launch_gemm_w32(ph.mode, ph.tag, ph.buf_ok[slot], ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot],
+                      ph.d_items[slot].as<GemmItem>(), st);
     if (ph.gemm_done) (void)hipEventRecord(ph.gemm_done, st);  // GEMM-only timing
     launch_splitk_reduce(ph.d_tiles[slot].as<SplitTile>(), ph.n_tiles[slot], ph.slots_f[slot].as<double>(), st);
   } else if (prec == PREC_F32) {
@@ -625,6 +637,7 @@ void Solver::build_sigma_plan(int k) {
   // phase B: gather items per output block of sigma
   phB_ = Phase();
   phB_.mode = GEMM_NT;
+  phB_.wg = true;
   std::vector<std::vector<std::vector<PItem>>> per(P.slabs.size());
   for (size_t si = 0; si < P.slabs.size(); ++si) per[si].resize(P.slabs[si].blocks.size());
   for (int b = 0; b < nmid; ++b) {

@@ -110,6 +110,8 @@ struct Phase {
   const void* last_bases[3][B_NBUF] = {};
   bool uploaded[3] = {false, false, false};
   bool buf_ok[3] = {false, false, false};  // every item fits the buffer-load kernels
+  bool wg = false;                         // may take the fp64 workgroup block kernel (NT)
+  bool wg_used[3] = {false, false, false};
 };
 
 // One side's factors for a middle cut: X_{beta,op} = sum_alpha c L[alpha] (left)
