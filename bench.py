@@ -287,7 +287,7 @@ def main():
         "setup_s": t_setup,
         "energy_last": energies[-1] if energies else None,
         "plan_reuse_per_step": (d["plan_hits"]) / args.steps,
-        "roofline": {"bound": "mfma", "kernel": "gemm_f64_wg<4> (sigma phase B, timed launches)",
+        "roofline": {"bound": "mfma", "kernel": "gemm_wg<double, 4> (sigma phase B, timed launches)",
                      "achieved": b_achieved, "peak": PEAK_FP64, "unit": "TFLOP/s",
                      "frac": b_achieved / PEAK_FP64, "traffic": TRAFFIC,
                      "launch_ms": b_launch_ms, "flops_per_launch": d["sigma_b_flops"] / nmv},

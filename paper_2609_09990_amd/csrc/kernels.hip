@@ -566,7 +566,19 @@ __global__ __launch_bounds__(256) void gemm_f64_w32(const GemmUnit* __restrict__
   }
 }
 
-// Block kernel for long item lists in NT mode (fp64): one workgroup per unit,
+__device__ inline void buf_pair_f32(__amdgpu_buffer_rsrc_t r, int e, float* x) {
+  const v2u32 v = __builtin_amdgcn_raw_buffer_load_b64(r, e * 4, 0, 0);
+  __builtin_memcpy(&x[0], &v, 4);
+  __builtin_memcpy(&x[1], reinterpret_cast<const char*>(&v) + 4, 4);
+}
+__device__ inline float buf_one_f32(__amdgpu_buffer_rsrc_t r, int e) {
+  const unsigned int v = __builtin_amdgcn_raw_buffer_load_b32(r, e * 4, 0, 0);
+  float x;
+  __builtin_memcpy(&x, &v, 4);
+  return x;
+}
+
+// Block kernel for long item lists in NT mode (fp64 or fp32): one workgroup per unit,
 // whose tile ((16 RB) x (16 CB), up to 96 x 64) covers a whole output block of
 // the sizes a sigma meets, so every item's operands are read once per block
 // rather than once per one-wave tile.  Wave w computes columns 16w .. 16w + 15
@@ -577,15 +589,38 @@ __global__ __launch_bounds__(256) void gemm_f64_w32(const GemmUnit* __restrict__
 // before the current slice's MFMAs, and one barrier per slice hands the LDS
 // buffers over.  Requires the buffer-load reach of every item (host-checked).
 constexpr int kWgKs = 32;   // k slice
-constexpr int kWgTmp = 97;  // LDS row pitch (doubles) of As[k][m]
+constexpr int kWgTmp = 97;  // LDS row pitch (elements) of As[k][m]
 
 struct WgStage {
   int it;  // item index, or -1 past the end
   int k0;  // first k of the slice
 };
 
-template <int RB>
-__device__ inline void wg_tile(const GemmUnit& u, const GemmItem* __restrict__ items, double (*As)[kWgKs][kWgTmp]) {
+// Element-type specifics of the block kernel: fp64 on v_mfma_f64_16x16x4f64
+// (accumulator element q of lane l: row l/16 + 4q), fp32 on
+// v_mfma_f32_16x16x4f32 (row 4 (l/16) + q); both take A[row l%16][k l/16] and
+// B[k l/16][col l%16] per 4-deep step, so the k pairing is shared.
+template <typename T>
+struct WgType;
+template <>
+struct WgType<double> {
+  typedef v4d acc_t;
+  __device__ static void pair(__amdgpu_buffer_rsrc_t r, int e, double* x) { buf_pair(r, e, x); }
+  __device__ static acc_t mfma(double a, double b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int row(int kq, int q) { return kq + 4 * q; }
+};
+template <>
+struct WgType<float> {
+  typedef v4f acc_t;
+  __device__ static void pair(__amdgpu_buffer_rsrc_t r, int e, float* x) { buf_pair_f32(r, e, x); }
+  __device__ static acc_t mfma(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int kq, int q) { return 4 * kq + q; }
+};
+
+template <typename T, int RB>
+__device__ inline void wg_tile(const GemmUnit& u, const GemmItem* __restrict__ items, T (*As)[kWgKs][kWgTmp]) {
+  typedef WgType<T> W;
+  typedef typename W::acc_t acc_t;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int r = lane & 15, kq = lane >> 4;
@@ -593,39 +628,39 @@ __device__ inline void wg_tile(const GemmUnit& u, const GemmItem* __restrict__ i
   const bool active = wave < CB;  // wave-uniform
   const int bn = u.n0 + 16 * wave + r;
   const bool bv = active && bn < u.N;
-  v4d acc[RB];
+  acc_t acc[RB];
 #pragma unroll
-  for (int i = 0; i < RB; ++i) acc[i] = (v4d){0.0, 0.0, 0.0, 0.0};
-  // A staging: 16 RB rows x 16 k-pairs per slice, RB b128 loads per thread
-  double sa[RB][2];
-  double sb[4][2];  // this lane's B pairs of the slice: k = k0 + 8 pb + 2 kq (+1)
-  auto load = [&](const GemmItem& g, int k0, double (&xa)[RB][2], double (&xb)[4][2]) {
+  for (int i = 0; i < RB; ++i) acc[i] = acc_t{};
+  // A staging: 16 RB rows x 16 k-pairs per slice, RB pair loads per thread
+  T sa[RB][2];
+  T sb[4][2];  // this lane's B pairs of the slice: k = k0 + 8 pb + 2 kq (+1)
+  auto load = [&](const GemmItem& g, int k0, T (&xa)[RB][2], T (&xb)[4][2]) {
     const long ea = (long)(u.M - 1) * g.lda + g.K;
     const long eb = (long)(u.N - 1) * g.ldb + g.K;
-    const __amdgpu_buffer_rsrc_t ra = buf_rsrc(g.A, ea * 8), rb = buf_rsrc(g.B, eb * 8);
+    const __amdgpu_buffer_rsrc_t ra = buf_rsrc(g.A, ea * (long)sizeof(T)), rb = buf_rsrc(g.B, eb * (long)sizeof(T));
     // pairs wholly past K are not fetched (their values are never used)
 #pragma unroll
     for (int j = 0; j < RB; ++j) {
       const int idx = tid + 256 * j, m = idx >> 4, kp = idx & 15;
       const int gm = u.m0 + m;
       const int off = gm < u.M ? gm * g.lda : (int)ea;
-      if (k0 + 2 * kp < g.K) buf_pair(ra, off + k0 + 2 * kp, xa[j]);
+      if (k0 + 2 * kp < g.K) W::pair(ra, off + k0 + 2 * kp, xa[j]);
     }
     if (active) {
       const int off = bv ? bn * g.ldb : (int)eb;
 #pragma unroll
       for (int pb = 0; pb < 4; ++pb)
-        if (k0 + 8 * pb < g.K) buf_pair(rb, off + k0 + 8 * pb + 2 * kq, xb[pb]);
+        if (k0 + 8 * pb < g.K) W::pair(rb, off + k0 + 8 * pb + 2 * kq, xb[pb]);
     }
   };
-  auto stash = [&](const GemmItem& g, int k0, const double (&xa)[RB][2], int buf) {
-    const double c = g.coef;
+  auto stash = [&](const GemmItem& g, int k0, const T (&xa)[RB][2], int buf) {
+    const T c = (T)g.coef;
 #pragma unroll
     for (int j = 0; j < RB; ++j) {
       const int idx = tid + 256 * j, m = idx >> 4, kp = idx & 15;
       const int k = k0 + 2 * kp;
-      As[buf][2 * kp][m] = k < g.K ? xa[j][0] * c : 0.0;
-      As[buf][2 * kp + 1][m] = k + 1 < g.K ? xa[j][1] * c : 0.0;
+      As[buf][2 * kp][m] = k < g.K ? xa[j][0] * c : (T)0;
+      As[buf][2 * kp + 1][m] = k + 1 < g.K ? xa[j][1] * c : (T)0;
     }
   };
   auto next = [&](WgStage s, int K) -> WgStage {
@@ -649,7 +684,7 @@ __device__ inline void wg_tile(const GemmUnit& u, const GemmItem* __restrict__ i
       gn = gq;
       if (nx.it + 1 < u.ie) gq = items[nx.it + 1];
     }
-    double na[RB][2], nb[4][2];
+    T na[RB][2], nb[4][2];
     if (nx.it >= 0) load(gn, nx.k0, na, nb);
     if (active) {
       // pair blocks of this slice: k = k0 + 8 pb + 2 kq + h, zeroed past K in A
@@ -659,12 +694,11 @@ __device__ inline void wg_tile(const GemmUnit& u, const GemmItem* __restrict__ i
         if (pb < np) {
           const int kk = 8 * pb + 2 * kq;
           const bool k0v = cur.k0 + kk < g.K, k1v = cur.k0 + kk + 1 < g.K;
-          const double b0 = (bv && k0v) ? sb[pb][0] : 0.0, b1 = (bv && k1v) ? sb[pb][1] : 0.0;
+          const T b0 = (bv && k0v) ? sb[pb][0] : (T)0, b1 = (bv && k1v) ? sb[pb][1] : (T)0;
 #pragma unroll
-          for (int i = 0; i < RB; ++i) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(As[buf][kk][16 * i + r], b0, acc[i], 0, 0, 0);
+          for (int i = 0; i < RB; ++i) acc[i] = W::mfma(As[buf][kk][16 * i + r], b0, acc[i]);
 #pragma unroll
-          for (int i = 0; i < RB; ++i)
-            acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(As[buf][kk + 1][16 * i + r], b1, acc[i], 0, 0, 0);
+          for (int i = 0; i < RB; ++i) acc[i] = W::mfma(As[buf][kk + 1][16 * i + r], b1, acc[i]);
         }
       }
     }
@@ -680,15 +714,15 @@ __device__ inline void wg_tile(const GemmUnit& u, const GemmItem* __restrict__ i
     g = gn;
   }
   if (!active) return;
-  double* C = (double*)u.C;
+  T* C = (T*)u.C;
   const int tn = 16 * CB;
 #pragma unroll
   for (int i = 0; i < RB; ++i)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int tr = 16 * i + kq + 4 * q, tc = 16 * wave + r;
+      const int tr = 16 * i + W::row(kq, q), tc = 16 * wave + r;
       const int gm = u.m0 + tr, gn = u.n0 + tc;
-      const double v = acc[i][q];
+      const T v = acc[i][q];
       if (u.accumulate == 2) {
         C[tr * tn + tc] = v;  // partial slot, full tile
       } else if (gm < u.M && gn < u.N) {
@@ -698,36 +732,24 @@ __device__ inline void wg_tile(const GemmUnit& u, const GemmItem* __restrict__ i
     }
 }
 
-template <int TAG>
-__global__ __launch_bounds__(256) void gemm_f64_wg(const GemmUnit* __restrict__ units,
-                                                   const GemmItem* __restrict__ items) {
-  __shared__ double As[2][kWgKs][kWgTmp];
+template <typename T, int TAG>
+__global__ __launch_bounds__(256) void gemm_wg(const GemmUnit* __restrict__ units,
+                                               const GemmItem* __restrict__ items) {
+  __shared__ T As[2][kWgKs][kWgTmp];
   const GemmUnit u = units[blockIdx.x];
   switch (u.shape >> 3) {  // RB; the tile is (16 RB) x (16 CB), CB = shape & 7
-    case 1: wg_tile<1>(u, items, As); break;
-    case 2: wg_tile<2>(u, items, As); break;
-    case 3: wg_tile<3>(u, items, As); break;
-    case 4: wg_tile<4>(u, items, As); break;
-    case 5: wg_tile<5>(u, items, As); break;
-    default: wg_tile<6>(u, items, As); break;
+    case 1: wg_tile<T, 1>(u, items, As); break;
+    case 2: wg_tile<T, 2>(u, items, As); break;
+    case 3: wg_tile<T, 3>(u, items, As); break;
+    case 4: wg_tile<T, 4>(u, items, As); break;
+    case 5: wg_tile<T, 5>(u, items, As); break;
+    default: wg_tile<T, 6>(u, items, As); break;
   }
 }
 
 // fp32 operands, fp32 accumulation (the precision form): the same one-wave tiles,
 // k pairing and buffer loads as the fp64 kernel, on v_mfma_f32_16x16x4f32, whose
 // accumulator element q of lane l is row 4 (l/16) + q, column l%16.
-__device__ inline void buf_pair_f32(__amdgpu_buffer_rsrc_t r, int e, float* x) {
-  const v2u32 v = __builtin_amdgcn_raw_buffer_load_b64(r, e * 4, 0, 0);
-  __builtin_memcpy(&x[0], &v, 4);
-  __builtin_memcpy(&x[1], reinterpret_cast<const char*>(&v) + 4, 4);
-}
-__device__ inline float buf_one_f32(__amdgpu_buffer_rsrc_t r, int e) {
-  const unsigned int v = __builtin_amdgcn_raw_buffer_load_b32(r, e * 4, 0, 0);
-  float x;
-  __builtin_memcpy(&x, &v, 4);
-  return x;
-}
-
 template <int MODE, int RB, int CB, bool BUF>
 __device__ inline void w32_tile_f32(const GemmUnit& u, const GemmItem* __restrict__ items, int lane) {
   const int r = lane & 15, kq = lane >> 4;
@@ -1393,14 +1415,18 @@ void launch_gemm_w32(int mode, int tag, bool buf, const GemmUnit* units, int n_u
 #undef DMRG_W32_LAUNCH
 }
 
-void launch_gemm_wg(int tag, const GemmUnit* units, int n_units, const GemmItem* items, hipStream_t s) {
+void launch_gemm_wg(int prec, int tag, const GemmUnit* units, int n_units, const GemmItem* items, hipStream_t s) {
   if (n_units <= 0) return;
+  if (prec == PREC_F32) {
+    gemm_wg<float, 0><<<n_units, 256, 0, s>>>(units, items);
+    return;
+  }
   switch (tag) {
-    case 1: gemm_f64_wg<1><<<n_units, 256, 0, s>>>(units, items); break;
-    case 2: gemm_f64_wg<2><<<n_units, 256, 0, s>>>(units, items); break;
-    case 3: gemm_f64_wg<3><<<n_units, 256, 0, s>>>(units, items); break;
-    case 4: gemm_f64_wg<4><<<n_units, 256, 0, s>>>(units, items); break;
-    default: gemm_f64_wg<0><<<n_units, 256, 0, s>>>(units, items); break;
+    case 1: gemm_wg<double, 1><<<n_units, 256, 0, s>>>(units, items); break;
+    case 2: gemm_wg<double, 2><<<n_units, 256, 0, s>>>(units, items); break;
+    case 3: gemm_wg<double, 3><<<n_units, 256, 0, s>>>(units, items); break;
+    case 4: gemm_wg<double, 4><<<n_units, 256, 0, s>>>(units, items); break;
+    default: gemm_wg<double, 0><<<n_units, 256, 0, s>>>(units, items); break;
   }
 }
 

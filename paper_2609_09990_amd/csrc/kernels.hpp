@@ -64,10 +64,11 @@ struct SplitTile {
   int ldc, M, N, m0, n0, ns, tm, tn;
 };
 void launch_splitk_reduce(const SplitTile* tiles, int n, const double* slots, hipStream_t s);
-// fp64 NT block kernel: one 256-thread workgroup per unit, tile (16 RB) x
+// NT block kernel (prec PREC_F64 or PREC_F32: operands, accumulation and
+// outputs in that type): one 256-thread workgroup per unit, tile (16 RB) x
 // (16 CB) with RB = shape >> 3 in 1..6 and CB = shape & 7 in 1..4; every item
 // must pass buffer_reach_ok.  Partial tiles (accumulate == 2) are 16 CB wide.
-void launch_gemm_wg(int tag, const GemmUnit* units, int n_units, const GemmItem* items, hipStream_t s);
+void launch_gemm_wg(int prec, int tag, const GemmUnit* units, int n_units, const GemmItem* items, hipStream_t s);
 // The same for fp32 operands, fp32 accumulation and fp32 outputs and slots.
 void launch_gemm_w32_f32(int mode, bool buf, const GemmUnit* units, int n_units, const GemmItem* items,
                          hipStream_t s);

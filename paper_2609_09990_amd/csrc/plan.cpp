@@ -224,9 +224,10 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
       buf_ok = buffer_reach_ok(ph.mode, u.M, u.N, p.K, p.lda, p.ldb, esz[p.abuf], esz[p.bbuf]);
     }
   ph.buf_ok[slot] = buf_ok;
-  // fp64 NT phases with long item lists (sigma phase B) take the workgroup block
-  // kernel: whole-block tiles up to 96 x 64, operands read once per block
-  const bool use_wg = ph.wg && prec == PREC_F64 && ph.mode == GEMM_NT && buf_ok;
+  // fp64 / fp32 NT phases with long item lists (sigma phase B) take the
+  // workgroup block kernel: whole-block tiles up to 96 x 64, operands read once
+  // per block
+  const bool use_wg = ph.wg && (prec == PREC_F64 || prec == PREC_F32) && ph.mode == GEMM_NT && buf_ok;
   ph.wg_used[slot] = use_wg;
   std::vector<GemmUnit>& units = ph.h_units[slot];
   units.clear();
@@ -328,12 +329,15 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
 void Solver::launch_resolved(Phase& ph, int prec, int slot) {
   if (prec == PREC_F64) {
     if (ph.wg_used[slot])
-      launch_gemm_wg(ph.tag, ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot], ph.d_items[slot].as<GemmItem>(), st);
+      launch_gemm_wg(PREC_F64, ph.tag, ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot], ph.d_items[slot].as<GemmItem>(), st);
     else
       launch_gemm_w32(ph.mode, ph.tag, ph.buf_ok[slot], ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot],
                       ph.d_items[slot].as<GemmItem>(), st);
     if (ph.gemm_done) (void)hipEventRecord(ph.gemm_done, st);  // GEMM-only timing
     launch_splitk_reduce(ph.d_tiles[slot].as<SplitTile>(), ph.n_tiles[slot], ph.slots_f[slot].as<double>(), st);
+  } else if (prec == PREC_F32 && ph.wg_used[slot]) {
+    launch_gemm_wg(PREC_F32, 0, ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot], ph.d_items[slot].as<GemmItem>(), st);
+    launch_splitk_reduce_f32(ph.d_tiles[slot].as<SplitTile>(), ph.n_tiles[slot], ph.slots_f[slot].as<float>(), st);
   } else if (prec == PREC_F32) {
     launch_gemm_w32_f32(ph.mode, ph.buf_ok[slot], ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot], ph.d_items[slot].as<GemmItem>(), st);
     launch_splitk_reduce_f32(ph.d_tiles[slot].as<SplitTile>(), ph.n_tiles[slot], ph.slots_f[slot].as<float>(), st);
