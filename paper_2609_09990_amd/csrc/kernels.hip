@@ -584,12 +584,14 @@ __device__ inline float buf_one_f32(__amdgpu_buffer_rsrc_t r, int e) {
 // rather than once per one-wave tile.  Wave w computes columns 16w .. 16w + 15
 // of all RB row blocks.  A slices (c * A, rows m, k contiguous in memory) are
 // staged through LDS, transposed to As[k][m] and shared by the four waves; each
-// wave reads its own 16 rows of B straight from memory.  Items are walked in
+// wave reads its own 16 rows of B straight from memory.  LDS holds A as
+// As[m][k], so each lane writes and reads its k pair with one 16-byte LDS op.  Items are walked in
 // k slices of 32 with one slice of lookahead: the next slice's loads are issued
 // before the current slice's MFMAs, and one barrier per slice hands the LDS
 // buffers over.  Requires the buffer-load reach of every item (host-checked).
 constexpr int kWgKs = 32;   // k slice
-constexpr int kWgTmp = 97;  // LDS row pitch (elements) of As[k][m]
+constexpr int kWgPk = 34;   // LDS row pitch (elements) of As[m][k]: 16-byte aligned k pairs; 16
+                            // lanes reading rows m..m+15 at one k pair hit 16 distinct 4-bank groups
 
 struct WgStage {
   int it;  // item index, or -1 past the end
@@ -617,8 +619,24 @@ struct WgType<float> {
   __device__ static int row(int kq, int q) { return 4 * kq + q; }
 };
 
+// Item descriptors are fetched one item ahead with a vector load (lane l < 10
+// takes dword l) and moved to scalar registers with readlane when used.  A
+// scalar load would share its wait counter with the LDS operations, so every
+// LDS wait of the slice would also wait for the descriptor to come from memory.
+__device__ inline uint32_t desc_word(const GemmItem* items, int j, int lane) {
+  return reinterpret_cast<const uint32_t*>(items + j)[lane < 10 ? lane : 0];
+}
+__device__ inline GemmItem desc_unpack(uint32_t w) {
+  uint32_t d[10];
+#pragma unroll
+  for (int i = 0; i < 10; ++i) d[i] = __builtin_amdgcn_readlane(w, i);
+  GemmItem g;
+  __builtin_memcpy(&g, d, sizeof(GemmItem));
+  return g;
+}
+
 template <typename T, int RB>
-__device__ inline void wg_tile(const GemmUnit& u, const GemmItem* __restrict__ items, T (*As)[kWgKs][kWgTmp]) {
+__device__ inline void wg_tile(const GemmUnit& u, const GemmItem* __restrict__ items, T (*As)[96][kWgPk]) {
   typedef WgType<T> W;
   typedef typename W::acc_t acc_t;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -659,8 +677,9 @@ __device__ inline void wg_tile(const GemmUnit& u, const GemmItem* __restrict__ i
     for (int j = 0; j < RB; ++j) {
       const int idx = tid + 256 * j, m = idx >> 4, kp = idx & 15;
       const int k = k0 + 2 * kp;
-      As[buf][2 * kp][m] = k < g.K ? xa[j][0] * c : (T)0;
-      As[buf][2 * kp + 1][m] = k + 1 < g.K ? xa[j][1] * c : (T)0;
+      T* dst = &As[buf][m][2 * kp];
+      dst[0] = k < g.K ? xa[j][0] * c : (T)0;
+      dst[1] = k + 1 < g.K ? xa[j][1] * c : (T)0;
     }
   };
   auto next = [&](WgStage s, int K) -> WgStage {
@@ -668,24 +687,23 @@ __device__ inline void wg_tile(const GemmUnit& u, const GemmItem* __restrict__ i
     return {s.it + 1 < u.ie ? s.it + 1 : -1, 0};
   };
   WgStage cur{u.ib < u.ie ? u.ib : -1, 0};
-  GemmItem g{}, gq{};  // current item; the next item's descriptor, fetched one item ahead
+  GemmItem g{};     // current item
+  uint32_t qw = 0;  // the next item's descriptor (one dword per lane), fetched one item ahead
   int buf = 0;
   if (cur.it >= 0) {
     g = items[cur.it];
-    if (cur.it + 1 < u.ie) gq = items[cur.it + 1];
     load(g, 0, sa, sb);
+    if (cur.it + 1 < u.ie) qw = desc_word(items, cur.it + 1, lane);
     stash(g, 0, sa, 0);
   }
   __syncthreads();
   while (cur.it >= 0) {
     const WgStage nx = next(cur, g.K);
-    GemmItem gn = g;
-    if (nx.it >= 0 && nx.it != cur.it) {
-      gn = gq;
-      if (nx.it + 1 < u.ie) gq = items[nx.it + 1];
-    }
+    const bool new_item = nx.it >= 0 && nx.it != cur.it;
+    const GemmItem gn = new_item ? desc_unpack(qw) : g;
     T na[RB][2], nb[4][2];
     if (nx.it >= 0) load(gn, nx.k0, na, nb);
+    if (new_item && nx.it + 1 < u.ie) qw = desc_word(items, nx.it + 1, lane);
     if (active) {
       // pair blocks of this slice: k = k0 + 8 pb + 2 kq + h, zeroed past K in A
       const int np = (min(kWgKs, g.K - cur.k0) + 7) >> 3;
@@ -695,10 +713,17 @@ __device__ inline void wg_tile(const GemmUnit& u, const GemmItem* __restrict__ i
           const int kk = 8 * pb + 2 * kq;
           const bool k0v = cur.k0 + kk < g.K, k1v = cur.k0 + kk + 1 < g.K;
           const T b0 = (bv && k0v) ? sb[pb][0] : (T)0, b1 = (bv && k1v) ? sb[pb][1] : (T)0;
+          T a[RB][2];
 #pragma unroll
-          for (int i = 0; i < RB; ++i) acc[i] = W::mfma(As[buf][kk][16 * i + r], b0, acc[i]);
+          for (int i = 0; i < RB; ++i) {
+            const T* src = &As[buf][16 * i + r][kk];
+            a[i][0] = src[0];
+            a[i][1] = src[1];
+          }
 #pragma unroll
-          for (int i = 0; i < RB; ++i) acc[i] = W::mfma(As[buf][kk + 1][16 * i + r], b1, acc[i]);
+          for (int i = 0; i < RB; ++i) acc[i] = W::mfma(a[i][0], b0, acc[i]);
+#pragma unroll
+          for (int i = 0; i < RB; ++i) acc[i] = W::mfma(a[i][1], b1, acc[i]);
         }
       }
     }
@@ -735,7 +760,7 @@ __device__ inline void wg_tile(const GemmUnit& u, const GemmItem* __restrict__ i
 template <typename T, int TAG>
 __global__ __launch_bounds__(256) void gemm_wg(const GemmUnit* __restrict__ units,
                                                const GemmItem* __restrict__ items) {
-  __shared__ T As[2][kWgKs][kWgTmp];
+  __shared__ __align__(16) T As[2][96][kWgPk];
   const GemmUnit u = units[blockIdx.x];
   switch (u.shape >> 3) {  // RB; the tile is (16 RB) x (16 CB), CB = shape & 7
     case 1: wg_tile<T, 1>(u, items, As); break;
