@@ -209,7 +209,7 @@ void Solver::grad_site(int k, std::vector<double>& g, double* norm) {
         bases[B_T] = grad_P_.p;
         bases[B_OUT] = grad_Q_.p;
         bases[B_XMIX] = grad_G_.p;
-        size_t esz[B_NBUF] = {8, 8, 8, 8, 8, 8, 8, 8};
+        size_t esz[B_NBUF] = {8, 8, 8, 8, 8, 8, 8, 8, 8};
         long sizes[B_NBUF] = {};
         sizes[B_PSI] = A.lay.size;
         sizes[B_ENVL] = envl.size;

@@ -1154,6 +1154,21 @@ __global__ void premix_kernel(double* __restrict__ out, const double* const* __r
   }
 }
 
+// out[out_off[g] + j] = sum_{i in [ptr[g], ptr[g+1])} coef[i] * srcs[i][j], j < nnz[g];
+// one workgroup per group, sources summed in order.
+__global__ void pairmix_kernel(double* __restrict__ out, const double* const* __restrict__ srcs,
+                               const int* __restrict__ ptr, const double* __restrict__ coef,
+                               const long* __restrict__ out_off, const int* __restrict__ nnz) {
+  const int g = blockIdx.x;
+  const int b = ptr[g], e = ptr[g + 1], n = nnz[g];
+  double* o = out + out_off[g];
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    double acc = 0.0;
+    for (int i = b; i < e; ++i) acc += coef[i] * srcs[i][j];
+    o[j] = acc;
+  }
+}
+
 __global__ void fill_kernel(double* x, long n, double v) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     x[i] = v;
@@ -1518,6 +1533,11 @@ void launch_premix(double* out, const double* const* srcs, const int* ptr, const
   if (n_out <= 0 || nnz <= 0) return;
   dim3 grid(grid_for(nnz, 256, 64), n_out);
   premix_kernel<<<grid, 256, 0, s>>>(out, srcs, ptr, coef, nnz);
+}
+
+void launch_pairmix(double* out, const double* const* srcs, const int* ptr, const double* coef, const long* out_off,
+                    const int* nnz, int n_groups, hipStream_t s) {
+  if (n_groups > 0) pairmix_kernel<<<n_groups, 256, 0, s>>>(out, srcs, ptr, coef, out_off, nnz);
 }
 
 void launch_fill(double* x, long n, double v, hipStream_t s) {

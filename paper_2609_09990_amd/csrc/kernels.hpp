@@ -87,6 +87,9 @@ void launch_premix(double* out, const double* const* srcs, const int* ptr, const
 // 16-byte aligned buffers).
 long launch_mfma_f64_peak(double* out, int n_blocks, int iters, hipStream_t s);
 void launch_stream_copy(const void* src, void* dst, long bytes, hipStream_t s);
+// Per group g: out[out_off[g] + j] = sum_{i in [ptr[g], ptr[g+1])} coef[i] * srcs[i][j], j < nnz[g].
+void launch_pairmix(double* out, const double* const* srcs, const int* ptr, const double* coef, const long* out_off,
+                    const int* nnz, int n_groups, hipStream_t s);
 void launch_fill(double* x, long n, double v, hipStream_t s);
 // desc per block (9 x int64): src_off, src_row_stride, src_col_stride, dst_off,
 // dst_row_stride, dst_col_stride, rows, cols, scale (bits of a double)

@@ -166,6 +166,32 @@ void Solver::run_premix(FactorSide& fs, const Env& env) {
   }
 }
 
+void Solver::run_pairmix(int k) {
+  const int ng = (int)pm_.out_off.size();
+  if (ng == 0) return;
+  pm_.mix.reserve(std::max<long>(pm_.size, 1) * sizeof(double));
+  std::vector<const double*>& srcs = pm_.h_srcs;
+  srcs.resize(pm_.src_off.size());
+  for (size_t i = 0; i < srcs.size(); ++i) {
+    const double* base = pm_.src_buf[i] == B_YMIX ? rf_.mix.as<double>() : right_[k + 2].buf.as<double>();
+    srcs[i] = base + pm_.src_off[i];
+  }
+  pm_.d_srcs.reserve(srcs.size() * sizeof(void*) + 8);
+  pm_.d_ptr.reserve(pm_.ptr.size() * sizeof(int) + 8);
+  pm_.d_coef.reserve(pm_.coef.size() * sizeof(double) + 8);
+  pm_.d_out_off.reserve(pm_.out_off.size() * sizeof(long) + 8);
+  pm_.d_nnz.reserve(pm_.nnz.size() * sizeof(int) + 8);
+  hip_check(hipMemcpyAsync(pm_.d_srcs.p, srcs.data(), srcs.size() * sizeof(void*), hipMemcpyHostToDevice, st), "pairmix srcs");
+  hip_check(hipMemcpyAsync(pm_.d_ptr.p, pm_.ptr.data(), pm_.ptr.size() * sizeof(int), hipMemcpyHostToDevice, st), "pairmix ptr");
+  hip_check(hipMemcpyAsync(pm_.d_coef.p, pm_.coef.data(), pm_.coef.size() * sizeof(double), hipMemcpyHostToDevice, st),
+            "pairmix coef");
+  hip_check(hipMemcpyAsync(pm_.d_out_off.p, pm_.out_off.data(), pm_.out_off.size() * sizeof(long), hipMemcpyHostToDevice, st),
+            "pairmix out");
+  hip_check(hipMemcpyAsync(pm_.d_nnz.p, pm_.nnz.data(), pm_.nnz.size() * sizeof(int), hipMemcpyHostToDevice, st), "pairmix nnz");
+  launch_pairmix(pm_.mix.as<double>(), pm_.d_srcs.as<const double*>(), pm_.d_ptr.as<int>(), pm_.d_coef.as<double>(),
+                 pm_.d_out_off.as<long>(), pm_.d_nnz.as<int>(), ng, st);
+}
+
 // One logical unit per output block; tiles are cut when the plan is resolved
 // (the tile shape depends on the kernel chosen for the precision).
 static void add_units(std::vector<PUnit>& units, int cbuf, long coff, int ldc, int M, int N, int ib,
@@ -453,7 +479,7 @@ void Solver::env_update_left(int k, const FactorSide& fs) {
   bases[B_T] = env_t_buf_.p;
   bases[B_XMIX] = fs.mix.p;
   bases[B_ENVL] = envk.buf.p;
-  size_t esz[B_NBUF] = {8, 8, 8, 8, 8, 8, 8, 8};
+  size_t esz[B_NBUF] = {8, 8, 8, 8, 8, 8, 8, 8, 8};
   long sizes[B_NBUF] = {};
   sizes[B_PSI] = A.lay.size;
   sizes[B_OUT] = out.size;
@@ -584,7 +610,7 @@ void Solver::env_update_right(int j, const FactorSide& fs) {
   bases[B_YMIX] = fs.mix.p;
   bases[B_ENVR] = envr.buf.p;
   bases[B_SITE2] = Bt.buf.p;
-  size_t esz[B_NBUF] = {8, 8, 8, 8, 8, 8, 8, 8};
+  size_t esz[B_NBUF] = {8, 8, 8, 8, 8, 8, 8, 8, 8};
   long sizes[B_NBUF] = {};
   sizes[B_OUT] = out.size;
   sizes[B_T] = usize;
@@ -639,6 +665,8 @@ void Solver::build_sigma_plan(int k) {
   }
   t_size_ = tsize;
   // phase B: gather items per output block of sigma
+  pm_ = PairMix();
+  pm_.ptr.push_back(0);
   phB_ = Phase();
   phB_.mode = GEMM_NT;
   phB_.wg = true;
@@ -679,7 +707,6 @@ void Solver::build_sigma_plan(int k) {
                                            rf_.fac[ur.f].alias ? B_ENVR : B_YMIX,
                                            rf_.fac[ur.f].off + ycls.blocks[yb].off, src.width,
                                            blk.mr, blk.mr, sc * wl * wr});
-                    phB_.flops += 2.0 * dst.ml * dst.blocks[ob].mr * blk.mr;
                   }
                 }
               }
@@ -695,10 +722,34 @@ void Solver::build_sigma_plan(int k) {
         if (x.aoff != y.aoff) return x.aoff < y.aoff;
         return x.boff < y.boff;
       });
-      int ib = (int)phB_.items.size();
-      phB_.items.insert(phB_.items.end(), v.begin(), v.end());
       const Slab& dst = P.slabs[so];
-      add_units(phB_.units, B_OUT, dst.off + dst.blocks[ob].col0, dst.width, dst.ml, dst.blocks[ob].mr, ib,
+      const int nb = dst.blocks[ob].mr;
+      int ib = (int)phB_.items.size();
+      // items with one A slice (adjacent after the sort) become one product with
+      // the weighted sum of their right blocks (N x K, row stride K)
+      for (size_t a = 0; a < v.size();) {
+        size_t b = a + 1;
+        while (b < v.size() && v[b].abuf == v[a].abuf && v[b].aoff == v[a].aoff && v[b].K == v[a].K &&
+               v[b].ldb == v[b].K && v[a].ldb == v[a].K)
+          ++b;
+        if (b - a == 1) {
+          phB_.items.push_back(v[a]);
+        } else {
+          for (size_t i = a; i < b; ++i) {
+            pm_.src_buf.push_back(v[i].bbuf);
+            pm_.src_off.push_back(v[i].boff);
+            pm_.coef.push_back(v[i].coef);
+          }
+          pm_.ptr.push_back((int)pm_.coef.size());
+          pm_.out_off.push_back(pm_.size);
+          pm_.nnz.push_back(nb * v[a].K);
+          phB_.items.push_back({v[a].abuf, v[a].aoff, B_YPAIR, pm_.size, v[a].lda, v[a].K, v[a].K, 1.0});
+          pm_.size += (long)nb * v[a].K;
+        }
+        phB_.flops += 2.0 * dst.ml * nb * v[a].K;
+        a = b;
+      }
+      add_units(phB_.units, B_OUT, dst.off + dst.blocks[ob].col0, dst.width, dst.ml, nb, ib,
                 (int)phB_.items.size(), 0);
     }
   if (opt_.verbose > 1) {

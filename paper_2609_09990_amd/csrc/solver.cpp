@@ -267,6 +267,7 @@ void Solver::prepare(int k) {
     c.key_r = bonds_at_build_r_;
     c.lf = std::move(lf_);
     c.rf = std::move(rf_);
+    c.pm = std::move(pm_);
     c.psi_lay = std::move(psi_lay_);
     c.phA = std::move(phA_);
     c.phB = std::move(phB_);
@@ -291,6 +292,7 @@ void Solver::prepare(int k) {
     StepPlan& c = hit->second;
     lf_ = std::move(c.lf);
     rf_ = std::move(c.rf);
+    pm_ = std::move(c.pm);
     psi_lay_ = std::move(c.psi_lay);
     phA_ = std::move(c.phA);
     phB_ = std::move(c.phB);
@@ -298,6 +300,7 @@ void Solver::prepare(int k) {
     plan_cache_.erase(hit);
     run_premix(lf_, left_[k]);
     run_premix(rf_, right_[k + 2]);
+    run_pairmix(k);
     st_.plan_hits++;
   } else {
     if (hit != plan_cache_.end()) plan_cache_.erase(hit);
@@ -306,6 +309,7 @@ void Solver::prepare(int k) {
     build_factor_side(rf_, false, k + 1);
     run_premix(rf_, right_[k + 2]);
     build_sigma_plan(k);
+    run_pairmix(k);
     for (int i = 0; i < 3; ++i) phA_.uploaded[i] = phB_.uploaded[i] = false;
   }
   plan_built_k_ = k;
@@ -355,7 +359,8 @@ void Solver::ensure_lowp(int prec) {
   Src src[] = {{B_ENVL, left_[k].buf.as<double>(), left_[k].size},
                {B_ENVR, right_[k + 2].buf.as<double>(), right_[k + 2].size},
                {B_XMIX, lf_.mix.as<double>(), lf_.premix_size},
-               {B_YMIX, rf_.mix.as<double>(), rf_.premix_size}};
+               {B_YMIX, rf_.mix.as<double>(), rf_.premix_size},
+               {B_YPAIR, pm_.mix.as<double>(), pm_.size}};
   size_t esz = prec == PREC_F32 ? 4 : 2;
   for (auto& s : src) {
     lowp_[s.id].reserve(std::max<long>(s.n, 1) * esz);
@@ -378,6 +383,7 @@ void Solver::sigma(int k, int prec, const double* psi, double* out) {
   sizes[B_T] = t_size_;
   sizes[B_XMIX] = lf_.premix_size;
   sizes[B_YMIX] = rf_.premix_size;
+  sizes[B_YPAIR] = pm_.size;
   sizes[B_ENVL] = left_[k].size;
   sizes[B_ENVR] = right_[k + 2].size;
   hipEvent_t e0, e1, e2, eg;
@@ -397,7 +403,8 @@ void Solver::sigma(int k, int prec, const double* psi, double* out) {
     bases[B_YMIX] = rf_.mix.p;
     bases[B_ENVL] = left_[k].buf.p;
     bases[B_ENVR] = right_[k + 2].buf.p;
-    size_t esz[B_NBUF] = {8, 8, 8, 8, 8, 8, 8, 8};
+    bases[B_YPAIR] = pm_.mix.p;
+    size_t esz[B_NBUF] = {8, 8, 8, 8, 8, 8, 8, 8, 8};
     launch_copy(psi_in_.as<double>(), psi, n, st);
     phA_.tag = 1 + 2 * kernel_tag_;
     phB_.tag = 2 + 2 * kernel_tag_;
@@ -414,7 +421,7 @@ void Solver::sigma(int k, int prec, const double* psi, double* out) {
     void* bases[B_NBUF] = {};
     for (int i = 0; i < B_NBUF; ++i) bases[i] = lowp_[i].p;
     size_t le = prec == PREC_F32 ? 4 : 2;
-    size_t esz[B_NBUF] = {le, 4, 4, le, le, le, le, le};
+    size_t esz[B_NBUF] = {le, 4, 4, le, le, le, le, le, le};
     if (prec == PREC_F32) launch_f64_to_f32(psi, lowp_[B_PSI].as<float>(), n, st);
     else launch_f64_to_bf16(psi, lowp_[B_PSI].as<uint16_t>(), n, st);
     (void)hipEventRecord(e0, st);

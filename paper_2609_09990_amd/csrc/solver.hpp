@@ -79,6 +79,7 @@ enum BufId : int {
   B_ENVL,      // left environment at cut k
   B_ENVR,      // right environment at cut k+2
   B_SITE2,     // second site tensor (right env update: B_j itself)
+  B_YPAIR,     // merged right-factor blocks of sigma phase B
   B_NBUF
 };
 
@@ -139,6 +140,22 @@ struct FactorSide {
   long premix_size = 0;
   DevMem mix;
   DevMem d_srcs, d_ptr, d_coef;
+  std::vector<const double*> h_srcs;
+};
+
+// Sigma phase B: items of one output block that share their A slice (the same
+// T_X columns) form one product with the coefficient-weighted sum of their
+// right-factor blocks, sum_j c_j T Y_j^T = T (sum_j c_j Y_j)^T.  The sums are
+// formed once per step, after the premix, into `mix`.
+struct PairMix {
+  std::vector<int> ptr;       // sources of group g: [ptr[g], ptr[g + 1])
+  std::vector<int> src_buf;   // B_YMIX or B_ENVR
+  std::vector<long> src_off;  // element offset of an N x K source block
+  std::vector<double> coef;
+  std::vector<long> out_off;  // per group: element offset in mix
+  std::vector<int> nnz;       // per group: N x K
+  long size = 0;
+  DevMem mix, d_srcs, d_ptr, d_coef, d_out_off, d_nnz;
   std::vector<const double*> h_srcs;
 };
 
@@ -226,6 +243,7 @@ class Solver {
   // step plan (cached for the prepared step)
   int plan_k_ = -1;
   FactorSide lf_, rf_;
+  PairMix pm_;
   TensorLayout psi_lay_;
   Phase phA_, phB_;
   long t_size_ = 0;
@@ -236,6 +254,7 @@ class Solver {
   struct StepPlan {
     std::vector<Sector> key_l, key_r;
     FactorSide lf, rf;
+    PairMix pm;
     TensorLayout psi_lay;
     Phase phA, phB;
     long t_size = 0;
@@ -267,6 +286,7 @@ class Solver {
   void make_env_layout(Env& e, int cut, const Bond& b);
   void build_factor_side(FactorSide& fs, bool left, int site);
   void run_premix(FactorSide& fs, const Env& env);
+  void run_pairmix(int k);
   void env_update_left(int k, const FactorSide& fs);
   void env_update_right(int j, const FactorSide& fs);
   void build_sigma_plan(int k);
