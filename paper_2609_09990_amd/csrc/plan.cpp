@@ -655,15 +655,18 @@ void Solver::build_sigma_plan(int k) {
       if (P.slab_of_left[eb.ri] < 0) continue;  // output rows would fall outside sigma
       toff[f][si] = tsize;
       trow[f][si] = eb.ri;
-      int ib = (int)phA_.items.size();
-      phA_.items.push_back({lf_.fac[f].alias ? B_ENVL : B_XMIX, lf_.fac[f].off + eb.off, B_PSI, sl.off,
-                            eb.mc, sl.width, eb.mc, 1.0});
-      add_units(phA_.units, B_T, tsize, sl.width, eb.mr, sl.width, ib, ib + 1, 0);
-      phA_.flops += 2.0 * eb.mr * eb.mc * sl.width;
       tsize += (long)eb.mr * sl.width;
     }
   }
   t_size_ = tsize;
+  // column blocks of each T_X slab that phase B reads; phase A computes only those
+  std::vector<std::vector<std::vector<char>>> tused(lf_.fac.size());
+  for (size_t f = 0; f < lf_.fac.size(); ++f)
+    if (!toff[f].empty()) {
+      tused[f].resize(P.slabs.size());
+      for (size_t si = 0; si < P.slabs.size(); ++si)
+        if (toff[f][si] >= 0) tused[f][si].assign(P.slabs[si].blocks.size(), 0);
+    }
   // phase B: gather items per output block of sigma
   pm_ = PairMix();
   pm_.ptr.push_back(0);
@@ -695,7 +698,8 @@ void Solver::build_sigma_plan(int k) {
                   int lo = trow[ul.f][si];
                   int so = P.slab_of_left[lo];
                   const Slab& dst = P.slabs[so];
-                  for (const auto& blk : src.blocks) {
+                  for (size_t sb = 0; sb < src.blocks.size(); ++sb) {
+                    const SlabBlock& blk = src.blocks[sb];
                     if (blk.phys != sin) continue;
                     int ro = bk2.find(bk2.sec[blk.ri].q + ycls.dq);
                     if (ro < 0) continue;
@@ -703,6 +707,7 @@ void Solver::build_sigma_plan(int k) {
                     if (yb < 0 || ycls.blocks[yb].ri != ro) continue;
                     int ob = dst.block_of(sout, ro);
                     if (ob < 0) continue;
+                    tused[ul.f][si][sb] = 1;
                     per[so][ob].push_back({B_T, toff[ul.f][si] + blk.col0,
                                            rf_.fac[ur.f].alias ? B_ENVR : B_YMIX,
                                            rf_.fac[ur.f].off + ycls.blocks[yb].off, src.width,
@@ -711,6 +716,32 @@ void Solver::build_sigma_plan(int k) {
                 }
               }
           }
+      }
+    }
+  }
+  // phase A: T_X = X psi over each run of consecutive column blocks that phase B reads
+  for (size_t f = 0; f < lf_.fac.size(); ++f) {
+    if (toff[f].empty()) continue;
+    const EnvClass& cls = envl.classes[lf_.fac[f].cls];
+    for (size_t si = 0; si < P.slabs.size(); ++si) {
+      if (toff[f][si] < 0) continue;
+      const Slab& sl = P.slabs[si];
+      const EnvBlock& eb = cls.blocks[cls.block_of_col[sl.li]];
+      const std::vector<char>& ub = tused[f][si];
+      for (size_t b0 = 0; b0 < ub.size();) {
+        if (!ub[b0]) {
+          ++b0;
+          continue;
+        }
+        size_t b1 = b0 + 1;
+        while (b1 < ub.size() && ub[b1] && sl.blocks[b1].col0 == sl.blocks[b1 - 1].col0 + sl.blocks[b1 - 1].mr) ++b1;
+        const int c0 = sl.blocks[b0].col0, w = sl.blocks[b1 - 1].col0 + sl.blocks[b1 - 1].mr - c0;
+        int ib = (int)phA_.items.size();
+        phA_.items.push_back({lf_.fac[f].alias ? B_ENVL : B_XMIX, lf_.fac[f].off + eb.off, B_PSI, sl.off + c0,
+                              eb.mc, sl.width, eb.mc, 1.0});
+        add_units(phA_.units, B_T, toff[f][si] + c0, sl.width, eb.mr, w, ib, ib + 1, 0);
+        phA_.flops += 2.0 * eb.mr * eb.mc * w;
+        b0 = b1;
       }
     }
   }
@@ -790,6 +821,17 @@ void Solver::build_sigma_plan(int k) {
       }
       fprintf(stderr, "phase B sharing: items %zu, distinct (block, A slice) %ld, distinct (block, B block) %ld, "
               "item A bytes %.3e, item B bytes %.3e\n", phB_.items.size(), ga, gb, abytes, bbytes);
+      // how much of T phase B reads: distinct (offset, K) column slices of T over all items
+      std::vector<std::pair<long, long>> sl;  // (offset, rows x K)
+      for (const PUnit& u : phB_.units)
+        for (int i = u.ib; i < u.ie; ++i)
+          if (phB_.items[i].abuf == B_T) sl.push_back({phB_.items[i].aoff, (long)u.M * phB_.items[i].K});
+      std::sort(sl.begin(), sl.end());
+      sl.erase(std::unique(sl.begin(), sl.end()), sl.end());
+      double tread = 0;
+      for (auto& x : sl) tread += x.second;
+      fprintf(stderr, "phase B reads %zu distinct T slices, %.3e of the %.3e doubles of T\n", sl.size(), tread,
+              (double)t_size_);
     }
     std::string dims;
     for (auto& s : bonds_[k].sec) dims += std::to_string(s.dim) + " ";
