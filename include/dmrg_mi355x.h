@@ -253,9 +253,10 @@ dmrg_status dmrg_measure_peaks(void* hip_stream, const void* src, void* dst, siz
 dmrg_status dmrg_set_precision(dmrg_solver* s, int precision);
 
 /* Profiling aid: the fp64 sigma kernels exist as two identical instantiations
- * (names gemm_f64_w32<mode, 1|2> and <mode, 3|4>); tag 0 (default) launches the
- * first pair, tag 1 the second, so a profiler can separate e.g. timed from
- * untimed launches.  No effect on results. */
+ * each (phase A: gemm_f64_w32<0, 1 | 3, ...>; phase B: gemm_wg<double, 2 | 4>);
+ * tag 0 (default) launches the first of each pair, tag 1 the second, so a
+ * profiler can separate e.g. timed from untimed launches.  No effect on
+ * results. */
 dmrg_status dmrg_set_kernel_tag(dmrg_solver* s, int tag);
 
 /* Run statistics (host doubles): [0] matvecs, [1] Davidson iterations,
