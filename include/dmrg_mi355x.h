@@ -270,10 +270,15 @@ dmrg_status dmrg_set_kernel_tag(dmrg_solver* s, int tag);
  * the environment updates it triggers), [19] step-preparation wall ms
  * (environments, factors, plans), [20] plan resolution and upload wall ms,
  * [21] Davidson wall ms, [22] step plans reused (a step's plan depends only on
- * its outer bonds and is kept per step; it is rebuilt when they change).
- * Times of [2]-[4], [10], [11], [16] are
- * HIP-event times on the solver stream and flops count unpadded block
- * products.  n: capacity of out. */
+ * its outer bonds and is kept per step; it is rebuilt when they change),
+ * [23] phase-A flops executed, [24] phase-B flops executed.
+ * Times of [2]-[4], [10], [11], [16] are HIP-event times on the solver stream
+ * and flops count unpadded block products.  The sigma flops [5], [12], [13]
+ * are algorithmic: every block product of the middle-cut factorisation (all
+ * columns of every T_X, every item).  The executed counts [23], [24] are
+ * lower: phase A skips T_X columns no item reads, and phase B merges items
+ * that share their T slice (sum_j c_j T Y_j^T = T (sum_j c_j Y_j)^T).
+ * n: capacity of out (up to 25 values are written). */
 dmrg_status dmrg_get_stats(const dmrg_solver* s, double* out, int n);
 
 const char* dmrg_last_error(void);

@@ -305,12 +305,13 @@ class Solver:
         return dh, dB, e
 
     def stats(self):
-        s = np.zeros(23)
-        _check(dmrg_get_stats(self.h, _ptr(s), 23))
+        s = np.zeros(25)
+        _check(dmrg_get_stats(self.h, _ptr(s), 25))
         keys = ["matvecs", "davidson_iters", "sigma_ms", "env_ms", "svd_ms", "sigma_flops", "tau",
                 "max_bond", "fallbacks", "converged", "sigma_a_ms", "sigma_b_ms", "sigma_a_flops",
                 "sigma_b_flops", "env_flops", "refinements", "sigma_b_gemm_ms", "grad_ms", "grad_flops",
-                "prepare_ms", "resolve_ms", "davidson_ms", "plan_hits"]
+                "prepare_ms", "resolve_ms", "davidson_ms", "plan_hits", "sigma_a_flops_exec",
+                "sigma_b_flops_exec"]
         return dict(zip(keys, s.tolist()))
 
     def __del__(self):

@@ -456,12 +456,13 @@ dmrg_status dmrg_get_stats(const dmrg_solver* s, double* out, int n) {
   return guard([&] {
     DMRG_REQUIRE(s && out, ST_EINVAL, "NULL argument");
     const Stats& t = s->s->stats();
-    double v[23] = {(double)t.matvecs, (double)t.davidson_iters, t.sigma_ms, t.env_ms, t.svd_ms,
+    double v[25] = {(double)t.matvecs, (double)t.davidson_iters, t.sigma_ms, t.env_ms, t.svd_ms,
                     t.sigma_flops, t.tau, (double)t.max_bond, (double)t.fallbacks, (double)t.converged,
                     t.sigma_a_ms, t.sigma_b_ms, t.sigma_a_flops, t.sigma_b_flops, t.env_flops,
                     (double)t.refinements, t.sigma_b_gemm_ms, t.grad_ms, t.grad_flops, t.prepare_ms,
-                    t.resolve_ms, t.davidson_ms, (double)t.plan_hits};
-    for (int i = 0; i < n && i < 23; ++i) out[i] = v[i];
+                    t.resolve_ms, t.davidson_ms, (double)t.plan_hits, t.sigma_a_flops_exec,
+                    t.sigma_b_flops_exec};
+    for (int i = 0; i < n && i < 25; ++i) out[i] = v[i];
   });
 }
 

@@ -639,6 +639,7 @@ void Solver::build_sigma_plan(int k) {
       for (auto& u : lf_.by_mid[b]) used[u.f] = 1;
   phA_ = Phase();
   phA_.mode = GEMM_NN;
+  phA_.flops_exec = 0;
   std::vector<std::vector<long>> toff(lf_.fac.size());
   std::vector<std::vector<int>> trow(lf_.fac.size());
   long tsize = 0;
@@ -656,6 +657,7 @@ void Solver::build_sigma_plan(int k) {
       toff[f][si] = tsize;
       trow[f][si] = eb.ri;
       tsize += (long)eb.mr * sl.width;
+      phA_.flops += 2.0 * eb.mr * eb.mc * sl.width;  // algorithmic: every T_X block
     }
   }
   t_size_ = tsize;
@@ -672,6 +674,7 @@ void Solver::build_sigma_plan(int k) {
   pm_.ptr.push_back(0);
   phB_ = Phase();
   phB_.mode = GEMM_NT;
+  phB_.flops_exec = 0;
   phB_.wg = true;
   std::vector<std::vector<std::vector<PItem>>> per(P.slabs.size());
   for (size_t si = 0; si < P.slabs.size(); ++si) per[si].resize(P.slabs[si].blocks.size());
@@ -740,7 +743,7 @@ void Solver::build_sigma_plan(int k) {
         phA_.items.push_back({lf_.fac[f].alias ? B_ENVL : B_XMIX, lf_.fac[f].off + eb.off, B_PSI, sl.off + c0,
                               eb.mc, sl.width, eb.mc, 1.0});
         add_units(phA_.units, B_T, toff[f][si] + c0, sl.width, eb.mr, w, ib, ib + 1, 0);
-        phA_.flops += 2.0 * eb.mr * eb.mc * w;
+        phA_.flops_exec += 2.0 * eb.mr * eb.mc * w;
         b0 = b1;
       }
     }
@@ -777,7 +780,8 @@ void Solver::build_sigma_plan(int k) {
           phB_.items.push_back({v[a].abuf, v[a].aoff, B_YPAIR, pm_.size, v[a].lda, v[a].K, v[a].K, 1.0});
           pm_.size += (long)nb * v[a].K;
         }
-        phB_.flops += 2.0 * dst.ml * nb * v[a].K;
+        for (size_t i = a; i < b; ++i) phB_.flops += 2.0 * dst.ml * nb * v[i].K;  // algorithmic: unmerged
+        phB_.flops_exec += 2.0 * dst.ml * nb * v[a].K;
         a = b;
       }
       add_units(phB_.units, B_OUT, dst.off + dst.blocks[ob].col0, dst.width, dst.ml, nb, ib,

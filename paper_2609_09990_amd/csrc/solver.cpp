@@ -444,6 +444,8 @@ void Solver::sigma(int k, int prec, const double* psi, double* out) {
   st_.sigma_b_gemm_ms += g;
   st_.sigma_a_flops += phA_.flops;
   st_.sigma_b_flops += phB_.flops;
+  st_.sigma_a_flops_exec += phA_.flops_exec < 0 ? phA_.flops : phA_.flops_exec;
+  st_.sigma_b_flops_exec += phB_.flops_exec < 0 ? phB_.flops : phB_.flops_exec;
   st_.sigma_ms += a + b;
   st_.sigma_flops += phA_.flops + phB_.flops;
   st_.matvecs++;

@@ -100,7 +100,8 @@ struct Phase {
   hipEvent_t gemm_done = nullptr;  // if set, recorded between the GEMM and the split-K reduction
   std::vector<PItem> items;
   std::vector<PUnit> units;
-  double flops = 0.0;  // useful (unpadded) flops
+  double flops = 0.0;       // algorithmic flops (see build_sigma_plan for sigma)
+  double flops_exec = -1;   // flops the launch executes, unpadded (-1: same as flops)
   // device copies per precision
   DevMem d_items[3], d_units[3];
   std::vector<GemmItem> h_items[3];  // host staging kept alive for async copies
@@ -165,6 +166,7 @@ struct Stats {
   double sigma_ms = 0, env_ms = 0, svd_ms = 0, davidson_other_ms = 0, premix_ms = 0;
   double sigma_flops = 0;
   double sigma_a_ms = 0, sigma_b_ms = 0, sigma_a_flops = 0, sigma_b_flops = 0, env_flops = 0;
+  double sigma_a_flops_exec = 0, sigma_b_flops_exec = 0;  // executed (merged / trimmed plan)
   double sigma_b_gemm_ms = 0;  // phase-B GEMM kernel alone (without the split-K reduction)
   double tau = 0;
   int max_bond = 0;

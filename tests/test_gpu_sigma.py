@@ -157,3 +157,18 @@ def test_precision_form_full_bond_equals_fci_cas8(prec):
     assert abs(e[0] - ref) <= 1e-10
     assert abs(sol.energy()[0] - ref) <= 1e-10
     assert st["refinements"] > 0
+
+
+def test_executed_flops_at_most_algorithmic():
+    """The merged / trimmed plan executes no more block-product flops than the
+    factorisation's algorithmic count, and the sigma it computes is unchanged
+    (parity above); the two counts are reported separately."""
+    _torch()
+    import paper_2609_09990_amd as pk
+    h, B, e0 = synth.make_hamiltonian(8, 32, 0)
+    sol = pk.Solver(pk.Problem(h, B, 4, 4, e0), M=64, tol=1e-9)
+    sol.sweep(1)
+    st = sol.stats()
+    assert 0 < st["sigma_a_flops_exec"] <= st["sigma_a_flops"]
+    assert 0 < st["sigma_b_flops_exec"] <= st["sigma_b_flops"]
+    assert abs(st["sigma_flops"] - st["sigma_a_flops"] - st["sigma_b_flops"]) <= 1e-6 * st["sigma_flops"]
