@@ -677,7 +677,13 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
       } else {
         ++stall;
       }
-      if (lo_done || stall >= 3) {
+      // the low-precision residual means nothing below the rounding floor of its
+      // sigma, ~10 u ||H_eff|| (u: fp32 2^-24, bf16 2^-8; ||H_eff|| >= |theta|)
+      double tmax = 0;
+      for (int i = 0; i < nr; ++i) tmax = std::max(tmax, std::fabs(evals[i]));
+      const double u_lo = prec == PREC_F32 ? 5.96e-8 : 3.91e-3;
+      const bool at_floor = rmax <= 10.0 * u_lo * tmax;
+      if (lo_done || stall >= 3 || at_floor) {
         // switch to fp64 for the rest of the step: exact sigma of the Ritz vectors,
         // restart from them; every later product is fp64, so the step converges on
         // an exact residual like the plain form (defect correction of the

@@ -172,3 +172,26 @@ def test_executed_flops_at_most_algorithmic():
     assert 0 < st["sigma_a_flops_exec"] <= st["sigma_a_flops"]
     assert 0 < st["sigma_b_flops_exec"] <= st["sigma_b_flops"]
     assert abs(st["sigma_flops"] - st["sigma_a_flops"] - st["sigma_b_flops"]) <= 1e-6 * st["sigma_flops"]
+
+
+def test_cached_step_plan_gives_the_same_sigma():
+    """A revisited step reuses its cached plan (factor premix and merged right
+    blocks rerun against the current environments): the sigma is bitwise equal
+    to the one computed from the freshly built plan, and equal to the oracle's."""
+    torch, pk, h, B, prob, sol, mps = _setup(8, 4, 4, 16, 40)
+    k = 3
+    size = sol.prepare(k)
+    psi = synth.random_twosite(mps["bonds"], k, seed=21)
+    x = torch.from_numpy(psi).cuda()
+    y1, y2 = torch.zeros_like(x), torch.zeros_like(x)
+    sol.sigma(k, x, y1)
+    hits0 = sol.stats()["plan_hits"]
+    sol.prepare(k + 1)
+    assert sol.prepare(k) == size
+    sol.sigma(k, x, y2)
+    torch.cuda.synchronize()
+    assert sol.stats()["plan_hits"] == hits0 + 1
+    assert torch.equal(y1, y2)
+    ref = embed.sigma_twosite(h, B, mps, k, psi, 4, 4)
+    err = np.linalg.norm(y2.cpu().numpy() - ref) / np.linalg.norm(ref)
+    assert err <= 1e-12, err
