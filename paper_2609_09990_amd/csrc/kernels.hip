@@ -1115,30 +1115,32 @@ __global__ __launch_bounds__(256) void gemm_bf16_w32(const GemmUnit* __restrict_
 }
 
 __global__ void splitk_reduce_f32(const SplitTile* __restrict__ tiles, const float* __restrict__ slots) {
+  // workgroup (tile, chunk of 256 elements): one element per thread
   const SplitTile t = tiles[blockIdx.x];
-  float* C = (float*)t.C;
-  for (int e = threadIdx.x; e < t.tm * t.tn; e += blockDim.x) {
-    int tr = e / t.tn, tc = e - tr * t.tn;
-    int gm = t.m0 + tr, gn = t.n0 + tc;
-    if (gm >= t.M || gn >= t.N) continue;
-    float acc = 0.f;
-    for (int s = 0; s < t.ns; ++s) acc += slots[t.s0 + (long)s * t.tm * t.tn + e];
-    C[(long)gm * t.ldc + gn] = acc;
-  }
+  const int e = blockIdx.y * blockDim.x + threadIdx.x;
+  if (e >= t.tm * t.tn) return;
+  const int tr = e / t.tn, tc = e - tr * t.tn;
+  const int gm = t.m0 + tr, gn = t.n0 + tc;
+  if (gm >= t.M || gn >= t.N) return;
+  float acc = 0.f;
+  const long step = (long)t.tm * t.tn;
+  for (int s = 0; s < t.ns; ++s) acc += slots[t.s0 + s * step + e];
+  ((float*)t.C)[(long)gm * t.ldc + gn] = acc;
 }
 
 // Split-K reduction: out tile += nothing; out tile = sum of its partial slots in order.
 __global__ void splitk_reduce(const SplitTile* __restrict__ tiles, const double* __restrict__ slots) {
+  // workgroup (tile, chunk of 256 elements): one element per thread
   const SplitTile t = tiles[blockIdx.x];
-  double* C = (double*)t.C;
-  for (int e = threadIdx.x; e < t.tm * t.tn; e += blockDim.x) {
-    int tr = e / t.tn, tc = e - tr * t.tn;
-    int gm = t.m0 + tr, gn = t.n0 + tc;
-    if (gm >= t.M || gn >= t.N) continue;
-    double acc = 0.0;
-    for (int s = 0; s < t.ns; ++s) acc += slots[t.s0 + (long)s * t.tm * t.tn + e];
-    C[(long)gm * t.ldc + gn] = acc;
-  }
+  const int e = blockIdx.y * blockDim.x + threadIdx.x;
+  if (e >= t.tm * t.tn) return;
+  const int tr = e / t.tn, tc = e - tr * t.tn;
+  const int gm = t.m0 + tr, gn = t.n0 + tc;
+  if (gm >= t.M || gn >= t.N) return;
+  double acc = 0.0;
+  const long step = (long)t.tm * t.tn;
+  for (int s = 0; s < t.ns; ++s) acc += slots[t.s0 + s * step + e];
+  ((double*)t.C)[(long)gm * t.ldc + gn] = acc;
 }
 
 __global__ void premix_kernel(double* __restrict__ out, const double* const* __restrict__ srcs,
@@ -1470,8 +1472,11 @@ void launch_gemm_wg(int prec, int tag, const GemmUnit* units, int n_units, const
   }
 }
 
+// tiles are at most 96 x 64 = 24 chunks of 256 elements
+constexpr int kReduceChunks = 24;
+
 void launch_splitk_reduce(const SplitTile* tiles, int n, const double* slots, hipStream_t s) {
-  if (n > 0) splitk_reduce<<<n, 256, 0, s>>>(tiles, slots);
+  if (n > 0) splitk_reduce<<<dim3(n, kReduceChunks), 256, 0, s>>>(tiles, slots);
 }
 
 void launch_gemm_w32_f32(int mode, bool buf, const GemmUnit* units, int n_units, const GemmItem* items,
@@ -1504,7 +1509,7 @@ void launch_gemm_w32_bf16(int mode, bool a_f32, bool buf, const GemmUnit* units,
 }
 
 void launch_splitk_reduce_f32(const SplitTile* tiles, int n, const float* slots, hipStream_t s) {
-  if (n > 0) splitk_reduce_f32<<<n, 256, 0, s>>>(tiles, slots);
+  if (n > 0) splitk_reduce_f32<<<dim3(n, kReduceChunks), 256, 0, s>>>(tiles, slots);
 }
 
 void launch_gemm(int prec, int mode, const GemmUnit* units, int n_units, const GemmItem* items,

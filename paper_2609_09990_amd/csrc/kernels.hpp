@@ -55,9 +55,9 @@ inline bool buffer_reach_ok(int mode, int M, int N, int K, int lda, int ldb, siz
   return ra < lim && rb < lim;
 }
 
-// Output tile (rows m0.., cols n0.. of an M x N block, tm x tn) = sum of ns
-// partial tiles (row-major tm x tn each) stored one after another from element
-// s0 of the slot buffer, summed in order.
+// Output tile (rows m0.., cols n0.. of an M x N block, tm x tn <= 96 x 64
+// elements) = sum of ns partial tiles (row-major tm x tn each) stored one after
+// another from element s0 of the slot buffer, summed in order.
 struct SplitTile {
   void* C;
   long s0;

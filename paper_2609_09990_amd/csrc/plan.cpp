@@ -318,6 +318,8 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
       const int nc = (int)cuts.size();
       const long first_tile = (long)tiles.size();
       for (const TileShape& t : ts) {
+        // the reduction covers tiles of up to 96 x 64 elements
+        DMRG_REQUIRE(t.tm * t.tn <= 96 * 64, ST_EINVAL, "split-K tile larger than the reduction covers");
         tiles.push_back({C, n_slot_elems, u.ldc, u.M, u.N, t.m0, t.n0, nc, t.tm, t.tn});
         n_slot_elems += (long)nc * t.tm * t.tn;
       }
