@@ -1008,6 +1008,10 @@ void Solver::svd_step(int k, bool l2r, int nr, std::vector<DevMem>& next_guess, 
   std::vector<GemmUnit> units;
   std::vector<int64_t> cdesc;
   SiteTensor fixed;  // the orthonormal side
+  // it takes over the allocation of the tensor it replaces (no longer read from
+  // here on): a stable address keeps the cached environment-update plan resolved
+  // and saves an allocation and a free per step
+  fixed.buf = std::move(mps_[l2r ? k : k + 1].buf);
   TensorLayout clay;  // center layout
   if (l2r) {
     fixed.lay = make_tensor_layout(bonds_[k], nb, site_phys_qn());
