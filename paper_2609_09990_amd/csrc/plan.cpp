@@ -228,6 +228,13 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
     return;
   }
   const auto tr0 = std::chrono::steady_clock::now();
+  if (opt_.verbose > 2) {
+    std::string moved;
+    for (int b = 0; b < B_NBUF; ++b)
+      if (ph.uploaded[slot] && ph.last_bases[slot][b] != bases[b]) moved += " " + std::to_string(b);
+    fprintf(stderr, "resolve: mode %d, %zu items, %s%s\n", ph.mode, ph.items.size(),
+            ph.uploaded[slot] ? "moved buffers" : "first use", moved.c_str());
+  }
   validate_phase(ph, sizes);
   for (int b = 0; b < B_NBUF; ++b) ph.last_bases[slot][b] = bases[b];
   ph.uploaded[slot] = true;
