@@ -297,10 +297,10 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
     double work = 0;
     for (const PUnit& u : ph.units)
       for (int i = u.ib; i < u.ie; ++i) work += ((u.M + 31) / 32) * ((u.N + 31) / 32) * ((ph.items[i].K + 3) / 4);
-    // about 16384 one-wave units; workgroup units are cut finer (32768, measured
+    // about 16384 one-wave units; workgroup units are cut finer (65536, measured
     // best for sigma phase B at CAS(20,20), M = 1024: smaller pieces of the
     // largest blocks spread over more CUs, against more split-K partial tiles)
-    const double chunk = std::max(DMRG_SPLIT_MIN, work / (use_wg ? 32768.0 : 16384.0));
+    const double chunk = std::max(DMRG_SPLIT_MIN, work / (use_wg ? 65536.0 : 16384.0));
     std::vector<std::pair<int, int>> cuts;
     for (const PUnit& u : ph.units) {
       char* C = (char*)bases[u.cbuf] + u.coff * esz[u.cbuf];
