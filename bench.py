@@ -28,7 +28,7 @@ PEAK_FP64 = 78.6  # TFLOP/s, MI355X dense FP64 matrix
 # HBM bytes per launch of the dominant kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
 # runs (profiles/sigma_phaseB_wg_merged_cas20_m1024_fp64.md), scaled by the same counters on a
 # plain copy (fetch x2.0, write x1.0); set to None whenever that kernel changes.
-TRAFFIC = None
+TRAFFIC = 2.49e10
 
 
 def cpu_baseline(pk, torch):
