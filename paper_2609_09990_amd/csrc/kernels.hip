@@ -544,8 +544,9 @@ __global__ __launch_bounds__(256) void gemm_f64_w32(const GemmUnit* __restrict__
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   // NN launches (sigma phase A: a factor block feeds every column tile of its
   // unit) give each XCD a contiguous range of units, so a block is fetched into
-  // one XCD's L2; workgroups are dispatched to the 8 XCDs round-robin.  The NT
-  // launch (phase B) keeps the plain order, which measured faster.
+  // one XCD's L2; workgroups are dispatched to the 8 XCDs round-robin.  NT
+  // launches keep the plain order, which measured faster for sigma's long-K
+  // products when they ran on this kernel.
   int wg = blockIdx.x;
   if constexpr (MODE == GEMM_NN) {
     const int nb = gridDim.x, q = nb >> 3, rem = nb & 7, x = wg & 7;
