@@ -392,7 +392,9 @@ void Solver::env_update_left(int k, const FactorSide& fs) {
   const Env& envk = left_[k];
   const SiteTensor& A = mps_[k];
   Env& out = left_[k + 1];
+  const auto te0 = std::chrono::steady_clock::now();
   make_env_layout(out, k + 1, bonds_[k + 1]);
+  const auto te1 = std::chrono::steady_clock::now();
   // the plan depends on bonds k, k+1 and the MPO only: reuse it while they hold
   EnvPlan& ep = env_plans_[{k, 0}];
   const bool hit = same_sectors(ep.key_a, bonds_[k].sec) && same_sectors(ep.key_b, bonds_[k + 1].sec);
@@ -495,11 +497,21 @@ void Solver::env_update_left(int k, const FactorSide& fs) {
   sizes[B_T] = zsize;
   sizes[B_XMIX] = fs.premix_size;
   sizes[B_ENVL] = envk.size;
+  const auto te2 = std::chrono::steady_clock::now();
   run_phase(pa, PREC_F64, bases, esz, sizes);
   run_phase(pb, PREC_F64, bases, esz, sizes);
+  const auto te3 = std::chrono::steady_clock::now();
   st_.env_flops += pa.flops + pb.flops;
   hip_check(hipStreamSynchronize(st), "env update");
   out.valid = true;
+  if (opt_.verbose > 2) {
+    auto ms = [](std::chrono::steady_clock::time_point x, std::chrono::steady_clock::time_point y) {
+      return std::chrono::duration<double, std::milli>(y - x).count();
+    };
+    fprintf(stderr, "env left k=%d: layout %.2f ms, plan %.2f ms (%s), launch %.2f ms, GPU wait %.2f ms\n", k,
+            ms(te0, te1), ms(te1, te2), hit ? "cached" : "built", ms(te2, te3),
+            ms(te3, std::chrono::steady_clock::now()));
+  }
 }
 
 // R_j[beta] = sum_{(op,Y)} s sum_{ss'} op[s][s'] B_s Y B_{s'}^T
@@ -509,7 +521,9 @@ void Solver::env_update_right(int j, const FactorSide& fs) {
   const Env& envr = right_[j + 1];
   const SiteTensor& Bt = mps_[j];
   Env& out = right_[j];
+  const auto te0 = std::chrono::steady_clock::now();
   make_env_layout(out, j, bonds_[j]);
+  const auto te1 = std::chrono::steady_clock::now();
   EnvPlan& ep = env_plans_[{j, 1}];
   const bool hit = same_sectors(ep.key_a, bonds_[j].sec) && same_sectors(ep.key_b, bonds_[j + 1].sec);
   if (!hit) {
@@ -626,11 +640,21 @@ void Solver::env_update_right(int j, const FactorSide& fs) {
   sizes[B_YMIX] = fs.premix_size;
   sizes[B_ENVR] = envr.size;
   sizes[B_SITE2] = Bt.lay.size;
+  const auto te2 = std::chrono::steady_clock::now();
   run_phase(pa, PREC_F64, bases, esz, sizes);
   run_phase(pb, PREC_F64, bases, esz, sizes);
+  const auto te3 = std::chrono::steady_clock::now();
   st_.env_flops += pa.flops + pb.flops;
   hip_check(hipStreamSynchronize(st), "env update");
   out.valid = true;
+  if (opt_.verbose > 2) {
+    auto ms = [](std::chrono::steady_clock::time_point x, std::chrono::steady_clock::time_point y) {
+      return std::chrono::duration<double, std::milli>(y - x).count();
+    };
+    fprintf(stderr, "env right j=%d: layout %.2f ms, plan %.2f ms (%s), launch %.2f ms, GPU wait %.2f ms\n", j,
+            ms(te0, te1), ms(te1, te2), hit ? "cached" : "built", ms(te2, te3),
+            ms(te3, std::chrono::steady_clock::now()));
+  }
 }
 
 void Solver::build_sigma_plan(int k) {
