@@ -112,6 +112,12 @@ Solver::Solver(const Problem* p, const Options& o, hipStream_t s) : prob_(p), op
 }
 
 Solver::~Solver() {
+  for (int i = 0; i < kAuxStreams; ++i) {
+    if (aux_rb_[i]) rocblas_destroy_handle(aux_rb_[i]);
+    if (aux_st_[i]) (void)hipStreamDestroy(aux_st_[i]);
+  }
+  for (hipEvent_t& e : aux_ev_)
+    if (e) (void)hipEventDestroy(e);
   if (rb_) rocblas_destroy_handle(rb_);
 }
 
@@ -917,14 +923,36 @@ void Solver::svd_step(int k, bool l2r, int nr, std::vector<DevMem>& next_guess, 
     }
     gemm_once(l2r ? GEMM_TN : GEMM_NT, items, units);
   }
-  for (auto& bk_ : buckets) {
-    int nbk = bk_.first;
-    int first = bk_.second[0];
-    rocblas_status rs = rocsolver_dsyevd_strided_batched(
-        rb_, rocblas_evect_original, rocblas_fill_upper, nbk, gram.as<double>() + goff[first], nbk,
-        (rocblas_stride)nbk * nbk, evals.as<double>() + eoff[first], nbk, evals.as<double>() + etot + eoff[first],
-        nbk, info.as<rocblas_int>(), (rocblas_int)bk_.second.size());
-    if (rs != rocblas_status_success) throw Error(ST_EHIP, "rocsolver_dsyevd_strided_batched failed");
+  // one bucket per auxiliary stream, joined back into the solver stream
+  if (!aux_st_[0]) {
+    for (int i = 0; i < kAuxStreams; ++i) {
+      hip_check(hipStreamCreateWithFlags(&aux_st_[i], hipStreamNonBlocking), "aux stream");
+      if (rocblas_create_handle(&aux_rb_[i]) != rocblas_status_success) throw Error(ST_EHIP, "rocblas handle");
+      rocblas_set_stream(aux_rb_[i], aux_st_[i]);
+    }
+    for (hipEvent_t& e : aux_ev_) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "aux event");
+  }
+  hip_check(hipEventRecord(aux_ev_[kAuxStreams], st), "eigensolve fork");
+  for (int i = 0; i < kAuxStreams; ++i) hip_check(hipStreamWaitEvent(aux_st_[i], aux_ev_[kAuxStreams], 0), "fork");
+  {
+    int bi = 0;
+    long info_off = 0;
+    for (auto& bk_ : buckets) {
+      int nbk = bk_.first;
+      int first = bk_.second[0];
+      rocblas_status rs = rocsolver_dsyevd_strided_batched(
+          aux_rb_[bi % kAuxStreams], rocblas_evect_original, rocblas_fill_upper, nbk, gram.as<double>() + goff[first],
+          nbk, (rocblas_stride)nbk * nbk, evals.as<double>() + eoff[first], nbk,
+          evals.as<double>() + etot + eoff[first], nbk, info.as<rocblas_int>() + info_off,
+          (rocblas_int)bk_.second.size());
+      if (rs != rocblas_status_success) throw Error(ST_EHIP, "rocsolver_dsyevd_strided_batched failed");
+      info_off += (long)bk_.second.size();
+      ++bi;
+    }
+  }
+  for (int i = 0; i < kAuxStreams; ++i) {
+    hip_check(hipEventRecord(aux_ev_[i], aux_st_[i]), "join");
+    hip_check(hipStreamWaitEvent(st, aux_ev_[i], 0), "join");
   }
   std::vector<double> E(etot);
   hip_check(hipMemcpyAsync(E.data(), evals.p, etot * 8, hipMemcpyDeviceToHost, st), "eigenvalues");

@@ -235,6 +235,12 @@ class Solver {
   Options opt_;
   hipStream_t st;
   rocblas_handle rb_ = nullptr;
+  // the truncation's batched eigensolves run one size bucket per stream (each
+  // bucket is a latency-bound chain of small kernels); default priority
+  static constexpr int kAuxStreams = 4;
+  hipStream_t aux_st_[kAuxStreams] = {};
+  rocblas_handle aux_rb_[kAuxStreams] = {};
+  hipEvent_t aux_ev_[kAuxStreams + 1] = {};
   int L_;
   std::vector<Bond> bonds_;
   std::vector<SiteTensor> mps_;
