@@ -16,6 +16,16 @@ Contents (plain, slow, fp64, written from the definitions):
               P^T H P psi (the definition of H_eff psi for a given MPS basis).
 * ``mlp``   - fp64 NumPy 3-layer MLP forward/backward and Adam (reference for
               the preconditioner network kernels).
+* ``mpo``   - the oracle's own MPO of H, built generically from the list of
+              normal-ordered second-quantised terms (an automaton: each term's
+              left string is carried until a switch site, its right string
+              after it); pinned by dense contraction against ``fock``.
+* ``blocks``- block-sparse environments on that MPO, the two-site sigma (whole
+              or chosen output blocks, with its own flop count) and the H_eff
+              diagonal; pinned against the projected FCI sigma of ``embed``.
+              It runs at production shape (CAS(20,20), M = 1024).
+* ``truncate`` - per-sector SVD truncation with the global sort, the cluster
+              rule, cut_rtol and tau; state averaging by concatenation.
 
 Every function's pin (what it is checked against other than itself) is listed
 in its docstring; the pins live in ``tests/test_oracle_*.py``.
