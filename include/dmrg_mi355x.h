@@ -234,6 +234,20 @@ dmrg_status dmrg_get_env(dmrg_solver* s, int cut, int side, double* host, int64_
 dmrg_status dmrg_block_gemm(int precision, int mode, int M, int N, int K, const void* A, int lda,
                             const void* B, int ldb, void* C, int ldc, double coef, void* hip_stream);
 
+/* Allocation-free dmrg_block_gemm, for callers that cannot allocate device
+ * memory (work under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments and result as dmrg_block_gemm; the tile
+ * and item descriptors live in a fixed device array inside the library
+ * (256 KiB per device, held until the process ends) instead of memory allocated
+ * per call, so the call makes no hipMalloc / hipFree and no host-to-device copy.
+ * Limit: the M x N output must fit 4096 tiles of 64 x 64 (e.g. M, N <= 4096),
+ * else DMRG_EINVAL.  Stream-ordered: it returns once the work is enqueued on
+ * hip_stream (dmrg_block_gemm synchronises).  Every call on one device shares
+ * that device's descriptor array: calls that overlap on one device (other
+ * streams or threads) race; calls in order on one stream do not. */
+dmrg_status dmrg_block_gemm_noalloc(int precision, int mode, int M, int N, int K, const void* A, int lda,
+                                    const void* B, int ldb, void* C, int ldc, double coef, void* hip_stream);
+
 /* Device ceilings for roofline reports, measured on the current device: the
  * fp64 MFMA rate of a register-only loop of v_mfma_f64_16x16x4 (four
  * independent accumulators per wave, 8 waves per SIMD) and the bandwidth of a

@@ -12,6 +12,7 @@ from ._lib import (  # noqa: F401
     Problem,
     Solver,
     dmrg_block_gemm,
+    dmrg_block_gemm_noalloc,
     dmrg_measure_peaks,
     measure_peaks,
     dmrg_diag,

@@ -53,6 +53,7 @@ dmrg_step = _decl("dmrg_step", [_p, _i, _i, _p, C.POINTER(_d)])
 dmrg_set_kernel_tag = _decl("dmrg_set_kernel_tag", [_p, _i])
 dmrg_get_stats = _decl("dmrg_get_stats", [_p, _p, _i])
 dmrg_block_gemm = _decl("dmrg_block_gemm", [_i, _i, _i, _i, _i, _p, _i, _p, _i, _p, _i, _d, _p])
+dmrg_block_gemm_noalloc = _decl("dmrg_block_gemm_noalloc", [_i, _i, _i, _i, _i, _p, _i, _p, _i, _p, _i, _d, _p])
 dmrg_measure_peaks = _decl("dmrg_measure_peaks", [_p, _p, _p, C.c_size_t, _p, _p])
 dmrg_get_env = _decl("dmrg_get_env", [_p, _i, _i, _p, _i64, C.POINTER(_i64)])
 dmrg_grad = _decl("dmrg_grad", [_p, _p, _p, _p, _p])

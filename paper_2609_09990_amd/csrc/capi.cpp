@@ -5,6 +5,7 @@
 #include <string>
 
 #include "../../include/dmrg_mi355x.h"
+#include "capi_guard.hpp"
 #include "mlp.hpp"
 #include "solver.hpp"
 
@@ -21,31 +22,16 @@ struct dmrg_mlp {
   MLP* m = nullptr;
 };
 
-namespace {
-thread_local std::string g_err;
-
-template <class F>
-dmrg_status guard(F&& f) {
-  try {
-    g_err.clear();
-    f();
-    return DMRG_OK;
-  } catch (const Error& e) {
-    g_err = e.what();
-    return (dmrg_status)e.code;
-  } catch (const std::bad_alloc&) {
-    g_err = "host allocation failed";
-    return DMRG_ENOMEM;
-  } catch (const std::exception& e) {
-    g_err = e.what();
-    return DMRG_EINVAL;
-  }
+namespace dmrg {
+std::string& last_error_slot() {
+  thread_local std::string msg;
+  return msg;
 }
-}  // namespace
+}  // namespace dmrg
 
 extern "C" {
 
-const char* dmrg_last_error(void) { return g_err.c_str(); }
+const char* dmrg_last_error(void) { return last_error_slot().c_str(); }
 
 void dmrg_options_default(dmrg_options* o) {
   if (!o) return;
@@ -253,7 +239,7 @@ dmrg_status dmrg_sweep(dmrg_solver* s, int n_sweeps, double* energies, double* t
     if (tau) *tau = t;
   });
   if (st == DMRG_OK && s && !s->s->last_converged()) {
-    g_err = "Davidson did not reach the tolerance in at least one step";
+    last_error_slot() = "Davidson did not reach the tolerance in at least one step";
     return DMRG_ENOCONV;
   }
   return st;
@@ -269,7 +255,7 @@ dmrg_status dmrg_step(dmrg_solver* s, int k, int direction, double* energies, do
     if (tau) *tau = t;
   });
   if (st == DMRG_OK && s && !s->s->last_converged()) {
-    g_err = "Davidson did not reach the tolerance";
+    last_error_slot() = "Davidson did not reach the tolerance";
     return DMRG_ENOCONV;
   }
   return st;
