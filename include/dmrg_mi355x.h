@@ -112,35 +112,80 @@ dmrg_status dmrg_set_mps(dmrg_solver* s, const int* n_sec, const int* sec, const
 /* Current bond tables: n_sec[0..n_orb] and up to cap sector triples. */
 dmrg_status dmrg_get_bonds(const dmrg_solver* s, int* n_sec, int* sec, int cap);
 
+/* The current MPS, the forward result of the DMRG node (Sec. II.C: integrals
+ * to the converged MPS), in the layout dmrg_set_mps takes: n_sec[0..n_orb]
+ * (always written), the concatenated sector triples into sec (when not NULL;
+ * sec_cap sectors must hold them all, else DMRG_EINVAL), and every site tensor
+ * concatenated in slab layout into data (host, when not NULL; data_cap
+ * doubles must hold them all, else DMRG_EINVAL).  *data_size receives the
+ * number of doubles; call with sec = data = NULL to size the buffers.  After
+ * a step or sweep the centre tensor of root 0 sits on the site the last step
+ * moved to; the other sites are orthonormal. */
+dmrg_status dmrg_export_mps(dmrg_solver* s, int* n_sec, int* sec, int sec_cap, double* data, int64_t data_cap,
+                            int64_t* data_size);
+
 /* Environments and plan for the two-site step on sites (k, k+1) of the current
- * MPS (any gauge); *n receives the two-site vector length. */
+ * MPS (any gauge): the left block, the two sites and the right block of the
+ * decimation step (Fig. 2, Sec. II.H), contracted against the MPO.  *n
+ * receives the two-site vector length.  Builds missing environments (their
+ * update is the MPO contraction of Sec. II.H) and the sigma plan; host
+ * planning plus GPU work, synchronises the stream. */
 dmrg_status dmrg_prepare(dmrg_solver* s, int k, int64_t* n);
 
-/* sigma = H_eff psi for the prepared step k (the effective Hamiltonian excludes
- * e_core).  psi, sigma: device arrays of the two-site length, slab layout.
+/* sigma = H_eff psi for step k: the matrix-free two-site effective Hamiltonian
+ * against the MPO (Sec. II.H, Fig. 2), never formed densely; the two-electron
+ * part enters through the Cholesky vectors (Sec. II.A).  The effective
+ * Hamiltonian excludes e_core.  psi, sigma: device arrays of n doubles, the
+ * two-site slab layout of step k (n must equal the length dmrg_prepare
+ * returns, else DMRG_EINVAL; step k is prepared first when it is not).
  * precision: DMRG_FP64 (fp64 MFMA), DMRG_FP32 (fp32 MFMA) or DMRG_BF16 (bf16
  * inputs, fp32 accumulation); the output is always fp64.  If flops is not NULL
- * it receives the useful (unpadded) floating-point operation count. */
-dmrg_status dmrg_sigma(dmrg_solver* s, int k, int precision, const double* psi, double* sigma,
+ * it receives the floating-point operations the launches execute (unpadded
+ * block products).  Stream-ordered; the call waits for the kernels to time
+ * them. */
+dmrg_status dmrg_sigma(dmrg_solver* s, int k, int precision, int64_t n, const double* psi, double* sigma,
                        double* flops);
 
-/* Diagonal of H_eff of the prepared step k into a device array. */
-dmrg_status dmrg_diag(dmrg_solver* s, int k, double* diag);
+/* Diagonal of H_eff of step k (the Jacobi / diagonal member of the two-site
+ * Davidson's preconditioner family, Sec. III) into a device array of n doubles
+ * (n as for dmrg_sigma).  Synchronises the device. */
+dmrg_status dmrg_diag(dmrg_solver* s, int k, int64_t n, double* diag);
 
-/* Two-site sweeps (left-to-right then right-to-left, (n_orb-1) steps each).
+/* Two-site sweeps (Sec. II.H, Fig. 2: at every bond a matrix-free Davidson
+ * solve of H_eff, then SVD decimation to M keeping chi_k states and discarding
+ * tau): left-to-right then right-to-left, (n_orb-1) steps each.
  * energies[n_states] (host): final Davidson Ritz values + e_core; tau: the
  * largest discarded weight of the last sweep.  DMRG_ENOCONV if a step did not
  * reach the tolerance (results still written). */
 dmrg_status dmrg_sweep(dmrg_solver* s, int n_sweeps, double* energies, double* tau);
 
-/* One two-site step on sites (k, k+1): Davidson on H_eff, SVD truncation to M,
- * environment update; direction 0 moves the center right (k -> k+1), 1 moves
- * it left.  A sweep is steps 0..n_orb-2 in direction 0 then n_orb-2..0 in 1.
+/* One two-site step on sites (k, k+1) (the decimation step of Fig. 2): Davidson
+ * on H_eff, SVD truncation to M, environment update; direction 0 moves the
+ * center right (k -> k+1), 1 moves it left.  A sweep is steps 0..n_orb-2 in
+ * direction 0 then n_orb-2..0 in 1.
  * The orthogonality centre must be on site k or k+1 (after solver creation it
  * is site 0; each step leaves it on the site it moved to; after dmrg_set_mps
  * the gauge is the caller's): else DMRG_ESTATE.
  * energies[n_states]: Ritz values + e_core; tau: discarded weight. */
 dmrg_status dmrg_step(dmrg_solver* s, int k, int direction, double* energies, double* tau);
+
+/* The SVD decimation of step k (Fig. 2: keep chi_k, discard tau = the sum of
+ * the squared discarded singular values) applied to caller-given two-site
+ * vectors instead of Davidson's: psi is a device array of n_states * n doubles
+ * (root r at r * n; n as for dmrg_sigma).  psi is read as a matrix with rows
+ * (left sector, s1) and columns (s2, right sector), block diagonal in the
+ * middle-bond sector; singular values of all sectors (of the weighted
+ * concatenation of the roots when n_states > 1) are sorted together and the
+ * largest M kept, never splitting values closer than tie_rtol * s_1 and, when
+ * truncating, dropping those <= cut_rtol * s_1 first (nothing is dropped while
+ * all fit).  Updates bond k+1, sites k and k+1 and the centre like dmrg_step
+ * (same centre requirement).  Outputs (host): *tau, *n_kept, and the kept
+ * singular values in descending order into sv[0..min(sv_cap, n_kept)) when sv
+ * is not NULL.  The singular values are square roots of eigenvalues of the
+ * sector density matrices: their squares are exact to rounding (~1e-16 of the
+ * norm), small values relatively less. */
+dmrg_status dmrg_truncate(dmrg_solver* s, int k, int direction, int64_t n, const double* psi, double* tau,
+                          double* sv, int sv_cap, int* n_kept);
 
 /* <Psi|H|Psi>/<Psi|Psi> + e_core of the current MPS (per root after a sweep). */
 dmrg_status dmrg_energy(dmrg_solver* s, double* energies);
@@ -262,8 +307,14 @@ dmrg_status dmrg_measure_peaks(void* hip_stream, const void* src, void* dst, siz
 
 /* Precision of the sigma products in later Davidson solves (dmrg_precision; the
  * option of the same name at creation).  fp64 is kept for the basis, the
- * subspace eigenproblem, the residual, the truncation and the environments; the
- * low-precision forms converge on an fp64 residual (defect correction). */
+ * subspace eigenproblem, the residual, the truncation and the environments.
+ * The low-precision forms run refinement cycles: the subspace restarts from
+ * Ritz vectors with fp64 products, new directions get fp32 / bf16 products,
+ * and when the residual estimate has dropped by 1e-4, stalled, or passed the
+ * tolerance the Ritz vectors get fp64 products again (defect correction).
+ * Convergence is declared only on such an exact fp64 residual; when a cycle
+ * cuts the exact residual by less than a factor 0.3, the rest of the step uses
+ * fp64 products. */
 dmrg_status dmrg_set_precision(dmrg_solver* s, int precision);
 
 /* Profiling aid: the fp64 sigma kernels exist as two identical instantiations
@@ -285,14 +336,16 @@ dmrg_status dmrg_set_kernel_tag(dmrg_solver* s, int tag);
  * (environments, factors, plans), [20] plan resolution and upload wall ms,
  * [21] Davidson wall ms, [22] step plans reused (a step's plan depends only on
  * its outer bonds and is kept per step; it is rebuilt when they change),
- * [23] phase-A flops executed, [24] phase-B flops executed.
+ * [23] phase-A flops executed, [24] phase-B flops executed, [25] sigma
+ * products in low precision (fp32 / bf16); [15] counts the precision form's
+ * refinement cycles (fp64 products of the Ritz vectors).
  * Times of [2]-[4], [10], [11], [16] are HIP-event times on the solver stream
  * and flops count unpadded block products.  The sigma flops [5], [12], [13]
  * are algorithmic: every block product of the middle-cut factorisation (all
  * columns of every T_X, every item).  The executed counts [23], [24] are
  * lower: phase A skips T_X columns no item reads, and phase B merges items
  * that share their T slice (sum_j c_j T Y_j^T = T (sum_j c_j Y_j)^T).
- * n: capacity of out (up to 25 values are written). */
+ * n: capacity of out (up to 26 values are written). */
 dmrg_status dmrg_get_stats(const dmrg_solver* s, double* out, int n);
 
 const char* dmrg_last_error(void);

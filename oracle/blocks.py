@@ -415,10 +415,10 @@ class TwoSite:
             return pack(self.bl, self.br, twosite_qn(), res)
         return res
 
-    def diag(self):
-        """Diagonal of H_eff as a slab-layout vector."""
+    def diag(self, blocks=None):
+        """Diagonal of H_eff as a slab-layout vector (blocks=None) or dict of the requested blocks."""
         res = {}
-        for (a, p, b) in self.output_blocks():
+        for (a, p, b) in (self.output_blocks() if blocks is None else blocks):
             s1, s2 = p // 4, p % 4
             D = np.zeros((self.bl.dim(a), self.br.dim(b)))
             for beta in self.betas:
@@ -436,4 +436,37 @@ class TwoSite:
                             continue
                         D += Ol[s1, s1] * Or[s2, s2] * np.outer(np.diag(X), np.diag(Y))
             res[(a, p, b)] = D
+        if blocks is not None:
+            return res
         return pack(self.bl, self.br, twosite_qn(), res)
+
+
+def twosite_from_sites(mps, k):
+    """psi[a s1 s2 b] = sum_m A_k[a s1 m] A_{k+1}[m s2 b] in slab layout."""
+    bonds, A = mps_blocks(mps)
+    bl, bm, br = bonds[k], bonds[k + 1], bonds[k + 2]
+    out = {}
+    for (a, s1, m), X in A[k].items():
+        for s2 in range(4):
+            b = br.find(_add(bm.q(m), SITE_QN[s2]))
+            if b is None or (m, s2, b) not in A[k + 1]:
+                continue
+            key = (a, 4 * s1 + s2, b)
+            prod = X @ A[k + 1][(m, s2, b)]
+            out[key] = out[key] + prod if key in out else prod
+    return pack(bl, br, twosite_qn(), out)
+
+
+def right_orthonormality_error(mps, first):
+    """max over sites x >= first and left sectors l of |sum_s A_s A_s^T - 1| (the
+    right block states at every cut >= first are orthonormal when this is ~0)."""
+    bonds, A = mps_blocks(mps)
+    err = 0.0
+    for x in range(first, len(A)):
+        for l in range(len(bonds[x])):
+            G = np.zeros((bonds[x].dim(l), bonds[x].dim(l)))
+            for (ll, s, r), X in A[x].items():
+                if ll == l:
+                    G += X @ X.T
+            err = max(err, float(np.max(np.abs(G - np.eye(G.shape[0])))))
+    return err

@@ -17,6 +17,7 @@ from ._lib import (  # noqa: F401
     measure_peaks,
     dmrg_diag,
     dmrg_energy,
+    dmrg_export_mps,
     dmrg_get_bonds,
     dmrg_get_env,
     dmrg_get_stats,
@@ -36,6 +37,7 @@ from ._lib import (  # noqa: F401
     dmrg_solver_destroy,
     dmrg_step,
     dmrg_sweep,
+    dmrg_truncate,
     lib,
 )
 

@@ -45,8 +45,10 @@ dmrg_solver_destroy = _decl("dmrg_solver_destroy", [_p], None)
 dmrg_set_mps = _decl("dmrg_set_mps", [_p, _p, _p, _p])
 dmrg_get_bonds = _decl("dmrg_get_bonds", [_p, _p, _p, _i])
 dmrg_prepare = _decl("dmrg_prepare", [_p, _i, C.POINTER(_i64)])
-dmrg_sigma = _decl("dmrg_sigma", [_p, _i, _i, _p, _p, C.POINTER(_d)])
-dmrg_diag = _decl("dmrg_diag", [_p, _i, _p])
+dmrg_sigma = _decl("dmrg_sigma", [_p, _i, _i, _i64, _p, _p, C.POINTER(_d)])
+dmrg_diag = _decl("dmrg_diag", [_p, _i, _i64, _p])
+dmrg_export_mps = _decl("dmrg_export_mps", [_p, _p, _p, _i, _p, _i64, C.POINTER(_i64)])
+dmrg_truncate = _decl("dmrg_truncate", [_p, _i, _i, _i64, _p, C.POINTER(_d), _p, _i, C.POINTER(_i)])
 dmrg_sweep = _decl("dmrg_sweep", [_p, _i, _p, C.POINTER(_d)])
 dmrg_energy = _decl("dmrg_energy", [_p, _p])
 dmrg_step = _decl("dmrg_step", [_p, _i, _i, _p, C.POINTER(_d)])
@@ -230,13 +232,64 @@ class Solver:
         _check(dmrg_prepare(self.h, k, C.byref(n)))
         return n.value
 
+    @staticmethod
+    def _dev_f64(t, name, numel=None):
+        """Device kernels take raw pointers: refuse anything but a contiguous
+        float64 tensor on the GPU (of numel elements when given)."""
+        if torch is None or not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor on the GPU")
+        if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous float64 CUDA tensor "
+                            f"(got {t.dtype}, device {t.device}, contiguous {t.is_contiguous()})")
+        if numel is not None and t.numel() != numel:
+            raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+
     def sigma(self, k, psi, out, precision=0):
+        """out = H_eff psi for step k; returns the executed flops."""
+        self._dev_f64(psi, "psi")
+        self._dev_f64(out, "out", psi.numel())
         fl = C.c_double()
-        _check(dmrg_sigma(self.h, k, precision, _ptr(psi), _ptr(out), C.byref(fl)))
+        _check(dmrg_sigma(self.h, k, precision, psi.numel(), _ptr(psi), _ptr(out), C.byref(fl)))
         return fl.value
 
     def diag(self, k, out):
-        _check(dmrg_diag(self.h, k, _ptr(out)))
+        self._dev_f64(out, "out")
+        _check(dmrg_diag(self.h, k, out.numel(), _ptr(out)))
+
+    def export_mps(self):
+        """The current MPS as {bonds: [[(N, 2Sz, dim), ...] per cut], sites: [flat float64 per site]}."""
+        L = self.problem.n
+        n_sec = np.zeros(L + 1, dtype=np.int32)
+        size = C.c_int64()
+        _check(dmrg_export_mps(self.h, _ptr(n_sec), None, 0, None, 0, C.byref(size)))
+        tot = int(n_sec.sum())
+        sec = np.zeros(3 * tot, dtype=np.int32)
+        data = np.zeros(size.value)
+        _check(dmrg_export_mps(self.h, _ptr(n_sec), _ptr(sec), tot, _ptr(data), size.value, C.byref(size)))
+        bonds, i = [], 0
+        for c in range(L + 1):
+            bonds.append([tuple(int(v) for v in sec[3 * j:3 * j + 3]) for j in range(i, i + n_sec[c])])
+            i += n_sec[c]
+        sites, off = [], 0
+        for k in range(L):
+            sz = _slab_size(bonds[k], bonds[k + 1])
+            sites.append(data[off:off + sz].copy())
+            off += sz
+        assert off == size.value
+        return {"bonds": bonds, "sites": sites}
+
+    def truncate(self, k, psi, direction=0, sv_cap=1 << 20):
+        """dmrg_truncate on device vectors psi (n_states x n, root-major, contiguous):
+        returns (tau, kept singular values descending)."""
+        self._dev_f64(psi, "psi")
+        if psi.numel() % self.n_states:
+            raise ValueError("psi must hold n_states vectors")
+        n = psi.numel() // self.n_states
+        tau = C.c_double()
+        nk = C.c_int()
+        sv = np.zeros(sv_cap)
+        _check(dmrg_truncate(self.h, k, direction, n, _ptr(psi), C.byref(tau), _ptr(sv), sv_cap, C.byref(nk)))
+        return tau.value, sv[:min(nk.value, sv_cap)].copy()
 
     def sweep(self, n_sweeps=1):
         e = np.zeros(self.n_states)
@@ -306,19 +359,31 @@ class Solver:
         return dh, dB, e
 
     def stats(self):
-        s = np.zeros(25)
-        _check(dmrg_get_stats(self.h, _ptr(s), 25))
+        s = np.zeros(26)
+        _check(dmrg_get_stats(self.h, _ptr(s), 26))
         keys = ["matvecs", "davidson_iters", "sigma_ms", "env_ms", "svd_ms", "sigma_flops", "tau",
                 "max_bond", "fallbacks", "converged", "sigma_a_ms", "sigma_b_ms", "sigma_a_flops",
                 "sigma_b_flops", "env_flops", "refinements", "sigma_b_gemm_ms", "grad_ms", "grad_flops",
                 "prepare_ms", "resolve_ms", "davidson_ms", "plan_hits", "sigma_a_flops_exec",
-                "sigma_b_flops_exec"]
+                "sigma_b_flops_exec", "lowp_matvecs"]
         return dict(zip(keys, s.tolist()))
 
     def __del__(self):
         if getattr(self, "h", None):
             dmrg_solver_destroy(self.h)
             self.h = None
+
+
+_SITE_QN = ((0, 0), (1, 1), (1, -1), (2, 0))
+
+
+def _slab_size(bond_l, bond_r):
+    """Doubles of a site tensor in slab layout between two bonds."""
+    right = {(N, s): d for N, s, d in bond_r}
+    size = 0
+    for N, s, ml in bond_l:
+        size += ml * sum(right.get((N + dn, s + ds), 0) for dn, ds in _SITE_QN)
+    return size
 
 
 def measure_peaks(nbytes=1 << 31, stream=None):

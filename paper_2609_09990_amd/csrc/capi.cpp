@@ -211,21 +211,76 @@ dmrg_status dmrg_prepare(dmrg_solver* s, int k, int64_t* n) {
   });
 }
 
-dmrg_status dmrg_sigma(dmrg_solver* s, int k, int precision, const double* psi, double* sigma,
+dmrg_status dmrg_sigma(dmrg_solver* s, int k, int precision, int64_t n, const double* psi, double* sigma,
                        double* flops) {
   return guard([&] {
     DMRG_REQUIRE(s && psi && sigma, ST_EINVAL, "NULL argument");
     DMRG_REQUIRE(precision >= 0 && precision <= 2, ST_EINVAL, "unknown precision");
+    const long len = s->s->twosite_size(k);
+    DMRG_REQUIRE(n == len, ST_EINVAL,
+                 "vector length " + std::to_string(n) + " is not the two-site length " + std::to_string(len));
     s->s->sigma(k, precision, psi, sigma);
-    if (flops) *flops = s->s->last_sigma_flops();
+    if (flops) *flops = s->s->last_sigma_flops_exec();
   });
 }
 
-dmrg_status dmrg_diag(dmrg_solver* s, int k, double* diag) {
+dmrg_status dmrg_diag(dmrg_solver* s, int k, int64_t n, double* diag) {
   return guard([&] {
     DMRG_REQUIRE(s && diag, ST_EINVAL, "NULL argument");
+    const long len = s->s->twosite_size(k);
+    DMRG_REQUIRE(n == len, ST_EINVAL,
+                 "vector length " + std::to_string(n) + " is not the two-site length " + std::to_string(len));
     s->s->diag(k, diag);
     hip_check(hipDeviceSynchronize(), "diag");
+  });
+}
+
+dmrg_status dmrg_export_mps(dmrg_solver* s, int* n_sec, int* sec, int sec_cap, double* data, int64_t data_cap,
+                            int64_t* data_size) {
+  return guard([&] {
+    DMRG_REQUIRE(s && n_sec && data_size, ST_EINVAL, "NULL argument");
+    const auto& b = s->s->bonds();
+    int total_sec = 0;
+    for (size_t c = 0; c < b.size(); ++c) {
+      n_sec[c] = (int)b[c].sec.size();
+      total_sec += n_sec[c];
+    }
+    if (sec) {
+      DMRG_REQUIRE(sec_cap >= total_sec, ST_EINVAL, "sector capacity too small");
+      int idx = 0;
+      for (const auto& bond : b)
+        for (const auto& x : bond.sec) {
+          sec[3 * idx] = x.q.n;
+          sec[3 * idx + 1] = x.q.sz;
+          sec[3 * idx + 2] = x.dim;
+          ++idx;
+        }
+    }
+    long total = 0;
+    for (size_t c = 0; c + 1 < b.size(); ++c)
+      total += make_tensor_layout(b[c], b[c + 1], site_phys_qn()).size;
+    *data_size = total;
+    if (data) {
+      DMRG_REQUIRE(data_cap >= total, ST_EINVAL, "data capacity too small");
+      std::vector<double> v = s->s->export_mps();
+      std::memcpy(data, v.data(), v.size() * sizeof(double));
+    }
+  });
+}
+
+dmrg_status dmrg_truncate(dmrg_solver* s, int k, int direction, int64_t n, const double* psi, double* tau,
+                          double* sv, int sv_cap, int* n_kept) {
+  return guard([&] {
+    DMRG_REQUIRE(s && psi && tau && n_kept, ST_EINVAL, "NULL argument");
+    DMRG_REQUIRE(direction == 0 || direction == 1, ST_EINVAL, "direction must be 0 or 1");
+    const long len = s->s->twosite_size(k);
+    DMRG_REQUIRE(n == len, ST_EINVAL,
+                 "vector length " + std::to_string(n) + " is not the two-site length " + std::to_string(len));
+    *tau = s->s->truncate(k, direction == 0, psi);
+    const auto& kept = s->s->last_kept_sv();
+    *n_kept = (int)kept.size();
+    if (sv)
+      for (int i = 0; i < sv_cap && i < (int)kept.size(); ++i) sv[i] = kept[i];
   });
 }
 
@@ -442,13 +497,13 @@ dmrg_status dmrg_get_stats(const dmrg_solver* s, double* out, int n) {
   return guard([&] {
     DMRG_REQUIRE(s && out, ST_EINVAL, "NULL argument");
     const Stats& t = s->s->stats();
-    double v[25] = {(double)t.matvecs, (double)t.davidson_iters, t.sigma_ms, t.env_ms, t.svd_ms,
+    double v[26] = {(double)t.matvecs, (double)t.davidson_iters, t.sigma_ms, t.env_ms, t.svd_ms,
                     t.sigma_flops, t.tau, (double)t.max_bond, (double)t.fallbacks, (double)t.converged,
                     t.sigma_a_ms, t.sigma_b_ms, t.sigma_a_flops, t.sigma_b_flops, t.env_flops,
                     (double)t.refinements, t.sigma_b_gemm_ms, t.grad_ms, t.grad_flops, t.prepare_ms,
                     t.resolve_ms, t.davidson_ms, (double)t.plan_hits, t.sigma_a_flops_exec,
-                    t.sigma_b_flops_exec};
-    for (int i = 0; i < n && i < 25; ++i) out[i] = v[i];
+                    t.sigma_b_flops_exec, (double)t.lowp_matvecs};
+    for (int i = 0; i < n && i < 26; ++i) out[i] = v[i];
   });
 }
 

@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 
+#include <stdexcept>
+
 #include "kernels.hpp"
 
 namespace dmrg {
@@ -1393,6 +1395,34 @@ __global__ __launch_bounds__(256) void jacobi_eig_kernel(const double* __restric
   for (int j = t; j < k; j += blockDim.x) evals[j] = A[order[j]][order[j]];
 }
 
+// Subspace rotation in place: V[:, i] = sum_j V[:, j] Y[i * k + j] for i < keep
+// (columns of V are vectors of length n, stride ldv; Y holds k-vectors one after
+// another).  Rows are independent: each thread reads all k entries of its row
+// before writing the keep new ones, so the update is safe in place.
+constexpr int kRotMax = 16;
+__global__ __launch_bounds__(256) void subspace_rotate_kernel(double* __restrict__ V, long ldv, int k,
+                                                              const double* __restrict__ Y, int keep, long n) {
+  __shared__ double Ys[64 * kRotMax];
+  for (int e = threadIdx.x; e < 64 * kRotMax; e += blockDim.x) {
+    const int j = e / kRotMax, i = e % kRotMax;
+    Ys[e] = (j < k && i < keep) ? Y[(long)i * k + j] : 0.0;
+  }
+  __syncthreads();
+  for (long r = (long)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (long)gridDim.x * blockDim.x) {
+    double acc[kRotMax];
+#pragma unroll
+    for (int i = 0; i < kRotMax; ++i) acc[i] = 0.0;
+    for (int j = 0; j < k; ++j) {
+      const double v = V[(long)j * ldv + r];
+#pragma unroll
+      for (int i = 0; i < kRotMax; ++i) acc[i] += v * Ys[j * kRotMax + i];
+    }
+#pragma unroll
+    for (int i = 0; i < kRotMax; ++i)
+      if (i < keep) V[(long)i * ldv + r] = acc[i];
+  }
+}
+
 __global__ void f64_to_f32_kernel(const double* x, float* y, long n) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     y[i] = (float)x[i];
@@ -1595,6 +1625,12 @@ void launch_scale_by_norm(double* x, long n, const double* nrm2, hipStream_t s) 
 void launch_precond_diag(const double* r, const double* diag, const double* theta, double* out,
                          long n, hipStream_t s) {
   precond_diag_kernel<<<grid_for(n), 256, 0, s>>>(r, diag, theta, out, n);
+}
+
+void launch_subspace_rotate(double* V, long ldv, int k, const double* Y, int keep, long n, hipStream_t s) {
+  if (n <= 0 || keep <= 0) return;
+  if (k > 64 || keep > kRotMax || keep > k) throw std::runtime_error("subspace rotation: k <= 64, keep <= 16 and <= k");
+  subspace_rotate_kernel<<<grid_for(n), 256, 0, s>>>(V, ldv, k, Y, keep, n);
 }
 
 void launch_jacobi_eig(const double* G, int ldg, int k, double* evals, double* evecs,

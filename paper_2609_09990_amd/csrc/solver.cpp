@@ -357,6 +357,9 @@ long Solver::twosite_size(int k) const {
 }
 
 double Solver::last_sigma_flops() const { return phA_.flops + phB_.flops; }
+double Solver::last_sigma_flops_exec() const {
+  return (phA_.flops_exec < 0 ? phA_.flops : phA_.flops_exec) + (phB_.flops_exec < 0 ? phB_.flops : phB_.flops_exec);
+}
 
 void Solver::ensure_lowp(int prec) {
   if (lowp_prec_ == prec) return;
@@ -455,6 +458,7 @@ void Solver::sigma(int k, int prec, const double* psi, double* out) {
   st_.sigma_ms += a + b;
   st_.sigma_flops += phA_.flops + phB_.flops;
   st_.matvecs++;
+  if (prec != PREC_F64) st_.lowp_matvecs++;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipEventDestroy(e2);
@@ -649,8 +653,21 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
   evals.assign(nr, 0.0);
   std::vector<double> rn(nr, 0.0), hv(2 * nr);
   int iter = 0;
-  bool exact_basis = (prec == PREC_F64);
-  int sprec = prec;  // precision of new sigma products (fp64 after the switch)
+  // Precision form: refinement cycles.  The start vectors' products are fp64, so
+  // the first residual is exact.  A cycle expands the subspace with low-precision
+  // products; their rounding error enters a Ritz vector weighted by its
+  // coefficients on the new directions, which are of the size of the residual at
+  // the cycle start, so a cycle can cut the exact residual by about the low
+  // precision's relative accuracy.  A cycle ends when the (mixed) residual
+  // estimate has dropped by kCycleCut, has stalled (no 10% drop in 3 iterations)
+  // or is below tol; the Ritz vectors then get fp64 products and the subspace
+  // restarts from them (exact again).  Convergence is declared only on an exact
+  // residual.  When a cycle fails to cut the exact residual by kMinGain the rest
+  // of the step is fp64.
+  const double kCycleCut = 1e-4, kMinGain = 0.3;
+  int sprec = prec;      // precision of new sigma products
+  int n_lowp = 0;        // columns of the subspace with low-precision products
+  double r_exact = -1.0; // exact residual at the start of the current cycle
   double best_lo = 1e300;
   int stall = 0;
   int conv = 0;
@@ -672,28 +689,29 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
       rmax = std::max(rmax, rn[i]);
     }
     if (opt_.verbose > 1)
-      fprintf(stderr, "  dav k=%d it=%d sub=%d E=%.12f r=%.3e exact=%d\n", k, iter, kcur, evals[0], rmax,
-              (int)exact_basis);
+      fprintf(stderr, "  dav k=%d it=%d sub=%d E=%.12f r=%.3e lowp_cols=%d\n", k, iter, kcur, evals[0], rmax, n_lowp);
     if (!std::isfinite(rmax)) throw Error(ST_ENOCONV, "non-finite Davidson residual");
-    bool lo_done = rmax <= opt_.davidson_tol;
-    if (!exact_basis) {
+    if (n_lowp == 0) {
+      // every product in the subspace is fp64: the residual is exact
+      if (rmax <= opt_.davidson_tol) {
+        conv = 1;
+        break;
+      }
+      if (sprec != PREC_F64) {
+        if (r_exact > 0 && rmax > kMinGain * r_exact) sprec = PREC_F64;  // the last cycle did not pay
+        r_exact = rmax;
+        best_lo = rmax;
+        stall = 0;
+      }
+    } else {
       if (rmax < 0.9 * best_lo) {
         best_lo = rmax;
         stall = 0;
       } else {
         ++stall;
       }
-      // the low-precision residual means nothing below the rounding floor of its
-      // sigma, ~10 u ||H_eff|| (u: fp32 2^-24, bf16 2^-8; ||H_eff|| >= |theta|)
-      double tmax = 0;
-      for (int i = 0; i < nr; ++i) tmax = std::max(tmax, std::fabs(evals[i]));
-      const double u_lo = prec == PREC_F32 ? 5.96e-8 : 3.91e-3;
-      const bool at_floor = rmax <= 10.0 * u_lo * tmax;
-      if (lo_done || stall >= 3 || at_floor) {
-        // switch to fp64 for the rest of the step: exact sigma of the Ritz vectors,
-        // restart from them; every later product is fp64, so the step converges on
-        // an exact residual like the plain form (defect correction of the
-        // low-precision solution)
+      if (rmax <= opt_.davidson_tol || rmax <= kCycleCut * r_exact || stall >= 3) {
+        // end of a cycle: fp64 products of the Ritz vectors, restart from them
         for (int i = 0; i < nr; ++i) launch_copy(V + (long)i * n, X + (long)i * n, n, st);
         for (int i = 0; i < nr; ++i) {
           sigma(k, PREC_F64, V + (long)i * n, AV + (long)i * n);
@@ -701,14 +719,10 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
         }
         for (int i = 0; i < nr; ++i) launch_dots(V, n, i + 1, AV + (long)i * n, n, part, G + (long)i * ldg, st);
         kcur = nr;
-        exact_basis = true;
-        sprec = PREC_F64;
+        n_lowp = 0;
         st_.refinements++;
         continue;
       }
-    } else if (lo_done) {
-      conv = 1;
-      break;
     }
     // training triple of root 0: features now, target once the step has converged
     if (rec && rn[0] > opt_.davidson_tol && (int)rec_slots.size() < kRecHist &&
@@ -747,15 +761,15 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
       }
       ++nnew;
     }
-    if (kcur + nnew > kmax) {  // thick restart with the Ritz vectors
-      for (int i = 0; i < nr; ++i)
-        launch_gemv(AV, n, kcur, evec + (long)i * kcur, 1.0, R + (long)i * n, 0.0, n, st);
-      for (int i = 0; i < nr; ++i) {
-        launch_copy(V + (long)i * n, X + (long)i * n, n, st);
-        launch_copy(AV + (long)i * n, R + (long)i * n, n, st);
-      }
-      for (int i = 0; i < nr; ++i) launch_dots(V, n, i + 1, AV + (long)i * n, n, part, G + (long)i * ldg, st);
-      kcur = nr;
+    if (kcur + nnew > kmax) {
+      // thick restart: keep the lowest Ritz vectors, more than the roots, so a
+      // near-degenerate neighbour of the last root is not lost at every restart
+      const int keep = std::min(kcur, std::min(16, std::max(nr + 2, kmax / 3)));
+      launch_subspace_rotate(V, n, kcur, evec, keep, n, st);
+      launch_subspace_rotate(AV, n, kcur, evec, keep, n, st);
+      for (int i = 0; i < keep; ++i) launch_dots(V, n, i + 1, AV + (long)i * n, n, part, G + (long)i * ldg, st);
+      kcur = keep;
+      if (n_lowp > 0) n_lowp = keep;  // their products mix low-precision columns
     }
     int added = 0;
     for (int j = 0; j < nnew; ++j) {
@@ -768,13 +782,26 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
       }
       if (append(Cc + (long)j * n, sprec)) ++added;
     }
+    if (sprec != PREC_F64) n_lowp += added;
     if (added == 0) {
+      if (n_lowp > 0) {  // nothing new to add on inexact products: end the cycle next iteration
+        stall = 3;
+        continue;
+      }
       conv = rmax <= 1e3 * opt_.davidson_tol;
       break;
     }
   }
   st_.davidson_iters += iter;
-  if (!conv) st_.converged = 0;
+  if (!conv) {
+    st_.converged = 0;
+    if (opt_.verbose)
+      fprintf(stderr, "  davidson k=%d not converged: %d iterations, subspace %d, residuals", k, iter, kcur);
+    if (opt_.verbose) {
+      for (int i = 0; i < nr; ++i) fprintf(stderr, " %.3e", rn[i]);
+      fprintf(stderr, " (tol %.1e, n %ld)\n", opt_.davidson_tol, n);
+    }
+  }
   last_converged_ = conv != 0;
   if (rec && conv && !rec_slots.empty()) {  // Delta = P_perp psi*, psi* oriented along psi_i
     for (size_t j = 0; j < rec_slots.size(); ++j) {
@@ -955,8 +982,15 @@ void Solver::svd_step(int k, bool l2r, int nr, std::vector<DevMem>& next_guess, 
     hip_check(hipStreamWaitEvent(st, aux_ev_[i], 0), "join");
   }
   std::vector<double> E(etot);
+  std::vector<rocblas_int> einfo(mids.size());
   hip_check(hipMemcpyAsync(E.data(), evals.p, etot * 8, hipMemcpyDeviceToHost, st), "eigenvalues");
+  hip_check(hipMemcpyAsync(einfo.data(), info.p, mids.size() * sizeof(rocblas_int), hipMemcpyDeviceToHost, st),
+            "eigensolve info");
   hip_check(hipStreamSynchronize(st), "eigensolve");
+  for (size_t i = 0; i < mids.size(); ++i)
+    if (einfo[i] != 0)
+      throw Error(ST_EHIP, "rocsolver_dsyevd did not converge for a density matrix (info " +
+                               std::to_string(einfo[i]) + ")");
   // singular values per sector, descending: the largest gd eigenvalues of each padded block
   std::vector<long> oS(mids.size());
   std::vector<int> kk(mids.size());
@@ -985,6 +1019,8 @@ void Solver::svd_step(int k, bool l2r, int nr, std::vector<DevMem>& next_guess, 
     while (keep > 1 && all_sv[keep - 1].s - all_sv[keep].s <= opt_.tie_rtol * s1) --keep;
   }
   if (keep < 1) keep = 1;
+  last_kept_sv_.resize(keep);
+  for (long i = 0; i < keep; ++i) last_kept_sv_[i] = all_sv[i].s;
   tau = 0;
   for (size_t i = keep; i < all_sv.size(); ++i) tau += all_sv[i].s * all_sv[i].s;
   std::vector<int> kept(mids.size(), 0);
@@ -1200,6 +1236,17 @@ double Solver::step(int k, bool l2r, std::vector<double>& energies) {
   guess_l2r_ = l2r;
   if (guess_k_ < 0 || guess_k_ + 1 >= L_) guess_k_ = -1;
   st_.svd_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  after_truncation(k, l2r);
+  st_.tau = tau;
+  if (opt_.verbose)
+    fprintf(stderr, "%s k=%d E=%.12f tau=%.2e M=%d\n", l2r ? "L->R" : "R->L", k, energies[0], tau,
+            bonds_[k + 1].total());
+  return tau;
+}
+
+// Environment of the new orthonormal site (its factors were built for the step)
+// and invalidation of every environment the changed sites enter.
+void Solver::after_truncation(int k, bool l2r) {
   auto t1 = std::chrono::steady_clock::now();
   if (l2r) {
     env_update_left(k, lf_);
@@ -1214,11 +1261,43 @@ double Solver::step(int k, bool l2r, std::vector<double>& energies) {
   hip_check(hipStreamSynchronize(st), "env");
   st_.env_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count();
   plan_k_ = -1;
+}
+
+double Solver::truncate(int k, bool l2r, const double* psi) {
+  DMRG_REQUIRE(k >= 0 && k + 1 < L_, ST_EINVAL, "two-site step out of range");
+  DMRG_REQUIRE(center_site_ < 0 || center_site_ == k || center_site_ == k + 1, ST_ESTATE,
+               "truncation away from the orthogonality centre (site " + std::to_string(center_site_) + ")");
+  prepare(k);
+  const long n = psi_lay_.size;
+  const int nr = opt_.n_states;
+  dv_X_.reserve((size_t)nr * n * 8);
+  launch_copy(dv_X_.as<double>(), psi, (long)nr * n, st);
+  double tau = 0;
+  auto t0 = std::chrono::steady_clock::now();
+  svd_step(k, l2r, nr, guess_, tau);
+  guess_k_ = l2r ? k + 1 : k - 1;
+  guess_l2r_ = l2r;
+  if (guess_k_ < 0 || guess_k_ + 1 >= L_) guess_k_ = -1;
+  st_.svd_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  after_truncation(k, l2r);
   st_.tau = tau;
-  if (opt_.verbose)
-    fprintf(stderr, "%s k=%d E=%.12f tau=%.2e M=%d\n", l2r ? "L->R" : "R->L", k, energies[0], tau,
-            bonds_[k + 1].total());
   return tau;
+}
+
+std::vector<double> Solver::export_mps() const {
+  long total = 0;
+  for (int k = 0; k < L_; ++k) total += mps_[k].lay.size;
+  std::vector<double> out(total);
+  long off = 0;
+  for (int k = 0; k < L_; ++k) {
+    const long sz = mps_[k].lay.size;
+    if (sz > 0)
+      hip_check(hipMemcpyAsync(out.data() + off, mps_[k].buf.p, sz * sizeof(double), hipMemcpyDeviceToHost, st),
+                "mps export");
+    off += sz;
+  }
+  hip_check(hipStreamSynchronize(st), "mps export");
+  return out;
 }
 
 double Solver::sweep(int n_sweeps, std::vector<double>& energies) {

@@ -176,6 +176,7 @@ struct Stats {
   double grad_ms = 0, grad_flops = 0;  // integral-gradient passes
   double prepare_ms = 0, resolve_ms = 0, davidson_ms = 0;  // host wall times
   int plan_hits = 0;  // step plans reused from the cache
+  int lowp_matvecs = 0;  // sigma products in fp32 / bf16
 };
 
 class MLP;
@@ -198,6 +199,14 @@ class Solver {
   double sweep(int n_sweeps, std::vector<double>& energies);
   double step(int k, bool left_to_right, std::vector<double>& energies);
   std::vector<double> mps_energy();
+  // Host copy of the current MPS: all site tensors concatenated in slab layout.
+  std::vector<double> export_mps() const;
+  // Truncation of step k applied to caller-given two-site vectors (device,
+  // n_states x n, root-major) instead of Davidson's: new bond k+1, sites k and
+  // k+1, the centre moved as a step moves it; returns tau.
+  double truncate(int k, bool left_to_right, const double* psi);
+  // Kept singular values of the last truncation, descending over all sectors.
+  const std::vector<double>& last_kept_sv() const { return last_kept_sv_; }
   // Energies of the roots w refers to and sum_r w_r dE_r/dh (n*n), dE_r/dB (nq*n*n).
   void grad(const std::vector<double>& w, std::vector<double>& dh, std::vector<double>& dB,
             std::vector<double>& energies);
@@ -224,7 +233,8 @@ class Solver {
   const Problem* prob() const { return prob_; }
 
   // sigma phase timing helpers for measurement
-  double last_sigma_flops() const;
+  double last_sigma_flops() const;       // algorithmic (every block product of the factorisation)
+  double last_sigma_flops_exec() const;  // executed by the launches (merged / trimmed plan, unpadded)
   // 0: sigma phases launch the tag-1/2 kernel instantiations, 1: tag-3/4
   void set_kernel_tag(int t) { kernel_tag_ = t ? 1 : 0; }
   int kernel_tag_ = 0;
@@ -311,6 +321,8 @@ class Solver {
 
   // learned preconditioner and training-triple store
   bool last_converged_ = true;
+  std::vector<double> last_kept_sv_;
+  void after_truncation(int k, bool left_to_right);
   int precond_ = 0;
   MLP* net_ = nullptr;
   std::vector<int64_t> fblocks_host_;  // feature blocks of the prepared step: off, ld, rows, cols

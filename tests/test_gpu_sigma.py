@@ -157,6 +157,7 @@ def test_precision_form_full_bond_equals_fci_cas8(prec):
     assert abs(e[0] - ref) <= 1e-10
     assert abs(sol.energy()[0] - ref) <= 1e-10
     assert st["refinements"] > 0
+    assert st["lowp_matvecs"] > 0  # the low-precision kernels really ran
 
 
 def test_executed_flops_at_most_algorithmic():
