@@ -574,6 +574,29 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
   };
   // orthonormalise t against V[0..kcur) (two passes of classical Gram-Schmidt), append
   // min_ratio: smallest accepted |t after projection|^2 / |t|^2
+  // error of each subspace column's product, in units of the low-precision
+  // sigma error per unit vector (0: fp64 product); rotations propagate it as
+  // independent errors (square root of the sum of squares)
+  std::vector<double> colerr(64, 0.0);
+  // Row i of the subspace matrix, G_ji = v_j . A v_i for j <= i.  H is
+  // symmetric, so the entry can also be formed as (A v_j) . v_i; with
+  // low-precision products the more accurate of the two columns' products is
+  // used, so couplings to fp64 columns (the roots after a refinement) are exact.
+  std::vector<double> gtmp(128);
+  auto gcol = [&](int i) {
+    launch_dots(V, n, i + 1, AV + (long)i * n, n, part, G + (long)i * ldg, st);
+    bool mixed = false;
+    for (int j = 0; j <= i; ++j) mixed = mixed || colerr[j] < colerr[i];
+    if (!mixed) return;
+    launch_dots(AV, n, i + 1, V + (long)i * n, n, part, sc + 64, st);
+    hip_check(hipMemcpyAsync(gtmp.data(), G + (long)i * ldg, (i + 1) * 8, hipMemcpyDeviceToHost, st), "g row");
+    hip_check(hipMemcpyAsync(gtmp.data() + 64, sc + 64, (i + 1) * 8, hipMemcpyDeviceToHost, st), "g row");
+    hip_check(hipStreamSynchronize(st), "g row");
+    for (int j = 0; j <= i; ++j)
+      if (colerr[j] < colerr[i]) gtmp[j] = gtmp[64 + j];
+    hip_check(hipMemcpyAsync(G + (long)i * ldg, gtmp.data(), (i + 1) * 8, hipMemcpyHostToDevice, st), "g row");
+    hip_check(hipStreamSynchronize(st), "g row");
+  };
   auto append = [&](const double* src, int sprec, double min_ratio = 1e-20) -> bool {
     if (src != t) launch_copy(t, src, n, st);
     launch_dots(t, n, 1, t, n, part, sc + 1, st);
@@ -590,7 +613,8 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
     launch_copy(V + (long)kcur * n, t, n, st);
     sigma(k, sprec, V + (long)kcur * n, AV + (long)kcur * n);
     ++matvecs;
-    launch_dots(V, n, kcur + 1, AV + (long)kcur * n, n, part, G + (long)kcur * ldg, st);
+    colerr[kcur] = sprec == PREC_F64 ? 0.0 : 1.0;
+    gcol(kcur);
     ++kcur;
     return true;
   };
@@ -653,23 +677,64 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
   evals.assign(nr, 0.0);
   std::vector<double> rn(nr, 0.0), hv(2 * nr);
   int iter = 0;
-  // Precision form: refinement cycles.  The start vectors' products are fp64, so
-  // the first residual is exact.  A cycle expands the subspace with low-precision
-  // products; their rounding error enters a Ritz vector weighted by its
-  // coefficients on the new directions, which are of the size of the residual at
-  // the cycle start, so a cycle can cut the exact residual by about the low
-  // precision's relative accuracy.  A cycle ends when the (mixed) residual
-  // estimate has dropped by kCycleCut, has stalled (no 10% drop in 3 iterations)
-  // or is below tol; the Ritz vectors then get fp64 products and the subspace
-  // restarts from them (exact again).  Convergence is declared only on an exact
-  // residual.  When a cycle fails to cut the exact residual by kMinGain the rest
-  // of the step is fp64.
-  const double kCycleCut = 1e-4, kMinGain = 0.3;
-  int sprec = prec;      // precision of new sigma products
-  int n_lowp = 0;        // columns of the subspace with low-precision products
-  double r_exact = -1.0; // exact residual at the start of the current cycle
-  double best_lo = 1e300;
-  int stall = 0;
+  // Precision form (defect correction).  The start vectors get fp64 products
+  // and one low-precision product of the first of them measures delta, the
+  // low-precision sigma error per unit vector at this step.  New directions get
+  // low-precision products; the error of a Ritz vector's product is then
+  // delta * sqrt(sum_j y_j^2 colerr_j^2) over its coefficients y.  While the
+  // residual estimate is far above that error the iteration is plain Davidson.
+  // When it comes within kNear of it (or below tol), the subspace is rotated
+  // to its lowest Ritz vectors and the roots' vectors get fp64 products
+  // (refinement): their residuals are exact again, and the other kept vectors'
+  // errors enter later Ritz vectors only through small coefficients.
+  // Convergence is declared only on a residual whose error bound is below
+  // tol / 10.  Two refinements that do not halve the exact residual end the low
+  // precision for this step (the rest is fp64).
+  const double kNear = 10.0;
+  int sprec = prec;  // precision of new sigma products
+  double delta = 0.0;
+  if (sprec != PREC_F64) {
+    const double one = 1.0;
+    hip_check(hipMemcpyAsync(sc + 40, &one, 8, hipMemcpyHostToDevice, st), "one");
+    sigma(k, sprec, V, t);
+    ++matvecs;
+    launch_axpy_dev(t, AV, sc + 40, -1.0, n, st);  // t - 1 * AV[0] (sc[40] = 1)
+    launch_dots(t, n, 1, t, n, part, sc + 41, st);
+    delta = std::sqrt(std::max(0.0, host_scalar(sc + 41)));
+  }
+  double r_last_ref = -1.0;  // exact residual after the last refinement
+  int bad_refs = 0;
+  bool after_ref = false;
+  std::vector<double> hy((size_t)64 * 64);
+  auto rotate_keep = [&](int keep) {
+    // V, AV <- the lowest `keep` Ritz vectors (in place); errors propagate
+    hip_check(hipMemcpyAsync(hy.data(), evec, (size_t)kcur * keep * 8, hipMemcpyDeviceToHost, st), "evecs");
+    launch_subspace_rotate(V, n, kcur, evec, keep, n, st);
+    launch_subspace_rotate(AV, n, kcur, evec, keep, n, st);
+    hip_check(hipStreamSynchronize(st), "rotate");
+    std::vector<double> ne(keep, 0.0);
+    for (int i = 0; i < keep; ++i) {
+      double acc = 0;
+      for (int j = 0; j < kcur; ++j) acc += hy[(size_t)i * kcur + j] * hy[(size_t)i * kcur + j] * colerr[j] * colerr[j];
+      ne[i] = std::sqrt(acc);
+    }
+    for (int i = 0; i < keep; ++i) colerr[i] = ne[i];
+    for (int i = 0; i < keep; ++i) gcol(i);
+    kcur = keep;
+  };
+  // refinement: rotate to the lowest Ritz vectors, fp64 products for the roots'
+  auto refine = [&]() {
+    const int keep = std::min(kcur, std::min(16, std::max(nr + 2, kmax / 3)));
+    rotate_keep(keep);
+    for (int i = 0; i < nr; ++i) {
+      sigma(k, PREC_F64, V + (long)i * n, AV + (long)i * n);
+      ++matvecs;
+      colerr[i] = 0.0;
+    }
+    for (int i = 0; i < keep; ++i) gcol(i);
+    st_.refinements++;
+    after_ref = true;
+  };
   int conv = 0;
   for (; iter < opt_.max_iter; ++iter) {
     launch_jacobi_eig(G, ldg, kcur, ev, evec, st);
@@ -681,48 +746,36 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
     }
     hip_check(hipMemcpyAsync(hv.data(), ev, nr * 8, hipMemcpyDeviceToHost, st), "evals");
     hip_check(hipMemcpyAsync(hv.data() + nr, sc + 16, nr * 8, hipMemcpyDeviceToHost, st), "rnorm");
+    if (delta > 0) hip_check(hipMemcpyAsync(hy.data(), evec, (size_t)kcur * nr * 8, hipMemcpyDeviceToHost, st), "evecs");
     hip_check(hipStreamSynchronize(st), "davidson");
-    double rmax = 0;
+    double rmax = 0, errmax = 0;
     for (int i = 0; i < nr; ++i) {
       evals[i] = hv[i];
       rn[i] = std::sqrt(std::max(0.0, hv[nr + i]));
       rmax = std::max(rmax, rn[i]);
+      if (delta > 0) {
+        double acc = 0;
+        for (int j = 0; j < kcur; ++j) acc += hy[(size_t)i * kcur + j] * hy[(size_t)i * kcur + j] * colerr[j] * colerr[j];
+        errmax = std::max(errmax, delta * std::sqrt(acc));
+      }
     }
     if (opt_.verbose > 1)
-      fprintf(stderr, "  dav k=%d it=%d sub=%d E=%.12f r=%.3e lowp_cols=%d\n", k, iter, kcur, evals[0], rmax, n_lowp);
+      fprintf(stderr, "  dav k=%d it=%d sub=%d E=%.12f r=%.3e err=%.1e prec=%d\n", k, iter, kcur, evals[0], rmax,
+              errmax, sprec);
     if (!std::isfinite(rmax)) throw Error(ST_ENOCONV, "non-finite Davidson residual");
-    if (n_lowp == 0) {
-      // every product in the subspace is fp64: the residual is exact
+    if (after_ref) {  // the roots' residuals are exact: judge the refinement
+      after_ref = false;
+      if (r_last_ref > 0 && rmax > 0.5 * r_last_ref && ++bad_refs >= 2) sprec = PREC_F64;
+      r_last_ref = rmax;
+    }
+    if (errmax <= 0.1 * opt_.davidson_tol) {
       if (rmax <= opt_.davidson_tol) {
         conv = 1;
         break;
       }
-      if (sprec != PREC_F64) {
-        if (r_exact > 0 && rmax > kMinGain * r_exact) sprec = PREC_F64;  // the last cycle did not pay
-        r_exact = rmax;
-        best_lo = rmax;
-        stall = 0;
-      }
-    } else {
-      if (rmax < 0.9 * best_lo) {
-        best_lo = rmax;
-        stall = 0;
-      } else {
-        ++stall;
-      }
-      if (rmax <= opt_.davidson_tol || rmax <= kCycleCut * r_exact || stall >= 3) {
-        // end of a cycle: fp64 products of the Ritz vectors, restart from them
-        for (int i = 0; i < nr; ++i) launch_copy(V + (long)i * n, X + (long)i * n, n, st);
-        for (int i = 0; i < nr; ++i) {
-          sigma(k, PREC_F64, V + (long)i * n, AV + (long)i * n);
-          ++matvecs;
-        }
-        for (int i = 0; i < nr; ++i) launch_dots(V, n, i + 1, AV + (long)i * n, n, part, G + (long)i * ldg, st);
-        kcur = nr;
-        n_lowp = 0;
-        st_.refinements++;
-        continue;
-      }
+    } else if (rmax <= opt_.davidson_tol || rmax <= kNear * errmax) {
+      refine();
+      continue;
     }
     // training triple of root 0: features now, target once the step has converged
     if (rec && rn[0] > opt_.davidson_tol && (int)rec_slots.size() < kRecHist &&
@@ -764,12 +817,7 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
     if (kcur + nnew > kmax) {
       // thick restart: keep the lowest Ritz vectors, more than the roots, so a
       // near-degenerate neighbour of the last root is not lost at every restart
-      const int keep = std::min(kcur, std::min(16, std::max(nr + 2, kmax / 3)));
-      launch_subspace_rotate(V, n, kcur, evec, keep, n, st);
-      launch_subspace_rotate(AV, n, kcur, evec, keep, n, st);
-      for (int i = 0; i < keep; ++i) launch_dots(V, n, i + 1, AV + (long)i * n, n, part, G + (long)i * ldg, st);
-      kcur = keep;
-      if (n_lowp > 0) n_lowp = keep;  // their products mix low-precision columns
+      rotate_keep(std::min(kcur, std::min(16, std::max(nr + 2, kmax / 3))));
     }
     int added = 0;
     for (int j = 0; j < nnew; ++j) {
@@ -782,10 +830,11 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
       }
       if (append(Cc + (long)j * n, sprec)) ++added;
     }
-    if (sprec != PREC_F64) n_lowp += added;
+
     if (added == 0) {
-      if (n_lowp > 0) {  // nothing new to add on inexact products: end the cycle next iteration
-        stall = 3;
+      if (errmax > 0.1 * opt_.davidson_tol) {  // nothing new to add on inexact products
+        sprec = PREC_F64;
+        refine();
         continue;
       }
       conv = rmax <= 1e3 * opt_.davidson_tol;
