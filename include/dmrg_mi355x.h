@@ -97,11 +97,36 @@ dmrg_status dmrg_mpo_dims(const dmrg_problem* p, int* dims);
 dmrg_status dmrg_mpo_site_nnz(const dmrg_problem* p, int site, int* nnz);
 dmrg_status dmrg_mpo_site(const dmrg_problem* p, int site, int* a, int* b, double* c, double* op);
 
-/* Solver on the current device.  Allocates its device memory (environments,
- * MPS, Davidson basis) and initialises a seeded right-canonical random MPS. */
+/* Solver on the current device with a seeded right-canonical random MPS (made
+ * on the host: creation allocates no device memory; the MPS reaches the device
+ * on the first call that needs device state).  Without a workspace the solver
+ * allocates its device buffers (environments, MPS, plans, Davidson basis) with
+ * hipMalloc as it needs them; after dmrg_workspace_attach every solver buffer,
+ * rocBLAS's workspace included, is carved from the attached memory. */
 dmrg_status dmrg_solver_create(const dmrg_problem* p, const dmrg_options* o, void* hip_stream,
                                dmrg_solver** out);
 void dmrg_solver_destroy(dmrg_solver* s);
+
+/* Device workspace (the paper's engine runs on one preallocated slab carved by
+ * the library, Sec. III).  dmrg_workspace_query writes the bytes to attach for
+ * the work ahead: an estimate from the current bonds and MPO (environments of
+ * every cut, the largest step's sigma intermediates and Davidson basis, the MPS
+ * and plans) before any workspace is attached; with one attached, at least 1.25
+ * times its peak use, and after a call failed with DMRG_ENOMEM at least 1.25
+ * times (what was in use + the request that did not fit).
+ * dmrg_workspace_attach hands the library dev_ptr[0..bytes) (device memory on
+ * the solver's device, caller-owned, e.g. a torch tensor; >= 1 MiB): the
+ * solver's state (MPS, bonds, centre tensors, settings, statistics) moves into
+ * it and every later solver buffer comes from it; the previous workspace (or
+ * the library's own buffers) is released, so the caller may free the old slab
+ * when the call returns.  Cached plans and environments are rebuilt on demand.
+ * When a later call needs more than is free it fails with DMRG_ENOMEM (nothing
+ * allocated): query again, attach a larger slab and repeat the call.  The
+ * memory must stay valid until the solver is destroyed or another workspace is
+ * attached.  The preconditioner network (dmrg_mlp) and the stand-alone calls
+ * (dmrg_block_gemm, dmrg_measure_peaks) allocate their own memory. */
+dmrg_status dmrg_workspace_query(const dmrg_solver* s, size_t* bytes);
+dmrg_status dmrg_workspace_attach(dmrg_solver* s, void* dev_ptr, size_t bytes);
 
 /* Replace the MPS.  n_sec[c] (c = 0..n_orb) sectors per bond, concatenated
  * sector tables sec[3*i] = N, sec[3*i+1] = 2Sz, sec[3*i+2] = dim; data = all
@@ -338,14 +363,17 @@ dmrg_status dmrg_set_kernel_tag(dmrg_solver* s, int tag);
  * its outer bonds and is kept per step; it is rebuilt when they change),
  * [23] phase-A flops executed, [24] phase-B flops executed, [25] sigma
  * products in low precision (fp32 / bf16); [15] counts the precision form's
- * refinement cycles (fp64 products of the Ritz vectors).
+ * refinement cycles (fp64 products of the Ritz vectors), [26] peak bytes in
+ * use in the attached workspace (0 without one), [27] device allocations the
+ * library made with hipMalloc since the workspace was attached (process-wide
+ * count; -1 without a workspace).
  * Times of [2]-[4], [10], [11], [16] are HIP-event times on the solver stream
  * and flops count unpadded block products.  The sigma flops [5], [12], [13]
  * are algorithmic: every block product of the middle-cut factorisation (all
  * columns of every T_X, every item).  The executed counts [23], [24] are
  * lower: phase A skips T_X columns no item reads, and phase B merges items
  * that share their T slice (sum_j c_j T Y_j^T = T (sum_j c_j Y_j)^T).
- * n: capacity of out (up to 26 values are written). */
+ * n: capacity of out (up to 28 values are written). */
 dmrg_status dmrg_get_stats(const dmrg_solver* s, double* out, int n);
 
 const char* dmrg_last_error(void);

@@ -38,6 +38,8 @@ from ._lib import (  # noqa: F401
     dmrg_step,
     dmrg_sweep,
     dmrg_truncate,
+    dmrg_workspace_attach,
+    dmrg_workspace_query,
     lib,
 )
 

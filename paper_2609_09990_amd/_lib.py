@@ -47,6 +47,8 @@ dmrg_get_bonds = _decl("dmrg_get_bonds", [_p, _p, _p, _i])
 dmrg_prepare = _decl("dmrg_prepare", [_p, _i, C.POINTER(_i64)])
 dmrg_sigma = _decl("dmrg_sigma", [_p, _i, _i, _i64, _p, _p, C.POINTER(_d)])
 dmrg_diag = _decl("dmrg_diag", [_p, _i, _i64, _p])
+dmrg_workspace_query = _decl("dmrg_workspace_query", [_p, C.POINTER(C.c_size_t)])
+dmrg_workspace_attach = _decl("dmrg_workspace_attach", [_p, _p, C.c_size_t])
 dmrg_export_mps = _decl("dmrg_export_mps", [_p, _p, _p, _i, _p, _i64, C.POINTER(_i64)])
 dmrg_truncate = _decl("dmrg_truncate", [_p, _i, _i, _i64, _p, C.POINTER(_d), _p, _i, C.POINTER(_i)])
 dmrg_sweep = _decl("dmrg_sweep", [_p, _i, _p, C.POINTER(_d)])
@@ -126,7 +128,7 @@ class Problem:
         return a, b, c, op.reshape(m, 4, 4)
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and dmrg_problem_destroy is not None:
             dmrg_problem_destroy(self.h)
             self.h = None
 
@@ -193,7 +195,10 @@ class Solver:
 
     def __init__(self, problem: Problem, M=256, n_states=1, weights=None, tol=1e-10, max_iter=200,
                  max_subspace=32, precision=0, precond=0, seed=1, tie_rtol=1e-10, cut_rtol=1e-14,
-                 verbose=0, stream=None):
+                 verbose=0, stream=None, workspace=False):
+        """workspace: False (the library allocates its device buffers), True (a
+        torch-allocated workspace of dmrg_workspace_query bytes, grown and
+        re-attached when a call reports DMRG_ENOMEM) or a byte count."""
         o = dmrg_options()
         dmrg_options_default(C.byref(o))
         o.M, o.n_states, o.davidson_tol, o.max_iter = M, n_states, tol, max_iter
@@ -209,6 +214,33 @@ class Solver:
         self.n_states = n_states
         self.h = C.c_void_p()
         _check(dmrg_solver_create(problem.h, C.byref(o), C.c_void_p(stream or 0), C.byref(self.h)))
+        self._ws = None
+        if workspace:
+            self.attach_workspace(None if workspace is True else int(workspace))
+
+    def workspace_query(self):
+        b = C.c_size_t()
+        _check(dmrg_workspace_query(self.h, C.byref(b)))
+        return b.value
+
+    def attach_workspace(self, nbytes=None):
+        """Allocate a device workspace with torch (nbytes, default the queried
+        size) and hand it to the library; the previous one is released after."""
+        nbytes = self.workspace_query() if nbytes is None else nbytes
+        buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        _check(dmrg_workspace_attach(self.h, C.c_void_p(buf.data_ptr()), nbytes))
+        self._ws = buf
+        return nbytes
+
+    def _grow(self, fn):
+        """Run fn(); with a torch workspace, a DMRG_ENOMEM re-attaches a larger one and runs it again."""
+        try:
+            return fn()
+        except DMRGError as e:
+            if e.code != -2 or self._ws is None:
+                raise
+            self.attach_workspace()
+            return fn()
 
     def set_mps(self, bonds, sites):
         n_sec = np.array([len(b) for b in bonds], dtype=np.int32)
@@ -229,7 +261,7 @@ class Solver:
 
     def prepare(self, k):
         n = C.c_int64()
-        _check(dmrg_prepare(self.h, k, C.byref(n)))
+        self._grow(lambda: _check(dmrg_prepare(self.h, k, C.byref(n))))
         return n.value
 
     @staticmethod
@@ -249,12 +281,12 @@ class Solver:
         self._dev_f64(psi, "psi")
         self._dev_f64(out, "out", psi.numel())
         fl = C.c_double()
-        _check(dmrg_sigma(self.h, k, precision, psi.numel(), _ptr(psi), _ptr(out), C.byref(fl)))
+        self._grow(lambda: _check(dmrg_sigma(self.h, k, precision, psi.numel(), _ptr(psi), _ptr(out), C.byref(fl))))
         return fl.value
 
     def diag(self, k, out):
         self._dev_f64(out, "out")
-        _check(dmrg_diag(self.h, k, out.numel(), _ptr(out)))
+        self._grow(lambda: _check(dmrg_diag(self.h, k, out.numel(), _ptr(out))))
 
     def export_mps(self):
         """The current MPS as {bonds: [[(N, 2Sz, dim), ...] per cut], sites: [flat float64 per site]}."""
@@ -302,9 +334,13 @@ class Solver:
     def step(self, k, direction=0):
         e = np.zeros(self.n_states)
         tau = C.c_double()
-        code = dmrg_step(self.h, k, direction, _ptr(e), C.byref(tau))
-        if code not in (0, -4):
-            _check(code)
+
+        def run():
+            code = dmrg_step(self.h, k, direction, _ptr(e), C.byref(tau))
+            if code not in (0, -4):
+                _check(code)
+            return code
+        code = self._grow(run)
         return e, tau.value, code == 0
 
     def set_precision(self, precision):
@@ -359,17 +395,17 @@ class Solver:
         return dh, dB, e
 
     def stats(self):
-        s = np.zeros(26)
-        _check(dmrg_get_stats(self.h, _ptr(s), 26))
+        s = np.zeros(28)
+        _check(dmrg_get_stats(self.h, _ptr(s), 28))
         keys = ["matvecs", "davidson_iters", "sigma_ms", "env_ms", "svd_ms", "sigma_flops", "tau",
                 "max_bond", "fallbacks", "converged", "sigma_a_ms", "sigma_b_ms", "sigma_a_flops",
                 "sigma_b_flops", "env_flops", "refinements", "sigma_b_gemm_ms", "grad_ms", "grad_flops",
                 "prepare_ms", "resolve_ms", "davidson_ms", "plan_hits", "sigma_a_flops_exec",
-                "sigma_b_flops_exec", "lowp_matvecs"]
+                "sigma_b_flops_exec", "lowp_matvecs", "workspace_peak_bytes", "device_allocs_since_attach"]
         return dict(zip(keys, s.tolist()))
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and dmrg_solver_destroy is not None:
             dmrg_solver_destroy(self.h)
             self.h = None
 

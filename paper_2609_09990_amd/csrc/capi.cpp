@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <string>
 
 #include "../../include/dmrg_mi355x.h"
@@ -15,9 +16,27 @@ struct dmrg_problem {
   Problem p;
 };
 struct dmrg_solver {
+  std::unique_ptr<Arena> arena;  // the attached workspace (outlives s)
   Solver* s = nullptr;
   const dmrg_problem* prob = nullptr;
+  Options opt;
+  hipStream_t stream = nullptr;
+  long allocs_at_attach = -1;
 };
+
+namespace {
+// Body of a call on a solver: buffers come from its workspace when one is
+// attached, and the initial MPS reaches the device on the first such call.
+template <class F>
+dmrg_status solver_call(dmrg_solver* s, F&& f) {
+  return guard([&] {
+    DMRG_REQUIRE(s && s->s, ST_EINVAL, "NULL solver");
+    ArenaScope scope(s->arena.get());
+    s->s->materialize();
+    f();
+  });
+}
+}  // namespace
 struct dmrg_mlp {
   MLP* m = nullptr;
 };
@@ -145,6 +164,8 @@ dmrg_status dmrg_solver_create(const dmrg_problem* p, const dmrg_options* o, voi
     DMRG_REQUIRE(op.max_iter >= 1, ST_EINVAL, "max_iter must be >= 1");
     auto* S = new dmrg_solver;
     S->prob = p;
+    S->opt = op;
+    S->stream = (hipStream_t)stream;
     try {
       S->s = new Solver(&p->p, op, (hipStream_t)stream);
     } catch (...) {
@@ -158,14 +179,14 @@ dmrg_status dmrg_solver_create(const dmrg_problem* p, const dmrg_options* o, voi
 void dmrg_solver_destroy(dmrg_solver* s) {
   if (!s) return;
   try {
-    delete s->s;
+    delete s->s;  // buffers return to the workspace, which is dropped after it
   } catch (...) {
   }
   delete s;
 }
 
 dmrg_status dmrg_set_mps(dmrg_solver* s, const int* n_sec, const int* sec, const double* data) {
-  return guard([&] {
+  return solver_call(s, [&] {
     DMRG_REQUIRE(s && n_sec && sec && data, ST_EINVAL, "NULL argument");
     int L = s->prob->p.n;
     std::vector<Bond> bonds(L + 1);
@@ -204,7 +225,7 @@ dmrg_status dmrg_get_bonds(const dmrg_solver* s, int* n_sec, int* sec, int cap) 
 }
 
 dmrg_status dmrg_prepare(dmrg_solver* s, int k, int64_t* n) {
-  return guard([&] {
+  return solver_call(s, [&] {
     DMRG_REQUIRE(s, ST_EINVAL, "NULL solver");
     s->s->prepare(k);
     if (n) *n = s->s->twosite_size(k);
@@ -213,7 +234,7 @@ dmrg_status dmrg_prepare(dmrg_solver* s, int k, int64_t* n) {
 
 dmrg_status dmrg_sigma(dmrg_solver* s, int k, int precision, int64_t n, const double* psi, double* sigma,
                        double* flops) {
-  return guard([&] {
+  return solver_call(s, [&] {
     DMRG_REQUIRE(s && psi && sigma, ST_EINVAL, "NULL argument");
     DMRG_REQUIRE(precision >= 0 && precision <= 2, ST_EINVAL, "unknown precision");
     const long len = s->s->twosite_size(k);
@@ -225,7 +246,7 @@ dmrg_status dmrg_sigma(dmrg_solver* s, int k, int precision, int64_t n, const do
 }
 
 dmrg_status dmrg_diag(dmrg_solver* s, int k, int64_t n, double* diag) {
-  return guard([&] {
+  return solver_call(s, [&] {
     DMRG_REQUIRE(s && diag, ST_EINVAL, "NULL argument");
     const long len = s->s->twosite_size(k);
     DMRG_REQUIRE(n == len, ST_EINVAL,
@@ -237,7 +258,7 @@ dmrg_status dmrg_diag(dmrg_solver* s, int k, int64_t n, double* diag) {
 
 dmrg_status dmrg_export_mps(dmrg_solver* s, int* n_sec, int* sec, int sec_cap, double* data, int64_t data_cap,
                             int64_t* data_size) {
-  return guard([&] {
+  return solver_call(s, [&] {
     DMRG_REQUIRE(s && n_sec && data_size, ST_EINVAL, "NULL argument");
     const auto& b = s->s->bonds();
     int total_sec = 0;
@@ -270,7 +291,7 @@ dmrg_status dmrg_export_mps(dmrg_solver* s, int* n_sec, int* sec, int sec_cap, d
 
 dmrg_status dmrg_truncate(dmrg_solver* s, int k, int direction, int64_t n, const double* psi, double* tau,
                           double* sv, int sv_cap, int* n_kept) {
-  return guard([&] {
+  return solver_call(s, [&] {
     DMRG_REQUIRE(s && psi && tau && n_kept, ST_EINVAL, "NULL argument");
     DMRG_REQUIRE(direction == 0 || direction == 1, ST_EINVAL, "direction must be 0 or 1");
     const long len = s->s->twosite_size(k);
@@ -285,7 +306,7 @@ dmrg_status dmrg_truncate(dmrg_solver* s, int k, int direction, int64_t n, const
 }
 
 dmrg_status dmrg_sweep(dmrg_solver* s, int n_sweeps, double* energies, double* tau) {
-  dmrg_status st = guard([&] {
+  dmrg_status st = solver_call(s, [&] {
     DMRG_REQUIRE(s && energies, ST_EINVAL, "NULL argument");
     DMRG_REQUIRE(n_sweeps >= 1, ST_EINVAL, "n_sweeps must be >= 1");
     std::vector<double> e;
@@ -301,7 +322,7 @@ dmrg_status dmrg_sweep(dmrg_solver* s, int n_sweeps, double* energies, double* t
 }
 
 dmrg_status dmrg_step(dmrg_solver* s, int k, int direction, double* energies, double* tau) {
-  dmrg_status st = guard([&] {
+  dmrg_status st = solver_call(s, [&] {
     DMRG_REQUIRE(s && energies, ST_EINVAL, "NULL argument");
     DMRG_REQUIRE(direction == 0 || direction == 1, ST_EINVAL, "direction must be 0 or 1");
     std::vector<double> e;
@@ -317,7 +338,7 @@ dmrg_status dmrg_step(dmrg_solver* s, int k, int direction, double* energies, do
 }
 
 dmrg_status dmrg_energy(dmrg_solver* s, double* energies) {
-  return guard([&] {
+  return solver_call(s, [&] {
     DMRG_REQUIRE(s && energies, ST_EINVAL, "NULL argument");
     auto e = s->s->mps_energy();
     for (size_t i = 0; i < e.size(); ++i) energies[i] = e[i];
@@ -326,7 +347,7 @@ dmrg_status dmrg_energy(dmrg_solver* s, double* energies) {
 
 dmrg_status dmrg_grad(dmrg_solver* s, const double* state_weights, double* dE_dh, double* dE_dB,
                       double* energies) {
-  return guard([&] {
+  return solver_call(s, [&] {
     DMRG_REQUIRE(s && dE_dh && (dE_dB || s->prob->p.nq == 0), ST_EINVAL, "NULL argument");
     const Problem& P = s->prob->p;
     int ns = s->s->n_states();
@@ -430,14 +451,14 @@ dmrg_status dmrg_set_precond(dmrg_solver* s, int precond, dmrg_mlp* net) {
 }
 
 dmrg_status dmrg_record_triples(dmrg_solver* s, int capacity, int sample) {
-  return guard([&] {
+  return solver_call(s, [&] {
     DMRG_REQUIRE(s, ST_EINVAL, "NULL argument");
     s->s->record_triples(capacity, sample);
   });
 }
 
 dmrg_status dmrg_take_triples(dmrg_solver* s, float* X, float* target, int cap, int* count) {
-  return guard([&] {
+  return solver_call(s, [&] {
     DMRG_REQUIRE(s && count && (cap == 0 || (X && target)), ST_EINVAL, "NULL argument");
     *count = s->s->take_triples(X, target, cap);
   });
@@ -445,7 +466,7 @@ dmrg_status dmrg_take_triples(dmrg_solver* s, float* X, float* target, int cap, 
 
 dmrg_status dmrg_precond_features(dmrg_solver* s, int k, const double* r, const double* d, double theta,
                                   float* X) {
-  return guard([&] {
+  return solver_call(s, [&] {
     DMRG_REQUIRE(s && r && d && X, ST_EINVAL, "NULL argument");
     DMRG_REQUIRE(k >= 0 && k + 1 < s->prob->p.n, ST_EINVAL, "two-site step out of range");
     s->s->features_host_theta(k, r, d, theta, X);
@@ -453,7 +474,7 @@ dmrg_status dmrg_precond_features(dmrg_solver* s, int k, const double* r, const 
 }
 
 dmrg_status dmrg_get_env(dmrg_solver* s, int cut, int side, double* host, int64_t cap, int64_t* size) {
-  return guard([&] {
+  return solver_call(s, [&] {
     DMRG_REQUIRE(s && size && (host || cap == 0), ST_EINVAL, "NULL argument");
     DMRG_REQUIRE(cut >= 0 && cut <= s->prob->p.n && (side == 0 || side == 1), ST_EINVAL, "bad cut/side");
     std::vector<double> v = s->s->env_host(cut, side);
@@ -486,6 +507,50 @@ dmrg_status dmrg_block_gemm(int precision, int mode, int M, int N, int K, const 
   });
 }
 
+dmrg_status dmrg_workspace_query(const dmrg_solver* s, size_t* bytes) {
+  return guard([&] {
+    DMRG_REQUIRE(s && s->s && bytes, ST_EINVAL, "NULL argument");
+    size_t est = s->s->workspace_estimate();
+    if (const Arena* a = s->arena.get()) {
+      size_t need = a->peak();
+      if (a->failed_request()) need = std::max(a->size(), a->in_use() + a->failed_request());
+      est = std::max(est, need + need / 4);
+    }
+    *bytes = est;
+  });
+}
+
+dmrg_status dmrg_workspace_attach(dmrg_solver* s, void* dev_ptr, size_t bytes) {
+  return guard([&] {
+    DMRG_REQUIRE(s && s->s && dev_ptr, ST_EINVAL, "NULL argument");
+    DMRG_REQUIRE(bytes >= (size_t(1) << 20), ST_EINVAL, "a workspace needs at least 1 MiB");
+    auto arena = std::make_unique<Arena>(dev_ptr, bytes);
+    SolverState state;
+    {
+      ArenaScope old_scope(s->arena.get());
+      state = s->s->save_state();
+    }
+    Solver* fresh = nullptr;
+    {
+      ArenaScope scope(arena.get());
+      fresh = new Solver(&s->prob->p, s->opt, s->stream);
+      try {
+        fresh->restore_state(state);
+      } catch (...) {
+        delete fresh;
+        throw;
+      }
+    }
+    {
+      ArenaScope old_scope(s->arena.get());
+      delete s->s;  // its buffers go back to the old workspace (or hipFree) before that one is dropped
+    }
+    s->s = fresh;
+    s->arena = std::move(arena);
+    s->allocs_at_attach = library_device_allocations();
+  });
+}
+
 dmrg_status dmrg_set_kernel_tag(dmrg_solver* s, int tag) {
   return guard([&] {
     DMRG_REQUIRE(s && (tag == 0 || tag == 1), ST_EINVAL, "tag must be 0 or 1");
@@ -497,13 +562,15 @@ dmrg_status dmrg_get_stats(const dmrg_solver* s, double* out, int n) {
   return guard([&] {
     DMRG_REQUIRE(s && out, ST_EINVAL, "NULL argument");
     const Stats& t = s->s->stats();
-    double v[26] = {(double)t.matvecs, (double)t.davidson_iters, t.sigma_ms, t.env_ms, t.svd_ms,
+    double v[28] = {(double)t.matvecs, (double)t.davidson_iters, t.sigma_ms, t.env_ms, t.svd_ms,
                     t.sigma_flops, t.tau, (double)t.max_bond, (double)t.fallbacks, (double)t.converged,
                     t.sigma_a_ms, t.sigma_b_ms, t.sigma_a_flops, t.sigma_b_flops, t.env_flops,
                     (double)t.refinements, t.sigma_b_gemm_ms, t.grad_ms, t.grad_flops, t.prepare_ms,
                     t.resolve_ms, t.davidson_ms, (double)t.plan_hits, t.sigma_a_flops_exec,
-                    t.sigma_b_flops_exec, (double)t.lowp_matvecs};
-    for (int i = 0; i < n && i < 26; ++i) out[i] = v[i];
+                    t.sigma_b_flops_exec, (double)t.lowp_matvecs,
+                    s->arena ? (double)s->arena->peak() : 0.0,
+                    s->allocs_at_attach >= 0 ? (double)(library_device_allocations() - s->allocs_at_attach) : -1.0};
+    for (int i = 0; i < n && i < 28; ++i) out[i] = v[i];
   });
 }
 

@@ -32,6 +32,52 @@ bool same_sectors(const std::vector<Sector>& a, const std::vector<Sector>& b) {
   return true;
 }
 
+size_t Solver::workspace_estimate() const {
+  // environment size of one cut from its bond and the MPO channels (as make_env_layout lays it out)
+  auto env_size = [&](int cut) {
+    const auto& ch = prob_->mpo.chans[cut];
+    std::vector<QN> dqs;
+    std::vector<long> count;
+    for (const auto& c : ch) {
+      int j = -1;
+      for (size_t x = 0; x < dqs.size(); ++x)
+        if (dqs[x] == c.dq) j = (int)x;
+      if (j < 0) {
+        dqs.push_back(c.dq);
+        count.push_back(0);
+        j = (int)dqs.size() - 1;
+      }
+      count[j]++;
+    }
+    std::vector<EnvClass> cls = make_env_classes(bonds_[cut], dqs);
+    long n = 0;
+    for (size_t j = 0; j < cls.size(); ++j) n += cls[j].nnz * count[j];
+    return n;
+  };
+  long env_total = 0, env_max = 0, psi_max = 0, mps = 0;
+  for (int c = 0; c <= L_; ++c) {
+    const long e = env_size(c);
+    env_total += 2 * e;  // left and right environments may both be kept at a cut
+    env_max = std::max(env_max, e);
+  }
+  for (int k = 0; k + 1 < L_; ++k)
+    psi_max = std::max(psi_max, make_tensor_layout(bonds_[k], bonds_[k + 2], twosite_phys_qn()).size);
+  for (int k = 0; k < L_; ++k) mps += make_tensor_layout(bonds_[k], bonds_[k + 1], site_phys_qn()).size;
+  const long kmax = std::min(opt_.max_subspace, 64);
+  long dmax = 0;
+  for (int c = 0; c <= L_; ++c) dmax = std::max<long>(dmax, prob_->mpo.dim(c));
+  // sigma intermediates: T (one block row per left factor and psi slab) and its
+  // low-precision copy grow as (MPO dimension) x |psi| (measured 2.2-2.4 times
+  // that product at CAS(12..20) half sweeps), the premixed factors, merged
+  // blocks and split-K partials as a few environments; Davidson: basis,
+  // products and per-root work vectors
+  const long doubles = env_total + 12 * env_max + 3 * dmax * psi_max + (2 * kmax + 16 + 4 * opt_.n_states) * psi_max +
+                       4 * mps;
+  // half again as much for fragmentation: grow-only buffers are released and
+  // re-carved as the bonds grow along a sweep
+  return (size_t)doubles * 12 + (size_t(256) << 20);
+}
+
 void Solver::make_env_layout(Env& e, int cut, const Bond& b) {
   const auto& ch = prob_->mpo.chans[cut];
   std::vector<QN> dqs;
@@ -66,6 +112,8 @@ void Solver::build_factor_side(FactorSide& fs, bool left, int site) {
   const Env& env = left ? left_[site] : right_[site + 1];
   int mid_cut = left ? site + 1 : site;
   fs = FactorSide();
+  fs.left = left;
+  fs.mix = left ? &lmix_ : &rmix_;
   fs.cut = left ? site : site + 1;
   fs.by_mid.assign(mpo.chans[mid_cut].size(), {});
   // group W entries by (middle channel, op)
@@ -145,7 +193,7 @@ void Solver::build_factor_side(FactorSide& fs, bool left, int site) {
 void Solver::run_premix(FactorSide& fs, const Env& env) {
   int n_out = (int)fs.out_off.size();
   if (n_out == 0) return;
-  fs.mix.reserve(std::max<long>(fs.premix_size, 1) * sizeof(double));
+  fs.mix->reserve(std::max<long>(fs.premix_size, 1) * sizeof(double));
   std::vector<const double*>& srcs = fs.h_srcs;
   srcs.resize(fs.src_off.size());
   for (size_t i = 0; i < srcs.size(); ++i) srcs[i] = env.buf.as<double>() + fs.src_off[i];
@@ -160,7 +208,7 @@ void Solver::run_premix(FactorSide& fs, const Env& env) {
   while (b < n_out) {
     int e = b + 1;
     while (e < n_out && fs.out_nnz[e] == fs.out_nnz[b] && fs.out_off[e] == fs.out_off[e - 1] + fs.out_nnz[e - 1]) ++e;
-    launch_premix(fs.mix.as<double>() + fs.out_off[b], fs.d_srcs.as<const double*>(), fs.d_ptr.as<int>() + b,
+    launch_premix(fs.mix->as<double>() + fs.out_off[b], fs.d_srcs.as<const double*>(), fs.d_ptr.as<int>() + b,
                   fs.d_coef.as<double>(), e - b, fs.out_nnz[b], st);
     b = e;
   }
@@ -169,11 +217,12 @@ void Solver::run_premix(FactorSide& fs, const Env& env) {
 void Solver::run_pairmix(int k) {
   const int ng = (int)pm_.out_off.size();
   if (ng == 0) return;
-  pm_.mix.reserve(std::max<long>(pm_.size, 1) * sizeof(double));
+  pm_.mix = &pmix_;
+  pm_.mix->reserve(std::max<long>(pm_.size, 1) * sizeof(double));
   std::vector<const double*>& srcs = pm_.h_srcs;
   srcs.resize(pm_.src_off.size());
   for (size_t i = 0; i < srcs.size(); ++i) {
-    const double* base = pm_.src_buf[i] == B_YMIX ? rf_.mix.as<double>() : right_[k + 2].buf.as<double>();
+    const double* base = pm_.src_buf[i] == B_YMIX ? rf_.mix->as<double>() : right_[k + 2].buf.as<double>();
     srcs[i] = base + pm_.src_off[i];
   }
   pm_.d_srcs.reserve(srcs.size() * sizeof(void*) + 8);
@@ -188,7 +237,7 @@ void Solver::run_pairmix(int k) {
   hip_check(hipMemcpyAsync(pm_.d_out_off.p, pm_.out_off.data(), pm_.out_off.size() * sizeof(long), hipMemcpyHostToDevice, st),
             "pairmix out");
   hip_check(hipMemcpyAsync(pm_.d_nnz.p, pm_.nnz.data(), pm_.nnz.size() * sizeof(int), hipMemcpyHostToDevice, st), "pairmix nnz");
-  launch_pairmix(pm_.mix.as<double>(), pm_.d_srcs.as<const double*>(), pm_.d_ptr.as<int>(), pm_.d_coef.as<double>(),
+  launch_pairmix(pm_.mix->as<double>(), pm_.d_srcs.as<const double*>(), pm_.d_ptr.as<int>(), pm_.d_coef.as<double>(),
                  pm_.d_out_off.as<long>(), pm_.d_nnz.as<int>(), ng, st);
 }
 
@@ -221,7 +270,7 @@ static void validate_phase(const Phase& ph, const long* sizes) {
 void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* esz, const long* sizes) {
   if (ph.units.empty()) return;
   int slot = prec == PREC_F64 ? 0 : (prec == PREC_F32 ? 1 : 2);
-  bool same = ph.uploaded[slot];
+  bool same = ph.uploaded[slot] && (ph.n_tiles[slot] == 0 || ph.slot_base[slot] == splitk_.p);
   for (int b = 0; b < B_NBUF && same; ++b) same = ph.last_bases[slot][b] == bases[b];
   if (same) {  // plan already resolved against these buffers
     launch_resolved(ph, prec, slot);
@@ -338,9 +387,13 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
         }
     }
     const size_t slot_esz = prec == PREC_F64 ? sizeof(double) : sizeof(float);
-    ph.slots_f[slot].reserve(std::max<long>(n_slot_elems, 1) * slot_esz);
-    for (auto& un : units)
-      if (un.accumulate == 2) un.C = (char*)ph.slots_f[slot].p + (intptr_t)un.C * slot_esz;
+    if (n_slot_elems > 0) {
+      // grow-only: a move invalidates other resolved plans, which re-resolve (slot_base)
+      splitk_.reserve(n_slot_elems * slot_esz);
+      for (auto& un : units)
+        if (un.accumulate == 2) un.C = (char*)splitk_.p + (intptr_t)un.C * slot_esz;
+    }
+    ph.slot_base[slot] = splitk_.p;
   } else {
     for (const PUnit& u : ph.units) {
       char* C = (char*)bases[u.cbuf] + u.coff * esz[u.cbuf];
@@ -369,17 +422,17 @@ void Solver::launch_resolved(Phase& ph, int prec, int slot) {
       launch_gemm_w32(ph.mode, ph.tag, ph.buf_ok[slot], ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot],
                       ph.d_items[slot].as<GemmItem>(), st);
     if (ph.gemm_done) (void)hipEventRecord(ph.gemm_done, st);  // GEMM-only timing
-    launch_splitk_reduce(ph.d_tiles[slot].as<SplitTile>(), ph.n_tiles[slot], ph.slots_f[slot].as<double>(), st);
+    launch_splitk_reduce(ph.d_tiles[slot].as<SplitTile>(), ph.n_tiles[slot], splitk_.as<double>(), st);
   } else if (prec == PREC_F32 && ph.wg_used[slot]) {
     launch_gemm_wg(PREC_F32, 0, ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot], ph.d_items[slot].as<GemmItem>(), st);
-    launch_splitk_reduce_f32(ph.d_tiles[slot].as<SplitTile>(), ph.n_tiles[slot], ph.slots_f[slot].as<float>(), st);
+    launch_splitk_reduce_f32(ph.d_tiles[slot].as<SplitTile>(), ph.n_tiles[slot], splitk_.as<float>(), st);
   } else if (prec == PREC_F32) {
     launch_gemm_w32_f32(ph.mode, ph.buf_ok[slot], ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot], ph.d_items[slot].as<GemmItem>(), st);
-    launch_splitk_reduce_f32(ph.d_tiles[slot].as<SplitTile>(), ph.n_tiles[slot], ph.slots_f[slot].as<float>(), st);
+    launch_splitk_reduce_f32(ph.d_tiles[slot].as<SplitTile>(), ph.n_tiles[slot], splitk_.as<float>(), st);
   } else if (prec == PREC_BF16 || prec == 3) {
     launch_gemm_w32_bf16(ph.mode, prec == 3, ph.buf_ok[slot], ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot],
                          ph.d_items[slot].as<GemmItem>(), st);
-    launch_splitk_reduce_f32(ph.d_tiles[slot].as<SplitTile>(), ph.n_tiles[slot], ph.slots_f[slot].as<float>(), st);
+    launch_splitk_reduce_f32(ph.d_tiles[slot].as<SplitTile>(), ph.n_tiles[slot], splitk_.as<float>(), st);
   } else {
     launch_gemm(prec, ph.mode, ph.d_units[slot].as<GemmUnit>(), ph.n_units[slot], ph.d_items[slot].as<GemmItem>(), st);
   }
@@ -488,7 +541,7 @@ void Solver::env_update_left(int k, const FactorSide& fs) {
   bases[B_PSI] = A.buf.p;
   bases[B_OUT] = out.buf.p;
   bases[B_T] = env_t_buf_.p;
-  bases[B_XMIX] = fs.mix.p;
+  bases[B_XMIX] = fs.mix->p;
   bases[B_ENVL] = envk.buf.p;
   size_t esz[B_NBUF] = {8, 8, 8, 8, 8, 8, 8, 8, 8};
   long sizes[B_NBUF] = {};
@@ -630,7 +683,7 @@ void Solver::env_update_right(int j, const FactorSide& fs) {
   void* bases[B_NBUF] = {};
   bases[B_OUT] = out.buf.p;
   bases[B_T] = env_t_buf_.p;
-  bases[B_YMIX] = fs.mix.p;
+  bases[B_YMIX] = fs.mix->p;
   bases[B_ENVR] = envr.buf.p;
   bases[B_SITE2] = Bt.buf.p;
   size_t esz[B_NBUF] = {8, 8, 8, 8, 8, 8, 8, 8, 8};
@@ -924,9 +977,9 @@ void Solver::build_diag_plan(int k) {
       if (desc_buf[i] == bufid) d.insert(d.end(), diag_desc_.begin() + 4 * i, diag_desc_.begin() + 4 * i + 4);
     if (d.empty()) continue;
     const double* src = bufid == B_ENVL ? left_[k].buf.as<double>()
-                        : bufid == B_XMIX ? lf_.mix.as<double>()
+                        : bufid == B_XMIX ? lf_.mix->as<double>()
                         : bufid == B_ENVR ? right_[k + 2].buf.as<double>()
-                                          : rf_.mix.as<double>();
+                                          : rf_.mix->as<double>();
     DevMem dd;
     dd.reserve(d.size() * sizeof(int64_t));
     hip_check(hipMemcpyAsync(dd.p, d.data(), d.size() * sizeof(int64_t), hipMemcpyHostToDevice, st), "diag desc");

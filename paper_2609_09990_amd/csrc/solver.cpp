@@ -6,6 +6,7 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -18,21 +19,111 @@ void hip_check(hipError_t e, const char* what) {
     throw Error(ST_EHIP, std::string("HIP error in ") + what + ": " + hipGetErrorString(e));
 }
 
+namespace {
+std::atomic<long> g_hip_allocs{0};
+constexpr size_t kGranule = 256;
+}  // namespace
+
+Arena*& current_arena() {
+  thread_local Arena* a = nullptr;
+  return a;
+}
+
+long library_device_allocations() { return g_hip_allocs.load(); }
+
+Arena::Arena(void* base, size_t bytes) : base_((char*)base), size_(bytes) {
+  const size_t skip = (kGranule - (uintptr_t)base_ % kGranule) % kGranule;
+  DMRG_REQUIRE(bytes > skip + kGranule, ST_EINVAL, "workspace too small");
+  free_[skip] = (bytes - skip) / kGranule * kGranule;
+}
+
+void* Arena::alloc(size_t bytes) {
+  const size_t need = (std::max<size_t>(bytes, 1) + kGranule - 1) / kGranule * kGranule;
+  // best fit; large buffers (environments, sigma intermediates, Davidson basis)
+  // are cut from the top of their range and small ones (plan tables) from the
+  // bottom, so the small ones do not split the space the large ones need
+  auto best = free_.end();
+  for (auto it = free_.begin(); it != free_.end(); ++it)
+    if (it->second >= need && (best == free_.end() || it->second < best->second)) best = it;
+  if (best != free_.end()) {
+    const size_t off = best->first, len = best->second;
+    free_.erase(best);
+    size_t at = off;
+    if (need >= (size_t(64) << 20)) {
+      at = off + len - need;
+      if (len > need) free_[off] = len - need;
+    } else if (len > need) {
+      free_[off + need] = len - need;
+    }
+    used_[at] = need;
+    in_use_ += need;
+    peak_ = std::max(peak_, in_use_);
+    return base_ + at;
+  }
+  failed_ = need;
+  throw Error(ST_ENOMEM, "workspace exhausted: " + std::to_string(need) + " bytes requested with " +
+                             std::to_string(in_use_) + " of " + std::to_string(size_) +
+                             " in use; dmrg_workspace_query gives the size to attach");
+}
+
+void Arena::free(void* p) {
+  const size_t off = (size_t)((char*)p - base_);
+  auto it = used_.find(off);
+  if (it == used_.end()) return;
+  size_t start = off, len = it->second;
+  in_use_ -= len;
+  used_.erase(it);
+  auto nx = free_.lower_bound(start);
+  if (nx != free_.end() && nx->first == start + len) {  // merge with the next free range
+    len += nx->second;
+    nx = free_.erase(nx);
+  }
+  if (nx != free_.begin()) {  // and with the previous one
+    auto pv = std::prev(nx);
+    if (pv->first + pv->second == start) {
+      start = pv->first;
+      len += pv->second;
+      free_.erase(pv);
+    }
+  }
+  free_[start] = len;
+}
+
 DevMem::~DevMem() { release(); }
 void DevMem::release() {
-  if (p) (void)hipFree(p);
+  if (p) {
+    if (arena) arena->free(p);
+    else (void)hipFree(p);
+  }
   p = nullptr;
   bytes = 0;
+  arena = nullptr;
 }
 void DevMem::reserve(size_t b) {
   if (b <= bytes && p) return;
+  const size_t grown = p ? bytes : 0;
   release();
   if (b == 0) b = 8;
+  if (Arena* a = current_arena()) {
+    // a grown buffer keeps a quarter of headroom: fewer reallocations, less fragmentation
+    const size_t want = grown ? std::max(b, grown + grown / 4) : b;
+    try {
+      p = a->alloc(want);
+      bytes = want;
+    } catch (const Error&) {
+      if (want == b) throw;
+      p = a->alloc(b);
+      bytes = b;
+    }
+    arena = a;
+    return;
+  }
   hipError_t e = hipMalloc(&p, b);
   if (e != hipSuccess) {
     p = nullptr;
     throw Error(ST_ENOMEM, "device allocation of " + std::to_string(b) + " bytes failed");
   }
+  ++g_hip_allocs;
   bytes = b;
 }
 
@@ -106,8 +197,6 @@ Solver::Solver(const Problem* p, const Options& o, hipStream_t s) : prob_(p), op
   opt_.max_subspace = std::max(std::min(opt_.max_subspace, 64), 2 * opt_.n_states + 2);
   DMRG_REQUIRE(opt_.precond == 0 || opt_.precond == 1, ST_EINVAL, "unknown preconditioner");
   precond_ = opt_.precond;
-  if (rocblas_create_handle(&rb_) != rocblas_status_success) throw Error(ST_EHIP, "rocblas handle");
-  rocblas_set_stream(rb_, st);
   init_random_mps();
 }
 
@@ -118,7 +207,6 @@ Solver::~Solver() {
   }
   for (hipEvent_t& e : aux_ev_)
     if (e) (void)hipEventDestroy(e);
-  if (rb_) rocblas_destroy_handle(rb_);
 }
 
 // Right-canonical random MPS in the target sector: every slab (rows of one
@@ -181,14 +269,84 @@ void Solver::init_random_mps() {
           for (int c = 0; c < sl.width; ++c) row[c] /= nrm;
         }
     }
-    t.buf.reserve(std::max<long>(t.lay.size, 1) * sizeof(double));
-    hip_check(hipMemcpy(t.buf.p, h.data(), t.lay.size * sizeof(double), hipMemcpyHostToDevice), "mps upload");
+    pending_mps_.insert(pending_mps_.end(), h.begin(), h.end());
   }
   for (auto& e : left_) e.valid = false;
   for (auto& e : right_) e.valid = false;
   plan_k_ = -1;
   centers_.clear();
   center_site_ = 0;  // every site right-canonical: the orthogonality centre is site 0
+}
+
+void Solver::materialize() {
+  if (pending_mps_.empty()) return;
+  long off = 0;
+  for (int k = 0; k < L_; ++k) {
+    SiteTensor& t = mps_[k];
+    t.buf.reserve(std::max<long>(t.lay.size, 1) * sizeof(double));
+    hip_check(hipMemcpy(t.buf.p, pending_mps_.data() + off, t.lay.size * sizeof(double), hipMemcpyHostToDevice),
+              "mps upload");
+    off += t.lay.size;
+  }
+  std::vector<double>().swap(pending_mps_);
+}
+
+SolverState Solver::save_state() {
+  SolverState s;
+  s.bonds = bonds_;
+  s.mps = pending_mps_.empty() ? export_mps() : pending_mps_;
+  s.center_site = center_site_;
+  for (const DevMem& c : centers_) {
+    std::vector<double> h(center_lay_.size);
+    if (center_lay_.size > 0)
+      hip_check(hipMemcpy(h.data(), c.p, center_lay_.size * sizeof(double), hipMemcpyDeviceToHost), "centre save");
+    s.centers.push_back(std::move(h));
+  }
+  if (!centers_.empty()) {
+    const int cs = center_site_;
+    s.center_bond_l = bonds_[cs].sec;
+    s.center_bond_r = bonds_[cs + 1].sec;
+  }
+  s.opt = opt_;
+  s.precond = precond_;
+  s.net = net_;
+  s.rec_cap = rec_cap_;
+  s.rec_sample = rec_sample_;
+  s.kernel_tag = kernel_tag_;
+  s.stats = st_;
+  return s;
+}
+
+void Solver::restore_state(const SolverState& s) {
+  std::vector<const double*> sites(L_);
+  long off = 0;
+  for (int k = 0; k < L_; ++k) {
+    sites[k] = s.mps.data() + off;
+    off += make_tensor_layout(s.bonds[k], s.bonds[k + 1], site_phys_qn()).size;
+  }
+  std::vector<double>().swap(pending_mps_);
+  set_mps(s.bonds, sites);
+  center_site_ = s.center_site;
+  if (!s.centers.empty() && s.center_site >= 0) {
+    Bond bl, br;
+    bl.sec = s.center_bond_l;
+    br.sec = s.center_bond_r;
+    center_lay_ = make_tensor_layout(bl, br, site_phys_qn());
+    centers_.resize(s.centers.size());
+    for (size_t r = 0; r < s.centers.size(); ++r) {
+      centers_[r].reserve(std::max<long>(center_lay_.size, 1) * 8);
+      if (center_lay_.size > 0)
+        hip_check(hipMemcpy(centers_[r].p, s.centers[r].data(), center_lay_.size * 8, hipMemcpyHostToDevice),
+                  "centre restore");
+    }
+  }
+  opt_ = s.opt;
+  precond_ = s.precond;
+  net_ = (MLP*)s.net;
+  rec_cap_ = s.rec_cap;
+  rec_sample_ = s.rec_sample;
+  kernel_tag_ = s.kernel_tag;
+  st_ = s.stats;
 }
 
 void Solver::set_mps(const std::vector<Bond>& bonds, const std::vector<const double*>& sites) {
@@ -203,6 +361,7 @@ void Solver::set_mps(const std::vector<Bond>& bonds, const std::vector<const dou
       if (i) DMRG_REQUIRE(bonds[c].sec[i - 1].q < bonds[c].sec[i].q, ST_EINVAL, "sectors must be sorted");
     }
   bonds_ = bonds;
+  std::vector<double>().swap(pending_mps_);
   for (int k = 0; k < L_; ++k) {
     SiteTensor& t = mps_[k];
     t.lay = make_tensor_layout(bonds_[k], bonds_[k + 1], site_phys_qn());
@@ -231,6 +390,7 @@ void Solver::ensure_left(int c) {
     return;
   }
   ensure_left(c - 1);
+  plan_k_ = -1;  // the update reuses the left premix buffer of the prepared step
   FactorSide fs;
   build_factor_side(fs, true, c - 1);
   run_premix(fs, left_[c - 1]);
@@ -253,6 +413,7 @@ void Solver::ensure_right(int c) {
     return;
   }
   ensure_right(c + 1);
+  plan_k_ = -1;  // the update reuses the right premix buffer of the prepared step
   FactorSide fs;
   build_factor_side(fs, false, c);
   run_premix(fs, right_[c + 1]);
@@ -367,9 +528,9 @@ void Solver::ensure_lowp(int prec) {
   struct Src { int id; const double* p; long n; };
   Src src[] = {{B_ENVL, left_[k].buf.as<double>(), left_[k].size},
                {B_ENVR, right_[k + 2].buf.as<double>(), right_[k + 2].size},
-               {B_XMIX, lf_.mix.as<double>(), lf_.premix_size},
-               {B_YMIX, rf_.mix.as<double>(), rf_.premix_size},
-               {B_YPAIR, pm_.mix.as<double>(), pm_.size}};
+               {B_XMIX, lmix_.as<double>(), lf_.premix_size},
+               {B_YMIX, rmix_.as<double>(), rf_.premix_size},
+               {B_YPAIR, pmix_.as<double>(), pm_.size}};
   size_t esz = prec == PREC_F32 ? 4 : 2;
   for (auto& s : src) {
     lowp_[s.id].reserve(std::max<long>(s.n, 1) * esz);
@@ -408,11 +569,11 @@ void Solver::sigma(int k, int prec, const double* psi, double* out) {
     bases[B_PSI] = psi_in_.p;
     bases[B_OUT] = out_buf_.p;
     bases[B_T] = t_buf_.p;
-    bases[B_XMIX] = lf_.mix.p;
-    bases[B_YMIX] = rf_.mix.p;
+    bases[B_XMIX] = lmix_.p;
+    bases[B_YMIX] = rmix_.p;
     bases[B_ENVL] = left_[k].buf.p;
     bases[B_ENVR] = right_[k + 2].buf.p;
-    bases[B_YPAIR] = pm_.mix.p;
+    bases[B_YPAIR] = pmix_.p;
     size_t esz[B_NBUF] = {8, 8, 8, 8, 8, 8, 8, 8, 8};
     launch_copy(psi_in_.as<double>(), psi, n, st);
     phA_.tag = 1 + 2 * kernel_tag_;
@@ -1016,11 +1177,30 @@ void Solver::svd_step(int k, bool l2r, int nr, std::vector<DevMem>& next_guess, 
     for (auto& bk_ : buckets) {
       int nbk = bk_.first;
       int first = bk_.second[0];
-      rocblas_status rs = rocsolver_dsyevd_strided_batched(
-          aux_rb_[bi % kAuxStreams], rocblas_evect_original, rocblas_fill_upper, nbk, gram.as<double>() + goff[first],
-          nbk, (rocblas_stride)nbk * nbk, evals.as<double>() + eoff[first], nbk,
-          evals.as<double>() + etot + eoff[first], nbk, info.as<rocblas_int>() + info_off,
-          (rocblas_int)bk_.second.size());
+      rocblas_handle hb = aux_rb_[bi % kAuxStreams];
+      auto call = [&]() {
+        return rocsolver_dsyevd_strided_batched(
+            hb, rocblas_evect_original, rocblas_fill_upper, nbk, gram.as<double>() + goff[first], nbk,
+            (rocblas_stride)nbk * nbk, evals.as<double>() + eoff[first], nbk, evals.as<double>() + etot + eoff[first],
+            nbk, info.as<rocblas_int>() + info_off, (rocblas_int)bk_.second.size());
+      };
+      if (current_arena()) {
+        // in an arena the handle's device workspace comes from it too: size query, then attach
+        size_t need = 0;
+        if (rocblas_start_device_memory_size_query(hb) != rocblas_status_success)
+          throw Error(ST_EHIP, "rocBLAS workspace size query");
+        (void)call();
+        if (rocblas_stop_device_memory_size_query(hb, &need) != rocblas_status_success)
+          throw Error(ST_EHIP, "rocBLAS workspace size query");
+        DevMem& w = rb_work_[bi % kAuxStreams];
+        if (need > w.bytes || !w.p) {
+          hip_check(hipStreamSynchronize(aux_st_[bi % kAuxStreams]), "rocBLAS workspace");
+          w.reserve(std::max<size_t>(need, 1 << 20));
+          if (rocblas_set_workspace(hb, w.p, w.bytes) != rocblas_status_success)
+            throw Error(ST_EHIP, "rocblas_set_workspace");
+        }
+      }
+      rocblas_status rs = call();
       if (rs != rocblas_status_success) throw Error(ST_EHIP, "rocsolver_dsyevd_strided_batched failed");
       info_off += (long)bk_.second.size();
       ++bi;
@@ -1082,8 +1262,34 @@ void Solver::svd_step(int k, bool l2r, int nr, std::vector<DevMem>& next_guess, 
       new_index[i] = (int)nb.sec.size();
       nb.sec.push_back({mids[i].q, kept[i]});
     }
-  bonds_[k + 1] = nb;
   st_.max_bond = std::max(st_.max_bond, nb.total());
+  // Every buffer the new tensors need is reserved before the bond table and the
+  // MPS change, so a failed allocation (DMRG_ENOMEM in a workspace) leaves the
+  // state as it was.
+  TensorLayout clay;  // center layout
+  const long fixed_size = l2r ? make_tensor_layout(bonds_[k], nb, site_phys_qn()).size
+                              : make_tensor_layout(nb, bonds_[k + 2], site_phys_qn()).size;
+  clay = l2r ? make_tensor_layout(nb, bonds_[k + 2], site_phys_qn()) : make_tensor_layout(bonds_[k], nb, site_phys_qn());
+  DevMem fresh_fixed;  // used when the tensor being replaced has too small an allocation
+  if (mps_[l2r ? k : k + 1].buf.bytes < (size_t)std::max<long>(fixed_size, 1) * 8)
+    fresh_fixed.reserve(std::max<long>(fixed_size, 1) * 8);
+  centers_.resize(nr);
+  for (int r = 0; r < nr; ++r) centers_[r].reserve(std::max<long>(clay.size, 1) * 8);
+  {
+    long su = 0;
+    for (size_t i = 0; i < mids.size(); ++i)
+      if (kept[i] > 0) su += (long)(l2r ? mids[i].R : mids[i].C) * kept[i];
+    (l2r ? Uv : Vv).reserve(std::max<long>(su, 1) * 8);
+  }
+  DevMem fresh_center;  // the centre site's new tensor, when its allocation is too small
+  {
+    const long other = make_tensor_layout(l2r ? nb : bonds_[k], l2r ? bonds_[k + 2] : nb, site_phys_qn()).size;
+    if (mps_[l2r ? k + 1 : k].buf.bytes < (size_t)std::max<long>(other, 1) * 8)
+      fresh_center.reserve(std::max<long>(other, 1) * 8);
+  }
+  // commit: from here on the bond table and the MPS change
+  if (fresh_center.p) mps_[l2r ? k + 1 : k].buf = std::move(fresh_center);
+  bonds_[k + 1] = nb;
   // kept singular vectors in descending order: U (R x nm, column-major) moving
   // right, V^T (nm x C, column-major) moving left
   std::vector<long> oU(mids.size(), 0), oV(mids.size(), 0);
@@ -1124,22 +1330,10 @@ void Solver::svd_step(int k, bool l2r, int nr, std::vector<DevMem>& next_guess, 
   // it takes over the allocation of the tensor it replaces (no longer read from
   // here on): a stable address keeps the cached environment-update plan resolved
   // and saves an allocation and a free per step
-  fixed.buf = std::move(mps_[l2r ? k : k + 1].buf);
-  TensorLayout clay;  // center layout
-  if (l2r) {
-    fixed.lay = make_tensor_layout(bonds_[k], nb, site_phys_qn());
-    clay = make_tensor_layout(nb, bonds_[k + 2], site_phys_qn());
-  } else {
-    fixed.lay = make_tensor_layout(nb, bonds_[k + 2], site_phys_qn());
-    clay = make_tensor_layout(bonds_[k], nb, site_phys_qn());
-  }
-  fixed.buf.reserve(std::max<long>(fixed.lay.size, 1) * 8);
+  fixed.buf = fresh_fixed.p ? std::move(fresh_fixed) : std::move(mps_[l2r ? k : k + 1].buf);
+  fixed.lay = l2r ? make_tensor_layout(bonds_[k], nb, site_phys_qn()) : make_tensor_layout(nb, bonds_[k + 2], site_phys_qn());
   launch_fill(fixed.buf.as<double>(), fixed.lay.size, 0.0, st);
-  centers_.resize(nr);
-  for (int r = 0; r < nr; ++r) {
-    centers_[r].reserve(std::max<long>(clay.size, 1) * 8);
-    launch_fill(centers_[r].as<double>(), clay.size, 0.0, st);
-  }
+  for (int r = 0; r < nr; ++r) launch_fill(centers_[r].as<double>(), clay.size, 0.0, st);
   for (size_t i = 0; i < mids.size(); ++i) {
     if (kept[i] == 0) continue;
     const Mid& m = mids[i];
@@ -1334,6 +1528,7 @@ double Solver::truncate(int k, bool l2r, const double* psi) {
 }
 
 std::vector<double> Solver::export_mps() const {
+  if (!pending_mps_.empty()) return pending_mps_;
   long total = 0;
   for (int k = 0; k < L_; ++k) total += mps_[k].lay.size;
   std::vector<double> out(total);

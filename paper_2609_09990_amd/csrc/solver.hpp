@@ -7,6 +7,7 @@
 
 #include <array>
 #include <map>
+#include <memory>
 #include <vector>
 
 #include "kernels.hpp"
@@ -30,16 +31,63 @@ struct Options {
   int verbose = 0;
 };
 
+// A caller-provided slab of device memory that the library carves into its
+// buffers (the single preallocated arena of the paper's device engine, Sec. III):
+// first fit over free ranges, 256-byte granules, neighbouring free ranges merged.
+class Arena {
+ public:
+  Arena(void* base, size_t bytes);
+  void* alloc(size_t bytes);  // Error(ST_ENOMEM) when no free range fits
+  void free(void* p);
+  size_t size() const { return size_; }
+  size_t in_use() const { return in_use_; }
+  size_t peak() const { return peak_; }
+  size_t failed_request() const { return failed_; }  // bytes of the last request that did not fit (0: none)
+  bool contains(const void* p) const { return (const char*)p >= base_ && (const char*)p < base_ + size_; }
+
+ private:
+  char* base_;
+  size_t size_;
+  std::map<size_t, size_t> free_, used_;  // offset -> length
+  size_t in_use_ = 0, peak_ = 0, failed_ = 0;
+};
+
+// Buffers reserved while an arena is current (thread-local, set around every
+// call on a solver that has a workspace) come from it; otherwise from hipMalloc.
+Arena*& current_arena();
+struct ArenaScope {
+  Arena* prev;
+  explicit ArenaScope(Arena* a) : prev(current_arena()) { current_arena() = a; }
+  ~ArenaScope() { current_arena() = prev; }
+  ArenaScope(const ArenaScope&) = delete;
+  ArenaScope& operator=(const ArenaScope&) = delete;
+};
+// Number of hipMalloc calls the library's buffers have made (process-wide).
+long library_device_allocations();
+
 // Grow-only device buffer.
 struct DevMem {
   void* p = nullptr;
   size_t bytes = 0;
+  Arena* arena = nullptr;  // the arena the memory came from (nullptr: hipMalloc)
   DevMem() = default;
   DevMem(const DevMem&) = delete;
   DevMem& operator=(const DevMem&) = delete;
-  DevMem(DevMem&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevMem(DevMem&& o) noexcept : p(o.p), bytes(o.bytes), arena(o.arena) {
+    o.p = nullptr;
+    o.bytes = 0;
+    o.arena = nullptr;
+  }
   DevMem& operator=(DevMem&& o) noexcept {
-    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    if (this != &o) {
+      release();
+      p = o.p;
+      bytes = o.bytes;
+      arena = o.arena;
+      o.p = nullptr;
+      o.bytes = 0;
+      o.arena = nullptr;
+    }
     return *this;
   }
   ~DevMem();
@@ -107,7 +155,8 @@ struct Phase {
   std::vector<GemmItem> h_items[3];  // host staging kept alive for async copies
   std::vector<GemmUnit> h_units[3];
   std::vector<SplitTile> h_tiles[3];
-  DevMem d_tiles[3], slots_f[3];     // split-K tile table and partial slots per precision slot
+  DevMem d_tiles[3];                 // split-K tile table per precision slot
+  const void* slot_base[3] = {};     // split-K scratch the units were resolved against
   int n_units[3] = {0, 0, 0}, n_tiles[3] = {0, 0, 0};
   const void* last_bases[3][B_NBUF] = {};
   bool uploaded[3] = {false, false, false};
@@ -139,7 +188,8 @@ struct FactorSide {
   std::vector<long> out_off;  // per premixed output (element offset in premix buffer)
   std::vector<long> out_nnz;
   long premix_size = 0;
-  DevMem mix;
+  bool left = true;
+  DevMem* mix = nullptr;  // the solver's premix buffer of this side (shared by every plan of the side)
   DevMem d_srcs, d_ptr, d_coef;
   std::vector<const double*> h_srcs;
 };
@@ -156,7 +206,8 @@ struct PairMix {
   std::vector<long> out_off;  // per group: element offset in mix
   std::vector<int> nnz;       // per group: N x K
   long size = 0;
-  DevMem mix, d_srcs, d_ptr, d_coef, d_out_off, d_nnz;
+  DevMem* mix = nullptr;  // the solver's merged-block buffer
+  DevMem d_srcs, d_ptr, d_coef, d_out_off, d_nnz;
   std::vector<const double*> h_srcs;
 };
 
@@ -181,10 +232,35 @@ struct Stats {
 
 class MLP;
 
+// What a solver carries over when its device memory moves to a new workspace.
+struct SolverState {
+  std::vector<Bond> bonds;
+  std::vector<double> mps;  // all site tensors in slab layout
+  int center_site = -1;
+  std::vector<std::vector<double>> centers;  // per-root centre tensors of the last truncation
+  std::vector<Sector> center_bond_l, center_bond_r;
+  Options opt;
+  int precond = 0;
+  void* net = nullptr;
+  int rec_cap = 0, rec_sample = 0;
+  int kernel_tag = 0;
+  Stats stats;
+};
+
 class Solver {
  public:
+  // The initial MPS is made on the host; it reaches the device on the first
+  // call that needs device state (materialize), so creating a solver allocates
+  // no device memory.
   Solver(const Problem* p, const Options& o, hipStream_t s);
   ~Solver();
+  void materialize();
+  SolverState save_state();
+  void restore_state(const SolverState& s);
+  // Device bytes a sweep at the current bonds is expected to need (environments
+  // of every cut, the largest step's sigma intermediates and Davidson basis, the
+  // MPS, plans); an estimate, see dmrg_workspace_query.
+  size_t workspace_estimate() const;
 
   // MPS management
   void init_random_mps();
@@ -244,12 +320,13 @@ class Solver {
   const Problem* prob_;
   Options opt_;
   hipStream_t st;
-  rocblas_handle rb_ = nullptr;
   // the truncation's batched eigensolves run one size bucket per stream (each
   // bucket is a latency-bound chain of small kernels); default priority
   static constexpr int kAuxStreams = 4;
   hipStream_t aux_st_[kAuxStreams] = {};
   rocblas_handle aux_rb_[kAuxStreams] = {};
+  DevMem rb_work_[kAuxStreams];  // rocBLAS workspaces when the solver runs in an arena
+  std::vector<double> pending_mps_;  // host copy of the initial MPS until materialize()
   hipEvent_t aux_ev_[kAuxStreams + 1] = {};
   int L_;
   std::vector<Bond> bonds_;
@@ -266,6 +343,13 @@ class Solver {
   Phase phA_, phB_;
   long t_size_ = 0;
   DevMem psi_in_, out_buf_, t_buf_;
+  // split-K partial tiles of whichever phase is running: phases run one after
+  // another on the solver stream, so one scratch serves every cached plan
+  DevMem splitk_;
+  // premixed factors of the step being solved (left, right) and its merged right
+  // blocks; filled at every prepare, grow-only, so their addresses (and the
+  // resolved plans) stay put from one step to the next
+  DevMem lmix_, rmix_, pmix_;
   DevMem env_t_buf_;  // intermediates of environment updates (kept apart so t_buf_ stays put)
   // Step plans by step k, reused when the outer bonds k and k+2 are unchanged
   // (the plan depends on them and the MPO only; values come from the buffers).
