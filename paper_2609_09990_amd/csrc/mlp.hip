@@ -5,6 +5,8 @@
 // block-GEMM engine (see mlp_net.cpp).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cmath>
 #include <cstring>
 
@@ -92,6 +94,115 @@ __global__ void layer3_kernel(float* __restrict__ z2, long n, int width, const f
   }
   acc = wave_sum(acc);
   if (lane == 0) y[row] = (float)(acc + b3[0]);
+}
+
+// Fused bf16 inference of the width-256 network, y = W3 relu(W2 relu(W1 x + b1)
+// + b2) + b3, without writing activations to memory.  Persistent workgroups of
+// 8 waves (one per CU: W2 in bf16, 256 x 256, is staged once in LDS with a row
+// pitch of 260) walk 32-row tiles: the tile's inputs are staged in LDS; layer 1
+// (thread t: columns 4 (t % 64).. whose W1 rows it keeps in registers, rows
+// 4 (t / 64)..) writes bf16 to LDS, the rounding the layered path applies;
+// layer 2 runs on v_mfma_f32_16x16x16 bf16 (wave w: rows 16 (w & 1).., columns
+// 64 (w >> 1)..: 4 tiles of 16 x 16); layer 3 is a dot product with W3 reduced
+// over lanes and the four column quarters.
+constexpr int kInfW = 256, kInfRows = 32, kInfPitch = kInfW + 4, kInfThreads = 512, kInfMaxIn = 16;
+typedef short v4s_t __attribute__((ext_vector_type(4)));
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(kInfThreads) void mlp_infer_bf16_kernel(
+    const float* __restrict__ X, long n, int nin, const float* __restrict__ W1, const float* __restrict__ b1,
+    const uint16_t* __restrict__ W2b, const float* __restrict__ b2, const float* __restrict__ W3,
+    const float* __restrict__ b3, float* __restrict__ y) {
+  __shared__ __align__(16) uint16_t W2s[kInfW * kInfPitch];
+  __shared__ __align__(16) uint16_t A1s[kInfRows * kInfPitch];
+  __shared__ float Xs[kInfRows * kInfMaxIn];
+  __shared__ float part[4][kInfRows];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < kInfW * kInfW / 4; e += kInfThreads) {  // 4 bf16 (8 bytes) per step
+    const int j = e / (kInfW / 4), i4 = (e % (kInfW / 4)) * 4;
+    *reinterpret_cast<uint2*>(W2s + j * kInfPitch + i4) = *reinterpret_cast<const uint2*>(W2b + (long)j * kInfW + i4);
+  }
+  // layer-1 role of this thread: columns c0..c0+3, rows r0..r0+3 of every tile
+  const int c0 = 4 * (tid & 63), r0 = 4 * (tid >> 6);
+  float w1[4][kInfMaxIn], bb[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    bb[c] = b1[c0 + c];
+#pragma unroll
+    for (int f = 0; f < kInfMaxIn; ++f) w1[c][f] = f < nin ? W1[(c0 + c) * nin + f] : 0.f;
+  }
+  const int rb = wave & 1, cb = (wave >> 1) * 64;
+  const long ntiles = (n + kInfRows - 1) / kInfRows;
+  for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long row0 = tile * kInfRows;
+    __syncthreads();  // W2s staged / the previous tile's Xs, A1s and part[] read
+    for (int e = tid; e < kInfRows * kInfMaxIn; e += kInfThreads) {
+      const int r = e / kInfMaxIn, f = e % kInfMaxIn;
+      Xs[e] = (f < nin && row0 + r < n) ? X[(row0 + r) * nin + f] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int r = r0 + rr;
+      float z[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) z[c] = bb[c];
+#pragma unroll
+      for (int f = 0; f < kInfMaxIn; ++f) {
+        const float xf = Xs[r * kInfMaxIn + f];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) z[c] = fmaf(xf, w1[c][f], z[c]);
+      }
+      uint2 pk;
+      pk.x = (uint32_t)bf16_rne(fmaxf(z[0], 0.f)) | ((uint32_t)bf16_rne(fmaxf(z[1], 0.f)) << 16);
+      pk.y = (uint32_t)bf16_rne(fmaxf(z[2], 0.f)) | ((uint32_t)bf16_rne(fmaxf(z[3], 0.f)) << 16);
+      *reinterpret_cast<uint2*>(A1s + r * kInfPitch + c0) = pk;
+    }
+    __syncthreads();
+    v4f_t acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = (v4f_t){0.f, 0.f, 0.f, 0.f};
+    const int ar = rb * 16 + (lane & 15);
+#pragma unroll 4
+    for (int k0 = 0; k0 < kInfW; k0 += 16) {
+      const int kk = k0 + 4 * (lane >> 4);
+      const uint2 av = *reinterpret_cast<const uint2*>(A1s + ar * kInfPitch + kk);
+      v4s_t a;
+      a[0] = (short)(av.x & 0xffff);
+      a[1] = (short)(av.x >> 16);
+      a[2] = (short)(av.y & 0xffff);
+      a[3] = (short)(av.y >> 16);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int j = cb + 16 * t + (lane & 15);  // B[k][col j] = W2[j][k]
+        const uint2 bv = *reinterpret_cast<const uint2*>(W2s + j * kInfPitch + kk);
+        v4s_t b;
+        b[0] = (short)(bv.x & 0xffff);
+        b[1] = (short)(bv.x >> 16);
+        b[2] = (short)(bv.y & 0xffff);
+        b[3] = (short)(bv.y >> 16);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+      }
+    }
+    // layer 3: element q of acc[t] is row 4 (lane >> 4) + q, column cb + 16 t + (lane & 15)
+    float sq[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int j = cb + 16 * t + (lane & 15);
+      const float bj = b2[j], wj = W3[j];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sq[q] = fmaf(fmaxf(acc[t][q] + bj, 0.f), wj, sq[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int m = 1; m < 16; m <<= 1) sq[q] += __shfl_xor(sq[q], m);
+    if ((lane & 15) == 0)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) part[wave >> 1][rb * 16 + 4 * (lane >> 4) + q] = sq[q];
+    __syncthreads();
+    if (tid < kInfRows && row0 + tid < n)
+      y[row0 + tid] = ((part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid])) + b3[0];
+  }
 }
 
 __global__ void seg_stats_kernel(const float* __restrict__ y, const float* __restrict__ t, int seglen,
@@ -290,6 +401,18 @@ void launch_mlp_layer1(const float* X, long n, int nin, const float* W1, const f
 void launch_mlp_layer3(float* z2, long n, int width, const float* b2, const float* W3, const float* b3, float* y,
                        bool store, hipStream_t s) {
   if (n > 0) layer3_kernel<<<(int)((n + 3) / 4), kThreads, 0, s>>>(z2, n, width, b2, W3, b3, y, store ? 1 : 0);
+}
+bool launch_mlp_infer_bf16(const float* X, long n, int nin, const float* W1, const float* b1, int width,
+                           const uint16_t* W2b, const float* b2, const float* W3, const float* b3, float* y,
+                           hipStream_t s) {
+  if (width != kInfW || nin < 1 || nin > kInfMaxIn) return false;
+  if (n <= 0) return true;
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const long ntiles = (n + kInfRows - 1) / kInfRows;
+  const int grid = (int)std::min<long>(ntiles, std::max(cus, 1));
+  mlp_infer_bf16_kernel<<<grid, kInfThreads, 0, s>>>(X, n, nin, W1, b1, W2b, b2, W3, b3, y);
+  return true;
 }
 void launch_seg_stats(const float* y, const float* t, int nseg, int seglen, double* stats, hipStream_t s) {
   if (nseg > 0) seg_stats_kernel<<<nseg, kThreads, 0, s>>>(y, t, seglen, stats);

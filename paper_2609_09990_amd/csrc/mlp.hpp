@@ -16,6 +16,11 @@ namespace dmrg {
 
 // ---- kernels (mlp.hip) ----
 // a1[i][j] = max(0, b1[j] + sum_f X[i][f] W1[j][f]); fp32 out and/or bf16 bits out.
+// Fused bf16 inference of a width-256 network (n_in <= 16), no activations in
+// memory; returns false (nothing launched) for other shapes.
+bool launch_mlp_infer_bf16(const float* X, long n, int nin, const float* W1, const float* b1, int width,
+                           const uint16_t* W2b, const float* b2, const float* W3, const float* b3, float* y,
+                           hipStream_t s);
 void launch_mlp_layer1(const float* X, long n, int nin, const float* W1, const float* b1, int width,
                        float* a1, uint16_t* a1b, hipStream_t s);
 // y[i] = b3 + sum_j max(0, z2[i][j] + b2[j]) W3[j]; if store, z2 <- max(0, z2 + b2).

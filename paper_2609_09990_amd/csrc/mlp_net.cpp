@@ -115,6 +115,9 @@ void MLP::forward(int prec, const float* X, long n, float* y, hipStream_t s) {
   if (n <= 0) return;
   if (!s) s = st_;
   const float* P = p_.as<float>();
+  if (prec == PREC_BF16 && launch_mlp_infer_bf16(X, n, nin_, P + oW1_, P + ob1_, w_, w2b_.as<uint16_t>(), P + ob2_,
+                                                 P + oW3_, P + ob3_, y, s))
+    return;
   z2_.reserve((size_t)n * w_ * 4);
   if (prec == PREC_BF16) {
     a1b_.reserve((size_t)n * w_ * 2);

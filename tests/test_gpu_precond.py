@@ -30,7 +30,7 @@ def _net_with_oracle_params(pk, F, W, seed):
     return net, Pd
 
 
-@pytest.mark.parametrize("F,W,n", [(8, 256, 1000), (5, 64, 77), (8, 256, 1)])
+@pytest.mark.parametrize("F,W,n", [(8, 256, 1000), (5, 64, 77), (8, 256, 1), (8, 256, 100003)])
 def test_mlp_forward_fp32_and_bf16(F, W, n):
     pk = _pk()
     net, Pd = _net_with_oracle_params(pk, F, W, 1)
@@ -148,3 +148,28 @@ def test_learned_preconditioner_gain_and_same_answer():
           f"matvecs={res[1][2]:.0f} fallbacks={res[1][3]:.0f}; gain={res[0][2] / res[1][2]:.3f}x")
     assert res[0][1] and res[1][1]
     assert abs(res[0][0] - res[1][0]) <= 1e-9
+    # on these Hamiltonians (the training family) the learned candidate needs fewer matvecs
+    assert res[1][2] <= res[0][2]
+
+
+def test_non_finite_network_falls_back_to_the_diagonal():
+    """A network with NaN weights gives non-finite candidates: each is judged and
+    replaced by the diagonal one, so the run equals the diagonal run."""
+    pk = _pk()
+    net = pk.MLP(8, 256, seed=0)
+    p = net.params()
+    p[:] = np.nan
+    net.set_params(p)
+    h, B, e0 = synth.make_hamiltonian(8, 32, 0)
+    res = {}
+    for mode in (0, 1):
+        sol = pk.Solver(pk.Problem(h, B, 4, 4, e0), M=64, tol=1e-10)
+        sol.set_precond(mode, net if mode else None)
+        e, tau, ok = sol.sweep(1)
+        st = sol.stats()
+        res[mode] = (e[0], ok, st["matvecs"], st["fallbacks"])
+    print(f"diag {res[0]}, NaN network {res[1]}", flush=True)
+    assert res[0][1] and res[1][1]
+    assert res[1][3] > 0  # every learned candidate was rejected
+    assert abs(res[0][0] - res[1][0]) <= 1e-10
+    assert res[1][2] == res[0][2]  # the diagonal candidate was used in every iteration
