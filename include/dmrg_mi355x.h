@@ -212,8 +212,47 @@ dmrg_status dmrg_step(dmrg_solver* s, int k, int direction, double* energies, do
 dmrg_status dmrg_truncate(dmrg_solver* s, int k, int direction, int64_t n, const double* psi, double* tau,
                           double* sv, int sv_cap, int* n_kept);
 
-/* <Psi|H|Psi>/<Psi|Psi> + e_core of the current MPS (per root after a sweep). */
+/* <Psi|H|Psi>/<Psi|Psi> + e_core of the current MPS: per root when the centre
+ * tensors of a sweep are present (centre on site 0), else energies[0] for the
+ * MPS as stored (any gauge). */
 dmrg_status dmrg_energy(dmrg_solver* s, double* energies);
+
+/* Excited states by penalty deflation (Sec. II.F: lower converged MPS kept
+ * resident and projected into every two-site optimisation through overlap
+ * environments).  dmrg_deflate_add copies a lower state Phi (same active space
+ * and sector; bonds and site tensors in the layout dmrg_set_mps takes, host
+ * memory) to the device; from then on every Davidson solve of the solver uses
+ * H_eff + sum_j weight_j |phi_j><phi_j| / <Phi_j|Phi_j>, phi_j the projection of
+ * Phi_j into the step's two-site space, and the diagonal preconditioner adds
+ * the penalty's diagonal.  Energies returned by dmrg_step / dmrg_sweep are those
+ * of H (the Ritz value minus the penalty's expectation).  weight (Ha) must be
+ * finite, positive and larger than the gap from the lower state to the target,
+ * else the target may keep a component of the lower state (dmrg_overlap shows
+ * it).  At most 32 lower states; DMRG_EINVAL on a malformed MPS or a zero norm.
+ * dmrg_sigma and dmrg_diag stay those of H_eff alone.  The dual penalty of
+ * Eq. (dualpen) is zero on every state of the (N, S_z) sector the solver works
+ * in, so it needs no term here.  dmrg_deflate_clear drops all lower states. */
+dmrg_status dmrg_deflate_add(dmrg_solver* s, const int* n_sec, const int* sec, const double* data, double weight);
+dmrg_status dmrg_deflate_clear(dmrg_solver* s);
+
+/* Projection of lower state j (added order) into the two-site space of step k,
+ * unscaled (Phi as given): phi[a s1 s2 b] = sum OL[a a'] Phi_k[a' s1 m]
+ * Phi_{k+1}[m s2 b'] OR[b b'] with the fp64 overlap environments OL (sites < k)
+ * and OR (sites > k+1) of the current MPS.  phi: device array of n doubles
+ * (n as for dmrg_sigma).  Synchronises the device. */
+dmrg_status dmrg_deflate_project(dmrg_solver* s, int k, int j, int64_t n, double* phi);
+
+/* <Psi|Phi_j> / (||Psi|| ||Phi_j||) of the current MPS and lower state j, a
+ * transition overlap contracted over the whole chain in fp64 (host *overlap). */
+dmrg_status dmrg_overlap(dmrg_solver* s, int j, double* overlap);
+
+/* <S^2> of the current MPS (the spin guard of Sec. II.F: the solver fixes N
+ * and S_z but is not spin-adapted, so S_z = 0 triplets share the sector):
+ * <S_- S_+> + S_z (S_z + 1) through the solver's environment and sigma kernels
+ * with a bond-dimension-4 MPO of S_- S_+.  s2[n_states] (host): per root when
+ * the centre tensors of a sweep are present (centre on site 0), else s2[0] for
+ * the MPS as stored (any gauge) and s2[1..] untouched. */
+dmrg_status dmrg_s_squared(dmrg_solver* s, double* s2);
 
 /* Integral gradient of the current MPS energy (Sec. II.C: the DMRG node's
  * adjoint; the MPS is held fixed, i.e. the Hellmann-Feynman term, exact for a

@@ -9,11 +9,15 @@ Contents (plain, slow, fp64, written from the definitions):
 * ``fci``   - determinant space with colexicographic string addressing
               (addr = sum_i C(o_i, i+1), the paper's CI addressing, Sec. III),
               Knowles-Handy sigma, dense / Davidson eigensolve, 1-/2-RDMs,
-              <S^2> via ||S_+ c||^2 (Sec. III), integral gradients.
+              <S^2> via ||S_+ c||^2 (Sec. III; per determinant, and with
+              sparse string ladder operators for large spaces), integral
+              gradients.
 * ``fock``  - brute-force Jordan-Wigner Fock-space Hamiltonian for tiny n, for
               any spin-orbital ordering (pins ``fci`` and the MPS sign rule).
 * ``embed`` - MPS -> Fock-space embedding and the two-site projected sigma
-              P^T H P psi (the definition of H_eff psi for a given MPS basis).
+              P^T H P psi (the definition of H_eff psi for a given MPS basis);
+              the projection P^T Phi of another state into a two-site space
+              and the MPS overlap (penalty deflation, Sec. II.F).
 * ``mlp``   - fp64 NumPy 3-layer MLP forward/backward and Adam (reference for
               the preconditioner network kernels).
 * ``mpo``   - the oracle's own MPO of H, built generically from the list of

@@ -183,3 +183,28 @@ def mps_energy(h, B, mps, n_alpha, n_beta, e_core=0.0):
     space = fci.DetSpace(n, n_alpha, n_beta)
     s = fci.sigma(space, h, fci.eri(B), c, e_core)
     return float(np.sum(c * s) / np.sum(c * c))
+
+
+def project_twosite(mps, k, other):
+    """Projection of the state `other` (an MPS of the same sites and sector) into
+    the two-site space of `mps` at step k (sites k, k+1), slab layout:
+    phi[a s1 s2 b] = sum_{x, y} U[x, a] Phi[x s1 s2 y] V[y, b], with U, V the
+    left / right block states of `mps` over the site-product basis (Sec. II.F:
+    a lower state seen from the two-site optimisation of another)."""
+    bonds = mps["bonds"]
+    A = site_tensors(mps)
+    U = left_basis(A, k)
+    V = right_basis(A, k + 2)
+    F = site_tensors(other)
+    full = left_basis(F, len(F)).reshape(-1)
+    full = full.reshape(U.shape[0], 4, 4, V.shape[0])
+    out = np.einsum("xa,xsuy,yb->asub", U, full, V)
+    out = out.reshape(out.shape[0], 16, out.shape[3])
+    return dense_to_slab(bonds[k], bonds[k + 2], twosite_qn(), out)
+
+
+def overlap(mps_a, mps_b):
+    """<A|B> / (||A|| ||B||) of two MPS over the site-product basis."""
+    a = left_basis(site_tensors(mps_a), len(mps_a["sites"])).reshape(-1)
+    b = left_basis(site_tensors(mps_b), len(mps_b["sites"])).reshape(-1)
+    return float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))

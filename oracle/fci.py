@@ -283,3 +283,43 @@ def s_squared(space: DetSpace, C: np.ndarray) -> float:
                 out[ia[b2 & ((1 << n) - 1)], ib[b2 >> n]] += s1 * s2 * C[i, j]
     sz = 0.5 * (space.na - space.nb)
     return float(np.sum(out * out)) + sz * (sz + 1) * float(np.sum(C * C))
+
+
+def _ladder_matrix(n: int, src: np.ndarray, dst: np.ndarray, p: int, create: bool):
+    """One spin's a+_p (create) or a_p on strings src -> dst, with the sign
+    (-1)^(#occupied orbitals below p) of moving the operator into place."""
+    index = {int(s): i for i, s in enumerate(dst)}
+    rows, cols, vals = [], [], []
+    for j, s in enumerate(src):
+        s = int(s)
+        occ = (s >> p) & 1
+        if occ == int(create):
+            continue
+        t = s ^ (1 << p)
+        sgn = -1.0 if bin(s & ((1 << p) - 1)).count("1") & 1 else 1.0
+        rows.append(index[t])
+        cols.append(j)
+        vals.append(sgn)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(len(dst), len(src)))
+
+
+def s_squared_sparse(space: DetSpace, C: np.ndarray) -> float:
+    """<S^2> = ||S_+ c||^2 + S_z (S_z + 1) with S_+ = sum_p a+_{p alpha} a_{p beta},
+    applied as sparse string operators: (S_+ C)[I'_a, I'_b] = sum_p
+    cre_p[I'_a, I_a] C[I_a, I_b] ann_p[I'_b, I_b] (up to the global sign
+    (-1)^(n_alpha) of taking a_{p beta} past the alpha string, which the norm drops)."""
+    n = space.n
+    C = C.reshape(space.shape)
+    sz = 0.5 * (space.na - space.nb)
+    base = sz * (sz + 1) * float(np.sum(C * C))
+    if space.nb == 0 or space.na == n:
+        return base
+    ta = strings(n, space.na + 1)
+    tb = strings(n, space.nb - 1)
+    out = np.zeros((len(ta), len(tb)))
+    for p in range(n):
+        cre = _ladder_matrix(n, space.sa, ta, p, True)
+        ann = _ladder_matrix(n, space.sb, tb, p, False)
+        out += cre @ (ann @ C.T).T
+    return float(np.sum(out * out)) + base
+

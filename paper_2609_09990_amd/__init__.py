@@ -15,6 +15,9 @@ from ._lib import (  # noqa: F401
     dmrg_block_gemm_noalloc,
     dmrg_measure_peaks,
     measure_peaks,
+    dmrg_deflate_add,
+    dmrg_deflate_clear,
+    dmrg_deflate_project,
     dmrg_diag,
     dmrg_energy,
     dmrg_export_mps,
@@ -27,6 +30,8 @@ from ._lib import (  # noqa: F401
     dmrg_mpo_site,
     dmrg_mpo_site_nnz,
     dmrg_options,
+    dmrg_overlap,
+    dmrg_s_squared,
     dmrg_options_default,
     dmrg_prepare,
     dmrg_problem_create,
@@ -44,5 +49,6 @@ from ._lib import (  # noqa: F401
 )
 
 from .autograd import DMRGEnergy, dmrg_energy  # noqa: F401,E402
+from .excited import excited_states  # noqa: F401,E402
 
 FP64, FP32, BF16 = 0, 1, 2

@@ -53,6 +53,11 @@ dmrg_export_mps = _decl("dmrg_export_mps", [_p, _p, _p, _i, _p, _i64, C.POINTER(
 dmrg_truncate = _decl("dmrg_truncate", [_p, _i, _i, _i64, _p, C.POINTER(_d), _p, _i, C.POINTER(_i)])
 dmrg_sweep = _decl("dmrg_sweep", [_p, _i, _p, C.POINTER(_d)])
 dmrg_energy = _decl("dmrg_energy", [_p, _p])
+dmrg_deflate_add = _decl("dmrg_deflate_add", [_p, _p, _p, _p, _d])
+dmrg_deflate_clear = _decl("dmrg_deflate_clear", [_p])
+dmrg_deflate_project = _decl("dmrg_deflate_project", [_p, _i, _i, _i64, _p])
+dmrg_overlap = _decl("dmrg_overlap", [_p, _i, C.POINTER(_d)])
+dmrg_s_squared = _decl("dmrg_s_squared", [_p, _p])
 dmrg_step = _decl("dmrg_step", [_p, _i, _i, _p, C.POINTER(_d)])
 dmrg_set_kernel_tag = _decl("dmrg_set_kernel_tag", [_p, _i])
 dmrg_get_stats = _decl("dmrg_get_stats", [_p, _p, _i])
@@ -370,6 +375,34 @@ class Solver:
         e = np.zeros(self.n_states)
         _check(dmrg_energy(self.h, _ptr(e)))
         return e
+
+    def deflate(self, mps, weight):
+        """Hold a lower state (an export_mps dict of the same problem) for penalty
+        deflation with the given weight (Ha); later solves see H + w |Phi><Phi|."""
+        n_sec = np.array([len(b) for b in mps["bonds"]], dtype=np.int32)
+        sec = np.array([x for b in mps["bonds"] for s in b for x in s], dtype=np.int32)
+        data = np.ascontiguousarray(np.concatenate(mps["sites"]), dtype=np.float64)
+        self._grow(lambda: _check(dmrg_deflate_add(self.h, _ptr(n_sec), _ptr(sec), _ptr(data), float(weight))))
+
+    def clear_deflation(self):
+        _check(dmrg_deflate_clear(self.h))
+
+    def deflate_project(self, k, j, out):
+        """Projection of lower state j into step k's two-site space (device out)."""
+        self._dev_f64(out, "out")
+        self._grow(lambda: _check(dmrg_deflate_project(self.h, k, j, out.numel(), _ptr(out))))
+
+    def overlap(self, j):
+        """Normalised <Psi|Phi_j> of the current MPS with lower state j (fp64)."""
+        v = C.c_double()
+        self._grow(lambda: _check(dmrg_overlap(self.h, j, C.byref(v))))
+        return v.value
+
+    def s_squared(self):
+        """Per-root <S^2> of the current MPS (centre on site 0, i.e. after a sweep)."""
+        v = np.zeros(self.n_states)
+        self._grow(lambda: _check(dmrg_s_squared(self.h, _ptr(v))))
+        return v
 
     def env(self, cut, side):
         """Environment arrays of the current MPS (side 0 left, 1 right), host copy."""

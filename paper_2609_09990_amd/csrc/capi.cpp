@@ -345,6 +345,57 @@ dmrg_status dmrg_energy(dmrg_solver* s, double* energies) {
   });
 }
 
+dmrg_status dmrg_deflate_add(dmrg_solver* s, const int* n_sec, const int* sec, const double* data, double weight) {
+  return solver_call(s, [&] {
+    DMRG_REQUIRE(s && n_sec && sec && data, ST_EINVAL, "NULL argument");
+    int L = s->prob->p.n;
+    std::vector<Bond> bonds(L + 1);
+    long idx = 0;
+    for (int c = 0; c <= L; ++c) {
+      DMRG_REQUIRE(n_sec[c] >= 1, ST_EINVAL, "every bond needs at least one sector");
+      for (int i = 0; i < n_sec[c]; ++i, ++idx)
+        bonds[c].sec.push_back({{sec[3 * idx], sec[3 * idx + 1]}, sec[3 * idx + 2]});
+    }
+    std::vector<const double*> sites(L);
+    long off = 0;
+    for (int k = 0; k < L; ++k) {
+      sites[k] = data + off;
+      off += make_tensor_layout(bonds[k], bonds[k + 1], site_phys_qn()).size;
+    }
+    s->s->deflate_add(bonds, sites, weight);
+  });
+}
+
+dmrg_status dmrg_deflate_clear(dmrg_solver* s) {
+  return solver_call(s, [&] {
+    DMRG_REQUIRE(s, ST_EINVAL, "NULL argument");
+    s->s->deflate_clear();
+  });
+}
+
+dmrg_status dmrg_deflate_project(dmrg_solver* s, int k, int j, int64_t n, double* phi) {
+  return solver_call(s, [&] {
+    DMRG_REQUIRE(s && phi, ST_EINVAL, "NULL argument");
+    DMRG_REQUIRE(n == s->s->twosite_size(k), ST_EINVAL, "length does not match the two-site space of step k");
+    s->s->deflate_project(k, j, 1.0, phi);
+  });
+}
+
+dmrg_status dmrg_overlap(dmrg_solver* s, int j, double* overlap) {
+  return solver_call(s, [&] {
+    DMRG_REQUIRE(s && overlap, ST_EINVAL, "NULL argument");
+    *overlap = s->s->overlap(j);
+  });
+}
+
+dmrg_status dmrg_s_squared(dmrg_solver* s, double* s2) {
+  return solver_call(s, [&] {
+    DMRG_REQUIRE(s && s2, ST_EINVAL, "NULL argument");
+    auto v = s->s->s_squared();
+    for (size_t i = 0; i < v.size(); ++i) s2[i] = v[i];
+  });
+}
+
 dmrg_status dmrg_grad(dmrg_solver* s, const double* state_weights, double* dE_dh, double* dE_dB,
                       double* energies) {
   return solver_call(s, [&] {

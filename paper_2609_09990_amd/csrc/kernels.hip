@@ -1,10 +1,21 @@
 // gfx950 kernels for the two-site sigma path.
 //
-// The workhorse is a grouped block GEMM: every output block of sigma (or of a
-// new environment, or of an intermediate T = X psi) is owned by one workgroup
-// per 64x64 tile, which accumulates all of its block products ("items") in a
-// fixed order with MFMA (64-wide wavefronts, 4 waves per workgroup, each wave a
-// 32x32 sub-tile).  No atomics: results are bitwise reproducible.
+// The workhorse is a grouped block GEMM: every output tile of sigma (or of a
+// new environment, or of an intermediate T = X psi) accumulates its block
+// products ("items") in a fixed order with MFMA, so results are bitwise
+// reproducible (no atomics; split-K partial tiles are summed in order by
+// splitk_reduce).  Three shapes:
+//  * gemm_wg: one 256-thread workgroup per unit, tiles up to 96 x 64 covering a
+//    whole output block, A slices staged through LDS and shared by the four
+//    waves, B rows by raw buffer loads, k slices of 32 with one of lookahead
+//    (sigma phase B, fp64 / fp32);
+//  * w32_tile: one wave per (16 RB) x (16 CB) tile reading operands straight
+//    from memory (phase A, environment updates, gradient, fp32 / bf16 forms);
+//  * gemm_f64 / gemm_f32 / gemm_bf16: plain 64 x 64 LDS tiles, four waves of
+//    32 x 32 (one-off products: two-site forms, overlaps, projections, the MLP,
+//    dmrg_block_gemm).
+// Plus the Davidson BLAS-1 kernels, the one-workgroup Jacobi eigensolver, the
+// diagonal, premix / pairmix and precision conversions.
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 
@@ -1268,6 +1279,18 @@ __global__ void precond_diag_kernel(const double* __restrict__ r, const double* 
   }
 }
 
+// d[i] += sum_{j<k} V[j ldv + i]^2 (diagonal of a rank-k update V V^T).
+__global__ void add_squares_kernel(double* __restrict__ d, const double* __restrict__ V, long ldv, int k, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    double acc = d[i];
+    for (int j = 0; j < k; ++j) {
+      const double v = V[(long)j * ldv + i];
+      acc = fma(v, v, acc);
+    }
+    d[i] = acc;
+  }
+}
+
 // Symmetric eigensolver for k <= 64 in one workgroup: cyclic Jacobi with the
 // round-robin (circle) pairing, so each round rotates k/2 disjoint pairs in parallel.
 __global__ __launch_bounds__(256) void jacobi_eig_kernel(const double* __restrict__ G, int ldg, int k,
@@ -1625,6 +1648,10 @@ void launch_scale_by_norm(double* x, long n, const double* nrm2, hipStream_t s) 
 void launch_precond_diag(const double* r, const double* diag, const double* theta, double* out,
                          long n, hipStream_t s) {
   precond_diag_kernel<<<grid_for(n), 256, 0, s>>>(r, diag, theta, out, n);
+}
+
+void launch_add_squares(double* d, const double* V, long ldv, int k, long n, hipStream_t s) {
+  if (n > 0 && k > 0) add_squares_kernel<<<grid_for(n), 256, 0, s>>>(d, V, ldv, k, n);
 }
 
 void launch_subspace_rotate(double* V, long ldv, int k, const double* Y, int keep, long n, hipStream_t s) {

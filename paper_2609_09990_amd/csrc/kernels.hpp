@@ -107,6 +107,8 @@ void launch_gemv(const double* V, long ldv, int k, const double* coef, double al
 void launch_scale_by_norm(double* x, long n, const double* nrm2, hipStream_t s);
 void launch_precond_diag(const double* r, const double* diag, const double* theta, double* out,
                          long n, hipStream_t s);
+// d[i] += sum_{j<k} V[j ldv + i]^2.
+void launch_add_squares(double* d, const double* V, long ldv, int k, long n, hipStream_t s);
 // In place: V[:, i] = sum_{j<k} V[:, j] Y[i k + j] for i < keep (k <= 64, keep <= 16).
 void launch_subspace_rotate(double* V, long ldv, int k, const double* Y, int keep, long n, hipStream_t s);
 void launch_jacobi_eig(const double* G, int ldg, int k, double* evals, double* evecs,

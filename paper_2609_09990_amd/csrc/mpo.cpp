@@ -415,4 +415,66 @@ MPO build_mpo(int L, int nq, const double* h, const double* B) {
   return m;
 }
 
+MPO build_spin_mpo(int L) {
+  DMRG_REQUIRE(L >= 2 && L <= 64, ST_EINVAL, "n_orb must be in [2, 64]");
+  // site states s = n_alpha + 2 n_beta, matrices [s][s']
+  Mat4 id{}, sp{}, sm{}, smsp{};
+  for (int s = 0; s < 4; ++s) id[s * 4 + s] = 1.0;
+  sp[1 * 4 + 2] = 1.0;    // |beta> -> |alpha>; |alpha beta> -> 0 (Pauli)
+  sm[2 * 4 + 1] = 1.0;    // |alpha> -> |beta>
+  smsp[2 * 4 + 2] = 1.0;  // s- s+ = n_beta (1 - n_alpha)
+  MPO m;
+  m.L = L;
+  m.nq = 0;
+  m.cmid = L / 2;
+  m.ops = {id, sp, sm, smsp};
+  enum { OP_ID = 0, OP_SP = 1, OP_SM = 2, OP_SMSP = 3 };
+  // channels of an inner cut in (dq, key) order: s- placed, I, H, s+ placed
+  const uint64_t kM = key1(CK_N1, Ladder{0, 1, 1}), kP = key1(CK_N1, Ladder{0, 0, 1});
+  m.chans.resize(L + 1);
+  m.chan_I.assign(L + 1, -1);
+  m.chan_H.assign(L + 1, -1);
+  std::vector<std::array<int, 4>> idx(L + 1, {-1, -1, -1, -1});  // I, H, P, M per cut
+  for (int c = 0; c <= L; ++c) {
+    const bool inner = c > 0 && c < L;
+    if (inner) {
+      idx[c][3] = (int)m.chans[c].size();
+      m.chans[c].push_back({kM, CK_N1, {0, -2}});
+    }
+    if (c < L) {
+      idx[c][0] = (int)m.chans[c].size();
+      m.chans[c].push_back({key0(CK_I), CK_I, {0, 0}});
+    }
+    if (c > 0) {
+      idx[c][1] = (int)m.chans[c].size();
+      m.chans[c].push_back({key0(CK_H), CK_H, {0, 0}});
+    }
+    if (inner) {
+      idx[c][2] = (int)m.chans[c].size();
+      m.chans[c].push_back({kP, CK_N1, {0, 2}});
+    }
+    m.chan_I[c] = idx[c][0];
+    m.chan_H[c] = idx[c][1];
+  }
+  m.W.resize(L);
+  m.prov.resize(L);
+  for (int k = 0; k < L; ++k) {
+    const auto& a = idx[k];
+    const auto& b = idx[k + 1];
+    auto add = [&](int ca, int cb, int op) {
+      if (ca >= 0 && cb >= 0) m.W[k].push_back({ca, cb, 1.0, op});
+    };
+    add(a[0], b[0], OP_ID);    // nothing yet
+    add(a[0], b[2], OP_SP);    // s+ on this site, s- to come
+    add(a[0], b[3], OP_SM);    // s- on this site, s+ to come
+    add(a[0], b[1], OP_SMSP);  // both on this site
+    add(a[2], b[2], OP_ID);
+    add(a[2], b[1], OP_SM);
+    add(a[3], b[3], OP_ID);
+    add(a[3], b[1], OP_SP);
+    add(a[1], b[1], OP_ID);    // done
+  }
+  return m;
+}
+
 }  // namespace dmrg

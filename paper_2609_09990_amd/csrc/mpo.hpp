@@ -66,4 +66,11 @@ struct MPO {
 // Builds the MPO from h (n*n row-major) and B (nq*n*n row-major).  Host only.
 MPO build_mpo(int L, int nq, const double* h, const double* B);
 
+// MPO of S_- S_+ = (sum_p s-_p)(sum_q s+_q), s+_p = a+_{p alpha} a_{p beta},
+// s-_p = a+_{p beta} a_{p alpha}: the spin diagnostic of Sec. II.F, since
+// <S^2> = <S_- S_+> + S_z (S_z + 1).  A sum-then-product operator of bond
+// dimension 4 (channels I, s+ placed, s- placed, H); the on-site operators are
+// even, so no Jordan-Wigner strings cross sites.  Host only.
+MPO build_spin_mpo(int L);
+
 }  // namespace dmrg

@@ -273,6 +273,7 @@ void Solver::init_random_mps() {
   }
   for (auto& e : left_) e.valid = false;
   for (auto& e : right_) e.valid = false;
+  ovl_invalidate(0, L_);
   plan_k_ = -1;
   centers_.clear();
   center_site_ = 0;  // every site right-canonical: the orthogonality centre is site 0
@@ -314,6 +315,18 @@ SolverState Solver::save_state() {
   s.rec_sample = rec_sample_;
   s.kernel_tag = kernel_tag_;
   s.stats = st_;
+  for (const Deflated& d : defl_) {
+    SolverState::Lower lo;
+    lo.bonds = d.bonds;
+    lo.w = d.w;
+    for (const SiteTensor& t : d.sites) {
+      const size_t at = lo.mps.size();
+      lo.mps.resize(at + t.lay.size);
+      if (t.lay.size > 0)
+        hip_check(hipMemcpy(lo.mps.data() + at, t.buf.p, t.lay.size * 8, hipMemcpyDeviceToHost), "deflated save");
+    }
+    s.lower.push_back(std::move(lo));
+  }
   return s;
 }
 
@@ -347,6 +360,16 @@ void Solver::restore_state(const SolverState& s) {
   rec_sample_ = s.rec_sample;
   kernel_tag_ = s.kernel_tag;
   st_ = s.stats;
+  defl_.clear();
+  for (const SolverState::Lower& lo : s.lower) {
+    std::vector<const double*> ptr(L_);
+    long o = 0;
+    for (int k = 0; k < L_; ++k) {
+      ptr[k] = lo.mps.data() + o;
+      o += make_tensor_layout(lo.bonds[k], lo.bonds[k + 1], site_phys_qn()).size;
+    }
+    deflate_add(lo.bonds, ptr, lo.w);
+  }
 }
 
 void Solver::set_mps(const std::vector<Bond>& bonds, const std::vector<const double*>& sites) {
@@ -370,6 +393,7 @@ void Solver::set_mps(const std::vector<Bond>& bonds, const std::vector<const dou
   }
   for (auto& e : left_) e.valid = false;
   for (auto& e : right_) e.valid = false;
+  ovl_invalidate(0, L_);
   plan_k_ = -1;
   centers_.clear();
   center_site_ = -1;  // gauge unknown
@@ -726,6 +750,24 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
   diag(k, D);
   const int prec = opt_.precision;
   int kcur = 0, matvecs = 0;
+  // penalty deflation (Sec. II.F): the operator is H_eff + Phi Phi^T with the
+  // projected lower states as the columns of Phi (scaled by sqrt(w_j) / ||Phi_j||),
+  // added in fp64 to every product; the preconditioner's diagonal includes it
+  const int nd = (int)defl_.size();
+  double* Phi = nullptr;
+  if (nd > 0) {
+    defl_phi_.reserve((size_t)nd * n * 8);
+    Phi = defl_phi_.as<double>();
+    for (int j = 0; j < nd; ++j) deflate_project(k, j, std::sqrt(defl_[j].w) / defl_[j].norm, Phi + (long)j * n);
+    launch_add_squares(D, Phi, n, nd, n, st);
+  }
+  auto apply = [&](int p, const double* x, double* y) {
+    sigma(k, p, x, y);
+    if (nd > 0) {
+      launch_dots(Phi, n, nd, x, n, part, sc + 128, st);
+      launch_gemv(Phi, n, nd, sc + 128, 1.0, y, 1.0, n, st);
+    }
+  };
 
   auto host_scalar = [&](const double* dptr) {
     double v;
@@ -772,7 +814,7 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
     if (!(nn > min_ratio * n0) || !std::isfinite(nn)) return false;
     launch_scale_by_norm(t, n, sc, st);
     launch_copy(V + (long)kcur * n, t, n, st);
-    sigma(k, sprec, V + (long)kcur * n, AV + (long)kcur * n);
+    apply(sprec, V + (long)kcur * n, AV + (long)kcur * n);
     ++matvecs;
     colerr[kcur] = sprec == PREC_F64 ? 0.0 : 1.0;
     gcol(kcur);
@@ -857,7 +899,7 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
   if (sprec != PREC_F64) {
     const double one = 1.0;
     hip_check(hipMemcpyAsync(sc + 40, &one, 8, hipMemcpyHostToDevice, st), "one");
-    sigma(k, sprec, V, t);
+    apply(sprec, V, t);
     ++matvecs;
     launch_axpy_dev(t, AV, sc + 40, -1.0, n, st);  // t - 1 * AV[0] (sc[40] = 1)
     launch_dots(t, n, 1, t, n, part, sc + 41, st);
@@ -888,7 +930,7 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
     const int keep = std::min(kcur, std::min(16, std::max(nr + 2, kmax / 3)));
     rotate_keep(keep);
     for (int i = 0; i < nr; ++i) {
-      sigma(k, PREC_F64, V + (long)i * n, AV + (long)i * n);
+      apply(PREC_F64, V + (long)i * n, AV + (long)i * n);
       ++matvecs;
       colerr[i] = 0.0;
     }
@@ -1022,6 +1064,15 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
     }
     hip_check(hipStreamSynchronize(st), "triples");
     rec_count_ += (int)rec_slots.size();
+  }
+  if (nd > 0) {  // energies of H: theta_r - sum_j (Phi_j . x_r)^2
+    std::vector<double> c((size_t)nd);
+    for (int i = 0; i < nr; ++i) {
+      launch_dots(Phi, n, nd, X + (long)i * n, n, part, sc + 160, st);
+      hip_check(hipMemcpyAsync(c.data(), sc + 160, (size_t)nd * 8, hipMemcpyDeviceToHost, st), "deflation");
+      hip_check(hipStreamSynchronize(st), "deflation");
+      for (int j = 0; j < nd; ++j) evals[i] -= c[j] * c[j];
+    }
   }
   // converged Ritz vectors are in X
   return matvecs;
@@ -1504,6 +1555,7 @@ void Solver::after_truncation(int k, bool l2r) {
   hip_check(hipStreamSynchronize(st), "env");
   st_.env_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count();
   plan_k_ = -1;
+  ovl_invalidate(k + 1, k + 1);  // overlaps through site k (left) or site k+1 (right)
 }
 
 double Solver::truncate(int k, bool l2r, const double* psi) {
@@ -1590,6 +1642,13 @@ std::vector<double> Solver::mps_energy() {
     double h[2];
     hip_check(hipMemcpyAsync(h, sc.p, 16, hipMemcpyDeviceToHost, st), "energy");
     hip_check(hipStreamSynchronize(st), "energy");
+    // psi . H_eff psi = <Psi|H|Psi> in any gauge (the left block of step 0 is the
+    // vacuum); psi . psi is <Psi|Psi> only for right-orthonormal sites 2.., so a
+    // single state takes its norm from the whole chain
+    if (nr == 1) {
+      const MPSView me{&bonds_, &mps_};
+      h[1] = chain_overlap(me, me);
+    }
     out.push_back(h[0] / h[1] + prob_->e_core);
   }
   return out;

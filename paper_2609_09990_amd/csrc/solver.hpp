@@ -245,6 +245,30 @@ struct SolverState {
   int rec_cap = 0, rec_sample = 0;
   int kernel_tag = 0;
   Stats stats;
+  struct Lower {
+    std::vector<Bond> bonds;
+    std::vector<double> mps;
+    double w;
+  };
+  std::vector<Lower> lower;  // states held for penalty deflation
+};
+
+// A lower state held on the device for penalty deflation (Sec. II.F), with its
+// overlap environments against the state being optimised: per cut, one
+// block-diagonal matrix <basis of Psi | part of Phi>, block per common sector
+// (the left one over the sites before the cut, the right one over the rest).
+struct Deflated {
+  double w = 0;     // penalty weight (energy units)
+  double norm = 1;  // ||Phi||
+  std::vector<Bond> bonds;
+  std::vector<SiteTensor> sites;
+  std::vector<DevMem> ol, orr;
+  std::vector<char> ol_ok, orr_ok;
+};
+// An MPS as the overlap contractions see it.
+struct MPSView {
+  const std::vector<Bond>* bonds;
+  const std::vector<SiteTensor>* sites;
 };
 
 class Solver {
@@ -283,6 +307,21 @@ class Solver {
   double truncate(int k, bool left_to_right, const double* psi);
   // Kept singular values of the last truncation, descending over all sectors.
   const std::vector<double>& last_kept_sv() const { return last_kept_sv_; }
+  // Penalty deflation (Sec. II.F): the Davidson operator of every later step is
+  // H_eff + sum_j w_j |phi_j><phi_j| / ||Phi_j||^2, phi_j the projection of the
+  // lower state Phi_j (held on the device) into the step's two-site space.
+  void deflate_add(const std::vector<Bond>& bonds, const std::vector<const double*>& sites, double w);
+  void deflate_clear();
+  int n_deflated() const { return (int)defl_.size(); }
+  // Projection of lower state j into step k's two-site space, times `scale`
+  // (device out of twosite_size(k) doubles).
+  void deflate_project(int k, int j, double scale, double* out);
+  // <Psi|Phi_j> / (||Psi|| ||Phi_j||) over the whole chain, in fp64.
+  double overlap(int j);
+  // Per-root <S^2> of the current MPS (orthogonality centre at site 0).
+  std::vector<double> s_squared();
+  // Device copy of another solver's MPS (same active space and sector).
+  void adopt_mps(const Solver& o);
   // Energies of the roots w refers to and sum_r w_r dE_r/dh (n*n), dE_r/dB (nq*n*n).
   void grad(const std::vector<double>& w, std::vector<double>& dh, std::vector<double>& dB,
             std::vector<double>& energies);
@@ -428,6 +467,15 @@ class Solver {
   TensorLayout center_lay_;
   long sU_total_ = 0;  // size of the kept singular-vector buffer of the last truncation
   int center_site_ = -1;
+  // penalty deflation
+  std::vector<Deflated> defl_;
+  DevMem defl_phi_, defl_t_, defl_a_, defl_b_;
+  void ensure_ovl_left(int j, int c);
+  void ensure_ovl_right(int j, int c);
+  void ovl_invalidate(int first_left, int last_right);  // OL[c >= first_left], OR[c <= last_right]
+  void ovl_update_left(const MPSView& bra, const MPSView& ket, int site, const double* in, double* out);
+  void ovl_update_right(const MPSView& bra, const MPSView& ket, int site, const double* in, double* out);
+  double chain_overlap(const MPSView& bra, const MPSView& ket);
   DevMem scratch_items_, scratch_units_;
   std::vector<GemmItem> scratch_h_items_;
   std::vector<GemmUnit> scratch_h_units_;

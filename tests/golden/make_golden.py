@@ -34,7 +34,7 @@ def main(names):
         h, B, e0 = synth.make_hamiltonian(n, nq, seed)
         t = time.time()
         w, vs, space = fci.solve(n, na, nb, h, B, nroots=nroots, e_core=e0, tol=1e-8)
-        s2 = [fci.s_squared(space, c) for c in vs] if space.size <= 70000 else None
+        s2 = [fci.s_squared_sparse(space, c) for c in vs]
         data[name] = {"n": n, "n_alpha": na, "n_beta": nb, "n_chol": nq, "seed": seed,
                       "energies": [float(x) for x in w], "s2": s2, "n_det": space.size,
                       "oracle_seconds": round(time.time() - t, 2)}

@@ -1,0 +1,129 @@
+"""Excited states by penalty deflation (Sec. II.F) on the GPU, through the C ABI,
+against the CPU oracle: the projection of a lower state into a two-site space,
+transition overlaps, <S^2>, and the lowest roots against FCI."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import embed, fci
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fci_energies.json")
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def test_projection_and_overlap_match_oracle():
+    """dmrg_deflate_project at every step (ragged, truncated bonds on both MPS)
+    and the whole-chain overlap against the oracle's explicit projection; then
+    after a step changes two sites of Psi, the overlap environments through them
+    are rebuilt (projection at the next step against the oracle on the new MPS)."""
+    torch = _torch()
+    import paper_2609_09990_amd as pk
+    n, na, nb = 6, 3, 3
+    h, B, e0 = synth.make_hamiltonian(n, 8, 0)
+    psi = synth.random_mps(n, na, nb, 12, seed=5)
+    phi = synth.random_mps(n, na, nb, 10, seed=9)
+    sol = pk.Solver(pk.Problem(h, B, na, nb, e0), M=12)
+    sol.set_mps(psi["bonds"], psi["sites"])
+    sol.deflate(phi, 1.0)
+    for k in range(n - 1):
+        size = sol.prepare(k)
+        out = torch.zeros(size, dtype=torch.float64, device="cuda")
+        sol.deflate_project(k, 0, out)
+        ref = embed.project_twosite(psi, k, phi)
+        err = np.linalg.norm(out.cpu().numpy() - ref) / np.linalg.norm(ref)
+        print(f"k={k} |phi|={np.linalg.norm(ref):.3e} err={err:.1e}", flush=True)
+        assert err <= 1e-12, (k, err)
+    o = sol.overlap(0)
+    assert abs(o - embed.overlap(psi, phi)) <= 1e-12
+    # a step moves the centre and rewrites sites 0, 1 of Psi
+    psi0 = pk.Solver(pk.Problem(h, B, na, nb, e0), M=12)  # right-canonical start, centre on site 0
+    start = psi0.export_mps()
+    sol.set_mps(start["bonds"], start["sites"])
+    sol.step(0, 0)
+    now = sol.export_mps()
+    size = sol.prepare(1)
+    out = torch.zeros(size, dtype=torch.float64, device="cuda")
+    sol.deflate_project(1, 0, out)
+    ref = embed.project_twosite(now, 1, phi)
+    assert np.linalg.norm(out.cpu().numpy() - ref) <= 1e-12 * np.linalg.norm(ref)
+    assert abs(sol.overlap(0) - embed.overlap(now, phi)) <= 1e-12
+
+
+def test_s_squared_and_energy_of_any_gauge_match_oracle():
+    """<S^2> (spin MPO through the sigma kernels) and <H> of an MPS in no
+    canonical form against the oracle's determinant-space values."""
+    _torch()
+    import paper_2609_09990_amd as pk
+    for (n, na, nb, M, seed) in [(6, 3, 3, 12, 5), (5, 3, 2, 8, 2), (6, 4, 2, 20, 7)]:
+        h, B, e0 = synth.make_hamiltonian(n, 8, seed)
+        mps = synth.random_mps(n, na, nb, M, seed=seed)
+        sol = pk.Solver(pk.Problem(h, B, na, nb, e0), M=M)
+        sol.set_mps(mps["bonds"], mps["sites"])
+        c = embed.mps_state(mps, na, nb)
+        space = fci.DetSpace(n, na, nb)
+        ref_s2 = fci.s_squared_sparse(space, c) / float(np.sum(c * c))
+        got_s2 = sol.s_squared()[0]
+        ref_e = embed.mps_energy(h, B, mps, na, nb, e0)
+        got_e = sol.energy()[0]
+        print(f"n={n} ({na},{nb}) S2 {got_s2:.12f} vs {ref_s2:.12f}, E {got_e:.12f} vs {ref_e:.12f}", flush=True)
+        assert abs(got_s2 - ref_s2) <= 1e-12 * max(1.0, ref_s2)
+        assert abs(got_e - ref_e) <= 1e-12 * max(1.0, abs(ref_e))
+
+
+def test_three_lowest_cas12_roots_by_deflation_equal_fci():
+    """CAS(12,12), N_Q = 64, seed 0 at full bond (M = 4096): the ground state and
+    two excited states by penalty deflation, each its own run holding the lower
+    ones, reproduce the three lowest FCI roots of the (6, 6) sector to 1e-10 Ha,
+    with <S^2> of each equal to the FCI root's."""
+    _torch()
+    import paper_2609_09990_amd as pk
+    g = json.load(open(GOLD))["cas12_nq64_s0"]
+    h, B, e0 = synth.make_hamiltonian(12, 64, 0)
+    prob = pk.Problem(h, B, 6, 6, e0)
+    res = pk.excited_states(prob, 3, M=4096, tol=1e-10, sweeps=3, conv_tol=1e-11)
+    for r in res["runs"]:
+        print({k: r[k] for k in ("energy", "s2", "overlaps", "sweeps", "weight", "converged")}, flush=True)
+    ref = np.array(g["energies"])
+    assert len(res["energies"]) == 3
+    assert np.max(np.abs(res["energies"] - ref)) <= 1e-10, res["energies"] - ref
+    assert np.max(np.abs(res["s2"] - np.array(g["s2"]))) <= 1e-8, (res["s2"], g["s2"])
+    for r in res["runs"]:
+        assert all(abs(o) <= 1e-6 for o in r["overlaps"])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_singlet_selection_cas8(prec):
+    """CAS(8,8), N_Q = 32, seed 0: between the two lowest singlets of the (4, 4)
+    sector lie M_s = 0 components of higher multiplets.  With spin = 0 they are
+    found, held as deflated states and not reported, and the two reported roots
+    are the two lowest singlets of the oracle FCI (to 1e-10 Ha, <S^2> below
+    1e-8); also with the FP32 sigma."""
+    _torch()
+    import paper_2609_09990_amd as pk
+    h, B, e0 = synth.make_hamiltonian(8, 32, 0)
+    w, vs, space = fci.solve(8, 4, 4, h, B, nroots=8, e_core=e0, tol=1e-10)
+    s2 = np.array([fci.s_squared_sparse(space, c) for c in vs])
+    singlets = w[np.abs(s2) < 1e-6][:2]
+    assert len(singlets) == 2
+    prob = pk.Problem(h, B, 4, 4, e0)
+    res = pk.excited_states(prob, 2, M=256, spin=0, tol=1e-10, sweeps=3, conv_tol=1e-11, precision=prec)
+    for r in res["runs"]:
+        print({k: r[k] for k in ("energy", "s2", "accepted", "sweeps", "weight")}, flush=True)
+    assert np.max(np.abs(res["energies"] - singlets)) <= 1e-10, (res["energies"], singlets)
+    assert np.all(np.abs(res["s2"]) <= 1e-8)
+    rejected = [r for r in res["runs"] if not r["accepted"]]
+    assert len(rejected) >= 2  # at least the two triplets below the second singlet
+    for r in rejected:  # each an exact spin multiplet with S >= 1 (triplets, a quintet)
+        S = (-1 + np.sqrt(1 + 4 * r["s2"])) / 2
+        assert abs(S - round(S)) < 1e-6 and round(S) >= 1, r["s2"]
