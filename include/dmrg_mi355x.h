@@ -73,10 +73,14 @@ typedef struct {
   double cut_rtol;     /* when truncating, singular values <= cut_rtol * s_1 go first; nothing is
                           dropped while all states fit in M */
   int verbose;         /* 0 quiet, 1 per step, 2 per Davidson iteration (stderr) */
+  long long sigma_chunk_bytes; /* bound on the sigma intermediates T (bytes; 0 = none): left factors
+                                  are taken in chunks whose T fits, phase A and B run per chunk and
+                                  phase B adds into sigma; less memory, more launches (slower) */
 } dmrg_options;
 
 /* Fills *o with defaults: M=256, 1 state, tol 1e-10, 200 iterations, subspace
- * 32, FP64, diagonal preconditioner, seed 1, tie_rtol 1e-10, cut_rtol 1e-14. */
+ * 32, FP64, diagonal preconditioner, seed 1, tie_rtol 1e-10, cut_rtol 1e-14,
+ * unbounded sigma intermediates. */
 void dmrg_options_default(dmrg_options* o);
 
 /* Active-space problem (Sec. II.A): n_orb spatial orbitals, n_alpha / n_beta

@@ -24,7 +24,8 @@ class dmrg_options(C.Structure):
     _fields_ = [("M", C.c_int), ("n_states", C.c_int), ("weights", C.POINTER(C.c_double)),
                 ("davidson_tol", C.c_double), ("max_iter", C.c_int), ("max_subspace", C.c_int),
                 ("precision", C.c_int), ("precond", C.c_int), ("seed", C.c_ulonglong),
-                ("tie_rtol", C.c_double), ("cut_rtol", C.c_double), ("verbose", C.c_int)]
+                ("tie_rtol", C.c_double), ("cut_rtol", C.c_double), ("verbose", C.c_int),
+                ("sigma_chunk_bytes", C.c_longlong)]
 
 
 def _decl(name, args, res=C.c_int):
@@ -200,7 +201,7 @@ class Solver:
 
     def __init__(self, problem: Problem, M=256, n_states=1, weights=None, tol=1e-10, max_iter=200,
                  max_subspace=32, precision=0, precond=0, seed=1, tie_rtol=1e-10, cut_rtol=1e-14,
-                 verbose=0, stream=None, workspace=False):
+                 verbose=0, stream=None, workspace=False, sigma_chunk_bytes=0):
         """workspace: False (the library allocates its device buffers), True (a
         torch-allocated workspace of dmrg_workspace_query bytes, grown and
         re-attached when a call reports DMRG_ENOMEM) or a byte count."""
@@ -209,6 +210,7 @@ class Solver:
         o.M, o.n_states, o.davidson_tol, o.max_iter = M, n_states, tol, max_iter
         o.max_subspace, o.precision, o.precond, o.seed = max_subspace, precision, precond, seed
         o.tie_rtol, o.cut_rtol, o.verbose = tie_rtol, cut_rtol, verbose
+        o.sigma_chunk_bytes = int(sigma_chunk_bytes)
         self._w = None
         if weights is not None:
             self._w = np.ascontiguousarray(weights, dtype=np.float64)

@@ -66,6 +66,7 @@ void dmrg_options_default(dmrg_options* o) {
   o->tie_rtol = 1e-10;
   o->cut_rtol = 1e-14;
   o->verbose = 0;
+  o->sigma_chunk_bytes = 0;
 }
 
 dmrg_status dmrg_problem_create(int n, int na, int nb, int nq, const double* h, const double* B,
@@ -159,6 +160,8 @@ dmrg_status dmrg_solver_create(const dmrg_problem* p, const dmrg_options* o, voi
     op.tie_rtol = o->tie_rtol;
     op.cut_rtol = o->cut_rtol;
     op.verbose = o->verbose;
+    DMRG_REQUIRE(o->sigma_chunk_bytes >= 0, ST_EINVAL, "sigma_chunk_bytes must be >= 0");
+    if (o->sigma_chunk_bytes > 0) op.sigma_chunk_bytes = o->sigma_chunk_bytes;
     DMRG_REQUIRE(op.precision >= 0 && op.precision <= 2, ST_EINVAL, "unknown precision");
     DMRG_REQUIRE(op.davidson_tol > 0, ST_EINVAL, "davidson_tol must be positive");
     DMRG_REQUIRE(op.max_iter >= 1, ST_EINVAL, "max_iter must be >= 1");

@@ -1139,10 +1139,11 @@ __global__ void splitk_reduce_f32(const SplitTile* __restrict__ tiles, const flo
   float acc = 0.f;
   const long step = (long)t.tm * t.tn;
   for (int s = 0; s < t.ns; ++s) acc += slots[t.s0 + s * step + e];
-  ((float*)t.C)[(long)gm * t.ldc + gn] = acc;
+  float* c = (float*)t.C + (long)gm * t.ldc + gn;
+  *c = t.acc ? *c + acc : acc;
 }
 
-// Split-K reduction: out tile += nothing; out tile = sum of its partial slots in order.
+// Split-K reduction: out tile = (out tile if acc) + sum of its partial slots in order.
 __global__ void splitk_reduce(const SplitTile* __restrict__ tiles, const double* __restrict__ slots) {
   // workgroup (tile, chunk of 256 elements): one element per thread
   const SplitTile t = tiles[blockIdx.x];
@@ -1154,7 +1155,8 @@ __global__ void splitk_reduce(const SplitTile* __restrict__ tiles, const double*
   double acc = 0.0;
   const long step = (long)t.tm * t.tn;
   for (int s = 0; s < t.ns; ++s) acc += slots[t.s0 + s * step + e];
-  ((double*)t.C)[(long)gm * t.ldc + gn] = acc;
+  double* c = (double*)t.C + (long)gm * t.ldc + gn;
+  *c = t.acc ? *c + acc : acc;
 }
 
 __global__ void premix_kernel(double* __restrict__ out, const double* const* __restrict__ srcs,

@@ -57,11 +57,13 @@ inline bool buffer_reach_ok(int mode, int M, int N, int K, int lda, int ldb, siz
 
 // Output tile (rows m0.., cols n0.. of an M x N block, tm x tn <= 96 x 64
 // elements) = sum of ns partial tiles (row-major tm x tn each) stored one after
-// another from element s0 of the slot buffer, summed in order.
+// another from element s0 of the slot buffer, summed in order; acc = 1 adds
+// that sum to the tile instead.
 struct SplitTile {
   void* C;
   long s0;
   int ldc, M, N, m0, n0, ns, tm, tn;
+  int acc, pad;
 };
 void launch_splitk_reduce(const SplitTile* tiles, int n, const double* slots, hipStream_t s);
 // NT block kernel (prec PREC_F64 or PREC_F32: operands, accumulation and

@@ -13,6 +13,7 @@
 // and the left (right) environment update reuses the same factors with the site
 // tensor in place of psi.
 #include <algorithm>
+#include <limits>
 #include <chrono>
 #include <cstring>
 
@@ -66,13 +67,16 @@ size_t Solver::workspace_estimate() const {
   const long kmax = std::min(opt_.max_subspace, 64);
   long dmax = 0;
   for (int c = 0; c <= L_; ++c) dmax = std::max<long>(dmax, prob_->mpo.dim(c));
-  // sigma intermediates: T (one block row per left factor and psi slab) and its
-  // low-precision copy grow as (MPO dimension) x |psi| (measured 2.2-2.4 times
-  // that product at CAS(12..20) half sweeps), the premixed factors, merged
-  // blocks and split-K partials as a few environments; Davidson: basis,
+  // sigma intermediates: T (one block row per left factor and psi slab) grows as
+  // (MPO dimension) x |psi| (measured 2.2-2.4 times that product at CAS(12..20)
+  // half sweeps) but is held one chunk at a time (with its low-precision copy);
+  // the merged right blocks stay below (MPO dimension) x |psi|; premixed
+  // factors and split-K partials as a few environments; Davidson: basis,
   // products and per-root work vectors
-  const long doubles = env_total + 12 * env_max + 3 * dmax * psi_max + (2 * kmax + 16 + 4 * opt_.n_states) * psi_max +
-                       4 * mps;
+  long sig = 3 * dmax * psi_max;
+  if (opt_.sigma_chunk_bytes > 0)
+    sig = std::min<long>(sig, 2 * (opt_.sigma_chunk_bytes / (long)sizeof(double)) + dmax * psi_max);
+  const long doubles = env_total + 12 * env_max + sig + (2 * kmax + 16 + 4 * opt_.n_states) * psi_max + 4 * mps;
   // half again as much for fragmentation: grow-only buffers are released and
   // re-carved as the bonds grow along a sweep
   return (size_t)doubles * 12 + (size_t(256) << 20);
@@ -346,6 +350,7 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
     double work = 0;
     for (const PUnit& u : ph.units)
       for (int i = u.ib; i < u.ie; ++i) work += ((u.M + 31) / 32) * ((u.N + 31) / 32) * ((ph.items[i].K + 3) / 4);
+    if (ph.split_work > 0) work = ph.split_work;
     // about 16384 one-wave units; workgroup units are cut finer (65536, measured
     // best for sigma phase B at CAS(20,20), M = 1024: smaller pieces of the
     // largest blocks spread over more CUs, against more split-K partial tiles)
@@ -376,7 +381,7 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
       for (const TileShape& t : ts) {
         // the reduction covers tiles of up to 96 x 64 elements
         DMRG_REQUIRE(t.tm * t.tn <= 96 * 64, ST_EINVAL, "split-K tile larger than the reduction covers");
-        tiles.push_back({C, n_slot_elems, u.ldc, u.M, u.N, t.m0, t.n0, nc, t.tm, t.tn});
+        tiles.push_back({C, n_slot_elems, u.ldc, u.M, u.N, t.m0, t.n0, nc, t.tm, t.tn, u.acc, 0});
         n_slot_elems += (long)nc * t.tm * t.tn;
       }
       for (int c = 0; c < nc; ++c)
@@ -723,15 +728,35 @@ void Solver::build_sigma_plan(int k) {
   for (int b = 0; b < nmid; ++b)
     if (!rf_.by_mid[b].empty())
       for (auto& u : lf_.by_mid[b]) used[u.f] = 1;
-  phA_ = Phase();
-  phA_.mode = GEMM_NN;
-  phA_.flops_exec = 0;
+  // Left factors in chunks of at most sigma_chunk_bytes of T_X (0: one chunk; a
+  // factor larger than the bound is a chunk of its own).  Phase A of a chunk
+  // writes its T_X into one chunk-sized buffer and phase B of the chunk consumes
+  // them at once, adding into sigma: the intermediates take one chunk of memory.
+  // (Measured at CAS(20,20), M = 1024: 8.5 ms per sigma unchunked, 9.5 ms with
+  // 1 GiB chunks, 13.8 ms with 128 MiB: the shorter launches cost more than the
+  // memory-side cache saves.)
+  const long chunk_cap = opt_.sigma_chunk_bytes > 0
+                             ? std::max<long>(1, opt_.sigma_chunk_bytes / (long)sizeof(double))
+                             : std::numeric_limits<long>::max();
+  std::vector<int> chunk_of(lf_.fac.size(), -1);
   std::vector<std::vector<long>> toff(lf_.fac.size());
   std::vector<std::vector<int>> trow(lf_.fac.size());
-  long tsize = 0;
+  std::vector<long> chunk_t;  // T_X doubles per chunk
   for (size_t f = 0; f < lf_.fac.size(); ++f) {
     if (!used[f]) continue;
     const EnvClass& cls = envl.classes[lf_.fac[f].cls];
+    long fs = 0;
+    for (size_t si = 0; si < P.slabs.size(); ++si) {
+      const Slab& sl = P.slabs[si];
+      int bi = cls.block_of_col[sl.li];
+      if (bi < 0) continue;
+      const EnvBlock& eb = cls.blocks[bi];
+      if (P.slab_of_left[eb.ri] < 0) continue;  // output rows would fall outside sigma
+      fs += (long)eb.mr * sl.width;
+    }
+    if (chunk_t.empty() || (chunk_t.back() > 0 && chunk_t.back() + fs > chunk_cap)) chunk_t.push_back(0);
+    const int c = (int)chunk_t.size() - 1;
+    chunk_of[f] = c;
     toff[f].assign(P.slabs.size(), -1);
     trow[f].assign(P.slabs.size(), -1);
     for (size_t si = 0; si < P.slabs.size(); ++si) {
@@ -739,14 +764,35 @@ void Solver::build_sigma_plan(int k) {
       int bi = cls.block_of_col[sl.li];
       if (bi < 0) continue;
       const EnvBlock& eb = cls.blocks[bi];
-      if (P.slab_of_left[eb.ri] < 0) continue;  // output rows would fall outside sigma
-      toff[f][si] = tsize;
+      if (P.slab_of_left[eb.ri] < 0) continue;
+      toff[f][si] = chunk_t[c];
       trow[f][si] = eb.ri;
-      tsize += (long)eb.mr * sl.width;
-      phA_.flops += 2.0 * eb.mr * eb.mc * sl.width;  // algorithmic: every T_X block
+      chunk_t[c] += (long)eb.mr * sl.width;
     }
   }
-  t_size_ = tsize;
+  if (chunk_t.empty()) chunk_t.push_back(0);  // sigma = 0 still needs its zero-writing tiles
+  const int nch = (int)chunk_t.size();
+  t_size_ = *std::max_element(chunk_t.begin(), chunk_t.end());
+  phA_.clear();
+  phB_.clear();
+  phA_.resize(nch);
+  phB_.resize(nch);
+  for (int c = 0; c < nch; ++c) {
+    phA_[c].mode = GEMM_NN;
+    phA_[c].flops_exec = 0;
+    phB_[c].mode = GEMM_NT;
+    phB_[c].flops_exec = 0;
+    phB_[c].wg = true;
+  }
+  for (size_t f = 0; f < lf_.fac.size(); ++f) {
+    if (chunk_of[f] < 0) continue;
+    const EnvClass& cls = envl.classes[lf_.fac[f].cls];
+    for (size_t si = 0; si < P.slabs.size(); ++si)
+      if (toff[f][si] >= 0) {
+        const EnvBlock& eb = cls.blocks[cls.block_of_col[P.slabs[si].li]];
+        phA_[chunk_of[f]].flops += 2.0 * eb.mr * eb.mc * P.slabs[si].width;  // algorithmic: every T_X block
+      }
+  }
   // column blocks of each T_X slab that phase B reads; phase A computes only those
   std::vector<std::vector<std::vector<char>>> tused(lf_.fac.size());
   for (size_t f = 0; f < lf_.fac.size(); ++f)
@@ -755,19 +801,19 @@ void Solver::build_sigma_plan(int k) {
       for (size_t si = 0; si < P.slabs.size(); ++si)
         if (toff[f][si] >= 0) tused[f][si].assign(P.slabs[si].blocks.size(), 0);
     }
-  // phase B: gather items per output block of sigma
+  // phase B: gather items per chunk and output block of sigma
   pm_ = PairMix();
   pm_.ptr.push_back(0);
-  phB_ = Phase();
-  phB_.mode = GEMM_NT;
-  phB_.flops_exec = 0;
-  phB_.wg = true;
-  std::vector<std::vector<std::vector<PItem>>> per(P.slabs.size());
-  for (size_t si = 0; si < P.slabs.size(); ++si) per[si].resize(P.slabs[si].blocks.size());
+  std::vector<std::vector<std::vector<std::vector<PItem>>>> per(nch);
+  for (int c = 0; c < nch; ++c) {
+    per[c].resize(P.slabs.size());
+    for (size_t si = 0; si < P.slabs.size(); ++si) per[c][si].resize(P.slabs[si].blocks.size());
+  }
   for (int b = 0; b < nmid; ++b) {
     if (lf_.by_mid[b].empty() || rf_.by_mid[b].empty()) continue;
     for (const auto& ul : lf_.by_mid[b]) {
       const Mat4& opl = mpo.ops[ul.op];
+      const int ch = chunk_of[ul.f];
       for (const auto& ur : rf_.by_mid[b]) {
         const Mat4& opr = mpo.ops[ur.op];
         const EnvClass& ycls = envr.classes[rf_.fac[ur.f].cls];
@@ -797,10 +843,10 @@ void Solver::build_sigma_plan(int k) {
                     int ob = dst.block_of(sout, ro);
                     if (ob < 0) continue;
                     tused[ul.f][si][sb] = 1;
-                    per[so][ob].push_back({B_T, toff[ul.f][si] + blk.col0,
-                                           rf_.fac[ur.f].alias ? B_ENVR : B_YMIX,
-                                           rf_.fac[ur.f].off + ycls.blocks[yb].off, src.width,
-                                           blk.mr, blk.mr, sc * wl * wr});
+                    per[ch][so][ob].push_back({B_T, toff[ul.f][si] + blk.col0,
+                                               rf_.fac[ur.f].alias ? B_ENVR : B_YMIX,
+                                               rf_.fac[ur.f].off + ycls.blocks[yb].off, src.width,
+                                               blk.mr, blk.mr, sc * wl * wr});
                   }
                 }
               }
@@ -811,6 +857,7 @@ void Solver::build_sigma_plan(int k) {
   // phase A: T_X = X psi over each run of consecutive column blocks that phase B reads
   for (size_t f = 0; f < lf_.fac.size(); ++f) {
     if (toff[f].empty()) continue;
+    Phase& pa = phA_[chunk_of[f]];
     const EnvClass& cls = envl.classes[lf_.fac[f].cls];
     for (size_t si = 0; si < P.slabs.size(); ++si) {
       if (toff[f][si] < 0) continue;
@@ -825,57 +872,73 @@ void Solver::build_sigma_plan(int k) {
         size_t b1 = b0 + 1;
         while (b1 < ub.size() && ub[b1] && sl.blocks[b1].col0 == sl.blocks[b1 - 1].col0 + sl.blocks[b1 - 1].mr) ++b1;
         const int c0 = sl.blocks[b0].col0, w = sl.blocks[b1 - 1].col0 + sl.blocks[b1 - 1].mr - c0;
-        int ib = (int)phA_.items.size();
-        phA_.items.push_back({lf_.fac[f].alias ? B_ENVL : B_XMIX, lf_.fac[f].off + eb.off, B_PSI, sl.off + c0,
-                              eb.mc, sl.width, eb.mc, 1.0});
-        add_units(phA_.units, B_T, toff[f][si] + c0, sl.width, eb.mr, w, ib, ib + 1, 0);
-        phA_.flops_exec += 2.0 * eb.mr * eb.mc * w;
+        int ib = (int)pa.items.size();
+        pa.items.push_back({lf_.fac[f].alias ? B_ENVL : B_XMIX, lf_.fac[f].off + eb.off, B_PSI, sl.off + c0,
+                            eb.mc, sl.width, eb.mc, 1.0});
+        add_units(pa.units, B_T, toff[f][si] + c0, sl.width, eb.mr, w, ib, ib + 1, 0);
+        pa.flops_exec += 2.0 * eb.mr * eb.mc * w;
         b0 = b1;
       }
     }
   }
-  for (size_t so = 0; so < P.slabs.size(); ++so)
-    for (size_t ob = 0; ob < per[so].size(); ++ob) {
-      auto& v = per[so][ob];  // blocks without items still get (zero-writing) tiles
-      // operand order: consecutive items read neighbouring stretches of T rows
-      std::stable_sort(v.begin(), v.end(), [](const PItem& x, const PItem& y) {
-        if (x.aoff != y.aoff) return x.aoff < y.aoff;
-        return x.boff < y.boff;
-      });
-      const Slab& dst = P.slabs[so];
-      const int nb = dst.blocks[ob].mr;
-      int ib = (int)phB_.items.size();
-      // items with one A slice (adjacent after the sort) become one product with
-      // the weighted sum of their right blocks (N x K, row stride K)
-      for (size_t a = 0; a < v.size();) {
-        size_t b = a + 1;
-        while (b < v.size() && v[b].abuf == v[a].abuf && v[b].aoff == v[a].aoff && v[b].K == v[a].K &&
-               v[b].ldb == v[b].K && v[a].ldb == v[a].K)
-          ++b;
-        if (b - a == 1) {
-          phB_.items.push_back(v[a]);
-        } else {
-          for (size_t i = a; i < b; ++i) {
-            pm_.src_buf.push_back(v[i].bbuf);
-            pm_.src_off.push_back(v[i].boff);
-            pm_.coef.push_back(v[i].coef);
+  // phase B of chunk c adds into sigma; chunk 0 writes every output block (zero
+  // where no item reaches it), later chunks only the blocks they have items for
+  for (int c = 0; c < nch; ++c) {
+    Phase& pb = phB_[c];
+    for (size_t so = 0; so < P.slabs.size(); ++so)
+      for (size_t ob = 0; ob < per[c][so].size(); ++ob) {
+        auto& v = per[c][so][ob];
+        if (c > 0 && v.empty()) continue;
+        // operand order: consecutive items read neighbouring stretches of T rows
+        std::stable_sort(v.begin(), v.end(), [](const PItem& x, const PItem& y) {
+          if (x.aoff != y.aoff) return x.aoff < y.aoff;
+          return x.boff < y.boff;
+        });
+        const Slab& dst = P.slabs[so];
+        const int nb = dst.blocks[ob].mr;
+        int ib = (int)pb.items.size();
+        // items with one A slice (adjacent after the sort) become one product with
+        // the weighted sum of their right blocks (N x K, row stride K)
+        for (size_t a = 0; a < v.size();) {
+          size_t b = a + 1;
+          while (b < v.size() && v[b].abuf == v[a].abuf && v[b].aoff == v[a].aoff && v[b].K == v[a].K &&
+                 v[b].ldb == v[b].K && v[a].ldb == v[a].K)
+            ++b;
+          if (b - a == 1) {
+            pb.items.push_back(v[a]);
+          } else {
+            for (size_t i = a; i < b; ++i) {
+              pm_.src_buf.push_back(v[i].bbuf);
+              pm_.src_off.push_back(v[i].boff);
+              pm_.coef.push_back(v[i].coef);
+            }
+            pm_.ptr.push_back((int)pm_.coef.size());
+            pm_.out_off.push_back(pm_.size);
+            pm_.nnz.push_back(nb * v[a].K);
+            pb.items.push_back({v[a].abuf, v[a].aoff, B_YPAIR, pm_.size, v[a].lda, v[a].K, v[a].K, 1.0});
+            pm_.size += (long)nb * v[a].K;
           }
-          pm_.ptr.push_back((int)pm_.coef.size());
-          pm_.out_off.push_back(pm_.size);
-          pm_.nnz.push_back(nb * v[a].K);
-          phB_.items.push_back({v[a].abuf, v[a].aoff, B_YPAIR, pm_.size, v[a].lda, v[a].K, v[a].K, 1.0});
-          pm_.size += (long)nb * v[a].K;
+          for (size_t i = a; i < b; ++i) pb.flops += 2.0 * dst.ml * nb * v[i].K;  // algorithmic: unmerged
+          pb.flops_exec += 2.0 * dst.ml * nb * v[a].K;
+          a = b;
         }
-        for (size_t i = a; i < b; ++i) phB_.flops += 2.0 * dst.ml * nb * v[i].K;  // algorithmic: unmerged
-        phB_.flops_exec += 2.0 * dst.ml * nb * v[a].K;
-        a = b;
+        add_units(pb.units, B_OUT, dst.off + dst.blocks[ob].col0, dst.width, dst.ml, nb, ib,
+                  (int)pb.items.size(), c == 0 ? 0 : 1);
       }
-      add_units(phB_.units, B_OUT, dst.off + dst.blocks[ob].col0, dst.width, dst.ml, nb, ib,
-                (int)phB_.items.size(), 0);
-    }
+  }
+  // split-K granularity of every chunk from the work of all chunks of the phase
+  // (pieces of the same size whatever the chunking)
+  for (std::vector<Phase>* v : {&phA_, &phB_}) {
+    double w = 0;
+    for (const Phase& ph : *v)
+      for (const PUnit& u : ph.units)
+        for (int i = u.ib; i < u.ie; ++i) w += ((u.M + 31) / 32) * ((u.N + 31) / 32) * ((ph.items[i].K + 3) / 4);
+    if (v->size() > 1)
+      for (Phase& ph : *v) ph.split_work = w;
+  }
   if (opt_.verbose > 1) {
     // shape statistics: executed (tile-padded) vs useful flops per phase
-    for (const Phase* ph : {&phA_, &phB_}) {
+    for (const Phase* ph : {&phA_[0], &phB_[0]}) {
       double padded = 0, kpad = 0, ksum = 0;
       long nit = 0;
       for (const PUnit& u : ph->units)
@@ -887,7 +950,7 @@ void Solver::build_sigma_plan(int k) {
           ++nit;
         }
       fprintf(stderr, "plan k=%d phase %s: units %zu items %zu (unit-items %ld) useful %.3e padded %.3e (x%.1f) "
-              "mean K %.1f (padded %.1f)\n", k, ph == &phA_ ? "A" : "B", ph->units.size(), ph->items.size(), nit,
+              "mean K %.1f (padded %.1f)\n", k, ph == &phA_[0] ? "A" : "B", ph->units.size(), ph->items.size(), nit,
               ph->flops, padded, padded / std::max(ph->flops, 1.0), ksum / std::max(nit, 1L), kpad / std::max(nit, 1L));
     }
     {
@@ -895,10 +958,10 @@ void Solver::build_sigma_plan(int k) {
       // (or one B block) in common, and the operand bytes items read
       long ga = 0, gb = 0;
       double abytes = 0, bbytes = 0;
-      for (const PUnit& u : phB_.units) {
+      for (const PUnit& u : phB_[0].units) {
         std::vector<long> ka, kb;
         for (int i = u.ib; i < u.ie; ++i) {
-          const PItem& p = phB_.items[i];
+          const PItem& p = phB_[0].items[i];
           ka.push_back(p.aoff * 16 + p.abuf);
           kb.push_back(p.boff * 16 + p.bbuf);
           abytes += 8.0 * u.M * p.K;
@@ -910,12 +973,12 @@ void Solver::build_sigma_plan(int k) {
         gb += std::unique(kb.begin(), kb.end()) - kb.begin();
       }
       fprintf(stderr, "phase B sharing: items %zu, distinct (block, A slice) %ld, distinct (block, B block) %ld, "
-              "item A bytes %.3e, item B bytes %.3e\n", phB_.items.size(), ga, gb, abytes, bbytes);
+              "item A bytes %.3e, item B bytes %.3e\n", phB_[0].items.size(), ga, gb, abytes, bbytes);
       // how much of T phase B reads: distinct (offset, K) column slices of T over all items
       std::vector<std::pair<long, long>> sl;  // (offset, rows x K)
-      for (const PUnit& u : phB_.units)
+      for (const PUnit& u : phB_[0].units)
         for (int i = u.ib; i < u.ie; ++i)
-          if (phB_.items[i].abuf == B_T) sl.push_back({phB_.items[i].aoff, (long)u.M * phB_.items[i].K});
+          if (phB_[0].items[i].abuf == B_T) sl.push_back({phB_[0].items[i].aoff, (long)u.M * phB_[0].items[i].K});
       std::sort(sl.begin(), sl.end());
       sl.erase(std::unique(sl.begin(), sl.end()), sl.end());
       double tread = 0;
@@ -926,8 +989,8 @@ void Solver::build_sigma_plan(int k) {
     std::string dims;
     for (auto& s : bonds_[k].sec) dims += std::to_string(s.dim) + " ";
     fprintf(stderr, "bond %d sectors %zu dims: %s\n", k, bonds_[k].sec.size(), dims.c_str());
-    fprintf(stderr, "factors: left %zu (premixed %zu) right %zu (premixed %zu), T %ld doubles, psi %ld\n",
-            lf_.fac.size(), lf_.out_off.size(), rf_.fac.size(), rf_.out_off.size(), t_size_, P.size);
+    fprintf(stderr, "factors: left %zu (premixed %zu) right %zu (premixed %zu), T chunks %d (largest %ld doubles), psi %ld\n",
+            lf_.fac.size(), lf_.out_off.size(), rf_.fac.size(), rf_.out_off.size(), nch, t_size_, P.size);
   }
 }
 

@@ -201,6 +201,7 @@ Solver::Solver(const Problem* p, const Options& o, hipStream_t s) : prob_(p), op
 }
 
 Solver::~Solver() {
+  for (hipEvent_t e : sig_ev_) (void)hipEventDestroy(e);
   for (int i = 0; i < kAuxStreams; ++i) {
     if (aux_rb_[i]) rocblas_destroy_handle(aux_rb_[i]);
     if (aux_st_[i]) (void)hipStreamDestroy(aux_st_[i]);
@@ -463,12 +464,13 @@ void Solver::prepare(int k) {
     c.phA = std::move(phA_);
     c.phB = std::move(phB_);
     c.t_size = t_size_;
-    for (Phase* ph : {&c.phA, &c.phB})
-      for (int i = 0; i < 3; ++i) {
-        std::vector<GemmItem>().swap(ph->h_items[i]);
-        std::vector<GemmUnit>().swap(ph->h_units[i]);
-        std::vector<SplitTile>().swap(ph->h_tiles[i]);
-      }
+    for (std::vector<Phase>* v : {&c.phA, &c.phB})
+      for (Phase& ph : *v)
+        for (int i = 0; i < 3; ++i) {
+          std::vector<GemmItem>().swap(ph.h_items[i]);
+          std::vector<GemmUnit>().swap(ph.h_units[i]);
+          std::vector<SplitTile>().swap(ph.h_tiles[i]);
+        }
     plan_built_k_ = -1;
   }
   auto same_bond = [](const std::vector<Sector>& a, const std::vector<Sector>& b) {
@@ -501,7 +503,9 @@ void Solver::prepare(int k) {
     run_premix(rf_, right_[k + 2]);
     build_sigma_plan(k);
     run_pairmix(k);
-    for (int i = 0; i < 3; ++i) phA_.uploaded[i] = phB_.uploaded[i] = false;
+    for (std::vector<Phase>* v : {&phA_, &phB_})
+      for (Phase& ph : *v)
+        for (int i = 0; i < 3; ++i) ph.uploaded[i] = false;
   }
   plan_built_k_ = k;
   bonds_at_build_l_ = bonds_[k].sec;
@@ -541,9 +545,17 @@ long Solver::twosite_size(int k) const {
   return make_tensor_layout(bonds_[k], bonds_[k + 2], twosite_phys_qn()).size;
 }
 
-double Solver::last_sigma_flops() const { return phA_.flops + phB_.flops; }
+double Solver::last_sigma_flops() const {
+  double f = 0;
+  for (const std::vector<Phase>* v : {&phA_, &phB_})
+    for (const Phase& ph : *v) f += ph.flops;
+  return f;
+}
 double Solver::last_sigma_flops_exec() const {
-  return (phA_.flops_exec < 0 ? phA_.flops : phA_.flops_exec) + (phB_.flops_exec < 0 ? phB_.flops : phB_.flops_exec);
+  double f = 0;
+  for (const std::vector<Phase>* v : {&phA_, &phB_})
+    for (const Phase& ph : *v) f += ph.flops_exec < 0 ? ph.flops : ph.flops_exec;
+  return f;
 }
 
 void Solver::ensure_lowp(int prec) {
@@ -580,16 +592,21 @@ void Solver::sigma(int k, int prec, const double* psi, double* out) {
   sizes[B_YPAIR] = pm_.size;
   sizes[B_ENVL] = left_[k].size;
   sizes[B_ENVR] = right_[k + 2].size;
-  hipEvent_t e0, e1, e2, eg;
-  (void)hipEventCreate(&e0);
-  (void)hipEventCreate(&e1);
-  (void)hipEventCreate(&e2);
-  (void)hipEventCreate(&eg);
-  bool have_eg = false;
-  if (prec == PREC_F64) {
-    have_eg = true;
+  // events per chunk c: [3c] before phase A, [3c+1] before phase B, [3c+2] after
+  // phase B's GEMM (before its split-K reduction); [3 nch] after the last chunk
+  const int nch = (int)phA_.size();
+  const size_t nev = 3 * (size_t)nch + 1;
+  while (sig_ev_.size() < nev) {
+    hipEvent_t e;
+    hip_check(hipEventCreate(&e), "event");
+    sig_ev_.push_back(e);
+  }
+  const bool f64 = prec == PREC_F64;
+  void* bases[B_NBUF] = {};
+  size_t esz[B_NBUF] = {8, 8, 8, 8, 8, 8, 8, 8, 8};
+  int pa_prec = PREC_F64, pb_prec = PREC_F64;
+  if (f64) {
     // fixed input/output buffers keep the resolved plan valid for every call
-    void* bases[B_NBUF] = {};
     bases[B_PSI] = psi_in_.p;
     bases[B_OUT] = out_buf_.p;
     bases[B_T] = t_buf_.p;
@@ -598,56 +615,58 @@ void Solver::sigma(int k, int prec, const double* psi, double* out) {
     bases[B_ENVL] = left_[k].buf.p;
     bases[B_ENVR] = right_[k + 2].buf.p;
     bases[B_YPAIR] = pmix_.p;
-    size_t esz[B_NBUF] = {8, 8, 8, 8, 8, 8, 8, 8, 8};
     launch_copy(psi_in_.as<double>(), psi, n, st);
-    phA_.tag = 1 + 2 * kernel_tag_;
-    phB_.tag = 2 + 2 * kernel_tag_;
-    (void)hipEventRecord(e0, st);
-    run_phase(phA_, PREC_F64, bases, esz, sizes);
-    (void)hipEventRecord(e1, st);
-    phB_.gemm_done = eg;
-    run_phase(phB_, PREC_F64, bases, esz, sizes);
-    phB_.gemm_done = nullptr;
-    (void)hipEventRecord(e2, st);
-    launch_copy(out, out_buf_.as<double>(), n, st);
   } else {
     ensure_lowp(prec);
-    void* bases[B_NBUF] = {};
     for (int i = 0; i < B_NBUF; ++i) bases[i] = lowp_[i].p;
-    size_t le = prec == PREC_F32 ? 4 : 2;
-    size_t esz[B_NBUF] = {le, 4, 4, le, le, le, le, le, le};
+    const size_t le = prec == PREC_F32 ? 4 : 2;
+    for (int i = 0; i < B_NBUF; ++i) esz[i] = le;
+    esz[B_OUT] = esz[B_T] = 4;
     if (prec == PREC_F32) launch_f64_to_f32(psi, lowp_[B_PSI].as<float>(), n, st);
     else launch_f64_to_bf16(psi, lowp_[B_PSI].as<uint16_t>(), n, st);
-    (void)hipEventRecord(e0, st);
-    run_phase(phA_, prec == PREC_F32 ? PREC_F32 : PREC_BF16, bases, esz, sizes);
-    (void)hipEventRecord(e1, st);
-    run_phase(phB_, prec == PREC_F32 ? PREC_F32 : 3, bases, esz, sizes);
-    (void)hipEventRecord(e2, st);
-    launch_f32_to_f64(lowp_[B_OUT].as<float>(), out, n, st);
+    pa_prec = prec == PREC_F32 ? PREC_F32 : PREC_BF16;
+    pb_prec = prec == PREC_F32 ? PREC_F32 : 3;
   }
-  hip_check(hipEventSynchronize(e2), "sigma");
-  float a = 0, b = 0;
-  (void)hipEventElapsedTime(&a, e0, e1);
-  (void)hipEventElapsedTime(&b, e1, e2);
-  float g = b;
-  if (have_eg) (void)hipEventElapsedTime(&g, e1, eg);
+  for (int c = 0; c < nch; ++c) {
+    phA_[c].tag = 1 + 2 * kernel_tag_;
+    phB_[c].tag = 2 + 2 * kernel_tag_;
+    (void)hipEventRecord(sig_ev_[3 * c], st);
+    run_phase(phA_[c], pa_prec, bases, esz, sizes);
+    (void)hipEventRecord(sig_ev_[3 * c + 1], st);
+    phB_[c].gemm_done = f64 ? sig_ev_[3 * c + 2] : nullptr;
+    run_phase(phB_[c], pb_prec, bases, esz, sizes);
+    phB_[c].gemm_done = nullptr;
+    if (!f64 || phB_[c].units.empty()) (void)hipEventRecord(sig_ev_[3 * c + 2], st);
+  }
+  (void)hipEventRecord(sig_ev_[3 * nch], st);
+  if (f64) launch_copy(out, out_buf_.as<double>(), n, st);
+  else launch_f32_to_f64(lowp_[B_OUT].as<float>(), out, n, st);
+  hip_check(hipEventSynchronize(sig_ev_[3 * nch]), "sigma");
+  float a = 0, b = 0, g = 0;
+  for (int c = 0; c < nch; ++c) {
+    float x = 0, y = 0, z = 0;
+    (void)hipEventElapsedTime(&x, sig_ev_[3 * c], sig_ev_[3 * c + 1]);
+    (void)hipEventElapsedTime(&y, sig_ev_[3 * c + 1], sig_ev_[3 * c + 3]);
+    (void)hipEventElapsedTime(&z, sig_ev_[3 * c + 1], sig_ev_[3 * c + 2]);
+    a += x;
+    b += y;
+    g += f64 ? z : y;
+  }
   sigma_phase_ms_[0] = a;
   sigma_phase_ms_[1] = b;
   st_.sigma_a_ms += a;
   st_.sigma_b_ms += b;
   st_.sigma_b_gemm_ms += g;
-  st_.sigma_a_flops += phA_.flops;
-  st_.sigma_b_flops += phB_.flops;
-  st_.sigma_a_flops_exec += phA_.flops_exec < 0 ? phA_.flops : phA_.flops_exec;
-  st_.sigma_b_flops_exec += phB_.flops_exec < 0 ? phB_.flops : phB_.flops_exec;
+  for (int c = 0; c < nch; ++c) {
+    st_.sigma_a_flops += phA_[c].flops;
+    st_.sigma_b_flops += phB_[c].flops;
+    st_.sigma_a_flops_exec += phA_[c].flops_exec < 0 ? phA_[c].flops : phA_[c].flops_exec;
+    st_.sigma_b_flops_exec += phB_[c].flops_exec < 0 ? phB_[c].flops : phB_[c].flops_exec;
+    st_.sigma_flops += phA_[c].flops + phB_[c].flops;
+  }
   st_.sigma_ms += a + b;
-  st_.sigma_flops += phA_.flops + phB_.flops;
   st_.matvecs++;
   if (prec != PREC_F64) st_.lowp_matvecs++;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  (void)hipEventDestroy(e2);
-  (void)hipEventDestroy(eg);
 }
 
 void Solver::diag(int k, double* out) {

@@ -29,6 +29,7 @@ struct Options {
   double tie_rtol = 1e-10;
   double cut_rtol = 1e-14;
   int verbose = 0;
+  long long sigma_chunk_bytes = 0;  // 0: all left factors in one chunk
 };
 
 // A caller-provided slab of device memory that the library carves into its
@@ -162,6 +163,7 @@ struct Phase {
   bool uploaded[3] = {false, false, false};
   bool buf_ok[3] = {false, false, false};  // every item fits the buffer-load kernels
   bool wg = false;                         // may take the fp64 workgroup block kernel (NT)
+  double split_work = 0;                   // > 0: split-K granularity from this work, not the phase's own
   bool wg_used[3] = {false, false, false};
 };
 
@@ -379,8 +381,9 @@ class Solver {
   FactorSide lf_, rf_;
   PairMix pm_;
   TensorLayout psi_lay_;
-  Phase phA_, phB_;
-  long t_size_ = 0;
+  std::vector<Phase> phA_, phB_;  // per chunk of left factors (build_sigma_plan)
+  long t_size_ = 0;               // T_X doubles of the largest chunk
+  std::vector<hipEvent_t> sig_ev_;  // phase boundaries of one sigma call (timing)
   DevMem psi_in_, out_buf_, t_buf_;
   // split-K partial tiles of whichever phase is running: phases run one after
   // another on the solver stream, so one scratch serves every cached plan
@@ -397,7 +400,7 @@ class Solver {
     FactorSide lf, rf;
     PairMix pm;
     TensorLayout psi_lay;
-    Phase phA, phB;
+    std::vector<Phase> phA, phB;
     long t_size = 0;
   };
   std::map<int, StepPlan> plan_cache_;

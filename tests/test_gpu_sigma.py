@@ -56,6 +56,35 @@ def test_sigma_matches_oracle_projection(n, na, nb, nq, M, k):
     assert flops > 0
 
 
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-6)])
+def test_chunked_sigma_matches_oracle(prec, tol):
+    """Sigma intermediates bounded to 1 MiB (many chunks of left factors, phase B
+    adding into sigma chunk by chunk) at CAS(10,10), M = 1024, middle bond: the
+    same sigma as the oracle, in fp64 and in fp32."""
+    torch = _torch()
+    import paper_2609_09990_amd as pk
+    h, B, e0 = synth.make_hamiltonian(10, 12, 0)
+    prob = pk.Problem(h, B, 5, 5, e0)
+    mps = synth.random_mps(10, 5, 5, 1024, seed=5)
+    k = 4
+    psi = synth.random_twosite(mps["bonds"], k, seed=11)
+    ref = embed.sigma_twosite(h, B, mps, k, psi, 5, 5)
+    outs = []
+    for chunk in (0, 1 << 20):
+        sol = pk.Solver(prob, M=1024, sigma_chunk_bytes=chunk)
+        sol.set_mps(mps["bonds"], mps["sites"])
+        sol.prepare(k)
+        d_psi = torch.from_numpy(psi).cuda()
+        d_out = torch.zeros_like(d_psi)
+        sol.sigma(k, d_psi, d_out, prec)
+        torch.cuda.synchronize()
+        outs.append(d_out.cpu().numpy())
+        err = np.linalg.norm(outs[-1] - ref) / np.linalg.norm(ref)
+        print(f"chunk={chunk} prec={prec} err={err:.2e}", flush=True)
+        assert err <= tol, err
+    assert np.linalg.norm(outs[0] - outs[1]) <= 4 * tol * np.linalg.norm(ref)
+
+
 def test_sigma_hermitian_and_deterministic():
     torch, pk, h, B, prob, sol, mps = _setup(8, 4, 4, 16, 60)
     k = 3
