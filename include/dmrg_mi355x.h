@@ -409,14 +409,15 @@ dmrg_status dmrg_set_kernel_tag(dmrg_solver* s, int tag);
  * refinement cycles (fp64 products of the Ritz vectors), [26] peak bytes in
  * use in the attached workspace (0 without one), [27] device allocations the
  * library made with hipMalloc since the workspace was attached (process-wide
- * count; -1 without a workspace).
+ * count; -1 without a workspace), [28] host wall ms spent building step plans
+ * (part of [19]), [29] host wall ms spent building environment-update plans.
  * Times of [2]-[4], [10], [11], [16] are HIP-event times on the solver stream
  * and flops count unpadded block products.  The sigma flops [5], [12], [13]
  * are algorithmic: every block product of the middle-cut factorisation (all
  * columns of every T_X, every item).  The executed counts [23], [24] are
  * lower: phase A skips T_X columns no item reads, and phase B merges items
  * that share their T slice (sum_j c_j T Y_j^T = T (sum_j c_j Y_j)^T).
- * n: capacity of out (up to 28 values are written). */
+ * n: capacity of out (up to 30 values are written). */
 dmrg_status dmrg_get_stats(const dmrg_solver* s, double* out, int n);
 
 const char* dmrg_last_error(void);

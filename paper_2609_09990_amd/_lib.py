@@ -430,13 +430,14 @@ class Solver:
         return dh, dB, e
 
     def stats(self):
-        s = np.zeros(28)
-        _check(dmrg_get_stats(self.h, _ptr(s), 28))
+        s = np.zeros(30)
+        _check(dmrg_get_stats(self.h, _ptr(s), 30))
         keys = ["matvecs", "davidson_iters", "sigma_ms", "env_ms", "svd_ms", "sigma_flops", "tau",
                 "max_bond", "fallbacks", "converged", "sigma_a_ms", "sigma_b_ms", "sigma_a_flops",
                 "sigma_b_flops", "env_flops", "refinements", "sigma_b_gemm_ms", "grad_ms", "grad_flops",
                 "prepare_ms", "resolve_ms", "davidson_ms", "plan_hits", "sigma_a_flops_exec",
-                "sigma_b_flops_exec", "lowp_matvecs", "workspace_peak_bytes", "device_allocs_since_attach"]
+                "sigma_b_flops_exec", "lowp_matvecs", "workspace_peak_bytes", "device_allocs_since_attach",
+                "plan_build_ms", "env_plan_ms"]
         return dict(zip(keys, s.tolist()))
 
     def __del__(self):

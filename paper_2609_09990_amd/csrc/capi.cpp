@@ -616,15 +616,16 @@ dmrg_status dmrg_get_stats(const dmrg_solver* s, double* out, int n) {
   return guard([&] {
     DMRG_REQUIRE(s && out, ST_EINVAL, "NULL argument");
     const Stats& t = s->s->stats();
-    double v[28] = {(double)t.matvecs, (double)t.davidson_iters, t.sigma_ms, t.env_ms, t.svd_ms,
+    double v[30] = {(double)t.matvecs, (double)t.davidson_iters, t.sigma_ms, t.env_ms, t.svd_ms,
                     t.sigma_flops, t.tau, (double)t.max_bond, (double)t.fallbacks, (double)t.converged,
                     t.sigma_a_ms, t.sigma_b_ms, t.sigma_a_flops, t.sigma_b_flops, t.env_flops,
                     (double)t.refinements, t.sigma_b_gemm_ms, t.grad_ms, t.grad_flops, t.prepare_ms,
                     t.resolve_ms, t.davidson_ms, (double)t.plan_hits, t.sigma_a_flops_exec,
                     t.sigma_b_flops_exec, (double)t.lowp_matvecs,
                     s->arena ? (double)s->arena->peak() : 0.0,
-                    s->allocs_at_attach >= 0 ? (double)(library_device_allocations() - s->allocs_at_attach) : -1.0};
-    for (int i = 0; i < n && i < 28; ++i) out[i] = v[i];
+                    s->allocs_at_attach >= 0 ? (double)(library_device_allocations() - s->allocs_at_attach) : -1.0,
+                    t.plan_build_ms, t.env_plan_ms};
+    for (int i = 0; i < n && i < 30; ++i) out[i] = v[i];
   });
 }
 

@@ -13,9 +13,11 @@
 // and the left (right) environment update reuses the same factors with the site
 // tensor in place of psi.
 #include <algorithm>
-#include <limits>
+#include <array>
 #include <chrono>
 #include <cstring>
+#include <limits>
+#include <thread>
 
 #include "solver.hpp"
 
@@ -25,6 +27,33 @@
 #endif
 
 namespace dmrg {
+
+namespace {
+// Host threads for plan building (the box's share of cores; at least 1).
+int plan_threads() {
+  static const int n = [] {
+    unsigned h = std::thread::hardware_concurrency();
+    return (int)std::max(1u, std::min(16u, h ? h : 1u));
+  }();
+  return n;
+}
+// f(t, begin, end) on contiguous ranges of [0, n), one per thread; the ranges
+// follow thread order, so results gathered by thread index are in serial order.
+template <class F>
+void parallel_ranges(long n, F&& f) {
+  const int nt = (int)std::min<long>(plan_threads(), std::max<long>(n / 4, 1));
+  if (nt <= 1) {
+    f(0, 0L, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t) {
+    const long b = n * t / nt, e = n * (t + 1) / nt;
+    th.emplace_back([&f, t, b, e] { f(t, b, e); });
+  }
+  for (auto& x : th) x.join();
+}
+}  // namespace
 
 bool same_sectors(const std::vector<Sector>& a, const std::vector<Sector>& b) {
   if (a.size() != b.size()) return false;
@@ -254,21 +283,34 @@ static void add_units(std::vector<PUnit>& units, int cbuf, long coff, int ldc, i
 
 // Host check that every tile of every item stays inside its buffer (in
 // elements); a plan bug becomes an error instead of a device fault.
-static void validate_phase(const Phase& ph, const long* sizes) {
-  for (const PUnit& u : ph.units) {
-    long cmax = u.coff + (long)(u.M - 1) * u.ldc + (u.N - 1);
-    if (u.coff < 0 || cmax >= sizes[u.cbuf]) throw Error(ST_EINVAL, "plan: output block out of bounds");
-    for (int i = u.ib; i < u.ie; ++i) {
-      const PItem& it = ph.items[i];
-      long amax, bmax;
-      if (ph.mode == GEMM_TN) amax = it.aoff + (long)(it.K - 1) * it.lda + (u.M - 1);
-      else amax = it.aoff + (long)(u.M - 1) * it.lda + (it.K - 1);
-      if (ph.mode == GEMM_NT) bmax = it.boff + (long)(u.N - 1) * it.ldb + (it.K - 1);
-      else bmax = it.boff + (long)(it.K - 1) * it.ldb + (u.N - 1);
-      if (it.K <= 0 || it.aoff < 0 || it.boff < 0 || amax >= sizes[it.abuf] || bmax >= sizes[it.bbuf])
-        throw Error(ST_EINVAL, "plan: operand block out of bounds");
+// Also returns whether every item fits the buffer-load kernels (buffer_reach_ok).
+static bool validate_phase(const Phase& ph, const long* sizes, const size_t* esz) {
+  std::vector<char> bad(plan_threads(), 0), reach(plan_threads(), 1);
+  parallel_ranges((long)ph.units.size(), [&](int t, long u0, long u1) {
+    for (long ui = u0; ui < u1 && !bad[t]; ++ui) {
+      const PUnit& u = ph.units[ui];
+      long cmax = u.coff + (long)(u.M - 1) * u.ldc + (u.N - 1);
+      if (u.coff < 0 || cmax >= sizes[u.cbuf]) bad[t] = 1;
+      for (int i = u.ib; i < u.ie && !bad[t]; ++i) {
+        const PItem& it = ph.items[i];
+        long amax, bmax;
+        if (ph.mode == GEMM_TN) amax = it.aoff + (long)(it.K - 1) * it.lda + (u.M - 1);
+        else amax = it.aoff + (long)(u.M - 1) * it.lda + (it.K - 1);
+        if (ph.mode == GEMM_NT) bmax = it.boff + (long)(u.N - 1) * it.ldb + (it.K - 1);
+        else bmax = it.boff + (long)(it.K - 1) * it.ldb + (u.N - 1);
+        if (it.K <= 0 || it.aoff < 0 || it.boff < 0 || amax >= sizes[it.abuf] || bmax >= sizes[it.bbuf]) bad[t] = 2;
+        if (reach[t] && !buffer_reach_ok(ph.mode, u.M, u.N, it.K, it.lda, it.ldb, esz[it.abuf], esz[it.bbuf]))
+          reach[t] = 0;
+      }
     }
+  });
+  for (char b : bad) {
+    if (b == 1) throw Error(ST_EINVAL, "plan: output block out of bounds");
+    if (b == 2) throw Error(ST_EINVAL, "plan: operand block out of bounds");
   }
+  bool ok = true;
+  for (char r : reach) ok = ok && r;
+  return ok;
 }
 
 void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* esz, const long* sizes) {
@@ -288,37 +330,36 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
     fprintf(stderr, "resolve: mode %d, %zu items, %s%s\n", ph.mode, ph.items.size(),
             ph.uploaded[slot] ? "moved buffers" : "first use", moved.c_str());
   }
-  validate_phase(ph, sizes);
+  const bool buf_ok = validate_phase(ph, sizes, esz);
   for (int b = 0; b < B_NBUF; ++b) ph.last_bases[slot][b] = bases[b];
   ph.uploaded[slot] = true;
-  std::vector<GemmItem>& items = ph.h_items[slot];
-  items.resize(ph.items.size());
-  for (size_t i = 0; i < items.size(); ++i) {
-    const PItem& p = ph.items[i];
-    items[i].A = (const char*)bases[p.abuf] + p.aoff * esz[p.abuf];
-    items[i].B = (const char*)bases[p.bbuf] + p.boff * esz[p.bbuf];
-    items[i].lda = p.lda;
-    items[i].ldb = p.ldb;
-    items[i].K = p.K;
-    items[i].pad = 0;
-    items[i].coef = p.coef;
-  }
-  bool buf_ok = true;
-  for (const PUnit& u : ph.units)
-    for (int i = u.ib; i < u.ie && buf_ok; ++i) {
+  // the tables are written into pinned staging buffers that every resolve of
+  // the solver reuses (no page faults, DMA uploads); the last upload from them
+  // must have finished (it precedes, in stream order, the kernels launched since)
+  if (stage_pending_) hip_check(hipEventSynchronize(stage_ev_), "staging");
+  const long n_items = (long)ph.items.size();
+  GemmItem* items = stage_items_.get<GemmItem>(n_items);
+  parallel_ranges(n_items, [&](int, long i0, long i1) {
+    for (long i = i0; i < i1; ++i) {
       const PItem& p = ph.items[i];
-      buf_ok = buffer_reach_ok(ph.mode, u.M, u.N, p.K, p.lda, p.ldb, esz[p.abuf], esz[p.bbuf]);
+      items[i].A = (const char*)bases[p.abuf] + p.aoff * esz[p.abuf];
+      items[i].B = (const char*)bases[p.bbuf] + p.boff * esz[p.bbuf];
+      items[i].lda = p.lda;
+      items[i].ldb = p.ldb;
+      items[i].K = p.K;
+      items[i].pad = 0;
+      items[i].coef = p.coef;
     }
+  });
   ph.buf_ok[slot] = buf_ok;
   // fp64 / fp32 NT phases with long item lists (sigma phase B) take the
   // workgroup block kernel: whole-block tiles up to 96 x 64, operands read once
   // per block
   const bool use_wg = ph.wg && (prec == PREC_F64 || prec == PREC_F32) && ph.mode == GEMM_NT && buf_ok;
   ph.wg_used[slot] = use_wg;
-  std::vector<GemmUnit>& units = ph.h_units[slot];
-  units.clear();
-  std::vector<SplitTile>& tiles = ph.h_tiles[slot];
-  tiles.clear();
+  GemmUnit* units = nullptr;
+  SplitTile* tiles = nullptr;
+  long nun = 0, ntl = 0;
   long n_slot_elems = 0;
   if (prec == PREC_F64 || prec == PREC_F32 || prec == PREC_BF16 || prec == 3) {
     // One-wave tiles of (16 RB) x (16 CB), RB <= 4, CB <= 2: block rows are cut
@@ -336,86 +377,151 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
       if (x < n) v.push_back({x, (n - x + 15) / 16 * 16});
     };
     struct TileShape { int m0, n0, tm, tn, shape; };
-    std::vector<std::pair<int, int>> rs, cs;
-    std::vector<TileShape> ts;
     // one-wave tiles: up to 64 x 32; workgroup block tiles: up to 96 x 64
     const int wm = use_wg ? 96 : 64, wn = use_wg ? 64 : 32;
-    auto tiles_of = [&](const PUnit& u) {
+    auto tiles_of = [&](const PUnit& u, std::vector<TileShape>& ts) {
+      std::vector<std::pair<int, int>> rs, cs;
       strips(u.M, wm, rs);
       strips(u.N, wn, cs);
       ts.clear();
       for (auto& r : rs)
         for (auto& c : cs) ts.push_back({r.first, c.first, r.second, c.second, 8 * (r.second / 16) + c.second / 16});
     };
+    // work in MFMA k-steps of 32 x 32 tiles (integers: the same sum in any order)
+    const long nu = (long)ph.units.size();
+    std::vector<long> wunit(nu, 0);
+    parallel_ranges(nu, [&](int, long u0, long u1) {
+      for (long x = u0; x < u1; ++x) {
+        const PUnit& u = ph.units[x];
+        long w = 0;
+        for (int i = u.ib; i < u.ie; ++i) w += (long)((u.M + 31) / 32) * ((u.N + 31) / 32) * ((ph.items[i].K + 3) / 4);
+        wunit[x] = w;
+      }
+    });
     double work = 0;
-    for (const PUnit& u : ph.units)
-      for (int i = u.ib; i < u.ie; ++i) work += ((u.M + 31) / 32) * ((u.N + 31) / 32) * ((ph.items[i].K + 3) / 4);
+    {
+      long wsum = 0;
+      for (long w : wunit) wsum += w;
+      work = (double)wsum;
+    }
     if (ph.split_work > 0) work = ph.split_work;
     // about 16384 one-wave units; workgroup units are cut finer (65536, measured
     // best for sigma phase B at CAS(20,20), M = 1024: smaller pieces of the
     // largest blocks spread over more CUs, against more split-K partial tiles)
     const double chunk = std::max(DMRG_SPLIT_MIN, work / (use_wg ? 65536.0 : 16384.0));
-    std::vector<std::pair<int, int>> cuts;
-    for (const PUnit& u : ph.units) {
-      char* C = (char*)bases[u.cbuf] + u.coff * esz[u.cbuf];
-      tiles_of(u);
-      double w = 0;
-      for (int i = u.ib; i < u.ie; ++i) w += (ph.items[i].K + 3) / 4;
-      if (w <= chunk || u.ie - u.ib <= 1) {
-        for (const TileShape& t : ts) units.push_back({C, u.ldc, u.M, u.N, t.m0, t.n0, u.ib, u.ie, u.acc, t.shape});
-        continue;
-      }
-      // the same item chunks for every tile of the block; units chunk-major, so the
-      // waves of one workgroup run one chunk on neighbouring tiles (shared rows of A
-      // or columns of B)
-      cuts.clear();
-      for (int b = u.ib; b < u.ie;) {
-        int e = b;
-        double cw = 0;
-        while (e < u.ie && (cw < chunk || e == b)) cw += (ph.items[e++].K + 3) / 4;
-        cuts.push_back({b, e});
-        b = e;
-      }
-      const int nc = (int)cuts.size();
-      const long first_tile = (long)tiles.size();
-      for (const TileShape& t : ts) {
-        // the reduction covers tiles of up to 96 x 64 elements
-        DMRG_REQUIRE(t.tm * t.tn <= 96 * 64, ST_EINVAL, "split-K tile larger than the reduction covers");
-        tiles.push_back({C, n_slot_elems, u.ldc, u.M, u.N, t.m0, t.n0, nc, t.tm, t.tn, u.acc, 0});
-        n_slot_elems += (long)nc * t.tm * t.tn;
-      }
-      for (int c = 0; c < nc; ++c)
-        for (size_t t = 0; t < ts.size(); ++t) {
-          const SplitTile& st_ = tiles[first_tile + t];
-          units.push_back({(void*)(intptr_t)(st_.s0 + (long)c * st_.tm * st_.tn), st_.tn, u.M, u.N, st_.m0, st_.n0,
-                           cuts[c].first, cuts[c].second, 2, ts[t].shape});
+    // pass 1 (parallel over blocks): tiles and item chunks of each block, counts
+    struct UnitPlan {
+      std::vector<TileShape> ts;
+      std::vector<std::pair<int, int>> cuts;  // empty: no split
+      long n_units = 0, n_tiles = 0, n_slot = 0;
+    };
+    std::vector<UnitPlan> up(nu);
+    std::vector<char> too_big(plan_threads(), 0);
+    parallel_ranges(nu, [&](int t, long u0, long u1) {
+      for (long x = u0; x < u1; ++x) {
+        const PUnit& u = ph.units[x];
+        UnitPlan& q = up[x];
+        tiles_of(u, q.ts);
+        long w = 0;
+        for (int i = u.ib; i < u.ie; ++i) w += (ph.items[i].K + 3) / 4;
+        if ((double)w <= chunk || u.ie - u.ib <= 1) {
+          q.n_units = (long)q.ts.size();
+          continue;
         }
+        // the same item chunks for every tile of the block; units chunk-major, so the
+        // waves of one workgroup run one chunk on neighbouring tiles (shared rows of A
+        // or columns of B)
+        for (int b = u.ib; b < u.ie;) {
+          int e = b;
+          double cw = 0;
+          while (e < u.ie && (cw < chunk || e == b)) cw += (ph.items[e++].K + 3) / 4;
+          q.cuts.push_back({b, e});
+          b = e;
+        }
+        const long nc = (long)q.cuts.size();
+        q.n_units = nc * (long)q.ts.size();
+        q.n_tiles = (long)q.ts.size();
+        for (const TileShape& ts : q.ts) {
+          // the reduction covers tiles of up to 96 x 64 elements
+          if (ts.tm * ts.tn > 96 * 64) too_big[t] = 1;
+          q.n_slot += nc * ts.tm * ts.tn;
+        }
+      }
+    });
+    for (char b : too_big) DMRG_REQUIRE(!b, ST_EINVAL, "split-K tile larger than the reduction covers");
+    // offsets, then pass 2 (parallel): units, tiles and slot offsets in place
+    std::vector<long> uat(nu), tat(nu), sat(nu);
+    for (long x = 0; x < nu; ++x) {
+      uat[x] = nun;
+      tat[x] = ntl;
+      sat[x] = n_slot_elems;
+      nun += up[x].n_units;
+      ntl += up[x].n_tiles;
+      n_slot_elems += up[x].n_slot;
     }
+    units = stage_units_.get<GemmUnit>(nun);
+    tiles = stage_tiles_.get<SplitTile>(ntl);
+    // grow-only: a move invalidates other resolved plans, which re-resolve (slot_base)
     const size_t slot_esz = prec == PREC_F64 ? sizeof(double) : sizeof(float);
-    if (n_slot_elems > 0) {
-      // grow-only: a move invalidates other resolved plans, which re-resolve (slot_base)
-      splitk_.reserve(n_slot_elems * slot_esz);
-      for (auto& un : units)
-        if (un.accumulate == 2) un.C = (char*)splitk_.p + (intptr_t)un.C * slot_esz;
-    }
+    if (n_slot_elems > 0) splitk_.reserve(n_slot_elems * slot_esz);
+    char* const slot0 = (char*)splitk_.p;
+    parallel_ranges(nu, [&](int, long u0, long u1) {
+      for (long x = u0; x < u1; ++x) {
+        const PUnit& u = ph.units[x];
+        const UnitPlan& q = up[x];
+        char* C = (char*)bases[u.cbuf] + u.coff * esz[u.cbuf];
+        GemmUnit* uo = units + uat[x];
+        if (q.cuts.empty()) {
+          for (const TileShape& t : q.ts) *uo++ = {C, u.ldc, u.M, u.N, t.m0, t.n0, u.ib, u.ie, u.acc, t.shape};
+          continue;
+        }
+        const int nc = (int)q.cuts.size();
+        long so = sat[x];
+        SplitTile* to = tiles + tat[x];
+        for (size_t t = 0; t < q.ts.size(); ++t) {
+          const TileShape& ts = q.ts[t];
+          to[t] = {C, so, u.ldc, u.M, u.N, ts.m0, ts.n0, nc, ts.tm, ts.tn, u.acc, 0};
+          so += (long)nc * ts.tm * ts.tn;
+        }
+        for (int c = 0; c < nc; ++c)
+          for (size_t t = 0; t < q.ts.size(); ++t) {
+            const SplitTile& st_ = to[t];
+            *uo++ = {slot0 + (st_.s0 + (long)c * st_.tm * st_.tn) * (long)slot_esz, st_.tn, u.M, u.N, st_.m0, st_.n0,
+                     q.cuts[c].first, q.cuts[c].second, 2, q.ts[t].shape};
+          }
+      }
+    });
     ph.slot_base[slot] = splitk_.p;
   } else {
+    std::vector<GemmUnit> v;
     for (const PUnit& u : ph.units) {
       char* C = (char*)bases[u.cbuf] + u.coff * esz[u.cbuf];
       for (int m0 = 0; m0 < u.M; m0 += 64)
-        for (int n0 = 0; n0 < u.N; n0 += 64) units.push_back({C, u.ldc, u.M, u.N, m0, n0, u.ib, u.ie, u.acc});
+        for (int n0 = 0; n0 < u.N; n0 += 64) v.push_back({C, u.ldc, u.M, u.N, m0, n0, u.ib, u.ie, u.acc});
     }
+    nun = (long)v.size();
+    units = stage_units_.get<GemmUnit>(nun);
+    std::copy(v.begin(), v.end(), units);
   }
-  ph.n_units[slot] = (int)units.size();
-  ph.n_tiles[slot] = (int)tiles.size();
-  ph.d_items[slot].reserve(items.size() * sizeof(GemmItem) + 64);
-  ph.d_units[slot].reserve(units.size() * sizeof(GemmUnit) + 64);
-  ph.d_tiles[slot].reserve(tiles.size() * sizeof(SplitTile) + 64);
-  hip_check(hipMemcpyAsync(ph.d_items[slot].p, items.data(), items.size() * sizeof(GemmItem), hipMemcpyHostToDevice, st), "items");
-  hip_check(hipMemcpyAsync(ph.d_units[slot].p, units.data(), units.size() * sizeof(GemmUnit), hipMemcpyHostToDevice, st), "units");
-  if (!tiles.empty())
-    hip_check(hipMemcpyAsync(ph.d_tiles[slot].p, tiles.data(), tiles.size() * sizeof(SplitTile), hipMemcpyHostToDevice, st), "tiles");
-  st_.resolve_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tr0).count();
+  ph.n_units[slot] = (int)nun;
+  ph.n_tiles[slot] = (int)ntl;
+  const auto tr1 = std::chrono::steady_clock::now();
+  ph.d_items[slot].reserve(n_items * sizeof(GemmItem) + 64);
+  ph.d_units[slot].reserve(nun * sizeof(GemmUnit) + 64);
+  ph.d_tiles[slot].reserve(ntl * sizeof(SplitTile) + 64);
+  hip_check(hipMemcpyAsync(ph.d_items[slot].p, items, n_items * sizeof(GemmItem), hipMemcpyHostToDevice, st), "items");
+  hip_check(hipMemcpyAsync(ph.d_units[slot].p, units, nun * sizeof(GemmUnit), hipMemcpyHostToDevice, st), "units");
+  if (ntl > 0)
+    hip_check(hipMemcpyAsync(ph.d_tiles[slot].p, tiles, ntl * sizeof(SplitTile), hipMemcpyHostToDevice, st), "tiles");
+  if (!stage_ev_) hip_check(hipEventCreateWithFlags(&stage_ev_, hipEventDisableTiming), "staging event");
+  hip_check(hipEventRecord(stage_ev_, st), "staging event");
+  stage_pending_ = true;
+  const auto tr2 = std::chrono::steady_clock::now();
+  st_.resolve_ms += std::chrono::duration<double, std::milli>(tr2 - tr0).count();
+  if (opt_.verbose > 1)
+    fprintf(stderr, "resolve: %ld items, %ld units: host %.2f ms, upload %.2f ms\n", n_items, nun,
+            std::chrono::duration<double, std::milli>(tr1 - tr0).count(),
+            std::chrono::duration<double, std::milli>(tr2 - tr1).count());
   launch_resolved(ph, prec, slot);
 }
 
@@ -556,6 +662,7 @@ void Solver::env_update_left(int k, const FactorSide& fs) {
   sizes[B_XMIX] = fs.premix_size;
   sizes[B_ENVL] = envk.size;
   const auto te2 = std::chrono::steady_clock::now();
+  st_.env_plan_ms += std::chrono::duration<double, std::milli>(te2 - te1).count();
   run_phase(pa, PREC_F64, bases, esz, sizes);
   run_phase(pb, PREC_F64, bases, esz, sizes);
   const auto te3 = std::chrono::steady_clock::now();
@@ -699,6 +806,7 @@ void Solver::env_update_right(int j, const FactorSide& fs) {
   sizes[B_ENVR] = envr.size;
   sizes[B_SITE2] = Bt.lay.size;
   const auto te2 = std::chrono::steady_clock::now();
+  st_.env_plan_ms += std::chrono::duration<double, std::milli>(te2 - te1).count();
   run_phase(pa, PREC_F64, bases, esz, sizes);
   run_phase(pb, PREC_F64, bases, esz, sizes);
   const auto te3 = std::chrono::steady_clock::now();
@@ -716,6 +824,8 @@ void Solver::env_update_right(int j, const FactorSide& fs) {
 }
 
 void Solver::build_sigma_plan(int k) {
+  using clk = std::chrono::steady_clock;
+  const auto tp0 = clk::now();
   const MPO& mpo = prob_->mpo;
   const Env& envl = left_[k];
   const Env& envr = right_[k + 2];
@@ -809,51 +919,126 @@ void Solver::build_sigma_plan(int k) {
     per[c].resize(P.slabs.size());
     for (size_t si = 0; si < P.slabs.size(); ++si) per[c][si].resize(P.slabs[si].blocks.size());
   }
-  for (int b = 0; b < nmid; ++b) {
-    if (lf_.by_mid[b].empty() || rf_.by_mid[b].empty()) continue;
-    for (const auto& ul : lf_.by_mid[b]) {
-      const Mat4& opl = mpo.ops[ul.op];
-      const int ch = chunk_of[ul.f];
-      for (const auto& ur : rf_.by_mid[b]) {
-        const Mat4& opr = mpo.ops[ur.op];
-        const EnvClass& ycls = envr.classes[rf_.fac[ur.f].cls];
-        double sc = ul.scale * ur.scale;
-        for (int s1 = 0; s1 < 4; ++s1)
-          for (int t1 = 0; t1 < 4; ++t1) {
-            double wl = opl[s1 * 4 + t1];
-            if (wl == 0.0) continue;
-            for (int s2 = 0; s2 < 4; ++s2)
-              for (int t2 = 0; t2 < 4; ++t2) {
-                double wr = opr[s2 * 4 + t2];
-                if (wr == 0.0) continue;
-                int sout = 4 * s1 + s2, sin = 4 * t1 + t2;
-                for (size_t si = 0; si < P.slabs.size(); ++si) {
-                  if (toff[ul.f][si] < 0) continue;
-                  const Slab& src = P.slabs[si];
-                  int lo = trow[ul.f][si];
-                  int so = P.slab_of_left[lo];
-                  const Slab& dst = P.slabs[so];
-                  for (size_t sb = 0; sb < src.blocks.size(); ++sb) {
-                    const SlabBlock& blk = src.blocks[sb];
-                    if (blk.phys != sin) continue;
-                    int ro = bk2.find(bk2.sec[blk.ri].q + ycls.dq);
-                    if (ro < 0) continue;
-                    int yb = ycls.block_of_col[blk.ri];
-                    if (yb < 0 || ycls.blocks[yb].ri != ro) continue;
-                    int ob = dst.block_of(sout, ro);
-                    if (ob < 0) continue;
-                    tused[ul.f][si][sb] = 1;
-                    per[ch][so][ob].push_back({B_T, toff[ul.f][si] + blk.col0,
-                                               rf_.fac[ur.f].alias ? B_ENVR : B_YMIX,
-                                               rf_.fac[ur.f].off + ycls.blocks[yb].off, src.width,
-                                               blk.mr, blk.mr, sc * wl * wr});
-                  }
-                }
-              }
-          }
-      }
+  // lookups: the block of each physical state in a slab (a slab has at most one
+  // per state: the right sector follows from the left one), each factor's slabs,
+  // and per right-factor class the output right sector of an input one
+  std::vector<std::array<int, 16>> blk_of(P.slabs.size());
+  for (size_t si = 0; si < P.slabs.size(); ++si) {
+    blk_of[si].fill(-1);
+    for (size_t sb = 0; sb < P.slabs[si].blocks.size(); ++sb) blk_of[si][P.slabs[si].blocks[sb].phys] = (int)sb;
+  }
+  std::vector<std::vector<int>> fslabs(lf_.fac.size());
+  for (size_t f = 0; f < lf_.fac.size(); ++f)
+    for (size_t si = 0; si < toff[f].size(); ++si)
+      if (toff[f][si] >= 0) fslabs[f].push_back((int)si);
+  std::vector<std::vector<int>> ro_of(envr.classes.size());  // right class -> (input sector -> output sector)
+  for (size_t c = 0; c < envr.classes.size(); ++c) {
+    const EnvClass& ycls = envr.classes[c];
+    ro_of[c].assign(bk2.sec.size(), -1);
+    for (size_t ri = 0; ri < bk2.sec.size(); ++ri) {
+      const int ro = bk2.find(bk2.sec[ri].q + ycls.dq);
+      const int yb = ycls.block_of_col[ri];
+      if (ro >= 0 && yb >= 0 && ycls.blocks[yb].ri == ro) ro_of[c][ri] = ro;
     }
   }
+  // items by middle-cut channel, in parallel over contiguous channel ranges;
+  // each range fills its own lists, appended in range order afterwards (the
+  // serial order, whatever the thread count); the T_X column blocks read are
+  // recorded alongside and marked after
+  struct Used {
+    int f, si, sb;
+  };
+  const int nthr = plan_threads();
+  std::vector<std::vector<std::vector<std::vector<std::vector<PItem>>>>> part(nthr);
+  std::vector<std::vector<Used>> uses(nthr);
+  parallel_ranges(nmid, [&](int t, long b0, long b1) {
+    auto& pt = part[t];
+    pt.resize(nch);
+    for (int c = 0; c < nch; ++c) {
+      pt[c].resize(P.slabs.size());
+      for (size_t si = 0; si < P.slabs.size(); ++si) pt[c][si].resize(P.slabs[si].blocks.size());
+    }
+    std::vector<Used>& ut = uses[t];
+    for (long b = b0; b < b1; ++b) {
+      if (lf_.by_mid[b].empty() || rf_.by_mid[b].empty()) continue;
+      for (const auto& ul : lf_.by_mid[b]) {
+        const Mat4& opl = mpo.ops[ul.op];
+        const int ch = chunk_of[ul.f];
+        const std::vector<int>& sls = fslabs[ul.f];
+        for (const auto& ur : rf_.by_mid[b]) {
+          const Mat4& opr = mpo.ops[ur.op];
+          const int ycl = rf_.fac[ur.f].cls;
+          const EnvClass& ycls = envr.classes[ycl];
+          const std::vector<int>& rmap = ro_of[ycl];
+          const int ybuf = rf_.fac[ur.f].alias ? B_ENVR : B_YMIX;
+          const long ybase = rf_.fac[ur.f].off;
+          double sc = ul.scale * ur.scale;
+          for (int s1 = 0; s1 < 4; ++s1)
+            for (int t1 = 0; t1 < 4; ++t1) {
+              double wl = opl[s1 * 4 + t1];
+              if (wl == 0.0) continue;
+              for (int s2 = 0; s2 < 4; ++s2)
+                for (int t2 = 0; t2 < 4; ++t2) {
+                  double wr = opr[s2 * 4 + t2];
+                  if (wr == 0.0) continue;
+                  int sout = 4 * s1 + s2, sin = 4 * t1 + t2;
+                  for (int si : sls) {
+                    const int sb = blk_of[si][sin];
+                    if (sb < 0) continue;
+                    const Slab& src = P.slabs[si];
+                    const SlabBlock& blk = src.blocks[sb];
+                    const int ro = rmap[blk.ri];
+                    if (ro < 0) continue;
+                    const int so = P.slab_of_left[trow[ul.f][si]];
+                    const int ob = blk_of[so][sout];
+                    if (ob < 0 || P.slabs[so].blocks[ob].ri != ro) continue;
+                    ut.push_back({ul.f, si, sb});
+                    pt[ch][so][ob].push_back({B_T, toff[ul.f][si] + blk.col0, ybuf,
+                                              ybase + ycls.blocks[ycls.block_of_col[blk.ri]].off, src.width,
+                                              blk.mr, blk.mr, sc * wl * wr});
+                  }
+                }
+            }
+        }
+      }
+    }
+  });
+  const auto tp05 = clk::now();
+  for (int t = 0; t < nthr; ++t) {
+    for (const Used& u : uses[t]) tused[u.f][u.si][u.sb] = 1;
+    std::vector<Used>().swap(uses[t]);
+  }
+  // every output block's list: the ranges' lists in range order, then sorted by
+  // operand (consecutive items read neighbouring stretches of T rows)
+  struct BlockRef {
+    int c, so, ob;
+  };
+  std::vector<BlockRef> blocks;
+  for (int c = 0; c < nch; ++c)
+    for (size_t so = 0; so < P.slabs.size(); ++so)
+      for (size_t ob = 0; ob < per[c][so].size(); ++ob) blocks.push_back({c, (int)so, (int)ob});
+  parallel_ranges((long)blocks.size(), [&](int, long i0, long i1) {
+    for (long i = i0; i < i1; ++i) {
+      const BlockRef& br = blocks[i];
+      auto& dst = per[br.c][br.so][br.ob];
+      size_t tot = 0;
+      for (int t = 0; t < nthr; ++t)
+        if (!part[t].empty()) tot += part[t][br.c][br.so][br.ob].size();
+      dst.reserve(tot);
+      for (int t = 0; t < nthr; ++t)
+        if (!part[t].empty()) {
+          auto& src = part[t][br.c][br.so][br.ob];
+          dst.insert(dst.end(), src.begin(), src.end());
+          std::vector<PItem>().swap(src);
+        }
+      std::stable_sort(dst.begin(), dst.end(), [](const PItem& x, const PItem& y) {
+        if (x.aoff != y.aoff) return x.aoff < y.aoff;
+        return x.boff < y.boff;
+      });
+    }
+  });
+  part.clear();
+  const auto tp1 = clk::now();
   // phase A: T_X = X psi over each run of consecutive column blocks that phase B reads
   for (size_t f = 0; f < lf_.fac.size(); ++f) {
     if (toff[f].empty()) continue;
@@ -881,51 +1066,118 @@ void Solver::build_sigma_plan(int k) {
       }
     }
   }
+  const auto tp2 = clk::now();
   // phase B of chunk c adds into sigma; chunk 0 writes every output block (zero
-  // where no item reaches it), later chunks only the blocks they have items for
-  for (int c = 0; c < nch; ++c) {
-    Phase& pb = phB_[c];
-    for (size_t so = 0; so < P.slabs.size(); ++so)
-      for (size_t ob = 0; ob < per[c][so].size(); ++ob) {
-        auto& v = per[c][so][ob];
-        if (c > 0 && v.empty()) continue;
-        // operand order: consecutive items read neighbouring stretches of T rows
-        std::stable_sort(v.begin(), v.end(), [](const PItem& x, const PItem& y) {
-          if (x.aoff != y.aoff) return x.aoff < y.aoff;
-          return x.boff < y.boff;
-        });
-        const Slab& dst = P.slabs[so];
-        const int nb = dst.blocks[ob].mr;
-        int ib = (int)pb.items.size();
-        // items with one A slice (adjacent after the sort) become one product with
-        // the weighted sum of their right blocks (N x K, row stride K)
-        for (size_t a = 0; a < v.size();) {
-          size_t b = a + 1;
-          while (b < v.size() && v[b].abuf == v[a].abuf && v[b].aoff == v[a].aoff && v[b].K == v[a].K &&
-                 v[b].ldb == v[b].K && v[a].ldb == v[a].K)
-            ++b;
-          if (b - a == 1) {
-            pb.items.push_back(v[a]);
-          } else {
-            for (size_t i = a; i < b; ++i) {
-              pm_.src_buf.push_back(v[i].bbuf);
-              pm_.src_off.push_back(v[i].boff);
-              pm_.coef.push_back(v[i].coef);
-            }
-            pm_.ptr.push_back((int)pm_.coef.size());
-            pm_.out_off.push_back(pm_.size);
-            pm_.nnz.push_back(nb * v[a].K);
-            pb.items.push_back({v[a].abuf, v[a].aoff, B_YPAIR, pm_.size, v[a].lda, v[a].K, v[a].K, 1.0});
-            pm_.size += (long)nb * v[a].K;
+  // where no item reaches it), later chunks only the blocks they have items for.
+  // Items with one A slice (adjacent after the sort) become one product with the
+  // weighted sum of their right blocks (N x K, row stride K): merged per block in
+  // parallel with block-local offsets into the merged-block buffer, then
+  // concatenated in block order.
+  struct Merged {
+    std::vector<PItem> items;  // B_YPAIR items carry block-local offsets
+    std::vector<int> src_buf, ptr_len, nnz;
+    std::vector<long> src_off;
+    std::vector<double> coef;
+    long pm_size = 0;
+    double flops = 0, flops_exec = 0;
+  };
+  std::vector<Merged> merged(blocks.size());
+  parallel_ranges((long)blocks.size(), [&](int, long i0, long i1) {
+    for (long i = i0; i < i1; ++i) {
+      const BlockRef& br = blocks[i];
+      auto& v = per[br.c][br.so][br.ob];
+      if (br.c > 0 && v.empty()) continue;
+      Merged& m = merged[i];
+      const Slab& dst = P.slabs[br.so];
+      const int nb = dst.blocks[br.ob].mr;
+      for (size_t a = 0; a < v.size();) {
+        size_t b = a + 1;
+        while (b < v.size() && v[b].abuf == v[a].abuf && v[b].aoff == v[a].aoff && v[b].K == v[a].K &&
+               v[b].ldb == v[b].K && v[a].ldb == v[a].K)
+          ++b;
+        if (b - a == 1) {
+          m.items.push_back(v[a]);
+        } else {
+          for (size_t j = a; j < b; ++j) {
+            m.src_buf.push_back(v[j].bbuf);
+            m.src_off.push_back(v[j].boff);
+            m.coef.push_back(v[j].coef);
           }
-          for (size_t i = a; i < b; ++i) pb.flops += 2.0 * dst.ml * nb * v[i].K;  // algorithmic: unmerged
-          pb.flops_exec += 2.0 * dst.ml * nb * v[a].K;
-          a = b;
+          m.ptr_len.push_back((int)(b - a));
+          m.nnz.push_back(nb * v[a].K);
+          m.items.push_back({v[a].abuf, v[a].aoff, B_YPAIR, m.pm_size, v[a].lda, v[a].K, v[a].K, 1.0});
+          m.pm_size += (long)nb * v[a].K;
         }
-        add_units(pb.units, B_OUT, dst.off + dst.blocks[ob].col0, dst.width, dst.ml, nb, ib,
-                  (int)pb.items.size(), c == 0 ? 0 : 1);
+        for (size_t j = a; j < b; ++j) m.flops += 2.0 * dst.ml * nb * v[j].K;  // algorithmic: unmerged
+        m.flops_exec += 2.0 * dst.ml * nb * v[a].K;
+        a = b;
       }
+      std::vector<PItem>().swap(v);
+    }
+  });
+  // offsets of every block's items (per chunk) and merged groups, then a parallel
+  // copy into place
+  std::vector<long> item_at(blocks.size(), -1), grp_at(blocks.size(), 0), src_at(blocks.size(), 0),
+      pm_at(blocks.size(), 0);
+  {
+    std::vector<long> n_items(nch, 0);
+    long ng = 0, nsrc = 0, npm = pm_.size;
+    for (size_t i = 0; i < blocks.size(); ++i) {
+      const BlockRef& br = blocks[i];
+      if (br.c > 0 && merged[i].items.empty()) continue;
+      item_at[i] = n_items[br.c];
+      n_items[br.c] += (long)merged[i].items.size();
+      grp_at[i] = ng;
+      ng += (long)merged[i].ptr_len.size();
+      src_at[i] = nsrc;
+      nsrc += (long)merged[i].src_buf.size();
+      pm_at[i] = npm;
+      npm += merged[i].pm_size;
+    }
+    for (int c = 0; c < nch; ++c) phB_[c].items.resize(n_items[c]);
+    const size_t g0 = pm_.out_off.size(), s0 = pm_.src_buf.size();
+    pm_.ptr.resize(g0 + 1 + ng);
+    pm_.out_off.resize(g0 + ng);
+    pm_.nnz.resize(g0 + ng);
+    pm_.src_buf.resize(s0 + nsrc);
+    pm_.src_off.resize(s0 + nsrc);
+    pm_.coef.resize(s0 + nsrc);
+    parallel_ranges((long)blocks.size(), [&](int, long i0, long i1) {
+      for (long i = i0; i < i1; ++i) {
+        if (item_at[i] < 0) continue;
+        const Merged& m = merged[i];
+        PItem* out = phB_[blocks[i].c].items.data() + item_at[i];
+        for (size_t j = 0; j < m.items.size(); ++j) {
+          out[j] = m.items[j];
+          if (out[j].bbuf == B_YPAIR) out[j].boff += pm_at[i];
+        }
+        long o = pm_at[i], sp = (long)s0 + src_at[i];
+        for (size_t g = 0; g < m.ptr_len.size(); ++g) {
+          const size_t gi = g0 + grp_at[i] + g;
+          pm_.out_off[gi] = o;
+          pm_.nnz[gi] = m.nnz[g];
+          o += m.nnz[g];
+          sp += m.ptr_len[g];
+          pm_.ptr[gi + 1] = (int)sp;
+        }
+        std::copy(m.src_buf.begin(), m.src_buf.end(), pm_.src_buf.begin() + s0 + src_at[i]);
+        std::copy(m.src_off.begin(), m.src_off.end(), pm_.src_off.begin() + s0 + src_at[i]);
+        std::copy(m.coef.begin(), m.coef.end(), pm_.coef.begin() + s0 + src_at[i]);
+      }
+    });
+    pm_.size = npm;
   }
+  for (size_t i = 0; i < blocks.size(); ++i) {
+    if (item_at[i] < 0) continue;
+    const BlockRef& br = blocks[i];
+    Phase& pb = phB_[br.c];
+    const Slab& dst = P.slabs[br.so];
+    pb.flops += merged[i].flops;
+    pb.flops_exec += merged[i].flops_exec;
+    add_units(pb.units, B_OUT, dst.off + dst.blocks[br.ob].col0, dst.width, dst.ml, dst.blocks[br.ob].mr,
+              (int)item_at[i], (int)(item_at[i] + merged[i].items.size()), br.c == 0 ? 0 : 1);
+  }
+  merged.clear();
   // split-K granularity of every chunk from the work of all chunks of the phase
   // (pieces of the same size whatever the chunking)
   for (std::vector<Phase>* v : {&phA_, &phB_}) {
@@ -937,6 +1189,9 @@ void Solver::build_sigma_plan(int k) {
       for (Phase& ph : *v) ph.split_work = w;
   }
   if (opt_.verbose > 1) {
+    auto ms = [](clk::time_point a, clk::time_point b) { return std::chrono::duration<double, std::milli>(b - a).count(); };
+    fprintf(stderr, "sigma plan k=%d (%d threads): items %.2f ms (generation %.2f), phase A %.2f ms, phase B %.2f ms\n",
+            k, plan_threads(), ms(tp0, tp1), ms(tp0, tp05), ms(tp1, tp2), ms(tp2, clk::now()));
     // shape statistics: executed (tile-padded) vs useful flops per phase
     for (const Phase* ph : {&phA_[0], &phB_[0]}) {
       double padded = 0, kpad = 0, ksum = 0;

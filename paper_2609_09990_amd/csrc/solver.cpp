@@ -89,6 +89,19 @@ void Arena::free(void* p) {
   free_[start] = len;
 }
 
+PinnedStage::~PinnedStage() {
+  if (p) (void)hipHostFree(p);
+}
+void* PinnedStage::reserve(size_t b) {
+  if (b <= bytes && p) return p;
+  if (p) (void)hipHostFree(p);
+  p = nullptr;
+  const size_t want = std::max(b, bytes + bytes / 2);
+  hip_check(hipHostMalloc(&p, want, hipHostMallocDefault), "pinned staging");
+  bytes = want;
+  return p;
+}
+
 DevMem::~DevMem() { release(); }
 void DevMem::release() {
   if (p) {
@@ -202,6 +215,10 @@ Solver::Solver(const Problem* p, const Options& o, hipStream_t s) : prob_(p), op
 
 Solver::~Solver() {
   for (hipEvent_t e : sig_ev_) (void)hipEventDestroy(e);
+  if (stage_ev_) {
+    (void)hipEventSynchronize(stage_ev_);  // the pinned staging is freed after this
+    (void)hipEventDestroy(stage_ev_);
+  }
   for (int i = 0; i < kAuxStreams; ++i) {
     if (aux_rb_[i]) rocblas_destroy_handle(aux_rb_[i]);
     if (aux_st_[i]) (void)hipStreamDestroy(aux_st_[i]);
@@ -464,13 +481,6 @@ void Solver::prepare(int k) {
     c.phA = std::move(phA_);
     c.phB = std::move(phB_);
     c.t_size = t_size_;
-    for (std::vector<Phase>* v : {&c.phA, &c.phB})
-      for (Phase& ph : *v)
-        for (int i = 0; i < 3; ++i) {
-          std::vector<GemmItem>().swap(ph.h_items[i]);
-          std::vector<GemmUnit>().swap(ph.h_units[i]);
-          std::vector<SplitTile>().swap(ph.h_tiles[i]);
-        }
     plan_built_k_ = -1;
   }
   auto same_bond = [](const std::vector<Sector>& a, const std::vector<Sector>& b) {
@@ -497,11 +507,19 @@ void Solver::prepare(int k) {
     st_.plan_hits++;
   } else {
     if (hit != plan_cache_.end()) plan_cache_.erase(hit);
+    const auto tb0 = std::chrono::steady_clock::now();
     build_factor_side(lf_, true, k);
     run_premix(lf_, left_[k]);
     build_factor_side(rf_, false, k + 1);
     run_premix(rf_, right_[k + 2]);
+    const auto tb1 = std::chrono::steady_clock::now();
     build_sigma_plan(k);
+    const auto tb2 = std::chrono::steady_clock::now();
+    st_.plan_build_ms += std::chrono::duration<double, std::milli>(tb2 - tb0).count();
+    if (opt_.verbose > 1)
+      fprintf(stderr, "plan k=%d: factor sides and premix %.2f ms, sigma plan %.2f ms\n", k,
+              std::chrono::duration<double, std::milli>(tb1 - tb0).count(),
+              std::chrono::duration<double, std::milli>(tb2 - tb1).count());
     run_pairmix(k);
     for (std::vector<Phase>* v : {&phA_, &phB_})
       for (Phase& ph : *v)

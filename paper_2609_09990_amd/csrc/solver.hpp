@@ -66,6 +66,18 @@ struct ArenaScope {
 // Number of hipMalloc calls the library's buffers have made (process-wide).
 long library_device_allocations();
 
+// Grow-only pinned host buffer (staging of plan tables for their uploads).
+struct PinnedStage {
+  void* p = nullptr;
+  size_t bytes = 0;
+  PinnedStage() = default;
+  PinnedStage(const PinnedStage&) = delete;
+  PinnedStage& operator=(const PinnedStage&) = delete;
+  ~PinnedStage();
+  void* reserve(size_t b);
+  template <class T> T* get(long n) { return (T*)reserve((size_t)std::max<long>(n, 1) * sizeof(T)); }
+};
+
 // Grow-only device buffer.
 struct DevMem {
   void* p = nullptr;
@@ -153,9 +165,6 @@ struct Phase {
   double flops_exec = -1;   // flops the launch executes, unpadded (-1: same as flops)
   // device copies per precision
   DevMem d_items[3], d_units[3];
-  std::vector<GemmItem> h_items[3];  // host staging kept alive for async copies
-  std::vector<GemmUnit> h_units[3];
-  std::vector<SplitTile> h_tiles[3];
   DevMem d_tiles[3];                 // split-K tile table per precision slot
   const void* slot_base[3] = {};     // split-K scratch the units were resolved against
   int n_units[3] = {0, 0, 0}, n_tiles[3] = {0, 0, 0};
@@ -230,6 +239,8 @@ struct Stats {
   double prepare_ms = 0, resolve_ms = 0, davidson_ms = 0;  // host wall times
   int plan_hits = 0;  // step plans reused from the cache
   int lowp_matvecs = 0;  // sigma products in fp32 / bf16
+  double plan_build_ms = 0;  // host: sigma step plans built (factor sides and items)
+  double env_plan_ms = 0;    // host: environment-update plans built
 };
 
 class MLP;
@@ -479,6 +490,9 @@ class Solver {
   void ovl_update_left(const MPSView& bra, const MPSView& ket, int site, const double* in, double* out);
   void ovl_update_right(const MPSView& bra, const MPSView& ket, int site, const double* in, double* out);
   double chain_overlap(const MPSView& bra, const MPSView& ket);
+  PinnedStage stage_items_, stage_units_, stage_tiles_;  // plan uploads (see run_phase)
+  hipEvent_t stage_ev_ = nullptr;                        // recorded after the last upload from them
+  bool stage_pending_ = false;
   DevMem scratch_items_, scratch_units_;
   std::vector<GemmItem> scratch_h_items_;
   std::vector<GemmUnit> scratch_h_units_;
