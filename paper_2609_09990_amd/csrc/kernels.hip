@@ -1281,6 +1281,23 @@ __global__ void precond_diag_kernel(const double* __restrict__ r, const double* 
   }
 }
 
+// Low-precision copy entries recomputed from fp64 with a shift:
+// dst[idx[i]] = round(src[idx[i]] - w[i] * s) (fp32 or bf16 by `bf16`).
+__global__ void shift_entries_kernel(const double* __restrict__ src, void* __restrict__ dst, int bf16,
+                                     const long* __restrict__ idx, const double* __restrict__ w, long n, double s) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const long e = idx[i];
+    const float v = (float)(src[e] - w[i] * s);
+    if (bf16) ((uint16_t*)dst)[e] = f2bf(v);
+    else ((float*)dst)[e] = v;
+  }
+}
+
+__global__ void axpy_kernel(double* __restrict__ y, const double* __restrict__ x, double a, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    y[i] += a * x[i];
+}
+
 // d[i] += sum_{j<k} V[j ldv + i]^2 (diagonal of a rank-k update V V^T).
 __global__ void add_squares_kernel(double* __restrict__ d, const double* __restrict__ V, long ldv, int k, long n) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
@@ -1650,6 +1667,15 @@ void launch_scale_by_norm(double* x, long n, const double* nrm2, hipStream_t s) 
 void launch_precond_diag(const double* r, const double* diag, const double* theta, double* out,
                          long n, hipStream_t s) {
   precond_diag_kernel<<<grid_for(n), 256, 0, s>>>(r, diag, theta, out, n);
+}
+
+void launch_shift_entries(const double* src, void* dst, bool bf16, const long* idx, const double* w, long n,
+                          double shift, hipStream_t s) {
+  if (n > 0) shift_entries_kernel<<<grid_for(n), 256, 0, s>>>(src, dst, bf16 ? 1 : 0, idx, w, n, shift);
+}
+
+void launch_axpy(double* y, const double* x, double a, long n, hipStream_t s) {
+  if (n > 0) axpy_kernel<<<grid_for(n), 256, 0, s>>>(y, x, a, n);
 }
 
 void launch_add_squares(double* d, const double* V, long ldv, int k, long n, hipStream_t s) {

@@ -109,6 +109,11 @@ void launch_gemv(const double* V, long ldv, int k, const double* coef, double al
 void launch_scale_by_norm(double* x, long n, const double* nrm2, hipStream_t s);
 void launch_precond_diag(const double* r, const double* diag, const double* theta, double* out,
                          long n, hipStream_t s);
+// dst[idx[i]] = round(src[idx[i]] - w[i] * shift) into an fp32 (bf16 = false) or bf16 copy.
+void launch_shift_entries(const double* src, void* dst, bool bf16, const long* idx, const double* w, long n,
+                          double shift, hipStream_t s);
+// y += a x
+void launch_axpy(double* y, const double* x, double a, long n, hipStream_t s);
 // d[i] += sum_{j<k} V[j ldv + i]^2.
 void launch_add_squares(double* d, const double* V, long ldv, int k, long n, hipStream_t s);
 // In place: V[:, i] = sum_{j<k} V[:, j] Y[i k + j] for i < keep (k <= 64, keep <= 16).

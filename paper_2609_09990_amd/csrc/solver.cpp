@@ -595,7 +595,85 @@ void Solver::ensure_lowp(int prec) {
   lowp_[B_PSI].reserve(std::max<long>(psi_lay_.size, 1) * esz);
   lowp_[B_T].reserve(std::max<long>(t_size_, 1) * 4);
   lowp_[B_OUT].reserve(std::max<long>(psi_lay_.size, 1) * 4);
+  setup_lowp_shift(k);
+  if (shift_on_) {
+    const double shift[3] = {shift_a_, shift_b_, shift_b_};
+    const int ids[3] = {B_ENVL, B_ENVR, B_YPAIR};
+    const double* srcs[3] = {left_[k].buf.as<double>(), right_[k + 2].buf.as<double>(), pmix_.as<double>()};
+    for (int i = 0; i < 3; ++i)
+      launch_shift_entries(srcs[i], lowp_[ids[i]].p, prec != PREC_F32, shift_idx_[i].as<long>(),
+                           shift_w_[i].as<double>(), shift_n_[i], shift[i], st);
+  }
   lowp_prec_ = prec;  // resolved low-precision plans stay valid while their buffers do (bases are compared)
+}
+
+void Solver::setup_lowp_shift(int k) {
+  shift_on_ = false;
+  shift_a_ = shift_b_ = 0.0;
+  for (long& n : shift_n_) n = 0;
+  if (center_site_ != k && center_site_ != k + 1) return;
+  const MPO& mpo = prob_->mpo;
+  const int chH = mpo.chan_H[k], chI = mpo.chan_I[k + 2];
+  std::vector<long> idx[3];
+  std::vector<double> w[3];
+  // a channel's square diagonal blocks: element offsets of their diagonals
+  auto diag_of = [](const Env& e, int ch, std::vector<long>& out, std::map<long, int>* blocks) {
+    const EnvClass& c = e.classes[e.chan_class[ch]];
+    const long base = e.chan_off(ch);
+    for (const EnvBlock& b : c.blocks) {
+      if (b.ri != b.ci || b.mr != b.mc) continue;
+      if (blocks) (*blocks)[base + b.off] = b.mr;
+      for (int i = 0; i < b.mr; ++i) out.push_back(base + b.off + (long)i * (b.mc + 1));
+    }
+  };
+  // the mean of those diagonal entries (host copy of the channel)
+  auto diag_mean = [&](const Env& e, int ch, const std::vector<long>& d) {
+    const long base = e.chan_off(ch), nnz = e.classes[e.chan_class[ch]].nnz;
+    std::vector<double> h(nnz);
+    hip_check(hipMemcpy(h.data(), e.buf.as<double>() + base, nnz * 8, hipMemcpyDeviceToHost), "shift");
+    double acc = 0;
+    for (long x : d) acc += h[x - base];
+    return d.empty() ? 0.0 : acc / (double)d.size();
+  };
+  // a channel read through a premixed factor would carry the shift into other terms
+  auto premixed = [](const FactorSide& fs, long off) {
+    return std::find(fs.src_off.begin(), fs.src_off.end(), off) != fs.src_off.end();
+  };
+  if (chH >= 0 && !premixed(lf_, left_[k].chan_off(chH))) {
+    diag_of(left_[k], chH, idx[0], nullptr);
+    shift_a_ = diag_mean(left_[k], chH, idx[0]);
+    w[0].assign(idx[0].size(), 1.0);
+  }
+  if (chI >= 0 && !premixed(rf_, right_[k + 2].chan_off(chI))) {
+    std::map<long, int> rblocks;
+    diag_of(right_[k + 2], chI, idx[1], &rblocks);
+    shift_b_ = diag_mean(right_[k + 2], chI, idx[1]);
+    w[1].assign(idx[1].size(), 1.0);
+    // merged right blocks that include a block of R_I: shift c b on their diagonals
+    for (size_t g = 0; g + 1 < pm_.ptr.size(); ++g)
+      for (int j = pm_.ptr[g]; j < pm_.ptr[g + 1]; ++j) {
+        if (pm_.src_buf[j] != B_ENVR) continue;
+        auto it = rblocks.find(pm_.src_off[j]);
+        if (it == rblocks.end()) continue;
+        const int d = it->second;
+        if ((long)d * d != pm_.nnz[g]) continue;
+        for (int i = 0; i < d; ++i) {
+          idx[2].push_back(pm_.out_off[g] + (long)i * (d + 1));
+          w[2].push_back(pm_.coef[j]);
+        }
+      }
+  }
+  if (idx[0].empty() && idx[1].empty()) return;
+  for (int i = 0; i < 3; ++i) {
+    shift_n_[i] = (long)idx[i].size();
+    shift_idx_[i].reserve(std::max<size_t>(idx[i].size(), 1) * 8);
+    shift_w_[i].reserve(std::max<size_t>(w[i].size(), 1) * 8);
+    if (!idx[i].empty()) {
+      hip_check(hipMemcpy(shift_idx_[i].p, idx[i].data(), idx[i].size() * 8, hipMemcpyHostToDevice), "shift");
+      hip_check(hipMemcpy(shift_w_[i].p, w[i].data(), w[i].size() * 8, hipMemcpyHostToDevice), "shift");
+    }
+  }
+  shift_on_ = true;
 }
 
 void Solver::sigma(int k, int prec, const double* psi, double* out) {
@@ -657,8 +735,12 @@ void Solver::sigma(int k, int prec, const double* psi, double* out) {
     if (!f64 || phB_[c].units.empty()) (void)hipEventRecord(sig_ev_[3 * c + 2], st);
   }
   (void)hipEventRecord(sig_ev_[3 * nch], st);
-  if (f64) launch_copy(out, out_buf_.as<double>(), n, st);
-  else launch_f32_to_f64(lowp_[B_OUT].as<float>(), out, n, st);
+  if (f64) {
+    launch_copy(out, out_buf_.as<double>(), n, st);
+  } else {
+    launch_f32_to_f64(lowp_[B_OUT].as<float>(), out, n, st);
+    if (shift_on_) launch_axpy(out, psi, shift_a_ + shift_b_, n, st);  // the shift back, in fp64
+  }
   hip_check(hipEventSynchronize(sig_ev_[3 * nch]), "sigma");
   float a = 0, b = 0, g = 0;
   for (int c = 0; c < nch; ++c) {

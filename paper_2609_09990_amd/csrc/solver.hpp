@@ -426,6 +426,17 @@ class Solver {
   std::vector<Sector> bonds_at_build_l_, bonds_at_build_r_;
   DevMem lowp_[B_NBUF];  // low-precision copies per buffer id
   int lowp_prec_ = -1;
+  // Shift of the low-precision operator (precision form): the block
+  // Hamiltonians of the step (left environment channel H at cut k, right channel
+  // I at cut k+2) enter the low-precision copies as L_H - a 1 and R_I - b 1, so
+  // their rounding error scales with their spread, not with the energy; the
+  // product then gets (a + b) psi back in fp64.  Only with orthonormal outer
+  // bases (centre on the two sites), where the partner channels are identities.
+  bool shift_on_ = false;
+  double shift_a_ = 0, shift_b_ = 0;
+  DevMem shift_idx_[3], shift_w_[3];
+  long shift_n_[3] = {0, 0, 0};
+  void setup_lowp_shift(int k);
   long lowp_size_[B_NBUF] = {0};
   // diag plan
   std::vector<DiagBlock> dblocks_;

@@ -137,6 +137,37 @@ def test_low_precision_sigma_close_to_fp64(prec, tol):
     assert err < tol, err
 
 
+@pytest.mark.parametrize("prec,tol", [(1, 2e-6), (2, 1e-2)])
+def test_shifted_low_precision_sigma_at_the_centre(prec, tol):
+    """With the orthogonality centre on the two sites the low-precision copies
+    hold the block Hamiltonians shifted by their diagonal means and the product
+    adds the shift back in fp64: the result is the same sigma as fp64, to the
+    low precision's tolerance, and no farther from it than without the shift."""
+    torch = _torch()
+    import paper_2609_09990_amd as pk
+    h, B, e0 = synth.make_hamiltonian(10, 12, 0)
+    prob = pk.Problem(h, B, 5, 5, e0)
+    sol = pk.Solver(prob, M=200, tol=1e-6)
+    for k in range(4):
+        sol.step(k, 0)
+    k = 4  # centre on site 4 after the steps
+    mps = sol.export_mps()
+    plain = pk.Solver(prob, M=200)
+    plain.set_mps(mps["bonds"], mps["sites"])  # gauge unknown: no shift
+    errs = []
+    for s in (sol, plain):
+        n = s.prepare(k)
+        x = torch.from_numpy(synth.random_twosite(mps["bonds"], k, seed=9)).cuda()
+        y64, ylo = torch.zeros_like(x), torch.zeros_like(x)
+        s.sigma(k, x, y64, 0)
+        s.sigma(k, x, ylo, prec)
+        torch.cuda.synchronize()
+        errs.append(float(torch.norm(ylo - y64) / torch.norm(y64)))
+    print(f"prec={prec}: shifted {errs[0]:.2e}, plain {errs[1]:.2e}", flush=True)
+    assert errs[0] < tol
+    assert errs[0] <= 1.5 * errs[1]
+
+
 def _gold(name):
     return json.load(open(GOLD))[name]
 
