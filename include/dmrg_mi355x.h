@@ -57,7 +57,21 @@ typedef enum {
 } dmrg_status;
 
 typedef enum { DMRG_FP64 = 0, DMRG_FP32 = 1, DMRG_BF16 = 2 } dmrg_precision;
-typedef enum { DMRG_PRECOND_DIAG = 0, DMRG_PRECOND_LEARNED = 1 } dmrg_precond;
+/* The two-site Davidson's run-time-selectable preconditioner family (Sec. III):
+ * DIAG (Jacobi: (theta - D)^-1 r, with the deflation penalty's diagonal when
+ * lower states are held), LEARNED (the network's correction, judged against the
+ * exact residual with DIAG as fallback), OLSEN (the diagonal correction less its
+ * component along (D - theta)^-1 x) and SHIFT_INVERT (up to 5 steps of projected
+ * conjugate gradients on (1 - xx^T)(H - theta)(1 - xx^T) t = -r, preconditioned by
+ * the projected diagonal, ended by a non-positive curvature, at pcg_rtol |r| or
+ * after pcg_steps steps (dmrg_options, default 0.1 and 5); each step costs one
+ * sigma product, counted in the matvecs). */
+typedef enum {
+  DMRG_PRECOND_DIAG = 0,
+  DMRG_PRECOND_LEARNED = 1,
+  DMRG_PRECOND_OLSEN = 2,
+  DMRG_PRECOND_SHIFT_INVERT = 3
+} dmrg_precond;
 
 typedef struct {
   int M;               /* bond dimension (kept states per bond) */
@@ -76,11 +90,13 @@ typedef struct {
   long long sigma_chunk_bytes; /* bound on the sigma intermediates T (bytes; 0 = none): left factors
                                   are taken in chunks whose T fits, phase A and B run per chunk and
                                   phase B adds into sigma; less memory, more launches (slower) */
+  int pcg_steps;       /* DMRG_PRECOND_SHIFT_INVERT: most inner CG steps per correction (>= 1) */
+  double pcg_rtol;     /* ... and it stops once the inner residual is <= pcg_rtol * |r| (>= 0) */
 } dmrg_options;
 
 /* Fills *o with defaults: M=256, 1 state, tol 1e-10, 200 iterations, subspace
  * 32, FP64, diagonal preconditioner, seed 1, tie_rtol 1e-10, cut_rtol 1e-14,
- * unbounded sigma intermediates. */
+ * unbounded sigma intermediates, 5 inner PCG steps to 0.1 |r|. */
 void dmrg_options_default(dmrg_options* o);
 
 /* Active-space problem (Sec. II.A): n_orb spatial orbitals, n_alpha / n_beta
@@ -314,9 +330,9 @@ dmrg_status dmrg_mlp_loss_grad(dmrg_mlp* m, const float* X, const float* target,
                                double* loss, float* grad);
 /* Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with the last gradient. */
 dmrg_status dmrg_mlp_adam_step(dmrg_mlp* m, double lr);
-/* Preconditioner of later Davidson solves: DMRG_PRECOND_DIAG (net ignored) or
- * DMRG_PRECOND_LEARNED with a network of n_in = 8 (borrowed: it must outlive
- * its use by the solver). */
+/* Preconditioner of later Davidson solves (dmrg_precond): DMRG_PRECOND_LEARNED
+ * takes a network of n_in = 8 (borrowed: it must outlive its use by the
+ * solver); the others ignore net. */
 dmrg_status dmrg_set_precond(dmrg_solver* s, int precond, dmrg_mlp* net);
 /* Training triples from later Davidson solves (root 0): at every iteration the
  * features of `sample` amplitudes (a seeded draw per step), and once the step
@@ -332,6 +348,18 @@ dmrg_status dmrg_take_triples(dmrg_solver* s, float* X, float* target, int cap, 
  * vectors r (residual) and d (diagonal of H_eff) and eigenvalue estimate theta. */
 dmrg_status dmrg_precond_features(dmrg_solver* s, int k, const double* r, const double* d, double theta,
                                   float* X);
+/* One correction vector of the preconditioner family (Sec. III) at two-site step
+ * k, as a Davidson iteration forms it: device vectors of the step's length n,
+ * x the Ritz vector (unit norm), r = H_eff x - theta x its residual, d the
+ * diagonal of H_eff (dmrg_diag); t (device, n, caller-owned) receives
+ * DMRG_PRECOND_DIAG: (theta - d)^-1 r (each |theta - d_i| floored at 1e-8),
+ * DMRG_PRECOND_OLSEN: that minus (x.q_r / x.q_x) q_x with q_x = (theta - d)^-1 x,
+ * DMRG_PRECOND_SHIFT_INVERT: the inner PCG of the shift-and-invert mode on the
+ * step's H_eff in fp64 (without deflation penalties; the solver's pcg_steps and
+ * pcg_rtol); *products (may be NULL)
+ * receives the sigma products it made.  DMRG_PRECOND_LEARNED is rejected. */
+dmrg_status dmrg_correction(dmrg_solver* s, int k, int mode, const double* x, const double* r, const double* d,
+                            double theta, double* t, int* products);
 
 /* Diagnostic export of an environment of the current MPS: side 0 = left block
  * (sites < cut), 1 = right block (sites >= cut).  Copies min(cap, size) doubles

@@ -23,6 +23,28 @@ The paper gives no formula for these features (it names a run-time-selectable
 preconditioner family, not a learned member), so this module is their
 definition; it is pinned by the invariances above and a hand-computed example
 (tests/test_oracle_precond.py).
+
+The other members of that family (Sec. III names Jacobi, the deflation-aware
+diagonal, Olsen and a shift-and-invert inner-PCG mode with an indefiniteness
+guard) are written here from their textbook definitions, since the paper
+states only their names:
+  Olsen:  t = q_r - (x.q_r / x.q_x) q_x, q_v = (theta - d)^-1 v (floored as
+          above), x the unit Ritz vector and r = (H - theta) x its residual;
+  shift-and-invert: the Jacobi-Davidson correction equation
+          P (theta - H) P t = P r,  P = 1 - x x^T,  t orthogonal to x,
+          solved approximately by preconditioned conjugate gradients with the
+          projected diagonal P (theta - d)^-1 as preconditioner.  Near the
+          lowest root both operators are negative definite on the complement
+          of x and CG runs as on their negatives.  The guard: an iteration
+          whose curvature p.A p is not negative (or whose rho = res.z is not
+          negative) stops; stopping at the first iteration returns the
+          projected diagonal correction.  Otherwise at most `steps`
+          iterations, ending early once |res| <= rtol |r|.
+Pins (tests/test_oracle_precond.py): x.t = 0 and the constant-diagonal
+closed form for Olsen; for the PCG, the exact solution of the projected
+system at full Krylov dimension, the Galerkin (energy-norm) minimiser over the
+explicitly built preconditioned Krylov space after 1-3 steps, and the guard
+on a positive definite shift.
 """
 from __future__ import annotations
 
@@ -68,3 +90,50 @@ def projected_target(psi_i, psi_star):
     c = float(p @ psi_star)
     s = psi_star if c >= 0 else -psi_star
     return s - abs(c) * p
+
+
+def olsen_candidate(x, r, d, theta):
+    """Olsen's correction: the diagonal correction less its component along
+    (theta - d)^-1 x, so that x.t = 0."""
+    qr = diag_candidate(r, d, theta)
+    qx = diag_candidate(x, d, theta)
+    return qr - (x @ qr) / (x @ qx) * qx
+
+
+def shift_invert_candidate(apply, x, r, d, theta, steps=5, rtol=0.1):
+    """Approximate solution of P (theta - H) P t = P r by preconditioned CG
+    (apply(v) = H v).  Returns (t, number of H products)."""
+    def proj(v):
+        return v - (x @ v) * x
+
+    def A(v):  # P (theta - H) P on vectors already orthogonal to x
+        return proj(theta * v - apply(v))
+
+    def Minv(v):
+        return proj(diag_candidate(v, d, theta))
+
+    rnorm = np.linalg.norm(r)
+    t = np.zeros_like(r)
+    res = proj(r)
+    z = Minv(res)
+    rho = res @ z
+    p = z.copy()
+    products = 0
+    for j in range(steps):
+        q = A(p)
+        products += 1
+        curv = p @ q
+        if not (curv < 0 and rho < 0):
+            if j == 0:
+                t = z.copy()
+            break
+        alpha = rho / curv
+        t = t + alpha * p
+        res = res - alpha * q
+        if j + 1 == steps or np.linalg.norm(res) <= rtol * rnorm:
+            break
+        z = Minv(res)
+        rho_new = res @ z
+        p = z + (rho_new / rho) * p
+        rho = rho_new
+    return t, products

@@ -52,3 +52,4 @@ from .autograd import DMRGEnergy, dmrg_energy  # noqa: F401,E402
 from .excited import excited_states  # noqa: F401,E402
 
 FP64, FP32, BF16 = 0, 1, 2
+PRECOND_DIAG, PRECOND_LEARNED, PRECOND_OLSEN, PRECOND_SHIFT_INVERT = 0, 1, 2, 3

@@ -25,7 +25,7 @@ class dmrg_options(C.Structure):
                 ("davidson_tol", C.c_double), ("max_iter", C.c_int), ("max_subspace", C.c_int),
                 ("precision", C.c_int), ("precond", C.c_int), ("seed", C.c_ulonglong),
                 ("tie_rtol", C.c_double), ("cut_rtol", C.c_double), ("verbose", C.c_int),
-                ("sigma_chunk_bytes", C.c_longlong)]
+                ("sigma_chunk_bytes", C.c_longlong), ("pcg_steps", C.c_int), ("pcg_rtol", C.c_double)]
 
 
 def _decl(name, args, res=C.c_int):
@@ -80,6 +80,7 @@ dmrg_set_precision = _decl("dmrg_set_precision", [_p, _i])
 dmrg_record_triples = _decl("dmrg_record_triples", [_p, _i, _i])
 dmrg_take_triples = _decl("dmrg_take_triples", [_p, _p, _p, _i, C.POINTER(_i)])
 dmrg_precond_features = _decl("dmrg_precond_features", [_p, _i, _p, _p, _d, _p])
+dmrg_correction = _decl("dmrg_correction", [_p, _i, _i, _p, _p, _p, _d, _p, _p])
 dmrg_last_error = _decl("dmrg_last_error", [], C.c_char_p)
 
 STATUS = {0: "DMRG_OK", -1: "DMRG_EINVAL", -2: "DMRG_ENOMEM", -3: "DMRG_EHIP", -4: "DMRG_ENOCONV",
@@ -201,7 +202,7 @@ class Solver:
 
     def __init__(self, problem: Problem, M=256, n_states=1, weights=None, tol=1e-10, max_iter=200,
                  max_subspace=32, precision=0, precond=0, seed=1, tie_rtol=1e-10, cut_rtol=1e-14,
-                 verbose=0, stream=None, workspace=False, sigma_chunk_bytes=0):
+                 verbose=0, stream=None, workspace=False, sigma_chunk_bytes=0, pcg_steps=5, pcg_rtol=0.1):
         """workspace: False (the library allocates its device buffers), True (a
         torch-allocated workspace of dmrg_workspace_query bytes, grown and
         re-attached when a call reports DMRG_ENOMEM) or a byte count."""
@@ -211,6 +212,7 @@ class Solver:
         o.max_subspace, o.precision, o.precond, o.seed = max_subspace, precision, precond, seed
         o.tie_rtol, o.cut_rtol, o.verbose = tie_rtol, cut_rtol, verbose
         o.sigma_chunk_bytes = int(sigma_chunk_bytes)
+        o.pcg_steps, o.pcg_rtol = int(pcg_steps), float(pcg_rtol)
         self._w = None
         if weights is not None:
             self._w = np.ascontiguousarray(weights, dtype=np.float64)
@@ -354,7 +356,8 @@ class Solver:
         _check(dmrg_set_precision(self.h, precision))
 
     def set_precond(self, precond, net=None):
-        """0: diagonal, 1: learned with the MLP `net` (kept alive by this object)."""
+        """0: diagonal, 1: learned with the MLP `net` (kept alive by this object),
+        2: Olsen, 3: shift-and-invert inner PCG."""
         self._net = net
         _check(dmrg_set_precond(self.h, precond, net.h if net is not None else None))
 
@@ -369,6 +372,13 @@ class Solver:
 
     def features(self, k, r, d, theta, X):
         _check(dmrg_precond_features(self.h, k, _ptr(r), _ptr(d), float(theta), _ptr(X)))
+
+    def correction(self, k, mode, x, r, d, theta, t):
+        """One correction of the preconditioner family into device t; returns the
+        sigma products it made."""
+        mv = C.c_int()
+        _check(dmrg_correction(self.h, k, mode, _ptr(x), _ptr(r), _ptr(d), float(theta), _ptr(t), C.byref(mv)))
+        return mv.value
 
     def set_kernel_tag(self, tag):
         _check(dmrg_set_kernel_tag(self.h, tag))

@@ -67,6 +67,8 @@ void dmrg_options_default(dmrg_options* o) {
   o->cut_rtol = 1e-14;
   o->verbose = 0;
   o->sigma_chunk_bytes = 0;
+  o->pcg_steps = 5;
+  o->pcg_rtol = 0.1;
 }
 
 dmrg_status dmrg_problem_create(int n, int na, int nb, int nq, const double* h, const double* B,
@@ -162,6 +164,9 @@ dmrg_status dmrg_solver_create(const dmrg_problem* p, const dmrg_options* o, voi
     op.verbose = o->verbose;
     DMRG_REQUIRE(o->sigma_chunk_bytes >= 0, ST_EINVAL, "sigma_chunk_bytes must be >= 0");
     if (o->sigma_chunk_bytes > 0) op.sigma_chunk_bytes = o->sigma_chunk_bytes;
+    DMRG_REQUIRE(o->pcg_steps >= 1 && o->pcg_rtol >= 0, ST_EINVAL, "pcg_steps must be >= 1 and pcg_rtol >= 0");
+    op.pcg_steps = o->pcg_steps;
+    op.pcg_rtol = o->pcg_rtol;
     DMRG_REQUIRE(op.precision >= 0 && op.precision <= 2, ST_EINVAL, "unknown precision");
     DMRG_REQUIRE(op.davidson_tol > 0, ST_EINVAL, "davidson_tol must be positive");
     DMRG_REQUIRE(op.max_iter >= 1, ST_EINVAL, "max_iter must be >= 1");
@@ -524,6 +529,18 @@ dmrg_status dmrg_precond_features(dmrg_solver* s, int k, const double* r, const 
     DMRG_REQUIRE(s && r && d && X, ST_EINVAL, "NULL argument");
     DMRG_REQUIRE(k >= 0 && k + 1 < s->prob->p.n, ST_EINVAL, "two-site step out of range");
     s->s->features_host_theta(k, r, d, theta, X);
+  });
+}
+
+dmrg_status dmrg_correction(dmrg_solver* s, int k, int mode, const double* x, const double* r, const double* d,
+                            double theta, double* t, int* products) {
+  return solver_call(s, [&] {
+    DMRG_REQUIRE(s && x && r && d && t, ST_EINVAL, "NULL argument");
+    DMRG_REQUIRE(k >= 0 && k + 1 < s->prob->p.n, ST_EINVAL, "two-site step out of range");
+    DMRG_REQUIRE(mode == DMRG_PRECOND_DIAG || mode == DMRG_PRECOND_OLSEN || mode == DMRG_PRECOND_SHIFT_INVERT,
+                 ST_EINVAL, "mode must be DIAG, OLSEN or SHIFT_INVERT");
+    int mv = s->s->correction_host_theta(k, mode, x, r, d, theta, t);
+    if (products) *products = mv;
   });
 }
 

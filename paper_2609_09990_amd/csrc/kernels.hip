@@ -1293,6 +1293,20 @@ __global__ void shift_entries_kernel(const double* __restrict__ src, void* __res
   }
 }
 
+__global__ void axpy_ratio_kernel(double* __restrict__ y, const double* __restrict__ x, const double* __restrict__ num,
+                                  const double* __restrict__ den, double sign, long n) {
+  const double a = sign * num[0] / den[0];
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    y[i] += a * x[i];
+}
+
+__global__ void xpby_ratio_kernel(double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ num,
+                                  const double* __restrict__ den, long n) {
+  const double b = num[0] / den[0];
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    p[i] = z[i] + b * p[i];
+}
+
 __global__ void axpy_kernel(double* __restrict__ y, const double* __restrict__ x, double a, long n) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     y[i] += a * x[i];
@@ -1672,6 +1686,15 @@ void launch_precond_diag(const double* r, const double* diag, const double* thet
 void launch_shift_entries(const double* src, void* dst, bool bf16, const long* idx, const double* w, long n,
                           double shift, hipStream_t s) {
   if (n > 0) shift_entries_kernel<<<grid_for(n), 256, 0, s>>>(src, dst, bf16 ? 1 : 0, idx, w, n, shift);
+}
+
+void launch_axpy_ratio(double* y, const double* x, const double* num, const double* den, double sign, long n,
+                       hipStream_t s) {
+  if (n > 0) axpy_ratio_kernel<<<grid_for(n), 256, 0, s>>>(y, x, num, den, sign, n);
+}
+
+void launch_xpby_ratio(double* p, const double* z, const double* num, const double* den, long n, hipStream_t s) {
+  if (n > 0) xpby_ratio_kernel<<<grid_for(n), 256, 0, s>>>(p, z, num, den, n);
 }
 
 void launch_axpy(double* y, const double* x, double a, long n, hipStream_t s) {

@@ -114,6 +114,10 @@ void launch_shift_entries(const double* src, void* dst, bool bf16, const long* i
                           double shift, hipStream_t s);
 // y += a x
 void launch_axpy(double* y, const double* x, double a, long n, hipStream_t s);
+// y += sign * (num[0] / den[0]) x and p = z + (num[0] / den[0]) p (device scalars)
+void launch_axpy_ratio(double* y, const double* x, const double* num, const double* den, double sign, long n,
+                       hipStream_t s);
+void launch_xpby_ratio(double* p, const double* z, const double* num, const double* den, long n, hipStream_t s);
 // d[i] += sum_{j<k} V[j ldv + i]^2.
 void launch_add_squares(double* d, const double* V, long ldv, int k, long n, hipStream_t s);
 // In place: V[:, i] = sum_{j<k} V[:, j] Y[i k + j] for i < keep (k <= 64, keep <= 16).

@@ -8,8 +8,8 @@
 namespace dmrg {
 
 void Solver::set_precond(int mode, MLP* net) {
-  DMRG_REQUIRE(mode == 0 || mode == 1, ST_EINVAL, "preconditioner must be DIAG or LEARNED");
-  DMRG_REQUIRE(mode == 0 || net, ST_EINVAL, "the learned preconditioner needs a network");
+  DMRG_REQUIRE(mode >= 0 && mode <= 3, ST_EINVAL, "preconditioner must be DIAG, LEARNED, OLSEN or SHIFT_INVERT");
+  DMRG_REQUIRE(mode != 1 || net, ST_EINVAL, "the learned preconditioner needs a network");
   DMRG_REQUIRE(!net || (net->n_in() == 8), ST_EINVAL, "the preconditioner network takes 8 features");
   precond_ = mode;
   net_ = net;

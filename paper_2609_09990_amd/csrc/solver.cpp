@@ -208,7 +208,7 @@ Solver::Solver(const Problem* p, const Options& o, hipStream_t s) : prob_(p), op
     for (double& w : opt_.weights) w /= wsum;
   }
   opt_.max_subspace = std::max(std::min(opt_.max_subspace, 64), 2 * opt_.n_states + 2);
-  DMRG_REQUIRE(opt_.precond == 0 || opt_.precond == 1, ST_EINVAL, "unknown preconditioner");
+  DMRG_REQUIRE(opt_.precond >= 0 && opt_.precond <= 3, ST_EINVAL, "unknown preconditioner");
   precond_ = opt_.precond;
   init_random_mps();
 }
@@ -829,6 +829,111 @@ void Solver::form_twosite(int k, const SiteTensor& a, const SiteTensor& b, doubl
 // is expanded with low-precision products; convergence is only declared on the
 // fp64 residual of the Ritz vectors (defect correction: on a stall or on low-
 // precision convergence the Ritz vectors' fp64 sigma replaces the subspace).
+// Olsen's correction (the preconditioner family of the two-site Davidson, Sec.
+// III): with q_r = -(D - theta)^-1 r (in t on entry) and q_x = -(D - theta)^-1 x,
+// t = q_r - (x.q_r / x.q_x) q_x: the diagonal correction less its part along
+// (D - theta)^-1 x, which for a nearly converged root only re-adds x.
+void Solver::olsen(const double* x, const double* D, const double* theta, double* t) {
+  const long n = psi_lay_.size;
+  double* qx = dv_pcg_.as<double>();
+  double* sc = dv_sc_.as<double>();
+  double* part = dv_part_.as<double>();
+  launch_precond_diag(x, D, theta, qx, n, st);
+  launch_dots(x, n, 1, t, n, part, sc + 192, st);
+  launch_dots(x, n, 1, qx, n, part, sc + 193, st);
+  launch_axpy_ratio(t, qx, sc + 192, sc + 193, -1.0, n, st);
+}
+
+// Shift-and-invert correction (the inner-PCG member of that family, Sec. III): a
+// few preconditioned conjugate-gradient steps on the projected correction
+// equation (1 - x x^T)(theta - H)(1 - x x^T) t = r, t orthogonal to x, with the
+// projected diagonal (theta - D)^-1 as preconditioner.  Both are negative
+// definite near the lowest root, where CG runs as on the positive pair; H - theta
+// is indefinite away from it, so a direction of non-negative curvature p.(theta -
+// H)p (or a non-negative rho) ends the iteration (the guard), and if that happens
+// on the first step the projected diagonal correction is taken.  Stops at
+// pcg_rtol |r| or after pcg_steps steps.  Returns the products made.
+template <class Apply>
+int Solver::shift_invert(const double* x, const double* r, const double* D, const double* theta, double rnorm,
+                         double* t, int prec, Apply& apply) {
+  const int kInner = opt_.pcg_steps;
+  const long n = psi_lay_.size;
+  double* res = dv_pcg_.as<double>();
+  double* z = res + n;
+  double* p = res + 2 * n;
+  double* w = res + 3 * n;
+  double* sc = dv_sc_.as<double>();
+  double* part = dv_part_.as<double>();
+  auto project = [&](double* v) {  // v -= (x.v) x
+    launch_dots(x, n, 1, v, n, part, sc + 195, st);
+    launch_axpy_dev(v, x, sc + 195, -1.0, n, st);
+  };
+  launch_fill(t, n, 0.0, st);
+  launch_copy(res, r, n, st);
+  project(res);
+  launch_precond_diag(res, D, theta, z, n, st);  // (theta - D)^-1 res
+  project(z);
+  launch_dots(res, n, 1, z, n, part, sc + 192, st);  // rho = res.z
+  launch_copy(p, z, n, st);
+  int mv = 0;
+  double h[2];
+  for (int j = 0; j < kInner; ++j) {
+    apply(prec, p, w);
+    ++mv;
+    launch_axpy_dev(w, p, theta, -1.0, n, st);  // w = (H - theta) p
+    project(w);
+    launch_dots(p, n, 1, w, n, part, sc + 193, st);  // p.(H - theta)p
+    hip_check(hipMemcpyAsync(h, sc + 192, 16, hipMemcpyDeviceToHost, st), "pcg");
+    hip_check(hipStreamSynchronize(st), "pcg");
+    if (!(h[1] > 0.0) || !(h[0] < 0.0)) {  // the guard: not a descent pair
+      if (j == 0) launch_copy(t, z, n, st);
+      break;
+    }
+    // alpha = rho / p.(theta - H)p = -rho / p.w; t += alpha p; res -= alpha (theta - H)p = res + alpha w
+    launch_axpy_ratio(t, p, sc + 192, sc + 193, -1.0, n, st);
+    launch_axpy_ratio(res, w, sc + 192, sc + 193, -1.0, n, st);
+    if (j + 1 == kInner) break;
+    launch_dots(res, n, 1, res, n, part, sc + 196, st);
+    double rr;
+    hip_check(hipMemcpyAsync(&rr, sc + 196, 8, hipMemcpyDeviceToHost, st), "pcg");
+    hip_check(hipStreamSynchronize(st), "pcg");
+    if (std::sqrt(std::max(rr, 0.0)) <= opt_.pcg_rtol * rnorm) break;
+    launch_precond_diag(res, D, theta, z, n, st);
+    project(z);
+    launch_dots(res, n, 1, z, n, part, sc + 194, st);  // rho'
+    launch_xpby_ratio(p, z, sc + 194, sc + 192, n, st);  // p = z + (rho'/rho) p
+    launch_copy(sc + 192, sc + 194, 1, st);
+  }
+  return mv;
+}
+
+// One correction of the preconditioner family outside a solve: x the Ritz
+// vector (unit norm), r its residual, d the diagonal of H_eff, theta the Ritz
+// value; the shift-and-invert products are the fp64 sigma of step k.
+int Solver::correction_host_theta(int k, int mode, const double* x, const double* r, const double* d,
+                                  double theta, double* t) {
+  if (plan_k_ != k) prepare(k);
+  const long n = psi_lay_.size;
+  dv_sc_.reserve(256 * 8);
+  dv_part_.reserve((size_t)512 * 64 * 8);
+  dv_pcg_.reserve((size_t)4 * n * 8);
+  double* sc = dv_sc_.as<double>();
+  hip_check(hipMemcpyAsync(sc + 203, &theta, 8, hipMemcpyHostToDevice, st), "theta");
+  launch_precond_diag(r, d, sc + 203, t, n, st);
+  int mv = 0;
+  if (mode == 2) olsen(x, d, sc + 203, t);
+  if (mode == 3) {
+    launch_dots(r, n, 1, r, n, dv_part_.as<double>(), sc + 204, st);
+    double rr;
+    hip_check(hipMemcpyAsync(&rr, sc + 204, 8, hipMemcpyDeviceToHost, st), "rnorm");
+    hip_check(hipStreamSynchronize(st), "rnorm");
+    auto apply = [&](int p, const double* a, double* b) { sigma(k, p, a, b); };
+    mv = shift_invert(x, r, d, sc + 203, std::sqrt(std::max(rr, 0.0)), t, PREC_F64, apply);
+  }
+  hip_check(hipStreamSynchronize(st), "correction");
+  return mv;
+}
+
 int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& evals) {
   if (plan_k_ != k) prepare(k);
   const auto td0 = std::chrono::steady_clock::now();
@@ -853,6 +958,7 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
   dv_diag_.reserve((size_t)n * 8);
   dv_part_.reserve((size_t)512 * 64 * 8);
   dv_sc_.reserve(256 * 8);
+  if (precond_ == 2 || precond_ == 3) dv_pcg_.reserve((size_t)4 * n * 8);
   double* V = dv_V_.as<double>();
   double* AV = dv_AV_.as<double>();
   double* G = dv_G_.as<double>();
@@ -1129,6 +1235,9 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
     for (int i = 0; i < nr; ++i) {
       if (rn[i] <= opt_.davidson_tol) continue;
       launch_precond_diag(R + (long)i * n, D, ev + i, Cc + (long)nnew * n, n, st);
+      if (precond_ == 2) olsen(X + (long)i * n, D, ev + i, Cc + (long)nnew * n);
+      else if (precond_ == 3) matvecs += shift_invert(X + (long)i * n, R + (long)i * n, D, ev + i, rn[i],
+                                                      Cc + (long)nnew * n, sprec, apply);
       if (lrn_on) {
         features(R + (long)i * n, D, ev + i, Cc + (long)nnew * n, F);
         net_->forward(PREC_BF16, F, n, Y, st);

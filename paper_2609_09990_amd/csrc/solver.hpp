@@ -30,6 +30,8 @@ struct Options {
   double cut_rtol = 1e-14;
   int verbose = 0;
   long long sigma_chunk_bytes = 0;  // 0: all left factors in one chunk
+  int pcg_steps = 5;                // shift-and-invert correction: inner CG steps ...
+  double pcg_rtol = 0.1;            // ... and relative residual at which they stop
 };
 
 // A caller-provided slab of device memory that the library carves into its
@@ -356,6 +358,8 @@ class Solver {
   int take_triples(float* X, float* T, int cap);
   int triple_sample() const { return rec_sample_; }
   // Features of the prepared step k for device vectors r, d and a host theta.
+  int correction_host_theta(int k, int mode, const double* x, const double* r, const double* d, double theta,
+                            double* t);
   void features_host_theta(int k, const double* r, const double* d, double theta, float* X);
   std::vector<double> env_host(int cut, int side);
   const Problem* prob() const { return prob_; }
@@ -463,6 +467,11 @@ class Solver {
   void svd_step(int k, bool left_to_right, int nr, std::vector<DevMem>& next_guess, double& tau);
   void form_twosite(int k, const SiteTensor& a, const SiteTensor& b, double* out);
   int davidson(int k, std::vector<DevMem>& guess, std::vector<double>& evals);
+  void olsen(const double* x, const double* D, const double* theta, double* t);
+  template <class Apply>
+  int shift_invert(const double* x, const double* r, const double* D, const double* theta, double rnorm, double* t,
+                   int prec, Apply& apply);
+  DevMem dv_pcg_;  // work vectors of the Olsen and shift-and-invert corrections
   void gemm_once(int mode, std::vector<GemmItem>& items, std::vector<GemmUnit>& units);
   void grad_site(int k, std::vector<double>& g, double* norm);
   DevMem grad_P_, grad_Q_, grad_G_;

@@ -127,3 +127,24 @@ def test_singlet_selection_cas8(prec):
     for r in rejected:  # each an exact spin multiplet with S >= 1 (triplets, a quintet)
         S = (-1 + np.sqrt(1 + 4 * r["s2"])) / 2
         assert abs(S - round(S)) < 1e-6 and round(S) >= 1, r["s2"]
+
+
+def test_shift_invert_excited_states_same_energies():
+    """CAS(8,8), N_Q = 32: the three lowest roots by penalty deflation with the
+    diagonal and with the shift-and-invert preconditioner agree to 1e-10 Ha and
+    equal FCI (wall time and matvecs printed)."""
+    _torch()
+    import time
+
+    import paper_2609_09990_amd as pk
+    g = json.load(open(GOLD))["cas8_nq32_s0"]
+    h, B, e0 = synth.make_hamiltonian(8, 32, 0)
+    prob = pk.Problem(h, B, 4, 4, e0)
+    out = {}
+    for mode in (0, 3):
+        t0 = time.perf_counter()
+        res = pk.excited_states(prob, 3, M=256, tol=1e-10, sweeps=3, conv_tol=1e-11, precond=mode)
+        out[mode] = res["energies"]
+        print(f"precond {mode}: {time.perf_counter() - t0:.2f} s, E = {res['energies']}", flush=True)
+    assert np.max(np.abs(out[0] - out[3])) <= 1e-10
+    assert np.max(np.abs(out[3] - np.array(g["energies"]))) <= 1e-10

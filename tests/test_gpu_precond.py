@@ -173,3 +173,81 @@ def test_non_finite_network_falls_back_to_the_diagonal():
     assert res[1][3] > 0  # every learned candidate was rejected
     assert abs(res[0][0] - res[1][0]) <= 1e-10
     assert res[1][2] == res[0][2]  # the diagonal candidate was used in every iteration
+
+
+def _near_ground(ts, x, eps):
+    """The oracle H_eff's lowest eigenvector (Lanczos over the oracle's sigma)
+    plus eps times the unit vector x, normalised."""
+    from scipy.sparse.linalg import LinearOperator, eigsh
+    n = x.size
+    op = LinearOperator((n, n), matvec=lambda v: ts.sigma(np.ascontiguousarray(v).reshape(-1)), dtype=float)
+    _, v = eigsh(op, k=1, which="SA", tol=1e-10)
+    y = v[:, 0] + eps * x / np.linalg.norm(x)
+    return y / np.linalg.norm(y)
+
+
+@pytest.mark.parametrize("n,na,nb,nq,M,k,near,steps,rtol", [
+    (6, 3, 3, 8, 12, 2, 0.1, 5, 0.1),    # defaults: stops on the residual
+    (6, 3, 3, 8, 12, 2, 0.1, 4, 0.0),    # four full CG steps
+    (6, 3, 3, 8, 12, 2, None, 5, 0.1),   # random x: theta mid-spectrum
+    (8, 4, 4, 16, 40, 3, 0.1, 3, 0.0),
+    (10, 5, 5, 12, 200, 4, None, 3, 0.0),  # blocks of up to 200 rows, ragged sectors
+])
+def test_correction_family_matches_oracle(n, na, nb, nq, M, k, near, steps, rtol):
+    """dmrg_correction for DIAG, OLSEN and SHIFT_INVERT against the oracle's
+    candidates on the same x, r, d, theta (all four from the oracle's H_eff):
+    element-wise to 1e-10 relative, the same number of sigma products."""
+    pk = _pk()
+    from oracle import blocks
+    from oracle import mpo as om
+    print(f"correction case n={n} M={M} k={k} near={near} steps={steps} rtol={rtol}", flush=True)
+    h, B, e0 = synth.make_hamiltonian(n, nq, 2)
+    mps = synth.random_mps(n, na, nb, M, seed=8)
+    sol = pk.Solver(pk.Problem(h, B, na, nb, e0), M=M, pcg_steps=steps, pcg_rtol=rtol)
+    sol.set_mps(mps["bonds"], mps["sites"])
+    size = sol.prepare(k)
+    ts = blocks.TwoSite(om.build_mpo(h, B), mps, k)
+    x = synth.random_twosite(mps["bonds"], k, seed=3)
+    assert x.size == size
+    x = _near_ground(ts, x, near) if near is not None else x / np.linalg.norm(x)
+    hx = ts.sigma(x)
+    theta = float(x @ hx)
+    r = hx - theta * x
+    d = ts.diag()
+    refs = {0: (opre.diag_candidate(r, d, theta), 0), 2: (opre.olsen_candidate(x, r, d, theta), 0),
+            3: opre.shift_invert_candidate(ts.sigma, x, r, d, theta, steps=steps, rtol=rtol)}
+    dx, dr, dd = (torch.from_numpy(np.ascontiguousarray(v)).cuda() for v in (x, r, d))
+    for mode, (ref, mv_ref) in refs.items():
+        t = torch.zeros(size, dtype=torch.float64, device="cuda")
+        mv = sol.correction(k, mode, dx, dr, dd, theta, t)
+        got = t.cpu().numpy()
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        print(f"  mode {mode}: products {mv} (oracle {mv_ref}) rel err {err:.2e}", flush=True)
+        assert mv == mv_ref
+        assert err <= 1e-10, (mode, err)
+    if near is not None and rtol == 0.0:
+        assert refs[3][1] == steps  # the CG ran every step
+
+
+def test_olsen_and_shift_invert_davidson_reach_fci():
+    """CAS(8,8), N_Q = 32 at full bond (M = 256): two sweeps with each member of
+    the preconditioner family reach the oracle's FCI energy to 1e-9 Ha; the
+    shift-and-invert mode counts its inner products among the matvecs."""
+    pk = _pk()
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fci_energies.json")))
+    e_fci = g["cas8_nq32_s0"]["energies"][0]
+    h, B, e0 = synth.make_hamiltonian(8, 32, 0)
+    out = {}
+    for mode in (0, 2, 3):
+        sol = pk.Solver(pk.Problem(h, B, 4, 4, e0), M=256, tol=1e-10, precond=mode)
+        e, tau, ok = sol.sweep(2)
+        st = sol.stats()
+        out[mode] = (e[0], ok, st["matvecs"], st["davidson_iters"])
+        print(f"precond {mode}: E={e[0]:.12f} converged={ok} matvecs={st['matvecs']:.0f} "
+              f"iterations={st['davidson_iters']:.0f}", flush=True)
+        assert ok
+        assert abs(e[0] - e_fci) <= 1e-9, (mode, e[0] - e_fci)
+    # the inner products are counted: more sigma products per iteration than one
+    assert out[3][2] / out[3][3] > out[0][2] / out[0][3]
