@@ -274,6 +274,42 @@ dmrg_status dmrg_overlap(dmrg_solver* s, int j, double* overlap);
  * the MPS as stored (any gauge) and s2[1..] untouched. */
 dmrg_status dmrg_s_squared(dmrg_solver* s, double* s2);
 
+/* ---- Determinant space: CI vectors and (transition) RDMs ----------------
+ * The device CI pipeline of Sec. III (colexicographic string ranks, string
+ * enumeration, RDMs formed on the device) applied to MPS states: the RDMs of
+ * the DMRG node's output (Sec. II.C: the node maps the integrals to the MPS and
+ * its RDMs) and the transition RDMs between deflated roots (Sec. II.F).
+ * Conventions: E_pq = sum_sigma a+_{p sigma} a_{q sigma}; a determinant is
+ * (prod_{p in I_a} a+_{p alpha})(prod_{p in I_b} a+_{p beta})|0> with creators in
+ * ascending orbital order, all alpha first; strings are ranked
+ * colexicographically (rank = sum_t C(o_t, t+1) over sorted occupied orbitals);
+ * a CI vector is the row-major matrix c[I_a][I_b], I_a < C(n, n_alpha),
+ * I_b < C(n, n_beta).  Device memory is the caller's unless said otherwise. */
+/* String counts C(n_orb, n_alpha) and C(n_orb, n_beta).  Host only. */
+dmrg_status dmrg_ci_dims(const dmrg_problem* p, int64_t* n_alpha_strings, int64_t* n_beta_strings);
+/* The CI vector of an MPS, as stored (no normalisation): state 0 = the
+ * solver's MPS (root 0), state j >= 1 = held state j-1 (dmrg_deflate_add).
+ * c: device array of n = C(n,n_alpha) C(n,n_beta) doubles (DMRG_EINVAL
+ * otherwise); at most 24 orbitals and n < 2^31.  Prefix and suffix partial
+ * products meet at the middle bond as block GEMMs; temporaries are the
+ * library's (workspace when one is attached). */
+dmrg_status dmrg_mps_to_ci(dmrg_solver* s, int state, double* c, int64_t n);
+/* Transition 1-/2-RDMs of device CI vectors bra, ket (may be the same pointer),
+ * unnormalised:
+ *   gamma[p*n+q] = <bra|E_pq|ket>,
+ *   Gamma[((p*n+q)*n+r)*n+s] = <bra|E_pq E_rs|ket> - d_qr gamma_ps
+ *     = sum_{sigma tau} <bra|a+_{p sigma} a+_{r tau} a_{s tau} a_{q sigma}|ket>,
+ * overlap = <bra|ket>; host outputs (n^2, n^4 doubles, 1; each may be NULL).
+ * At most 16 orbitals.  E_rs c for all rs in passes of determinants (a gather
+ * kernel over string-excitation tables), then one fp64 MFMA product of
+ * (n^2 + 1) x (n^2 + 1) over the determinants; runs on `stream` and returns
+ * when the outputs are written. */
+dmrg_status dmrg_ci_rdm12(const dmrg_problem* p, const double* bra, const double* ket, double* gamma, double* Gamma,
+                          double* overlap, void* stream);
+/* The same for MPS states (numbering as dmrg_mps_to_ci), each normalised:
+ * gamma, Gamma and overlap of <bra|.|ket> / (|bra| |ket|). */
+dmrg_status dmrg_rdm12(dmrg_solver* s, int bra_state, int ket_state, double* gamma, double* Gamma, double* overlap);
+
 /* Integral gradient of the current MPS energy (Sec. II.C: the DMRG node's
  * adjoint; the MPS is held fixed, i.e. the Hellmann-Feynman term, exact for a
  * converged full-bond state; at truncated bond it is the gradient of

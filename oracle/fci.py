@@ -12,7 +12,8 @@ factorisation (pq|rs) = sum_Q B^Q_pq B^Q_rs):
 
 Pins: ``tests/test_oracle_fci.py`` (brute-force Fock space, free fermions,
 Hubbard dimer, Hermiticity, S^2 integrality, RDM traces, Euler identity, finite
-differences of the energy).
+differences of the energy; transition RDMs against products of brute-force
+Fock-space one-body operators and a hand-worked two-orbital case).
 """
 from __future__ import annotations
 
@@ -234,6 +235,26 @@ def rdm12(space: DetSpace, C: np.ndarray):
     gamma = np.einsum("ab,pqab->pq", C, D)
     # <E_pq E_rs> = <E_qp c | E_rs c>
     EE = np.einsum("qpab,rsab->pqrs", D, D)
+    Gp = EE - np.einsum("qr,ps->pqrs", np.eye(n), gamma)
+    return gamma, Gp
+
+
+def trdm12(space: DetSpace, Cbra: np.ndarray, Cket: np.ndarray):
+    """Transition RDMs by nested application, straight from the definitions:
+    gamma_pq = <bra|E_pq|ket>, Gamma'_pqrs = <bra|E_pq E_rs|ket> - d_qr gamma_ps
+    (E_rs applied to the ket first, then E_pq; no adjoint identity used)."""
+    n = space.n
+    Cb = Cbra.reshape(space.shape)
+    Ck = Cket.reshape(space.shape)
+    gamma = np.empty((n, n))
+    EE = np.empty((n, n, n, n))
+    for r in range(n):
+        for s in range(n):
+            D = space.apply_E(r, s, Ck)
+            gamma[r, s] = np.sum(Cb * D)
+            for p in range(n):
+                for q in range(n):
+                    EE[p, q, r, s] = np.sum(Cb * space.apply_E(p, q, D))
     Gp = EE - np.einsum("qr,ps->pqrs", np.eye(n), gamma)
     return gamma, Gp
 

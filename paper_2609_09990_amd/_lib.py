@@ -81,6 +81,10 @@ dmrg_record_triples = _decl("dmrg_record_triples", [_p, _i, _i])
 dmrg_take_triples = _decl("dmrg_take_triples", [_p, _p, _p, _i, C.POINTER(_i)])
 dmrg_precond_features = _decl("dmrg_precond_features", [_p, _i, _p, _p, _d, _p])
 dmrg_correction = _decl("dmrg_correction", [_p, _i, _i, _p, _p, _p, _d, _p, _p])
+dmrg_ci_dims = _decl("dmrg_ci_dims", [_p, _p, _p])
+dmrg_mps_to_ci = _decl("dmrg_mps_to_ci", [_p, _i, _p, _i64])
+dmrg_ci_rdm12 = _decl("dmrg_ci_rdm12", [_p, _p, _p, _p, _p, _p, _p])
+dmrg_rdm12 = _decl("dmrg_rdm12", [_p, _i, _i, _p, _p, _p])
 dmrg_last_error = _decl("dmrg_last_error", [], C.c_char_p)
 
 STATUS = {0: "DMRG_OK", -1: "DMRG_EINVAL", -2: "DMRG_ENOMEM", -3: "DMRG_EHIP", -4: "DMRG_ENOCONV",
@@ -122,6 +126,27 @@ class Problem:
         d = np.zeros(self.n + 1, dtype=np.int32)
         _check(dmrg_mpo_dims(self.h, _ptr(d)))
         return d
+
+    def ci_dims(self):
+        """(C(n, n_alpha), C(n, n_beta)): the CI matrix shape."""
+        a, b = C.c_int64(), C.c_int64()
+        _check(dmrg_ci_dims(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def ci_rdm12(self, bra, ket=None, stream=None):
+        """Unnormalised (transition) 1-/2-RDMs of device CI vectors: (gamma[n, n],
+        Gamma[n, n, n, n], <bra|ket>), gamma_pq = <bra|E_pq|ket>, Gamma_pqrs =
+        <bra|E_pq E_rs|ket> - d_qr gamma_ps."""
+        ket = bra if ket is None else ket
+        na, nb = self.ci_dims()
+        Solver._dev_f64(bra, "bra", na * nb)
+        Solver._dev_f64(ket, "ket", na * nb)
+        if stream is None and torch is not None:
+            stream = torch.cuda.current_stream().cuda_stream
+        n = self.n
+        g, G, o = np.zeros((n, n)), np.zeros((n, n, n, n)), C.c_double()
+        _check(dmrg_ci_rdm12(self.h, _ptr(bra), _ptr(ket), _ptr(g), _ptr(G), C.byref(o), stream))
+        return g, G, o.value
 
     def mpo_site(self, k):
         nnz = C.c_int()
@@ -398,6 +423,25 @@ class Solver:
 
     def clear_deflation(self):
         _check(dmrg_deflate_clear(self.h))
+
+    def mps_to_ci(self, state=0, out=None):
+        """CI matrix [C(n, n_alpha), C(n, n_beta)] (device float64) of this MPS
+        (state 0) or of held state `state` (1..), as stored."""
+        na, nb = self.problem.ci_dims()
+        if out is None:
+            out = torch.empty((na, nb), dtype=torch.float64, device="cuda")
+        self._dev_f64(out, "out", na * nb)
+        self._grow(lambda: _check(dmrg_mps_to_ci(self.h, state, _ptr(out), na * nb)))
+        return out
+
+    def rdm12(self, bra=0, ket=None):
+        """Normalised (transition) 1-/2-RDMs of MPS states (0: this MPS, j >= 1:
+        held state j-1): (gamma[n, n], Gamma[n, n, n, n], overlap)."""
+        ket = bra if ket is None else ket
+        n = self.problem.n
+        g, G, o = np.zeros((n, n)), np.zeros((n, n, n, n)), C.c_double()
+        self._grow(lambda: _check(dmrg_rdm12(self.h, bra, ket, _ptr(g), _ptr(G), C.byref(o))))
+        return g, G, o.value
 
     def deflate_project(self, k, j, out):
         """Projection of lower state j into step k's two-site space (device out)."""

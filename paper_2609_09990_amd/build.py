@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdmrg_mi355x.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["kernels.hip", "mpo.cpp", "layout.cpp", "plan.cpp", "solver.cpp", "grad.cpp", "deflate.cpp", "precond.cpp", "mlp.hip", "mlp_net.cpp", "capi.cpp", "peaks.hip", "noalloc.hip"]
+SOURCES = ["kernels.hip", "mpo.cpp", "layout.cpp", "plan.cpp", "solver.cpp", "grad.cpp", "deflate.cpp", "precond.cpp", "mlp.hip", "mlp_net.cpp", "capi.cpp", "peaks.hip", "noalloc.hip", "ci.cpp", "ci_kernels.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # packed fp32 arithmetic stays off (hand-written or compiler-made)

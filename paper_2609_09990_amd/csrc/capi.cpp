@@ -404,6 +404,60 @@ dmrg_status dmrg_s_squared(dmrg_solver* s, double* s2) {
   });
 }
 
+dmrg_status dmrg_ci_dims(const dmrg_problem* p, int64_t* n_alpha_strings, int64_t* n_beta_strings) {
+  return guard([&] {
+    DMRG_REQUIRE(p && n_alpha_strings && n_beta_strings, ST_EINVAL, "NULL argument");
+    *n_alpha_strings = ci_dimension(p->p.n, p->p.n_alpha, 0);
+    *n_beta_strings = ci_dimension(p->p.n, p->p.n_beta, 0);
+  });
+}
+
+dmrg_status dmrg_mps_to_ci(dmrg_solver* s, int state, double* c, int64_t n) {
+  return solver_call(s, [&] {
+    DMRG_REQUIRE(s && c, ST_EINVAL, "NULL argument");
+    const Problem& P = s->prob->p;
+    DMRG_REQUIRE(n == ci_dimension(P.n, P.n_alpha, P.n_beta), ST_EINVAL, "n must be the CI dimension");
+    s->s->mps_to_ci(state, c);
+  });
+}
+
+dmrg_status dmrg_ci_rdm12(const dmrg_problem* p, const double* bra, const double* ket, double* gamma, double* Gamma,
+                          double* overlap, void* stream) {
+  return guard([&] {
+    DMRG_REQUIRE(p && bra && ket, ST_EINVAL, "NULL argument");
+    ci_rdm12(p->p.n, p->p.n_alpha, p->p.n_beta, (hipStream_t)stream, bra, ket, 1.0, gamma, Gamma, overlap);
+  });
+}
+
+dmrg_status dmrg_rdm12(dmrg_solver* s, int bra_state, int ket_state, double* gamma, double* Gamma, double* overlap) {
+  return solver_call(s, [&] {
+    DMRG_REQUIRE(s, ST_EINVAL, "NULL argument");
+    const Problem& P = s->prob->p;
+    const long N = ci_dimension(P.n, P.n_alpha, P.n_beta);
+    DevMem cb, ck, part, nrm;
+    cb.reserve((size_t)N * 8);
+    s->s->mps_to_ci(bra_state, cb.as<double>());
+    const bool same = bra_state == ket_state;
+    if (!same) {
+      ck.reserve((size_t)N * 8);
+      s->s->mps_to_ci(ket_state, ck.as<double>());
+    }
+    const double* kv = same ? cb.as<double>() : ck.as<double>();
+    part.reserve((size_t)512 * 64 * 8);
+    nrm.reserve(16);
+    launch_dots(cb.as<double>(), N, 1, cb.as<double>(), N, part.as<double>(), nrm.as<double>(), s->stream);
+    launch_dots(kv, N, 1, kv, N, part.as<double>(), nrm.as<double>() + 1, s->stream);
+    double h[2];
+    hip_check(hipMemcpyAsync(h, nrm.p, 16, hipMemcpyDeviceToHost, s->stream), "norms");
+    hip_check(hipStreamSynchronize(s->stream), "norms");
+    DMRG_REQUIRE(h[0] > 0 && h[1] > 0, ST_ESTATE, "a state has zero norm");
+    const double scale = 1.0 / std::sqrt(h[0] * h[1]);
+    double ov = 0;
+    ci_rdm12(P.n, P.n_alpha, P.n_beta, s->stream, cb.as<double>(), kv, scale, gamma, Gamma, &ov);
+    if (overlap) *overlap = ov * scale;
+  });
+}
+
 dmrg_status dmrg_grad(dmrg_solver* s, const double* state_weights, double* dE_dh, double* dE_dB,
                       double* energies) {
   return solver_call(s, [&] {

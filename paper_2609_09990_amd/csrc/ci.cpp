@@ -1,0 +1,336 @@
+// Determinant-space view of MPS states and their (transition) 1-/2-RDMs (the
+// device CI pipeline of Sec. III; conventions in ci.hpp).
+//
+// MPS -> CI.  The chain is cut at c = L/2.  Left of the cut every prefix of
+// physical states (s_0 .. s_{c-1}) that reaches a sector q of bond c carries the
+// row vector A_0[s_0] ... A_{c-1}[s_{c-1}]; right of it every suffix carries
+// A_c[s_c] ... A_{L-1}[s_{L-1}].  Both families grow one site at a time as block
+// GEMMs (all prefixes of one sector times one site block), and the amplitudes
+// of sector q are the product P_q S_q^T of its prefix and suffix matrices, one
+// GEMM per sector.  A determinant's string ranks split into a prefix part and a
+// suffix part (the suffix's ranks counted after the prefix's electrons, fixed by
+// q), and so does its sign, so a scatter kernel places every amplitude.
+//
+// RDMs.  With the excited copies T_x = E_rs |c> (x = r n + s) and T_{n^2} = |c>,
+//   <bra| E_pq |ket> = <bra | T^ket_{pq}>,
+//   <bra| E_pq E_rs |ket> = <E_qp bra | E_rs ket> = <T^bra_{qp} | T^ket_{rs}>,
+// so one product G = T^bra (T^ket)^T of (n^2 + 1) rows over all determinants
+// gives gamma, Gamma' = <E_pq E_rs> - d_qr gamma_ps and <bra|ket>.  The
+// determinants are taken in passes whose copies fit a fixed budget; G is a
+// split-K sum on the fp64 MFMA block kernel, partial tiles reduced in a fixed
+// order (deterministic), passes added in order.
+#include <algorithm>
+#include <cmath>
+
+#include "ci.hpp"
+#include "solver.hpp"
+
+namespace dmrg {
+namespace {
+
+long binom(int n, int k) {
+  if (k < 0 || k > n) return 0;
+  long r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+int popc(uint32_t x) { return __builtin_popcount(x); }
+
+// Colexicographic rank contribution of the occupied orbitals of `bits`, the
+// first of them being electron number t0 of its spin.
+long colex_part(uint32_t bits, int t0) {
+  long r = 0;
+  int t = t0;
+  for (int o = 0; o < 32; ++o)
+    if (bits >> o & 1u) r += binom(o, ++t);
+  return r;
+}
+
+std::vector<uint32_t> colex_strings(int n, int k) {
+  std::vector<uint32_t> out(binom(n, k));
+  for (uint32_t m = 0; m < (1u << n); ++m)
+    if (popc(m) == k) out[colex_part(m, 0)] = m;
+  return out;
+}
+
+// tab[x * N + J] = +-(I + 1) when E_rs |I> = +-|J> (x = r n + s), else 0:
+// a_s removes s from I with (-1)^(electrons below s), a+_r inserts r into what
+// is left with (-1)^(electrons below r).
+std::vector<int> excitation_table(int n, const std::vector<uint32_t>& strs) {
+  const long N = (long)strs.size();
+  std::vector<int> t((long)n * n * N, 0);
+  for (long J = 0; J < N; ++J) {
+    const uint32_t j = strs[J];
+    for (int r = 0; r < n; ++r) {
+      if (!(j >> r & 1u)) continue;
+      for (int s = 0; s < n; ++s) {
+        if (s != r && (j >> s & 1u)) continue;
+        const uint32_t i = (j & ~(1u << r)) | (1u << s);
+        const uint32_t i1 = i & ~(1u << s);
+        const int par = popc(i & ((1u << s) - 1)) + popc(i1 & ((1u << r) - 1));
+        const int I = (int)colex_part(i, 0) + 1;
+        t[((long)r * n + s) * N + J] = (par & 1) ? -I : I;
+      }
+    }
+  }
+  return t;
+}
+
+void tiles64(std::vector<GemmUnit>& units, double* C, int ldc, int M, int N, int ib, int ie) {
+  for (int m0 = 0; m0 < M; m0 += 64)
+    for (int n0 = 0; n0 < N; n0 += 64) units.push_back({C, ldc, M, N, m0, n0, ib, ie, 0});
+}
+
+template <class T>
+void upload(DevMem& d, const std::vector<T>& v, hipStream_t st) {
+  d.reserve(std::max<size_t>(v.size(), 1) * sizeof(T));
+  if (!v.empty()) hip_check(hipMemcpyAsync(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st), "ci upload");
+}
+
+}  // namespace
+
+long ci_dimension(int n, int na, int nb) { return binom(n, na) * binom(n, nb); }
+
+void Solver::mps_to_ci(int state, double* c) {
+  DMRG_REQUIRE(state >= 0 && state <= (int)defl_.size(), ST_EINVAL, "state must be 0 (this MPS) or a held state");
+  const std::vector<Bond>& B = state == 0 ? bonds_ : defl_[state - 1].bonds;
+  const std::vector<SiteTensor>& S = state == 0 ? mps_ : defl_[state - 1].sites;
+  const int L = prob_->n;
+  DMRG_REQUIRE((int)S.size() == L && (int)B.size() == L + 1, ST_ESTATE, "no MPS");
+  DMRG_REQUIRE(L <= 24, ST_EINVAL, "the CI vector is built for at most 24 orbitals");
+  const long Nb = binom(L, prob_->n_beta);
+  DMRG_REQUIRE(ci_dimension(L, prob_->n_alpha, prob_->n_beta) < (1L << 31), ST_EINVAL, "CI space too large");
+  DMRG_REQUIRE(B[0].sec.size() == 1 && B[0].sec[0].dim == 1 && B[L].sec.size() == 1 && B[L].sec[0].dim == 1,
+               ST_ESTATE, "boundary bonds must hold one state");
+  const int cut = L / 2;
+  struct Str {
+    uint32_t a, b;
+  };
+  struct Part {
+    int src, dst;
+    long r0;
+    const double* blk;
+    int ldb;
+  };
+  const double one = 1.0;
+  std::vector<GemmItem> items;
+  std::vector<GemmUnit> units;
+  // prefixes: sites 0 .. cut-1, one matrix (prefixes x sector dim) per sector
+  std::vector<std::vector<Str>> pre(1, std::vector<Str>{{0u, 0u}});
+  std::vector<long> poff(1, 0);
+  DevMem P, Pn;
+  P.reserve(8);
+  hip_check(hipMemcpyAsync(P.p, &one, 8, hipMemcpyHostToDevice, st), "ci");
+  for (int k = 0; k < cut; ++k) {
+    const Bond& bl = B[k];
+    const Bond& br = B[k + 1];
+    const SiteTensor& A = S[k];
+    std::vector<std::vector<Str>> npre(br.sec.size());
+    std::vector<Part> parts;
+    for (size_t i = 0; i < bl.sec.size(); ++i) {
+      if (pre[i].empty() || A.lay.slab_of_left[i] < 0) continue;
+      const Slab& sb = A.lay.slabs[A.lay.slab_of_left[i]];
+      for (int s = 0; s < 4; ++s) {
+        const int j = br.find(bl.sec[i].q + site_qn(s));
+        const int bi = j < 0 ? -1 : sb.block_of(s, j);
+        if (bi < 0) continue;
+        parts.push_back({(int)i, j, (long)npre[j].size(), A.buf.as<double>() + sb.off + sb.blocks[bi].col0, sb.width});
+        for (const Str& p : pre[i]) npre[j].push_back({p.a | (uint32_t)(s & 1) << k, p.b | (uint32_t)(s >> 1) << k});
+      }
+    }
+    std::vector<long> noff(br.sec.size(), 0);
+    long tot = 0;
+    for (size_t j = 0; j < br.sec.size(); ++j) {
+      noff[j] = tot;
+      tot += (long)npre[j].size() * br.sec[j].dim;
+    }
+    Pn.reserve(std::max<long>(tot, 1) * 8);
+    items.clear();
+    units.clear();
+    for (const Part& pt : parts) {
+      const int di = bl.sec[pt.src].dim, dj = br.sec[pt.dst].dim;
+      const int ib = (int)items.size();
+      items.push_back({P.as<double>() + poff[pt.src], pt.blk, di, pt.ldb, di, 0, 1.0});
+      tiles64(units, Pn.as<double>() + noff[pt.dst] + pt.r0 * dj, dj, (int)pre[pt.src].size(), dj, ib, ib + 1);
+    }
+    gemm_once(GEMM_NN, items, units);
+    std::swap(P, Pn);
+    pre.swap(npre);
+    poff.swap(noff);
+  }
+  // suffixes: sites cut .. L-1, one matrix (suffixes x sector dim) per sector
+  std::vector<std::vector<Str>> suf(1, std::vector<Str>{{0u, 0u}});
+  std::vector<long> soff(1, 0);
+  DevMem Sm, Sn;
+  Sm.reserve(8);
+  hip_check(hipMemcpyAsync(Sm.p, &one, 8, hipMemcpyHostToDevice, st), "ci");
+  for (int k = L - 1; k >= cut; --k) {
+    const Bond& bl = B[k];
+    const Bond& br = B[k + 1];
+    const SiteTensor& A = S[k];
+    std::vector<std::vector<Str>> nsuf(bl.sec.size());
+    std::vector<Part> parts;
+    for (size_t j = 0; j < br.sec.size(); ++j) {
+      if (suf[j].empty()) continue;
+      for (int s = 0; s < 4; ++s) {
+        const int i = bl.find(br.sec[j].q - site_qn(s));
+        if (i < 0 || A.lay.slab_of_left[i] < 0) continue;
+        const Slab& sb = A.lay.slabs[A.lay.slab_of_left[i]];
+        const int bi = sb.block_of(s, (int)j);
+        if (bi < 0) continue;
+        parts.push_back({(int)j, i, (long)nsuf[i].size(), A.buf.as<double>() + sb.off + sb.blocks[bi].col0, sb.width});
+        for (const Str& x : suf[j]) nsuf[i].push_back({x.a | (uint32_t)(s & 1) << k, x.b | (uint32_t)(s >> 1) << k});
+      }
+    }
+    std::vector<long> noff(bl.sec.size(), 0);
+    long tot = 0;
+    for (size_t i = 0; i < bl.sec.size(); ++i) {
+      noff[i] = tot;
+      tot += (long)nsuf[i].size() * bl.sec[i].dim;
+    }
+    Sn.reserve(std::max<long>(tot, 1) * 8);
+    items.clear();
+    units.clear();
+    for (const Part& pt : parts) {
+      const int dj = br.sec[pt.src].dim, di = bl.sec[pt.dst].dim;
+      const int ib = (int)items.size();
+      items.push_back({Sm.as<double>() + soff[pt.src], pt.blk, dj, pt.ldb, dj, 0, 1.0});
+      tiles64(units, Sn.as<double>() + noff[pt.dst] + pt.r0 * di, di, (int)suf[pt.src].size(), di, ib, ib + 1);
+    }
+    gemm_once(GEMM_NT, items, units);
+    std::swap(Sm, Sn);
+    suf.swap(nsuf);
+    soff.swap(noff);
+  }
+  // amplitudes per sector of the cut, rank and sign tables, scatter
+  const Bond& bc = B[cut];
+  std::vector<CiSector> secs;
+  std::vector<int> pa, pb, sa, sb;
+  std::vector<double> ps, ss;
+  long amp = 0;
+  items.clear();
+  units.clear();
+  std::vector<std::pair<size_t, long>> amp_at;
+  for (size_t i = 0; i < bc.sec.size(); ++i) {
+    const long np = (long)pre[i].size(), ns = (long)suf[i].size();
+    if (np == 0 || ns == 0) continue;
+    const QN q = bc.sec[i].q;
+    const int a0 = (q.n + q.sz) / 2, b0 = (q.n - q.sz) / 2;
+    secs.push_back({amp, (long)pa.size(), (long)sa.size(), (int)np, (int)ns});
+    for (const Str& p : pre[i]) {
+      int par = 0;
+      for (int o = 0; o < cut; ++o)
+        if (p.a >> o & 1u) par += popc(p.b & ((1u << o) - 1));
+      pa.push_back((int)colex_part(p.a, 0));
+      pb.push_back((int)colex_part(p.b, 0));
+      ps.push_back(par & 1 ? -1.0 : 1.0);
+    }
+    for (const Str& x : suf[i]) {
+      int par = popc(x.a) * b0;
+      for (int o = cut; o < L; ++o)
+        if (x.a >> o & 1u) par += popc(x.b & ((1u << o) - 1));
+      sa.push_back((int)colex_part(x.a, a0));
+      sb.push_back((int)colex_part(x.b, b0));
+      ss.push_back(par & 1 ? -1.0 : 1.0);
+    }
+    amp_at.push_back({i, amp});
+    amp += np * ns;
+  }
+  DevMem Amp;
+  Amp.reserve(std::max<long>(amp, 1) * 8);
+  for (const auto& [i, off] : amp_at) {
+    const int d = bc.sec[i].dim, np = (int)pre[i].size(), ns = (int)suf[i].size();
+    const int ib = (int)items.size();
+    items.push_back({P.as<double>() + poff[i], Sm.as<double>() + soff[i], d, d, d, 0, 1.0});
+    tiles64(units, Amp.as<double>() + off, ns, np, ns, ib, ib + 1);
+  }
+  gemm_once(GEMM_NT, items, units);
+  DevMem dsec, dpa, dpb, dps, dsa, dsb, dss;
+  upload(dsec, secs, st);
+  upload(dpa, pa, st);
+  upload(dpb, pb, st);
+  upload(dps, ps, st);
+  upload(dsa, sa, st);
+  upload(dsb, sb, st);
+  upload(dss, ss, st);
+  launch_fill(c, ci_dimension(L, prob_->n_alpha, prob_->n_beta), 0.0, st);
+  launch_ci_scatter(Amp.as<double>(), dsec.as<CiSector>(), (int)secs.size(), dpa.as<int>(), dpb.as<int>(),
+                    dps.as<double>(), dsa.as<int>(), dsb.as<int>(), dss.as<double>(), c, Nb, st);
+  hip_check(hipStreamSynchronize(st), "mps_to_ci");
+}
+
+void ci_rdm12(int n, int na, int nb, hipStream_t st, const double* bra, const double* ket, double scale,
+              double* gamma, double* Gamma, double* overlap) {
+  DMRG_REQUIRE(n >= 1 && n <= 16, ST_EINVAL, "RDMs from CI vectors need 1..16 orbitals");
+  const std::vector<uint32_t> sa = colex_strings(n, na), sb = colex_strings(n, nb);
+  const long NA = (long)sa.size(), NB = (long)sb.size(), N = NA * NB;
+  const int n2 = n * n, rows = n2 + 1;
+  DevMem ta, tb;
+  upload(ta, excitation_table(n, sa), st);
+  upload(tb, excitation_table(n, sb), st);
+  constexpr long CL = 8192;  // determinants per split-K item
+  const long per_pass = std::max<long>(1, (512L << 20) / ((long)rows * CL * 8)) * CL;
+  const long pass = std::min(per_pass, (N + CL - 1) / CL * CL);
+  const bool same = bra == ket;
+  DevMem Tb, Tk, G, dg, dG, slots, ditems, dunits, dtiles;
+  Tb.reserve((size_t)rows * pass * 8);
+  if (!same) Tk.reserve((size_t)rows * pass * 8);
+  const double* TK = same ? Tb.as<double>() : Tk.as<double>();
+  G.reserve((size_t)rows * rows * 8);
+  // output tiles of the block kernel: strips of 96 rows and 64 columns, the last
+  // of each rounded up to a multiple of 16
+  struct Tile {
+    int m0, n0, tm, tn;
+  };
+  std::vector<Tile> tl;
+  for (int m0 = 0; m0 < rows; m0 += 96)
+    for (int n0 = 0; n0 < rows; n0 += 64)
+      tl.push_back({m0, n0, std::min(96, (rows - m0 + 15) / 16 * 16), std::min(64, (rows - n0 + 15) / 16 * 16)});
+  const long nt = (long)tl.size();
+  for (long d0 = 0; d0 < N; d0 += pass) {
+    const long dend = std::min(N, d0 + pass), nch = (dend - d0 + CL - 1) / CL;
+    launch_ci_excite(bra, NA, NB, n2, ta.as<int>(), tb.as<int>(), Tb.as<double>(), CL, d0, dend, st);
+    if (!same) launch_ci_excite(ket, NA, NB, n2, ta.as<int>(), tb.as<int>(), Tk.as<double>(), CL, d0, dend, st);
+    std::vector<GemmItem> items;
+    for (long g = 0; g < nch; ++g) {
+      const int K = (int)std::min(CL, dend - d0 - g * CL);
+      DMRG_REQUIRE(buffer_reach_ok(GEMM_NT, rows, rows, K, (int)CL, (int)CL, 8, 8), ST_EINVAL, "determinant chunk beyond the block kernel reach");
+      items.push_back({Tb.as<double>() + g * rows * CL, TK + g * rows * CL, (int)CL, (int)CL, K, 0, 1.0});
+    }
+    // about 2048 workgroups: the items split into ng contiguous groups per tile
+    const long ng = std::max<long>(1, std::min<long>(nch, 2048 / nt));
+    std::vector<SplitTile> tiles;
+    std::vector<GemmUnit> units;
+    long so = 0;
+    for (const Tile& t : tl) {
+      tiles.push_back({G.p, so, rows, rows, rows, t.m0, t.n0, (int)ng, t.tm, t.tn, d0 > 0 ? 1 : 0, 0});
+      so += ng * t.tm * t.tn;
+    }
+    slots.reserve((size_t)so * 8);
+    for (long gi = 0; gi < ng; ++gi) {
+      const int ib = (int)(nch * gi / ng), ie = (int)(nch * (gi + 1) / ng);
+      for (long t = 0; t < nt; ++t) {
+        const SplitTile& s = tiles[t];
+        units.push_back({slots.as<double>() + s.s0 + gi * s.tm * s.tn, s.tn, rows, rows, s.m0, s.n0, ib, ie, 2,
+                         8 * (s.tm / 16) + s.tn / 16});
+      }
+    }
+    upload(ditems, items, st);
+    upload(dunits, units, st);
+    upload(dtiles, tiles, st);
+    launch_gemm_wg(PREC_F64, 5, dunits.as<GemmUnit>(), (int)units.size(), ditems.as<GemmItem>(), st);
+    launch_splitk_reduce(dtiles.as<SplitTile>(), (int)nt, slots.as<double>(), st);
+    hip_check(hipStreamSynchronize(st), "rdm pass");
+  }
+  dg.reserve((size_t)n2 * 8);
+  dG.reserve((size_t)n2 * n2 * 8);
+  launch_rdm_assemble(G.as<double>(), rows, n, scale, dg.as<double>(), dG.as<double>(), st);
+  if (gamma) hip_check(hipMemcpyAsync(gamma, dg.p, (size_t)n2 * 8, hipMemcpyDeviceToHost, st), "rdm out");
+  if (Gamma) hip_check(hipMemcpyAsync(Gamma, dG.p, (size_t)n2 * n2 * 8, hipMemcpyDeviceToHost, st), "rdm out");
+  if (overlap)
+    hip_check(hipMemcpyAsync(overlap, G.as<double>() + (long)n2 * rows + n2, 8, hipMemcpyDeviceToHost, st), "rdm out");
+  hip_check(hipStreamSynchronize(st), "rdm");
+}
+
+}  // namespace dmrg

@@ -1555,6 +1555,7 @@ void launch_gemm_wg(int prec, int tag, const GemmUnit* units, int n_units, const
     case 2: gemm_wg<double, 2><<<n_units, 256, 0, s>>>(units, items); break;
     case 3: gemm_wg<double, 3><<<n_units, 256, 0, s>>>(units, items); break;
     case 4: gemm_wg<double, 4><<<n_units, 256, 0, s>>>(units, items); break;
+    case 5: gemm_wg<double, 5><<<n_units, 256, 0, s>>>(units, items); break;
     default: gemm_wg<double, 0><<<n_units, 256, 0, s>>>(units, items); break;
   }
 }

@@ -358,6 +358,9 @@ class Solver {
   int take_triples(float* X, float* T, int cap);
   int triple_sample() const { return rec_sample_; }
   // Features of the prepared step k for device vectors r, d and a host theta.
+  // CI vector (row-major c[I_a][I_b], colex strings) of this MPS (state 0) or of
+  // held state `state` (1..n_deflated), as stored
+  void mps_to_ci(int state, double* c);
   int correction_host_theta(int k, int mode, const double* x, const double* r, const double* d, double theta,
                             double* t);
   void features_host_theta(int k, const double* r, const double* d, double theta, float* X);
@@ -517,5 +520,12 @@ class Solver {
   std::vector<GemmItem> scratch_h_items_;
   std::vector<GemmUnit> scratch_h_units_;
 };
+
+// Determinant-space helpers (ci.cpp): the CI dimension C(n, n_a) C(n, n_b), and
+// the (transition) 1-/2-RDMs of device CI vectors, times `scale`, to host arrays
+// (gamma n^2, Gamma n^4, overlap <bra|ket> unscaled; each may be NULL).
+long ci_dimension(int n, int na, int nb);
+void ci_rdm12(int n, int na, int nb, hipStream_t st, const double* bra, const double* ket, double scale,
+              double* gamma, double* Gamma, double* overlap);
 
 }  // namespace dmrg
