@@ -204,6 +204,21 @@ dmrg_status dmrg_diag(dmrg_solver* s, int k, int64_t n, double* diag);
  * reach the tolerance (results still written). */
 dmrg_status dmrg_sweep(dmrg_solver* s, int n_sweeps, double* energies, double* tau);
 
+/* One-site sweeps at the current bond dimensions (Sec. II.E: a truncated
+ * two-site fixed point is not stationary on the tangent space of its own bond
+ * dimension, so its Hellmann-Feynman gradient differs from the derivative of
+ * its energy by an amount that tracks the discarded weight).  Every step
+ * optimises one site inside the two-site space (Davidson on P H_eff P, P the
+ * projector on that site's tensors with the neighbour fixed) and moves the
+ * centre by SVD without truncation.  *energy (host): the last step's energy +
+ * e_core; *tangent_residual (may be NULL): the largest first-iteration
+ * residual of the last sweep, the norm of the largest block of the gauge-free
+ * tangent gradient B_k = V_L X_k; once it is ~0, dmrg_grad is the exact
+ * gradient of the variational energy at this bond dimension.  One state; the
+ * MPS must be right-orthonormal from site 1 (as after dmrg_sweep or a previous
+ * call; DMRG_ESTATE if the centre is elsewhere).  DMRG_ENOCONV as dmrg_sweep. */
+dmrg_status dmrg_stationarize(dmrg_solver* s, int n_sweeps, double* energy, double* tangent_residual);
+
 /* One two-site step on sites (k, k+1) (the decimation step of Fig. 2): Davidson
  * on H_eff, SVD truncation to M, environment update; direction 0 moves the
  * center right (k -> k+1), 1 moves it left.  A sweep is steps 0..n_orb-2 in

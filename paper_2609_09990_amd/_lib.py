@@ -81,6 +81,7 @@ dmrg_record_triples = _decl("dmrg_record_triples", [_p, _i, _i])
 dmrg_take_triples = _decl("dmrg_take_triples", [_p, _p, _p, _i, C.POINTER(_i)])
 dmrg_precond_features = _decl("dmrg_precond_features", [_p, _i, _p, _p, _d, _p])
 dmrg_correction = _decl("dmrg_correction", [_p, _i, _i, _p, _p, _p, _d, _p, _p])
+dmrg_stationarize = _decl("dmrg_stationarize", [_p, _i, _p, _p])
 dmrg_ci_dims = _decl("dmrg_ci_dims", [_p, _p, _p])
 dmrg_mps_to_ci = _decl("dmrg_mps_to_ci", [_p, _i, _p, _i64])
 dmrg_ci_rdm12 = _decl("dmrg_ci_rdm12", [_p, _p, _p, _p, _p, _p, _p])
@@ -364,6 +365,15 @@ class Solver:
         if code not in (0, -4):
             _check(code)
         return e, tau.value, code == 0
+
+    def stationarize(self, n_sweeps=1):
+        """One-site sweeps at the current bond dimensions: (energy, largest local
+        tangent gradient of the last sweep, converged)."""
+        e, r = C.c_double(), C.c_double()
+        code = dmrg_stationarize(self.h, n_sweeps, C.byref(e), C.byref(r))
+        if code not in (0, -4):
+            _check(code)
+        return e.value, r.value, code == 0
 
     def step(self, k, direction=0):
         e = np.zeros(self.n_states)

@@ -313,6 +313,22 @@ dmrg_status dmrg_truncate(dmrg_solver* s, int k, int direction, int64_t n, const
   });
 }
 
+dmrg_status dmrg_stationarize(dmrg_solver* s, int n_sweeps, double* energy, double* tangent_residual) {
+  dmrg_status st = solver_call(s, [&] {
+    DMRG_REQUIRE(s && energy, ST_EINVAL, "NULL argument");
+    DMRG_REQUIRE(n_sweeps >= 1, ST_EINVAL, "n_sweeps must be >= 1");
+    std::vector<double> e;
+    const double r = s->s->stationarize(n_sweeps, e);
+    *energy = e.empty() ? 0.0 : e[0];
+    if (tangent_residual) *tangent_residual = r;
+  });
+  if (st == DMRG_OK && s && !s->s->last_converged()) {
+    last_error_slot() = "Davidson did not reach the tolerance in at least one step";
+    return DMRG_ENOCONV;
+  }
+  return st;
+}
+
 dmrg_status dmrg_sweep(dmrg_solver* s, int n_sweeps, double* energies, double* tau) {
   dmrg_status st = solver_call(s, [&] {
     DMRG_REQUIRE(s && energies, ST_EINVAL, "NULL argument");

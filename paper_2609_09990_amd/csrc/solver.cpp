@@ -992,6 +992,7 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
       launch_dots(Phi, n, nd, x, n, part, sc + 128, st);
       launch_gemv(Phi, n, nd, sc + 128, 1.0, y, 1.0, n, st);
     }
+    if (onesite_) onesite_project(k, y);
   };
 
   auto host_scalar = [&](const double* dptr) {
@@ -1190,6 +1191,7 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
     if (opt_.verbose > 1)
       fprintf(stderr, "  dav k=%d it=%d sub=%d E=%.12f r=%.3e err=%.1e prec=%d\n", k, iter, kcur, evals[0], rmax,
               errmax, sprec);
+    if (onesite_ && iter == 0) first_res_ = std::max(first_res_, rmax);  // the local tangent gradient
     if (!std::isfinite(rmax)) throw Error(ST_ENOCONV, "non-finite Davidson residual");
     if (after_ref) {  // the roots' residuals are exact: judge the refinement
       after_ref = false;
@@ -1242,7 +1244,9 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
         features(R + (long)i * n, D, ev + i, Cc + (long)nnew * n, F);
         net_->forward(PREC_BF16, F, n, Y, st);
         launch_f32_to_f64(Y, Lc + (long)nnew * n, n, st);
+        if (onesite_) onesite_project(k, Lc + (long)nnew * n);
       }
+      if (onesite_) onesite_project(k, Cc + (long)nnew * n);
       ++nnew;
     }
     if (kcur + nnew > kmax) {
@@ -1841,6 +1845,103 @@ double Solver::sweep(int n_sweeps, std::vector<double>& energies) {
   last_converged_ = all_ok;
   st_.tau = tau_max;
   return tau_max;
+}
+
+// x <- P x for the one-site space of the step: with site k+1 frozen (F,
+// right-orthonormal) X = x F^T over (s2, bond k+2) and x = X F; with site k
+// frozen (left-orthonormal) Y = F^T x over (bond k, s1) and x = F Y.
+void Solver::onesite_project(int k, double* x) {
+  const TensorLayout P = make_tensor_layout(bonds_[k], bonds_[k + 2], twosite_phys_qn());
+  std::vector<GemmItem> items;
+  std::vector<GemmUnit> units;
+  if (onesite_ > 0) {
+    const SiteTensor& F = mps_[k + 1];
+    os_tmp_.lay = make_tensor_layout(bonds_[k], bonds_[k + 1], site_phys_qn());
+    os_tmp_.buf.reserve(std::max<long>(os_tmp_.lay.size, 1) * 8);
+    for (const Slab& xs : os_tmp_.lay.slabs) {
+      const int pi = P.slab_of_left[xs.li];
+      for (const SlabBlock& xb : xs.blocks) {  // X[a, s1, m]
+        const int ib = (int)items.size();
+        const int fi = F.lay.slab_of_left[xb.ri];
+        if (pi >= 0 && fi >= 0) {
+          const Slab& ps = P.slabs[pi];
+          const Slab& fs = F.lay.slabs[fi];
+          for (const SlabBlock& fb : fs.blocks) {  // F[m, s2, b]
+            const int pb = ps.block_of(4 * xb.phys + fb.phys, fb.ri);
+            if (pb < 0) continue;
+            items.push_back({x + ps.off + ps.blocks[pb].col0, F.buf.as<double>() + fs.off + fb.col0, ps.width,
+                             fs.width, fb.mr, 0, 1.0});
+          }
+        }
+        tile_units(units, os_tmp_.buf.as<double>() + xs.off + xb.col0, xs.width, xs.ml, xb.mr, ib,
+                   (int)items.size());
+      }
+    }
+    gemm_once(GEMM_NT, items, units);
+    form_twosite(k, os_tmp_, F, x);
+  } else {
+    const SiteTensor& F = mps_[k];
+    os_tmp_.lay = make_tensor_layout(bonds_[k + 1], bonds_[k + 2], site_phys_qn());
+    os_tmp_.buf.reserve(std::max<long>(os_tmp_.lay.size, 1) * 8);
+    for (const Slab& ys : os_tmp_.lay.slabs) {
+      for (const SlabBlock& yb : ys.blocks) {  // Y[m, s2, b]
+        const int ib = (int)items.size();
+        for (const Slab& fs : F.lay.slabs) {  // F[a, s1, m]
+          const int pi = P.slab_of_left[fs.li];
+          if (pi < 0) continue;
+          const Slab& ps = P.slabs[pi];
+          for (const SlabBlock& fb : fs.blocks) {
+            if (fb.ri != ys.li) continue;
+            const int pb = ps.block_of(4 * fb.phys + yb.phys, yb.ri);
+            if (pb < 0) continue;
+            items.push_back({F.buf.as<double>() + fs.off + fb.col0, x + ps.off + ps.blocks[pb].col0, fs.width,
+                             ps.width, fs.ml, 0, 1.0});
+          }
+        }
+        tile_units(units, os_tmp_.buf.as<double>() + ys.off + yb.col0, ys.width, ys.ml, yb.mr, ib,
+                   (int)items.size());
+      }
+    }
+    gemm_once(GEMM_TN, items, units);
+    form_twosite(k, F, os_tmp_, x);
+  }
+}
+
+// One-site sweeps at fixed bond dimensions (Sec. II.E: a truncated two-site
+// fixed point is not stationary on the tangent space of its own bond
+// dimension).  Each two-site step optimises one site inside the two-site space
+// (the projected Davidson above) and the SVD moves the centre without
+// truncation, so the bond dimensions stay (only numerically zero singular
+// values can go).  At a fixed point every one-site tensor is the lowest
+// eigenvector of its effective Hamiltonian: the gauge-free tangent gradient,
+// whose blocks are the first-iteration residuals of the steps, vanishes, and
+// the Hellmann-Feynman gradient is the exact derivative of the variational
+// energy at this bond dimension.
+double Solver::stationarize(int n_sweeps, std::vector<double>& energies) {
+  DMRG_REQUIRE(opt_.n_states == 1, ST_EINVAL, "one-site sweeps take one state");
+  DMRG_REQUIRE(center_site_ <= 0, ST_ESTATE, "one-site sweeps start with the centre on site 0");
+  struct Reset {
+    int& f;
+    ~Reset() { f = 0; }
+  } reset{onesite_};
+  bool all_ok = true;
+  for (int sw = 0; sw < n_sweeps; ++sw) {
+    first_res_ = 0;
+    for (int k = 0; k + 1 < L_; ++k) {
+      onesite_ = 1;
+      guess_k_ = -1;
+      step(k, true, energies);
+      all_ok = all_ok && last_converged_;
+    }
+    for (int k = L_ - 2; k >= 0; --k) {
+      onesite_ = -1;
+      guess_k_ = -1;
+      step(k, false, energies);
+      all_ok = all_ok && last_converged_;
+    }
+  }
+  last_converged_ = all_ok;
+  return first_res_;
 }
 
 // <Psi_r|H|Psi_r>/<Psi_r|Psi_r> of the current MPS (root r via its center tensor).

@@ -312,6 +312,10 @@ class Solver {
   void sigma(int k, int prec, const double* psi, double* out);
   void diag(int k, double* out);
   double sweep(int n_sweeps, std::vector<double>& energies);
+  // One-site sweeps at the current bond dimensions (the stationarity of the
+  // truncated MPS, Sec. II.E); returns the largest local tangent gradient of the
+  // last sweep.  Needs one state, sites 1.. right-orthonormal (as after a sweep).
+  double stationarize(int n_sweeps, std::vector<double>& energies);
   double step(int k, bool left_to_right, std::vector<double>& energies);
   std::vector<double> mps_energy();
   // Host copy of the current MPS: all site tensors concatenated in slab layout.
@@ -475,6 +479,14 @@ class Solver {
   int shift_invert(const double* x, const double* r, const double* D, const double* theta, double rnorm, double* t,
                    int prec, Apply& apply);
   DevMem dv_pcg_;  // work vectors of the Olsen and shift-and-invert corrections
+  // one-site mode of a two-site step: +1 optimises site k with site k+1 frozen
+  // (right-orthonormal), -1 optimises site k+1 with site k frozen (left-
+  // orthonormal); the Davidson then works on P H_eff P, P the projector on that
+  // one-site space inside the two-site space
+  int onesite_ = 0;
+  double first_res_ = 0;  // largest first-iteration residual of one-site steps
+  SiteTensor os_tmp_;
+  void onesite_project(int k, double* x);
   void gemm_once(int mode, std::vector<GemmItem>& items, std::vector<GemmUnit>& units);
   void grad_site(int k, std::vector<double>& g, double* norm);
   DevMem grad_P_, grad_Q_, grad_G_;

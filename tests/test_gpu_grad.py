@@ -217,3 +217,57 @@ def test_config4_two_roots_cas16_m512_finite_difference_gap():
     fd = float((0.5 * (ep[0] + ep[1]) - 0.5 * (em[0] + em[1])) / (2 * eps))
     print(f"state average: analytic={analytic:.9f} fd={fd:.9f} gap={abs(analytic - fd):.3e}", flush=True)
     assert abs(analytic - fd) <= 1e-6 * abs(analytic)
+
+
+def _stationary(sol, max_sweeps=200, tol=1e-7):
+    """One-site sweeps until the largest local tangent gradient is below tol."""
+    for _ in range(max_sweeps):
+        e, res, ok = sol.stationarize(1)
+        if res <= tol:
+            return e, res
+    return e, res
+
+
+def test_stationary_truncated_mps_gradient_equals_finite_difference():
+    """CAS(8,8), N_Q = 32 at M = 24 (truncated, tau ~ 1e-2).  The two-site fixed point is
+    not tangent-stationary: its Hellmann-Feynman gradient misses the central
+    finite difference of the two-site DMRG energy by an amount of the order of
+    the discarded weight.  One-site sweeps at the same bond dimensions drive the
+    gauge-free tangent gradient to zero (1e-7: one-site sweeps converge
+    linearly); then dmrg_grad equals the central finite difference (step 1e-4
+    along a random symmetric h direction) of the stationary energy at that bond
+    dimension to 1e-5, and the energy is variational."""
+    pk = _pk()
+    h, B, e0 = synth.make_hamiltonian(8, 32, 0)
+    e_fci = json.load(open(GOLDEN))["cas8_nq32_s0"]["energies"][0]
+    M, eps = 24, 1e-4
+    rng = np.random.default_rng(5)
+    D = rng.normal(size=(8, 8))
+    D = D + D.T
+    sol = pk.Solver(pk.Problem(h, B, 4, 4, e0), M=M, tol=1e-11)
+    e2, tau, _ = sol.sweep(6)
+    dh2, _, _ = sol.grad()
+    two = sol.export_mps()
+    e_two_state = sol.energy()[0]
+    es, res = _stationary(sol)
+    assert res <= 1e-7, res
+    dh, _, (e_grad,) = sol.grad()
+    stat = sol.export_mps()
+
+    def energy(sign, start, stationary):
+        s = pk.Solver(pk.Problem(h + sign * eps * D, B, 4, 4, e0), M=M, tol=1e-11)
+        s.set_mps(start["bonds"], start["sites"])
+        if stationary:
+            s.sweep(1)  # canonical form with the centre on site 0 (nothing to truncate at these bonds)
+            return _stationary(s)[0]
+        return s.sweep(6)[0][0]
+
+    fd = (energy(1, stat, True) - energy(-1, stat, True)) / (2 * eps)
+    fd2 = (energy(1, two, False) - energy(-1, two, False)) / (2 * eps)
+    hf, hf2 = float(np.sum(dh * D)), float(np.sum(dh2 * D))
+    print(f"tau {tau:.2e}; two-site: E(Ritz) {e2[0]:.10f} E(state) {e_two_state:.10f} FD {fd2:.8f} HF {hf2:.8f} "
+          f"gap {abs(fd2 - hf2):.2e}; stationary: E {es:.10f} res {res:.1e} FD {fd:.8f} HF {hf:.8f} "
+          f"gap {abs(fd - hf):.2e}", flush=True)
+    assert abs(e_grad - es) <= 1e-10
+    assert e_fci - 1e-10 <= es <= e_two_state + 1e-10
+    assert abs(fd - hf) <= 1e-5 * max(1.0, abs(hf))
