@@ -92,11 +92,17 @@ typedef struct {
                                   phase B adds into sigma; less memory, more launches (slower) */
   int pcg_steps;       /* DMRG_PRECOND_SHIFT_INVERT: most inner CG steps per correction (>= 1) */
   double pcg_rtol;     /* ... and it stops once the inner residual is <= pcg_rtol * |r| (>= 0) */
+  double trunc_tol;    /* > 0: per-bond adaptive bond dimension (Sec. II.H, dynamically adapted
+                          per-bond M): each truncation keeps the fewest states whose discarded
+                          weight is <= trunc_tol of the total (a cluster at that cut kept whole
+                          while M allows), at least m_min and at most M; 0: fixed M */
+  int m_min;           /* lower bound of the adaptive bond dimension (>= 1) */
 } dmrg_options;
 
 /* Fills *o with defaults: M=256, 1 state, tol 1e-10, 200 iterations, subspace
  * 32, FP64, diagonal preconditioner, seed 1, tie_rtol 1e-10, cut_rtol 1e-14,
- * unbounded sigma intermediates, 5 inner PCG steps to 0.1 |r|. */
+ * unbounded sigma intermediates, 5 inner PCG steps to 0.1 |r|, fixed M
+ * (trunc_tol 0, m_min 1). */
 void dmrg_options_default(dmrg_options* o);
 
 /* Active-space problem (Sec. II.A): n_orb spatial orbitals, n_alpha / n_beta

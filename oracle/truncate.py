@@ -74,9 +74,15 @@ def sector_matrix(blocks, bond_k, bond_k2, rows, cols):
     return M
 
 
-def truncate(psis, bonds_k, bonds_k2, M, left_to_right=True, weights=None, tie_rtol=1e-10, cut_rtol=1e-14):
+def truncate(psis, bonds_k, bonds_k2, M, left_to_right=True, weights=None, tie_rtol=1e-10, cut_rtol=1e-14,
+             trunc_tol=0.0, m_min=1):
     """Returns dict(bond=[(N, 2Sz, kept)] sorted, kept=descending kept values,
-    tau, spectra={q_m: all singular values, descending})."""
+    tau, spectra={q_m: all singular values, descending}).
+
+    trunc_tol > 0 (adaptive bond dimension): the first cut is the fewest values
+    whose discarded weight sum(s^2) is at most trunc_tol times the total, raised
+    to m_min; if that is below M it is taken and moved down the list (more kept)
+    while it would split a cluster and M allows; the M rules above follow."""
     bk, bk2 = Bond(bonds_k), Bond(bonds_k2)
     psis = [np.asarray(p, dtype=float) for p in psis]
     nr = len(psis)
@@ -95,6 +101,16 @@ def truncate(psis, bonds_k, bonds_k2, M, left_to_right=True, weights=None, tie_r
     vals = np.array([v for v, _ in allsv])
     keep = min(len(vals), M)
     s1 = vals[0] if len(vals) else 0.0
+    if trunc_tol > 0 and len(vals):
+        total = float(np.sum(vals ** 2))
+        kt = len(vals)
+        while kt > 1 and float(np.sum(vals[kt - 1:] ** 2)) <= trunc_tol * total:
+            kt -= 1
+        kt = max(kt, m_min)
+        if kt < keep:
+            keep = kt
+            while keep < min(len(vals), M) and vals[keep - 1] - vals[keep] <= tie_rtol * s1:
+                keep += 1
     if keep < len(vals):
         while keep > 0 and vals[keep - 1] <= cut_rtol * s1:
             keep -= 1

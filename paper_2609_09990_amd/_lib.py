@@ -25,7 +25,8 @@ class dmrg_options(C.Structure):
                 ("davidson_tol", C.c_double), ("max_iter", C.c_int), ("max_subspace", C.c_int),
                 ("precision", C.c_int), ("precond", C.c_int), ("seed", C.c_ulonglong),
                 ("tie_rtol", C.c_double), ("cut_rtol", C.c_double), ("verbose", C.c_int),
-                ("sigma_chunk_bytes", C.c_longlong), ("pcg_steps", C.c_int), ("pcg_rtol", C.c_double)]
+                ("sigma_chunk_bytes", C.c_longlong), ("pcg_steps", C.c_int), ("pcg_rtol", C.c_double),
+                ("trunc_tol", C.c_double), ("m_min", C.c_int)]
 
 
 def _decl(name, args, res=C.c_int):
@@ -228,7 +229,8 @@ class Solver:
 
     def __init__(self, problem: Problem, M=256, n_states=1, weights=None, tol=1e-10, max_iter=200,
                  max_subspace=32, precision=0, precond=0, seed=1, tie_rtol=1e-10, cut_rtol=1e-14,
-                 verbose=0, stream=None, workspace=False, sigma_chunk_bytes=0, pcg_steps=5, pcg_rtol=0.1):
+                 verbose=0, stream=None, workspace=False, sigma_chunk_bytes=0, pcg_steps=5, pcg_rtol=0.1,
+                 trunc_tol=0.0, m_min=1):
         """workspace: False (the library allocates its device buffers), True (a
         torch-allocated workspace of dmrg_workspace_query bytes, grown and
         re-attached when a call reports DMRG_ENOMEM) or a byte count."""
@@ -239,6 +241,7 @@ class Solver:
         o.tie_rtol, o.cut_rtol, o.verbose = tie_rtol, cut_rtol, verbose
         o.sigma_chunk_bytes = int(sigma_chunk_bytes)
         o.pcg_steps, o.pcg_rtol = int(pcg_steps), float(pcg_rtol)
+        o.trunc_tol, o.m_min = float(trunc_tol), int(m_min)
         self._w = None
         if weights is not None:
             self._w = np.ascontiguousarray(weights, dtype=np.float64)

@@ -69,6 +69,8 @@ void dmrg_options_default(dmrg_options* o) {
   o->sigma_chunk_bytes = 0;
   o->pcg_steps = 5;
   o->pcg_rtol = 0.1;
+  o->trunc_tol = 0;
+  o->m_min = 1;
 }
 
 dmrg_status dmrg_problem_create(int n, int na, int nb, int nq, const double* h, const double* B,
@@ -167,6 +169,10 @@ dmrg_status dmrg_solver_create(const dmrg_problem* p, const dmrg_options* o, voi
     DMRG_REQUIRE(o->pcg_steps >= 1 && o->pcg_rtol >= 0, ST_EINVAL, "pcg_steps must be >= 1 and pcg_rtol >= 0");
     op.pcg_steps = o->pcg_steps;
     op.pcg_rtol = o->pcg_rtol;
+    DMRG_REQUIRE(o->trunc_tol >= 0 && o->trunc_tol < 1 && o->m_min >= 1, ST_EINVAL,
+                 "trunc_tol must be in [0, 1) and m_min >= 1");
+    op.trunc_tol = o->trunc_tol;
+    op.m_min = o->m_min;
     DMRG_REQUIRE(op.precision >= 0 && op.precision <= 2, ST_EINVAL, "unknown precision");
     DMRG_REQUIRE(op.davidson_tol > 0, ST_EINVAL, "davidson_tol must be positive");
     DMRG_REQUIRE(op.max_iter >= 1, ST_EINVAL, "max_iter must be >= 1");

@@ -1521,6 +1521,25 @@ void Solver::svd_step(int k, bool l2r, int nr, std::vector<DevMem>& next_guess, 
   std::stable_sort(all_sv.begin(), all_sv.end(), [](const SV& a, const SV& b) { return a.s > b.s; });
   double s1 = all_sv.empty() ? 0.0 : all_sv[0].s;
   long keep = std::min<long>((long)all_sv.size(), opt_.M);
+  // Adaptive bond dimension (dynamic block-state selection): the fewest states
+  // whose discarded weight is at most trunc_tol of the total, at least m_min,
+  // at most M; a cluster at such a cut is kept whole while M allows.
+  if (opt_.trunc_tol > 0 && !all_sv.empty()) {
+    double total = 0, tail = 0;
+    for (const SV& v : all_sv) total += v.s * v.s;
+    long kt = (long)all_sv.size();
+    while (kt > 1 && tail + all_sv[kt - 1].s * all_sv[kt - 1].s <= opt_.trunc_tol * total) {
+      tail += all_sv[kt - 1].s * all_sv[kt - 1].s;
+      --kt;
+    }
+    kt = std::max<long>(kt, opt_.m_min);
+    if (kt < keep) {
+      keep = kt;
+      while (keep < std::min<long>((long)all_sv.size(), opt_.M) &&
+             all_sv[keep - 1].s - all_sv[keep].s <= opt_.tie_rtol * s1)
+        ++keep;
+    }
+  }
   // Nothing is dropped while every state fits (the exact regime: singular values
   // from density-matrix eigenvalues resolve only down to ~1e-8 s_1, so a small
   // one cannot be told from a zero one, and keeping both is exact).  When states

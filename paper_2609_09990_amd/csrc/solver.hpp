@@ -32,6 +32,8 @@ struct Options {
   long long sigma_chunk_bytes = 0;  // 0: all left factors in one chunk
   int pcg_steps = 5;                // shift-and-invert correction: inner CG steps ...
   double pcg_rtol = 0.1;            // ... and relative residual at which they stop
+  double trunc_tol = 0;             // adaptive bond dimension: discarded weight per bond (0: fixed M)
+  int m_min = 1;                    // ... never fewer states than this
 };
 
 // A caller-provided slab of device memory that the library carves into its

@@ -231,3 +231,56 @@ def test_config2_exact_bond_cas12_equals_fci():
           f"matvecs {sol.stats()['matvecs']:.0f}", flush=True)
     assert ok
     assert np.max(np.abs(np.array(e) - np.array(g))) <= 1e-10
+
+
+@pytest.mark.parametrize("direction", [0, 1])
+def test_adaptive_truncation_matches_oracle(direction):
+    """trunc_tol (adaptive bond dimension) on a constructed spectrum with a
+    degenerate mirror pair: the tolerance falls where it would keep one copy of
+    the pair, so the cut keeps both; new bond, tau and kept values as the oracle."""
+    torch = _torch()
+    import paper_2609_09990_amd as pk
+    n, na, nb, k = 8, 4, 4, 3
+    h, B, e0 = synth.make_hamiltonian(n, 16, 4)
+    mps = synth.random_mps(n, na, nb, 64, seed=9)
+    bonds = mps["bonds"]
+    spectra, v = _constructed(bonds, k, 3)
+    psis = [truncate.psi_from_spectra(bonds[k], bonds[k + 2], spectra, seed=4)]
+    vals = np.sort(np.concatenate(list(spectra.values())))[::-1]
+    i = int(np.nonzero(np.abs(vals - v) <= 1e-15)[0][0])  # first copy of v
+    w = vals ** 2
+    tol = float(np.sum(w[i + 1:]) + 0.5 * w[i])  # room for dropping one copy of v, not two
+    ref = truncate.truncate(psis, bonds[k], bonds[k + 2], 4096, left_to_right=(direction == 0), trunc_tol=tol)
+    sol = pk.Solver(pk.Problem(h, B, na, nb, e0), M=4096, trunc_tol=tol)
+    sol.set_mps(bonds, mps["sites"])
+    tau, sv = sol.truncate(k, torch.from_numpy(np.concatenate(psis)).cuda(), direction)
+    newbond = [tuple(s) for s in sol.bonds()[k + 1]]
+    print(f"dir={direction}: kept {len(sv)} (oracle {len(ref['kept'])}, first copy at {i}), tau {tau:.3e} "
+          f"(oracle {ref['tau']:.3e}, tol {tol:.3e})", flush=True)
+    assert len(ref["kept"]) == i + 2  # both copies kept
+    assert newbond == [tuple(s) for s in ref["bond"]]
+    assert len(sv) == len(ref["kept"])
+    assert np.max(np.abs(sv ** 2 - ref["kept"] ** 2)) <= 1e-13
+    assert abs(tau - ref["tau"]) <= 1e-13 and tau <= tol
+
+
+def test_adaptive_bond_dimension_dmrg_cas8():
+    """CAS(8,8), N_Q = 32 with trunc_tol = 1e-6 and M = 4096: the bond
+    dimensions adapt per bond (below the full bonds, not all equal), every
+    truncation of the last sweep discards at most the tolerance, and the energy
+    lies above the oracle's FCI energy by less than 1e-4 Ha."""
+    _torch()
+    import paper_2609_09990_amd as pk
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fci_energies.json")))
+    e_fci = gold["cas8_nq32_s0"]["energies"][0]
+    h, B, e0 = synth.make_hamiltonian(8, 32, 0)
+    sol = pk.Solver(pk.Problem(h, B, 4, 4, e0), M=4096, tol=1e-9, trunc_tol=1e-6)
+    for _ in range(4):
+        e, tau, ok = sol.sweep(1)
+    dims = [sum(d for _, _, d in b) for b in sol.bonds()]
+    full = [sum(d for _, _, d in b) for b in synth.random_mps(8, 4, 4, 10 ** 6, seed=0)["bonds"]]
+    print(f"E {e[0]:.10f} FCI {e_fci:.10f} dE {e[0] - e_fci:.2e} tau {tau:.2e} bonds {dims} full {full}", flush=True)
+    assert tau <= 1e-6
+    assert -1e-9 <= e[0] - e_fci <= 1e-4
+    assert all(d <= f for d, f in zip(dims, full)) and sum(dims) < sum(full)
+    assert len(set(dims[2:-2])) > 1

@@ -98,3 +98,49 @@ def test_single_sector_is_numpy_svd_and_sa_is_density_matrix():
         evc = np.sort(np.clip(np.linalg.eigvalsh(rho_c), 0, None))[::-1]
         n = len(sa_l["spectra"][qm])
         assert np.allclose(sa_l["spectra"][qm] ** 2, evc[:n], atol=1e-13)
+
+
+def _pair_spectra():
+    """A big sector [0.9, 0.5, 0.3] and a mirror pair of sectors with [0.7, 0.2]
+    each, normalised; returns (bk, bk2, psi, sorted values, index of the first 0.2)."""
+    bk, bk2 = _bonds()
+    bK, bK2 = blocks.Bond(bk), blocks.Bond(bk2)
+    size = {}
+    for qm, rows, cols in truncate.middle_sectors(bK, bK2):
+        size[qm] = min(sum(bK.dim(a) for _, a in rows), sum(bK2.dim(b) for _, b in cols))
+    pair = next(q for q in size if q[1] > 0 and size[q] >= 2 and size.get((q[0], -q[1]), 0) >= 2)
+    big = next(q for q in size if q not in (pair, (pair[0], -pair[1])) and size[q] >= 3)
+    spectra = {big: [0.9, 0.5, 0.3], pair: [0.7, 0.2], (pair[0], -pair[1]): [0.7, 0.2]}
+    tot = np.sqrt(sum(np.sum(np.square(v)) for v in spectra.values()))
+    spectra = {q: np.asarray(v) / tot for q, v in spectra.items()}
+    psi = truncate.psi_from_spectra(bk, bk2, spectra, seed=3)
+    vals = np.sort(np.concatenate(list(spectra.values())))[::-1]
+    return bk, bk2, psi, vals, int(np.nonzero(np.isclose(vals, 0.2 / tot))[0][0])
+
+
+def test_adaptive_cut_is_the_fewest_states_within_the_tolerance():
+    bk, bk2, psi, vals, _ = _pair_spectra()  # 0.9, 0.7, 0.7, 0.5, 0.3, 0.2, 0.2 (scaled)
+    w = vals ** 2
+    # tolerance between the weights of the last value and of the last three:
+    # dropping 0.3 and both 0.2 stays within it, dropping 0.5 too does not
+    tol = 0.5 * (np.sum(w[4:]) + np.sum(w[3:]))
+    res = truncate.truncate([psi], bk, bk2, M=100, trunc_tol=tol)
+    assert len(res["kept"]) == 4 and res["tau"] <= tol and abs(res["tau"] - np.sum(w[4:])) < 1e-13
+    # M still caps the count; m_min raises it
+    assert len(truncate.truncate([psi], bk, bk2, M=3, trunc_tol=tol)["kept"]) == 3
+    assert len(truncate.truncate([psi], bk, bk2, M=100, trunc_tol=tol, m_min=6)["kept"]) == 7  # cluster kept whole
+    assert len(truncate.truncate([psi], bk, bk2, M=100, trunc_tol=0.99)["kept"]) == 1
+    # trunc_tol = 0 is the fixed-M rule: everything fits, nothing goes (zeros included)
+    assert len(truncate.truncate([psi], bk, bk2, M=100, trunc_tol=0.0)["kept"]) > 7
+
+
+def test_adaptive_cut_keeps_a_cluster_whole():
+    """The tolerance would keep one copy of the degenerate pair: the cut moves
+    down the list to keep both while M allows, else the M rule drops both."""
+    bk, bk2, psi, vals, first02 = _pair_spectra()
+    w = vals ** 2
+    tol = 0.5 * (w[-1] + np.sum(w[-2:]))  # allows dropping one copy only
+    res = truncate.truncate([psi], bk, bk2, M=100, trunc_tol=tol)
+    assert len(res["kept"]) == first02 + 2 and res["tau"] < 1e-24
+    capped = truncate.truncate([psi], bk, bk2, M=first02 + 1, trunc_tol=tol)
+    assert len(capped["kept"]) == first02
