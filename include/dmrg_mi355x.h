@@ -331,6 +331,29 @@ dmrg_status dmrg_ci_rdm12(const dmrg_problem* p, const double* bra, const double
  * gamma, Gamma and overlap of <bra|.|ket> / (|bra| |ket|). */
 dmrg_status dmrg_rdm12(dmrg_solver* s, int bra_state, int ket_state, double* gamma, double* Gamma, double* overlap);
 
+/* ---- Orbital entanglement and ordering (Sec. II.H: the pairwise mutual
+ * information orders the lattice through the Fiedler vector) ---------------
+ * From a device CI vector c (2..16 orbitals, any norm).  Two-orbital density
+ * matrices: for each pair i < j (pairs in the order (0,1), (0,2), ..., (1,2),
+ * ...), with the pair's spin orbitals moved to the front of every determinant
+ * in the order (i alpha, j alpha, i beta, j beta), rho = Tr_rest |c><c| /
+ * <c|c> over the 16 local states L = s_i + 4 s_j, s = n_alpha + 2 n_beta;
+ * rho: host [n(n-1)/2][16][16].  Computed by one kernel over determinants and
+ * pairs (each environment of a pair taken once, <= 4 amplitudes, fixed-order
+ * sums). */
+dmrg_status dmrg_orbital_rdm2(const dmrg_problem* p, const double* c, double* rho, void* stream);
+/* One-orbital entropies s1[n] (natural log, from the diagonal one-orbital
+ * density matrices) and mutual information I[n*n] = (s_i + s_j - s_ij) / 2
+ * (zero diagonal), host outputs. */
+dmrg_status dmrg_mutual_information(const dmrg_problem* p, const double* c, double* s1, double* I, void* stream);
+/* Orbital order from a mutual-information matrix (host only, 2..64 orbitals):
+ * the eigenvector of the second-smallest eigenvalue of diag(sum_j I_ij) - I,
+ * sign fixed so that its largest-magnitude component (first such) is
+ * positive; order[n] lists the orbitals by ascending component (stable);
+ * fiedler[n] (may be NULL) receives the vector.  Reorder h and B^Q by it (new
+ * orbital t = old order[t]) for the next calculation. */
+dmrg_status dmrg_fiedler_order(int n, const double* I, int* order, double* fiedler);
+
 /* Integral gradient of the current MPS energy (Sec. II.C: the DMRG node's
  * adjoint; the MPS is held fixed, i.e. the Hellmann-Feynman term, exact for a
  * converged full-bond state; at truncated bond it is the gradient of

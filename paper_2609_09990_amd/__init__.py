@@ -45,7 +45,18 @@ from ._lib import (  # noqa: F401
     dmrg_truncate,
     dmrg_workspace_attach,
     dmrg_workspace_query,
+    dmrg_ci_dims,
+    dmrg_ci_rdm12,
+    dmrg_correction,
+    dmrg_fiedler_order,
+    dmrg_mps_to_ci,
+    dmrg_mutual_information,
+    dmrg_orbital_rdm2,
+    dmrg_rdm12,
+    dmrg_stationarize,
+    fiedler_order,
     lib,
+    reorder_integrals,
 )
 
 from .autograd import DMRGEnergy, dmrg_energy  # noqa: F401,E402

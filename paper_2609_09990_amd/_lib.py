@@ -83,6 +83,9 @@ dmrg_take_triples = _decl("dmrg_take_triples", [_p, _p, _p, _i, C.POINTER(_i)])
 dmrg_precond_features = _decl("dmrg_precond_features", [_p, _i, _p, _p, _d, _p])
 dmrg_correction = _decl("dmrg_correction", [_p, _i, _i, _p, _p, _p, _d, _p, _p])
 dmrg_stationarize = _decl("dmrg_stationarize", [_p, _i, _p, _p])
+dmrg_orbital_rdm2 = _decl("dmrg_orbital_rdm2", [_p, _p, _p, _p])
+dmrg_mutual_information = _decl("dmrg_mutual_information", [_p, _p, _p, _p, _p])
+dmrg_fiedler_order = _decl("dmrg_fiedler_order", [_i, _p, _p, _p])
 dmrg_ci_dims = _decl("dmrg_ci_dims", [_p, _p, _p])
 dmrg_mps_to_ci = _decl("dmrg_mps_to_ci", [_p, _i, _p, _i64])
 dmrg_ci_rdm12 = _decl("dmrg_ci_rdm12", [_p, _p, _p, _p, _p, _p, _p])
@@ -149,6 +152,28 @@ class Problem:
         g, G, o = np.zeros((n, n)), np.zeros((n, n, n, n)), C.c_double()
         _check(dmrg_ci_rdm12(self.h, _ptr(bra), _ptr(ket), _ptr(g), _ptr(G), C.byref(o), stream))
         return g, G, o.value
+
+    def orbital_rdm2(self, c, stream=None):
+        """Two-orbital density matrices of a device CI vector: [n(n-1)/2, 16, 16]."""
+        na, nb = self.ci_dims()
+        Solver._dev_f64(c, "c", na * nb)
+        if stream is None and torch is not None:
+            stream = torch.cuda.current_stream().cuda_stream
+        n = self.n
+        rho = np.zeros((n * (n - 1) // 2, 16, 16))
+        _check(dmrg_orbital_rdm2(self.h, _ptr(c), _ptr(rho), stream))
+        return rho
+
+    def mutual_information(self, c, stream=None):
+        """(one-orbital entropies s1[n], mutual information I[n, n]) of a device CI vector."""
+        na, nb = self.ci_dims()
+        Solver._dev_f64(c, "c", na * nb)
+        if stream is None and torch is not None:
+            stream = torch.cuda.current_stream().cuda_stream
+        n = self.n
+        s1, I = np.zeros(n), np.zeros((n, n))
+        _check(dmrg_mutual_information(self.h, _ptr(c), _ptr(s1), _ptr(I), stream))
+        return s1, I
 
     def mpo_site(self, k):
         nnz = C.c_int()
@@ -537,3 +562,19 @@ def measure_peaks(nbytes=1 << 31, stream=None):
                               nbytes, C.byref(f), C.byref(c)))
     del src, dst
     return f.value, c.value
+
+
+def fiedler_order(I):
+    """Orbital order (new orbital t = old order[t]) and the Fiedler vector of a
+    mutual-information matrix (dmrg_fiedler_order)."""
+    I = np.ascontiguousarray(I, dtype=np.float64)
+    n = I.shape[0]
+    order, v = np.zeros(n, dtype=np.int32), np.zeros(n)
+    _check(dmrg_fiedler_order(n, _ptr(I), _ptr(order), _ptr(v)))
+    return order, v
+
+
+def reorder_integrals(h, B, order):
+    """h and B^Q in the orbital order `order` (new orbital t = old order[t])."""
+    o = np.asarray(order)
+    return np.ascontiguousarray(h[np.ix_(o, o)]), np.ascontiguousarray(B[:, o][:, :, o])

@@ -451,6 +451,29 @@ dmrg_status dmrg_ci_rdm12(const dmrg_problem* p, const double* bra, const double
   });
 }
 
+dmrg_status dmrg_orbital_rdm2(const dmrg_problem* p, const double* c, double* rho, void* stream) {
+  return guard([&] {
+    DMRG_REQUIRE(p && c && rho, ST_EINVAL, "NULL argument");
+    std::vector<double> r;
+    orbital_rdm2(p->p.n, p->p.n_alpha, p->p.n_beta, (hipStream_t)stream, c, r);
+    std::copy(r.begin(), r.end(), rho);
+  });
+}
+
+dmrg_status dmrg_mutual_information(const dmrg_problem* p, const double* c, double* s1, double* I, void* stream) {
+  return guard([&] {
+    DMRG_REQUIRE(p && c && s1 && I, ST_EINVAL, "NULL argument");
+    mutual_information(p->p.n, p->p.n_alpha, p->p.n_beta, (hipStream_t)stream, c, s1, I);
+  });
+}
+
+dmrg_status dmrg_fiedler_order(int n, const double* I, int* order, double* fiedler) {
+  return guard([&] {
+    DMRG_REQUIRE(I && order, ST_EINVAL, "NULL argument");
+    fiedler_order(n, I, order, fiedler);
+  });
+}
+
 dmrg_status dmrg_rdm12(dmrg_solver* s, int bra_state, int ket_state, double* gamma, double* Gamma, double* overlap) {
   return solver_call(s, [&] {
     DMRG_REQUIRE(s, ST_EINVAL, "NULL argument");

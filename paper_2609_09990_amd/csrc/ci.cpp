@@ -88,9 +88,193 @@ void upload(DevMem& d, const std::vector<T>& v, hipStream_t st) {
   if (!v.empty()) hip_check(hipMemcpyAsync(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st), "ci upload");
 }
 
+// rank of every n-bit mask among the strings with k bits, -1 for the others
+std::vector<int> rank_table(int n, int k) {
+  std::vector<int> r((size_t)1 << n, -1);
+  for (uint32_t m = 0; m < (1u << n); ++m)
+    if (popc(m) == k) r[m] = (int)colex_part(m, 0);
+  return r;
+}
+
+// Eigenvalues (ascending) and, if V, eigenvectors (columns of the row-major
+// n x n V) of a symmetric matrix by cyclic Jacobi rotations (small n only).
+void jacobi_eigh(std::vector<double> A, int n, std::vector<double>& w, std::vector<double>* V) {
+  std::vector<double> Q((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0, tot = 0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        tot += A[(size_t)i * n + j] * A[(size_t)i * n + j];
+        if (i != j) off += A[(size_t)i * n + j] * A[(size_t)i * n + j];
+      }
+    if (off <= 1e-30 * std::max(tot, 1e-300)) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[(size_t)p * n + q];
+        if (apq == 0.0) continue;
+        const double th = (A[(size_t)q * n + q] - A[(size_t)p * n + p]) / (2 * apq);
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1));
+        const double cs = 1 / std::sqrt(t * t + 1), sn = t * cs;
+        for (int k = 0; k < n; ++k) {  // columns p, q
+          const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
+          A[(size_t)k * n + p] = cs * akp - sn * akq;
+          A[(size_t)k * n + q] = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < n; ++k) {  // rows p, q
+          const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
+          A[(size_t)p * n + k] = cs * apk - sn * aqk;
+          A[(size_t)q * n + k] = sn * apk + cs * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double qkp = Q[(size_t)k * n + p], qkq = Q[(size_t)k * n + q];
+          Q[(size_t)k * n + p] = cs * qkp - sn * qkq;
+          Q[(size_t)k * n + q] = sn * qkp + cs * qkq;
+        }
+      }
+  }
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(),
+                   [&](int a, int b) { return A[(size_t)a * n + a] < A[(size_t)b * n + b]; });
+  w.resize(n);
+  for (int i = 0; i < n; ++i) w[i] = A[(size_t)idx[i] * n + idx[i]];
+  if (V) {
+    V->assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int k = 0; k < n; ++k) (*V)[(size_t)k * n + i] = Q[(size_t)k * n + idx[i]];
+  }
+}
+
+double entropy_of(const std::vector<double>& rho, int n) {
+  std::vector<double> w;
+  jacobi_eigh(rho, n, w, nullptr);
+  double s = 0;
+  for (double x : w)
+    if (x > 1e-300) s -= x * std::log(x);
+  return s;
+}
+
 }  // namespace
 
 long ci_dimension(int n, int na, int nb) { return binom(n, na) * binom(n, nb); }
+
+void orbital_rdm2(int n, int na, int nb, hipStream_t st, const double* c, std::vector<double>& rho) {
+  DMRG_REQUIRE(n >= 2 && n <= 16, ST_EINVAL, "orbital density matrices from CI vectors need 2..16 orbitals");
+  const std::vector<uint32_t> sa = colex_strings(n, na), sb = colex_strings(n, nb);
+  const long NB = (long)sb.size(), N = (long)sa.size() * NB;
+  std::vector<int> pairs;
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) {
+      pairs.push_back(i);
+      pairs.push_back(j);
+    }
+  const int np = (int)pairs.size() / 2;
+  const int nblk = (int)std::max<long>(1, std::min<long>((N + 255) / 256, (2048 + np - 1) / np));
+  DevMem dsa, dsb, dra, drb, dpairs, part, out;
+  upload(dsa, sa, st);
+  upload(dsb, sb, st);
+  upload(dra, rank_table(n, na), st);
+  upload(drb, rank_table(n, nb), st);
+  upload(dpairs, pairs, st);
+  part.reserve((size_t)np * nblk * 36 * 8);
+  out.reserve((size_t)np * 36 * 8);
+  launch_orb_pairs(c, dsa.as<uint32_t>(), dsb.as<uint32_t>(), dra.as<int>(), drb.as<int>(), NB, N, dpairs.as<int>(), np,
+                   nblk, part.as<double>(), st);
+  launch_orb_sum(part.as<double>(), np, nblk, out.as<double>(), st);
+  std::vector<double> e((size_t)np * 36);
+  hip_check(hipMemcpyAsync(e.data(), out.p, e.size() * 8, hipMemcpyDeviceToHost, st), "orbital rdm");
+  hip_check(hipStreamSynchronize(st), "orbital rdm");
+  // expand the 36 entries of each pair: block (k_alpha, k_beta), states
+  // (alpha configuration, beta configuration) in the kernel's order
+  rho.assign((size_t)np * 256, 0.0);
+  static const int kOff[9] = {0, 1, 5, 6, 10, 26, 30, 31, 35};
+  for (int p = 0; p < np; ++p) {
+    double* R = rho.data() + (size_t)p * 256;
+    double tr = 0;
+    for (int ka = 0; ka < 3; ++ka)
+      for (int kb = 0; kb < 3; ++kb) {
+        const int nA = ka == 1 ? 2 : 1, nB = kb == 1 ? 2 : 1, q = nA * nB;
+        int L[4];
+        for (int pa = 0; pa < nA; ++pa)
+          for (int pb = 0; pb < nB; ++pb) {
+            const int ai = ka == 2 || (ka == 1 && pa == 0), aj = ka == 2 || (ka == 1 && pa == 1);
+            const int bi = kb == 2 || (kb == 1 && pb == 0), bj = kb == 2 || (kb == 1 && pb == 1);
+            L[pa * nB + pb] = (ai + 2 * bi) + 4 * (aj + 2 * bj);
+          }
+        for (int x = 0; x < q; ++x)
+          for (int y = 0; y < q; ++y) R[L[x] * 16 + L[y]] = e[(size_t)p * 36 + kOff[3 * ka + kb] + x * q + y];
+        for (int x = 0; x < q; ++x) tr += R[L[x] * 16 + L[x]];
+      }
+    DMRG_REQUIRE(tr > 0, ST_EINVAL, "zero CI vector");
+    for (int x = 0; x < 256; ++x) R[x] /= tr;
+  }
+}
+
+void mutual_information(int n, int na, int nb, hipStream_t st, const double* c, double* s1, double* I) {
+  std::vector<double> rho;
+  orbital_rdm2(n, na, nb, st, c, rho);
+  std::vector<double> s2((size_t)n * n, 0.0);
+  std::vector<double> one(n, -1.0);
+  int p = 0;
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j, ++p) {
+      const std::vector<double> R(rho.begin() + (size_t)p * 256, rho.begin() + (size_t)(p + 1) * 256);
+      s2[(size_t)i * n + j] = entropy_of(R, 16);
+      if (one[i] < 0 || one[j] < 0) {  // one-orbital matrices: diagonal partial traces
+        double di[4] = {0, 0, 0, 0}, dj[4] = {0, 0, 0, 0};
+        for (int L = 0; L < 16; ++L) {
+          di[L % 4] += R[L * 16 + L];
+          dj[L / 4] += R[L * 16 + L];
+        }
+        auto h = [](const double* d) {
+          double s = 0;
+          for (int t = 0; t < 4; ++t)
+            if (d[t] > 1e-300) s -= d[t] * std::log(d[t]);
+          return s;
+        };
+        if (one[i] < 0) one[i] = h(di);
+        if (one[j] < 0) one[j] = h(dj);
+      }
+    }
+  for (int i = 0; i < n; ++i) {
+    s1[i] = one[i];
+    I[(size_t)i * n + i] = 0;
+    for (int j = i + 1; j < n; ++j)
+      I[(size_t)i * n + j] = I[(size_t)j * n + i] = 0.5 * (one[i] + one[j] - s2[(size_t)i * n + j]);
+  }
+}
+
+void fiedler_order(int n, const double* I, int* order, double* fiedler) {
+  DMRG_REQUIRE(n >= 2 && n <= 64, ST_EINVAL, "ordering needs 2..64 orbitals");
+  std::vector<double> Lap((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double d = 0;
+    for (int j = 0; j < n; ++j)
+      if (j != i) {
+        Lap[(size_t)i * n + j] = -I[(size_t)i * n + j];
+        d += I[(size_t)i * n + j];
+      }
+    Lap[(size_t)i * n + i] = d;
+  }
+  std::vector<double> w, V;
+  jacobi_eigh(Lap, n, w, &V);
+  std::vector<double> v(n);
+  int big = 0;
+  for (int i = 0; i < n; ++i) {
+    v[i] = V[(size_t)i * n + 1];
+    if (std::fabs(v[i]) > std::fabs(v[big])) big = i;
+  }
+  if (v[big] < 0)
+    for (double& x : v) x = -x;
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return v[a] < v[b]; });
+  for (int i = 0; i < n; ++i) {
+    order[i] = idx[i];
+    if (fiedler) fiedler[i] = v[i];
+  }
+}
 
 void Solver::mps_to_ci(int state, double* c) {
   DMRG_REQUIRE(state >= 0 && state <= (int)defl_.size(), ST_EINVAL, "state must be 0 (this MPS) or a held state");

@@ -48,4 +48,16 @@ void launch_ci_excite(const double* c, long na, long nb, int n2, const int* ta, 
 void launch_rdm_assemble(const double* G, int ldg, int n, double scale, double* gamma, double* Gamma,
                          hipStream_t s);
 
+// Two-orbital density matrices of a CI vector (unnormalised), for every pair
+// (pairs[2 p], pairs[2 p + 1]), i < j: with the pair's spin orbitals moved to the
+// front in the order (i alpha, j alpha, i beta, j beta), rho = sum over the
+// configurations of the other orbitals of v v^T.  Only the 36 entries of the 9
+// blocks of equal pair (N_alpha, N_beta) can be non-zero; partial[(p * nblk + b)
+// * 36 + e] receives workgroup b's sums (nblk = grid size per pair), and
+// launch_orb_sum adds them in order into out[p * 36 + e].  sa / sb: the strings
+// by rank; rank_a / rank_b: the rank of every n-bit mask (-1 if not a string).
+void launch_orb_pairs(const double* c, const uint32_t* sa, const uint32_t* sb, const int* rank_a, const int* rank_b,
+                      long nb, long ndet, const int* pairs, int npairs, int nblk, double* partial, hipStream_t s);
+void launch_orb_sum(const double* partial, int npairs, int nblk, double* out, hipStream_t s);
+
 }  // namespace dmrg

@@ -74,6 +74,81 @@ __global__ void rdm_assemble_kernel(const double* __restrict__ G, int ldg, int n
   }
 }
 
+// Offsets of the 9 blocks of a two-orbital density matrix in its 36 entries,
+// block b = 3 k_alpha + k_beta (electrons of each spin on the pair), sizes
+// 1, 2, 1 states for k = 0, 1, 2 of each spin.
+__constant__ int kOrbOff[9] = {0, 1, 5, 6, 10, 26, 30, 31, 35};
+
+// One workgroup: determinants of a grid-stride range for one pair.  A thread
+// takes the environments (configurations of the other orbitals) whose
+// representative determinant it holds (one electron of a spin on the pair sits
+// on i), gathers the <= 4 amplitudes of that environment, and adds their outer
+// product to its own LDS row; rows are summed in a fixed order at the end.
+__global__ __launch_bounds__(256) void orb_pairs_kernel(const double* __restrict__ c, const uint32_t* __restrict__ sa,
+                                                        const uint32_t* __restrict__ sb, const int* __restrict__ rank_a,
+                                                        const int* __restrict__ rank_b, long nb, long ndet,
+                                                        const int* __restrict__ pairs, double* __restrict__ partial) {
+  __shared__ double acc[256][37];
+  const int tid = threadIdx.x;
+  const int i = pairs[2 * blockIdx.y], j = pairs[2 * blockIdx.y + 1];
+  const uint32_t mi = 1u << i, mj = 1u << j;
+  for (int e = 0; e < 36; ++e) acc[tid][e] = 0.0;
+  for (long d = (long)blockIdx.x * 256 + tid; d < ndet; d += (long)gridDim.x * 256) {
+    const long ia = d / nb, ib = d - ia * nb;
+    const uint32_t a = sa[ia], b = sb[ib];
+    const int ai = a >> i & 1, aj = a >> j & 1, bi = b >> i & 1, bj = b >> j & 1;
+    const int ka = ai + aj, kb = bi + bj;
+    if ((ka == 1 && !ai) || (kb == 1 && !bi)) continue;  // not the environment's representative
+    const uint32_t ea = a & ~(mi | mj), eb = b & ~(mi | mj);
+    uint32_t A[2], B[2];
+    const int nA = ka == 1 ? 2 : 1, nB = kb == 1 ? 2 : 1;
+    A[0] = ka == 0 ? 0u : (ka == 1 ? mi : (mi | mj));
+    A[1] = mj;
+    B[0] = kb == 0 ? 0u : (kb == 1 ? mi : (mi | mj));
+    B[1] = mj;
+    const int na_env = __popc(ea);
+    double v[4];
+    int q = 0;
+    for (int pa = 0; pa < nA; ++pa)
+      for (int pb = 0; pb < nB; ++pb) {
+        const uint32_t a2 = ea | A[pa], b2 = eb | B[pb];
+        const long idx = (long)rank_a[a2] * nb + rank_b[b2];
+        // local creators moved in front of the environment's (alpha-first order)
+        const int par = (int)(a2 >> i & 1) * __popc(ea & (mi - 1)) + (int)(a2 >> j & 1) * __popc(ea & (mj - 1)) +
+                        (int)(b2 >> i & 1) * (na_env + __popc(eb & (mi - 1))) +
+                        (int)(b2 >> j & 1) * (na_env + __popc(eb & (mj - 1)));
+        v[q++] = (par & 1 ? -1.0 : 1.0) * c[idx];
+      }
+    const int off = kOrbOff[3 * ka + kb];
+    for (int p = 0; p < q; ++p)
+      for (int r = 0; r < q; ++r) acc[tid][off + p * q + r] += v[p] * v[r];
+  }
+  __syncthreads();
+  if (tid < 36) {
+    double s = 0.0;
+    for (int t = 0; t < 256; ++t) s += acc[t][tid];
+    partial[((long)blockIdx.y * gridDim.x + blockIdx.x) * 36 + tid] = s;
+  }
+}
+
+__global__ void orb_sum_kernel(const double* __restrict__ partial, int npairs, int nblk, double* __restrict__ out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= npairs * 36) return;
+  const int p = x / 36, e = x % 36;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += partial[((long)p * nblk + b) * 36 + e];
+  out[x] = s;
+}
+
+void launch_orb_pairs(const double* c, const uint32_t* sa, const uint32_t* sb, const int* rank_a, const int* rank_b,
+                      long nb, long ndet, const int* pairs, int npairs, int nblk, double* partial, hipStream_t s) {
+  if (npairs > 0) orb_pairs_kernel<<<dim3(nblk, npairs), 256, 0, s>>>(c, sa, sb, rank_a, rank_b, nb, ndet, pairs, partial);
+}
+
+void launch_orb_sum(const double* partial, int npairs, int nblk, double* out, hipStream_t s) {
+  if (npairs > 0) orb_sum_kernel<<<(npairs * 36 + 255) / 256, 256, 0, s>>>(partial, npairs, nblk, out);
+}
+
 void launch_ci_scatter(const double* amp, const CiSector* secs, int n_secs, const int* pa, const int* pb,
                        const double* ps, const int* sa, const int* sb, const double* ss, double* c, long nb,
                        hipStream_t s) {

@@ -539,6 +539,13 @@ class Solver {
 // the (transition) 1-/2-RDMs of device CI vectors, times `scale`, to host arrays
 // (gamma n^2, Gamma n^4, overlap <bra|ket> unscaled; each may be NULL).
 long ci_dimension(int n, int na, int nb);
+// Orbital entanglement from a device CI vector (2..16 orbitals): two-orbital
+// density matrices of all pairs i < j (host, [pair][16][16], trace 1), the
+// one-orbital entropies s1[n] and mutual information I[n][n]; and the ordering
+// of orbitals by the Fiedler vector of I's graph Laplacian (host only).
+void orbital_rdm2(int n, int na, int nb, hipStream_t st, const double* c, std::vector<double>& rho);
+void mutual_information(int n, int na, int nb, hipStream_t st, const double* c, double* s1, double* I);
+void fiedler_order(int n, const double* I, int* order, double* fiedler);
 void ci_rdm12(int n, int na, int nb, hipStream_t st, const double* bra, const double* ket, double scale,
               double* gamma, double* Gamma, double* overlap);
 

@@ -105,3 +105,25 @@ def test_mpo_keeps_structure_of_exact_zero_integrals():
     Hf = fock.hamiltonian(h, B, fock.site_product_basis(n), fock.interleaved_positions(n)).toarray()
     assert np.max(np.abs(_dense_mpo(prob) - Hf)) < 1e-12
     assert list(prob.mpo_dims()) == list(ref_dims)
+
+
+def test_fiedler_order_matches_oracle():
+    """dmrg_fiedler_order (host only) against the oracle's numpy eigenvector on
+    random symmetric non-negative matrices and a shuffled path graph."""
+    import paper_2609_09990_amd as pk
+    from oracle import orbital
+    rng = np.random.default_rng(4)
+    for n in (2, 5, 12, 20):
+        I = rng.uniform(0, 1, size=(n, n))
+        I = I + I.T
+        np.fill_diagonal(I, 0)
+        order, v = pk.fiedler_order(I)
+        ref_order, ref_v = orbital.fiedler_order(I)
+        assert np.abs(v - ref_v).max() < 1e-10
+        assert list(order) == list(ref_order)
+    perm = np.array([3, 0, 6, 2, 5, 1, 4])
+    I = np.zeros((7, 7))
+    for k in range(6):
+        I[perm[k], perm[k + 1]] = I[perm[k + 1], perm[k]] = 1.0
+    order, _ = pk.fiedler_order(I)
+    assert list(order) in (list(perm), list(perm[::-1]))
