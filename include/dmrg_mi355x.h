@@ -327,6 +327,22 @@ dmrg_status dmrg_mps_to_ci(dmrg_solver* s, int state, double* c, int64_t n);
  * when the outputs are written. */
 dmrg_status dmrg_ci_rdm12(const dmrg_problem* p, const double* bra, const double* ket, double* gamma, double* Gamma,
                           double* overlap, void* stream);
+/* The all-active two-electron operator on a device CI vector (the fused
+ * four-particle contraction of Sec. III: the two-electron block is contracted
+ * into the ket, so <EEEE>-type densities contracted with it are three-body
+ * densities of (bra, V ket) and the n^8 object is never formed):
+ *   out = V c,  V = 1/2 sum_pqrs (pq|rs) E_pq E_rs,  (pq|rs) = sum_Q B^Q_pq B^Q_rs,
+ * streamed through the problem's Cholesky factors (E_rs c for all rs, two
+ * GEMMs over the factors, one gather sum); out: device, same length as c, not
+ * aliasing it.  At most 16 orbitals. */
+dmrg_status dmrg_ci_apply_v(const dmrg_problem* p, const double* c, double* out, void* stream);
+/* Transition three-body density of device CI vectors (unnormalised):
+ *   Gamma3[((((p*n+q)*n+r)*n+s)*n+t)*n+u] = <bra|E_pq E_rs E_tu|ket>
+ * (host, n^6 doubles).  E_tu ket is kept for all tu, E_rs of each is formed in
+ * passes of determinants and the fp64 MFMA split-K product with the bra's
+ * copies accumulates the density.  At most 12 orbitals.  With ket = V c
+ * (dmrg_ci_apply_v) it gives sum_vwxy (vw|xy)/2 <bra|E_pq E_rs E_tu E_vw E_xy|c>. */
+dmrg_status dmrg_ci_rdm3(const dmrg_problem* p, const double* bra, const double* ket, double* Gamma3, void* stream);
 /* The same for MPS states (numbering as dmrg_mps_to_ci), each normalised:
  * gamma, Gamma and overlap of <bra|.|ket> / (|bra| |ket|). */
 dmrg_status dmrg_rdm12(dmrg_solver* s, int bra_state, int ket_state, double* gamma, double* Gamma, double* overlap);

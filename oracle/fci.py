@@ -259,6 +259,45 @@ def trdm12(space: DetSpace, Cbra: np.ndarray, Cket: np.ndarray):
     return gamma, Gp
 
 
+def rdm3(space: DetSpace, Cbra: np.ndarray, Cket: np.ndarray, picks=None):
+    """Transition three-body density <bra|E_pq E_rs E_tu|ket> by nested
+    application (E_tu first).  picks: optional list of (p, q, r, s, t, u) to
+    evaluate one by one (returns a list); else the full n^6 array."""
+    n = space.n
+    Cb = Cbra.reshape(space.shape)
+    Ck = Cket.reshape(space.shape)
+    if picks is not None:
+        return [float(np.sum(Cb * space.apply_E(p, q, space.apply_E(r, s, space.apply_E(t, u, Ck)))))
+                for p, q, r, s, t, u in picks]
+    out = np.empty((n,) * 6)
+    for t in range(n):
+        for u in range(n):
+            D1 = space.apply_E(t, u, Ck)
+            for r in range(n):
+                for s in range(n):
+                    D2 = space.apply_E(r, s, D1)
+                    for p in range(n):
+                        for q in range(n):
+                            out[p, q, r, s, t, u] = np.sum(Cb * space.apply_E(p, q, D2))
+    return out
+
+
+def apply_v(space: DetSpace, B: np.ndarray, C: np.ndarray) -> np.ndarray:
+    """V C, V = 1/2 sum_pqrs (pq|rs) E_pq E_rs, term by term from the definition."""
+    n = space.n
+    g = eri(B)
+    C = C.reshape(space.shape)
+    out = np.zeros(space.shape)
+    for r in range(n):
+        for s in range(n):
+            D = space.apply_E(r, s, C)
+            for p in range(n):
+                for q in range(n):
+                    if g[p, q, r, s] != 0.0:
+                        out += 0.5 * g[p, q, r, s] * space.apply_E(p, q, D)
+    return out
+
+
 def energy_from_rdm(h, B, gamma, Gp, e_core=0.0):
     g = eri(B)
     return e_core + np.einsum("pq,pq->", h, gamma) + 0.5 * np.einsum("pqrs,pqrs->", g, Gp)

@@ -46,7 +46,9 @@ from ._lib import (  # noqa: F401
     dmrg_workspace_attach,
     dmrg_workspace_query,
     dmrg_ci_dims,
+    dmrg_ci_apply_v,
     dmrg_ci_rdm12,
+    dmrg_ci_rdm3,
     dmrg_correction,
     dmrg_fiedler_order,
     dmrg_mps_to_ci,

@@ -84,6 +84,8 @@ dmrg_precond_features = _decl("dmrg_precond_features", [_p, _i, _p, _p, _d, _p])
 dmrg_correction = _decl("dmrg_correction", [_p, _i, _i, _p, _p, _p, _d, _p, _p])
 dmrg_stationarize = _decl("dmrg_stationarize", [_p, _i, _p, _p])
 dmrg_orbital_rdm2 = _decl("dmrg_orbital_rdm2", [_p, _p, _p, _p])
+dmrg_ci_apply_v = _decl("dmrg_ci_apply_v", [_p, _p, _p, _p])
+dmrg_ci_rdm3 = _decl("dmrg_ci_rdm3", [_p, _p, _p, _p, _p])
 dmrg_mutual_information = _decl("dmrg_mutual_information", [_p, _p, _p, _p, _p])
 dmrg_fiedler_order = _decl("dmrg_fiedler_order", [_i, _p, _p, _p])
 dmrg_ci_dims = _decl("dmrg_ci_dims", [_p, _p, _p])
@@ -152,6 +154,31 @@ class Problem:
         g, G, o = np.zeros((n, n)), np.zeros((n, n, n, n)), C.c_double()
         _check(dmrg_ci_rdm12(self.h, _ptr(bra), _ptr(ket), _ptr(g), _ptr(G), C.byref(o), stream))
         return g, G, o.value
+
+    def ci_apply_v(self, c, out=None, stream=None):
+        """V c, V = 1/2 sum (pq|rs) E_pq E_rs (device CI vectors)."""
+        na, nb = self.ci_dims()
+        Solver._dev_f64(c, "c", na * nb)
+        if out is None:
+            out = torch.empty_like(c)
+        Solver._dev_f64(out, "out", na * nb)
+        if stream is None and torch is not None:
+            stream = torch.cuda.current_stream().cuda_stream
+        _check(dmrg_ci_apply_v(self.h, _ptr(c), _ptr(out), stream))
+        return out
+
+    def ci_rdm3(self, bra, ket=None, stream=None):
+        """<bra|E_pq E_rs E_tu|ket> (unnormalised) as a host array [n]*6."""
+        ket = bra if ket is None else ket
+        na, nb = self.ci_dims()
+        Solver._dev_f64(bra, "bra", na * nb)
+        Solver._dev_f64(ket, "ket", na * nb)
+        if stream is None and torch is not None:
+            stream = torch.cuda.current_stream().cuda_stream
+        n = self.n
+        out = np.zeros((n,) * 6)
+        _check(dmrg_ci_rdm3(self.h, _ptr(bra), _ptr(ket), _ptr(out), stream))
+        return out
 
     def orbital_rdm2(self, c, stream=None):
         """Two-orbital density matrices of a device CI vector: [n(n-1)/2, 16, 16]."""

@@ -451,6 +451,21 @@ dmrg_status dmrg_ci_rdm12(const dmrg_problem* p, const double* bra, const double
   });
 }
 
+dmrg_status dmrg_ci_apply_v(const dmrg_problem* p, const double* c, double* out, void* stream) {
+  return guard([&] {
+    DMRG_REQUIRE(p && c && out, ST_EINVAL, "NULL argument");
+    DMRG_REQUIRE(c != out, ST_EINVAL, "out must not alias c");
+    ci_apply_v(p->p.n, p->p.n_alpha, p->p.n_beta, p->p.nq, p->p.B.data(), (hipStream_t)stream, c, out);
+  });
+}
+
+dmrg_status dmrg_ci_rdm3(const dmrg_problem* p, const double* bra, const double* ket, double* Gamma3, void* stream) {
+  return guard([&] {
+    DMRG_REQUIRE(p && bra && ket && Gamma3, ST_EINVAL, "NULL argument");
+    ci_rdm3(p->p.n, p->p.n_alpha, p->p.n_beta, (hipStream_t)stream, bra, ket, 1.0, Gamma3);
+  });
+}
+
 dmrg_status dmrg_orbital_rdm2(const dmrg_problem* p, const double* c, double* rho, void* stream) {
   return guard([&] {
     DMRG_REQUIRE(p && c && rho, ST_EINVAL, "NULL argument");

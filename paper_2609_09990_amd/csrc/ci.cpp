@@ -82,6 +82,9 @@ void tiles64(std::vector<GemmUnit>& units, double* C, int ldc, int M, int N, int
     for (int n0 = 0; n0 < N; n0 += 64) units.push_back({C, ldc, M, N, m0, n0, ib, ie, 0});
 }
 
+// one generic-kernel GEMM launch over 64 x 64 tiles (items and units uploaded here)
+void gemm_tiles(int mode, const std::vector<GemmItem>& items, const std::vector<GemmUnit>& units, hipStream_t st);
+
 template <class T>
 void upload(DevMem& d, const std::vector<T>& v, hipStream_t st) {
   d.reserve(std::max<size_t>(v.size(), 1) * sizeof(T));
@@ -155,9 +158,137 @@ double entropy_of(const std::vector<double>& rho, int n) {
   return s;
 }
 
+void gemm_tiles(int mode, const std::vector<GemmItem>& items, const std::vector<GemmUnit>& units, hipStream_t st) {
+  if (units.empty()) return;
+  DevMem di, du;
+  upload(di, items, st);
+  upload(du, units, st);
+  launch_gemm(PREC_F64, mode, du.as<GemmUnit>(), (int)units.size(), di.as<GemmItem>(), st);
+  hip_check(hipStreamSynchronize(st), "ci gemm");
+}
+
+// Split-K product G (M x N, row-major, ldg = N) [+]= sum over chunks g of
+// A_g (M x K_g) B_g^T (N x K_g) on the fp64 MFMA block kernel: A_g = A + g
+// astride, B_g = B + g bstride, both with leading dimension cl; about 2048
+// workgroups, partial tiles reduced in a fixed order; acc adds to G.
+void splitk_nt(const double* A, long astride, const double* B, long bstride, long cl, int M, int N,
+               const std::vector<int>& K, double* G, bool acc, hipStream_t st) {
+  struct Tile {
+    int m0, n0, tm, tn;
+  };
+  std::vector<Tile> tl;
+  for (int m0 = 0; m0 < M; m0 += 96)
+    for (int n0 = 0; n0 < N; n0 += 64)
+      tl.push_back({m0, n0, std::min(96, (M - m0 + 15) / 16 * 16), std::min(64, (N - n0 + 15) / 16 * 16)});
+  const long nt = (long)tl.size(), nch = (long)K.size();
+  std::vector<GemmItem> items;
+  for (long g = 0; g < nch; ++g) {
+    DMRG_REQUIRE(buffer_reach_ok(GEMM_NT, M, N, K[g], (int)cl, (int)cl, 8, 8), ST_EINVAL,
+                 "determinant chunk beyond the block kernel reach");
+    items.push_back({A + g * astride, B + g * bstride, (int)cl, (int)cl, K[g], 0, 1.0});
+  }
+  const long ng = std::max<long>(1, std::min<long>(nch, 2048 / std::max<long>(nt, 1)));
+  std::vector<SplitTile> tiles;
+  std::vector<GemmUnit> units;
+  long so = 0;
+  for (const Tile& t : tl) {
+    tiles.push_back({G, so, N, M, N, t.m0, t.n0, (int)ng, t.tm, t.tn, acc ? 1 : 0, 0});
+    so += ng * t.tm * t.tn;
+  }
+  DevMem slots, ditems, dunits, dtiles;
+  slots.reserve((size_t)so * 8);
+  for (long gi = 0; gi < ng; ++gi) {
+    const int ib = (int)(nch * gi / ng), ie = (int)(nch * (gi + 1) / ng);
+    for (long t = 0; t < nt; ++t) {
+      const SplitTile& s = tiles[t];
+      units.push_back({slots.as<double>() + s.s0 + gi * s.tm * s.tn, s.tn, M, N, s.m0, s.n0, ib, ie, 2,
+                       8 * (s.tm / 16) + s.tn / 16});
+    }
+  }
+  upload(ditems, items, st);
+  upload(dunits, units, st);
+  upload(dtiles, tiles, st);
+  launch_gemm_wg(PREC_F64, 5, dunits.as<GemmUnit>(), (int)units.size(), ditems.as<GemmItem>(), st);
+  launch_splitk_reduce(dtiles.as<SplitTile>(), (int)nt, slots.as<double>(), st);
+  hip_check(hipStreamSynchronize(st), "split-K product");
+}
+
 }  // namespace
 
 long ci_dimension(int n, int na, int nb) { return binom(n, na) * binom(n, nb); }
+
+// V c with V = 1/2 sum_pqrs (pq|rs) E_pq E_rs and (pq|rs) = sum_Q B^Q_pq B^Q_rs,
+// streamed through the factors: T_rs = E_rs c, W_Q = sum_rs B^Q_rs T_rs,
+// U_pq = sum_Q B^Q_pq W_Q, V c = 1/2 sum_pq E_pq U_pq (two GEMMs and two
+// gather kernels; (pq|rs) is never formed).
+void ci_apply_v(int n, int na, int nb, int nq, const double* Bh, hipStream_t st, const double* c, double* out) {
+  DMRG_REQUIRE(n >= 1 && n <= 16 && nq >= 0, ST_EINVAL, "the two-electron operator on CI vectors needs 1..16 orbitals");
+  const std::vector<uint32_t> sa = colex_strings(n, na), sb = colex_strings(n, nb);
+  const long NA = (long)sa.size(), NB = (long)sb.size(), N = NA * NB;
+  const int n2 = n * n;
+  if (nq == 0) {
+    launch_fill(out, N, 0.0, st);
+    hip_check(hipStreamSynchronize(st), "apply V");
+    return;
+  }
+  DevMem ta, tb, T, W, U, Bd;
+  upload(ta, excitation_table(n, sa), st);
+  upload(tb, excitation_table(n, sb), st);
+  T.reserve((size_t)(n2 + 1) * N * 8);
+  W.reserve((size_t)nq * N * 8);
+  U.reserve((size_t)n2 * N * 8);
+  Bd.reserve((size_t)nq * n2 * 8);
+  hip_check(hipMemcpyAsync(Bd.p, Bh, (size_t)nq * n2 * 8, hipMemcpyHostToDevice, st), "B");
+  launch_ci_excite(c, NA, NB, n2, ta.as<int>(), tb.as<int>(), T.as<double>(), N, 0, N, st);
+  std::vector<GemmItem> items{{Bd.as<double>(), T.as<double>(), n2, (int)N, n2, 0, 1.0}};
+  std::vector<GemmUnit> units;
+  tiles64(units, W.as<double>(), (int)N, nq, (int)N, 0, 1);
+  gemm_tiles(GEMM_NN, items, units, st);  // W = B T (nq x N)
+  items = {{Bd.as<double>(), W.as<double>(), n2, (int)N, nq, 0, 1.0}};
+  units.clear();
+  tiles64(units, U.as<double>(), (int)N, n2, (int)N, 0, 1);
+  gemm_tiles(GEMM_TN, items, units, st);  // U = B^T W (n^2 x N)
+  launch_ci_apply_sum(U.as<double>(), N, NA, NB, n2, ta.as<int>(), tb.as<int>(), 0.5, out, N, st);
+  hip_check(hipStreamSynchronize(st), "apply V");
+}
+
+// Gamma3[pqrstu] = scale <bra|E_pq E_rs E_tu|ket> = scale <E_qp bra | E_rs E_tu ket>:
+// the copies E_tu ket are kept whole, E_rs of each is formed per pass of
+// determinants, and one split-K product of (n^2 + 1) bra rows with n^2 (n^2 + 1)
+// ket rows per pass accumulates G.
+void ci_rdm3(int n, int na, int nb, hipStream_t st, const double* bra, const double* ket, double scale, double* out) {
+  DMRG_REQUIRE(n >= 1 && n <= 12, ST_EINVAL, "the three-body density from CI vectors needs 1..12 orbitals");
+  const std::vector<uint32_t> sa = colex_strings(n, na), sb = colex_strings(n, nb);
+  const long NA = (long)sa.size(), NB = (long)sb.size(), N = NA * NB;
+  const int n2 = n * n, rows = n2 + 1, nbr = n2 * rows;
+  constexpr long CL = 4096;
+  DevMem ta, tb, Tk, T1, T2, G, d3;
+  upload(ta, excitation_table(n, sa), st);
+  upload(tb, excitation_table(n, sb), st);
+  Tk.reserve((size_t)rows * N * 8);
+  launch_ci_excite(ket, NA, NB, n2, ta.as<int>(), tb.as<int>(), Tk.as<double>(), N, 0, N, st);  // [x][N]
+  const long per_pass = std::max<long>(1, (4L << 30) / ((long)nbr * CL * 8)) * CL;
+  const long pass = std::min(per_pass, (N + CL - 1) / CL * CL);
+  T1.reserve((size_t)rows * pass * 8);
+  T2.reserve((size_t)nbr * pass * 8);
+  G.reserve((size_t)rows * nbr * 8);
+  for (long d0 = 0; d0 < N; d0 += pass) {
+    const long dend = std::min(N, d0 + pass), nch = (dend - d0 + CL - 1) / CL;
+    launch_ci_excite(bra, NA, NB, n2, ta.as<int>(), tb.as<int>(), T1.as<double>(), CL, d0, dend, st);
+    for (int x = 0; x < n2; ++x)  // chunk g of E_rs (E_x ket) at T2 + g nbr CL + x rows CL
+      launch_ci_excite(Tk.as<double>() + (long)x * N, NA, NB, n2, ta.as<int>(), tb.as<int>(),
+                       T2.as<double>() + (long)x * rows * CL, CL, d0, dend, st, (long)nbr * CL);
+    std::vector<int> K;
+    for (long g = 0; g < nch; ++g) K.push_back((int)std::min(CL, dend - d0 - g * CL));
+    splitk_nt(T1.as<double>(), rows * CL, T2.as<double>(), (long)nbr * CL, CL, rows, nbr, K, G.as<double>(), d0 > 0,
+              st);
+  }
+  const long n6 = (long)n2 * n2 * n2;
+  d3.reserve((size_t)n6 * 8);
+  launch_rdm3_assemble(G.as<double>(), nbr, n, rows, scale, d3.as<double>(), st);
+  hip_check(hipMemcpyAsync(out, d3.p, (size_t)n6 * 8, hipMemcpyDeviceToHost, st), "rdm3 out");
+  hip_check(hipStreamSynchronize(st), "rdm3");
+}
 
 void orbital_rdm2(int n, int na, int nb, hipStream_t st, const double* c, std::vector<double>& rho) {
   DMRG_REQUIRE(n >= 2 && n <= 16, ST_EINVAL, "orbital density matrices from CI vectors need 2..16 orbitals");

@@ -34,11 +34,10 @@ __global__ void ci_scatter_kernel(const double* __restrict__ amp, const CiSector
 // alpha-excitation reads are row gathers of c and the beta ones stay in a row.
 __global__ void ci_excite_kernel(const double* __restrict__ c, long na, long nb, int n2,
                                  const int* __restrict__ ta, const int* __restrict__ tb, double* __restrict__ T,
-                                 long cl, long d0, long dend) {
+                                 long cl, long gstride, long d0, long dend) {
   const int x = blockIdx.y;
   const long g = blockIdx.z;
-  const long rows = n2 + 1;
-  double* out = T + (g * rows + x) * cl;
+  double* out = T + g * gstride + (long)x * cl;
   for (long j = (long)blockIdx.x * blockDim.x + threadIdx.x; j < cl; j += (long)gridDim.x * blockDim.x) {
     const long d = d0 + g * cl + j;
     if (d >= dend) break;
@@ -157,11 +156,51 @@ void launch_ci_scatter(const double* amp, const CiSector* secs, int n_secs, cons
 }
 
 void launch_ci_excite(const double* c, long na, long nb, int n2, const int* ta, const int* tb, double* T, long cl,
-                      long d0, long dend, hipStream_t s) {
+                      long d0, long dend, hipStream_t s, long gstride) {
   const long nch = (dend - d0 + cl - 1) / cl;
   if (nch <= 0) return;
-  ci_excite_kernel<<<dim3(grid_cap(cl, 64), n2 + 1, (unsigned)nch), 256, 0, s>>>(c, na, nb, n2, ta, tb, T, cl, d0,
-                                                                                 dend);
+  if (gstride <= 0) gstride = (long)(n2 + 1) * cl;
+  ci_excite_kernel<<<dim3(grid_cap(cl, 64), n2 + 1, (unsigned)nch), 256, 0, s>>>(c, na, nb, n2, ta, tb, T, cl,
+                                                                                 gstride, d0, dend);
+}
+
+// out[d] = scale * sum_{x < n2} (E_x U_x)[d], U_x the rows of U (row-major, ldu).
+__global__ void ci_apply_sum_kernel(const double* __restrict__ U, long ldu, long na, long nb, int n2,
+                                    const int* __restrict__ ta, const int* __restrict__ tb, double scale,
+                                    double* __restrict__ out, long ndet) {
+  for (long d = (long)blockIdx.x * blockDim.x + threadIdx.x; d < ndet; d += (long)gridDim.x * blockDim.x) {
+    const long ia = d / nb, ib = d - ia * nb;
+    double v = 0.0;
+    for (int x = 0; x < n2; ++x) {
+      const double* u = U + (long)x * ldu;
+      const int xa = ta[(long)x * na + ia];
+      if (xa != 0) v += (xa > 0 ? 1.0 : -1.0) * u[(long)(abs(xa) - 1) * nb + ib];
+      const int xb = tb[(long)x * nb + ib];
+      if (xb != 0) v += (xb > 0 ? 1.0 : -1.0) * u[ia * nb + (abs(xb) - 1)];
+    }
+    out[d] = scale * v;
+  }
+}
+
+void launch_ci_apply_sum(const double* U, long ldu, long na, long nb, int n2, const int* ta, const int* tb,
+                         double scale, double* out, long ndet, hipStream_t s) {
+  if (ndet > 0) ci_apply_sum_kernel<<<grid_cap(ndet), 256, 0, s>>>(U, ldu, na, nb, n2, ta, tb, scale, out, ndet);
+}
+
+// Gamma3[((((p n + q) n + r) n + s) n + t) n + u] = scale G[(q n + p) ldg + (t n + u) rows + r n + s]
+__global__ void rdm3_assemble_kernel(const double* __restrict__ G, long ldg, int n, int rows, double scale,
+                                     double* __restrict__ out) {
+  const long n2 = (long)n * n, n6 = n2 * n2 * n2;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n6; i += (long)gridDim.x * blockDim.x) {
+    const int u = (int)(i % n), t = (int)(i / n % n), s = (int)(i / n2 % n), r = (int)(i / (n2 * n) % n);
+    const int q = (int)(i / (n2 * n2) % n), p = (int)(i / (n2 * n2 * n));
+    out[i] = scale * G[(long)(q * n + p) * ldg + (long)(t * n + u) * rows + r * n + s];
+  }
+}
+
+void launch_rdm3_assemble(const double* G, long ldg, int n, int rows, double scale, double* out, hipStream_t s) {
+  const long n2 = (long)n * n;
+  rdm3_assemble_kernel<<<grid_cap(n2 * n2 * n2), 256, 0, s>>>(G, ldg, n, rows, scale, out);
 }
 
 void launch_rdm_assemble(const double* G, int ldg, int n, double scale, double* gamma, double* Gamma,

@@ -546,6 +546,12 @@ long ci_dimension(int n, int na, int nb);
 void orbital_rdm2(int n, int na, int nb, hipStream_t st, const double* c, std::vector<double>& rho);
 void mutual_information(int n, int na, int nb, hipStream_t st, const double* c, double* s1, double* I);
 void fiedler_order(int n, const double* I, int* order, double* fiedler);
+// V c for the all-active two-electron operator V = 1/2 sum (pq|rs) E_pq E_rs,
+// streamed through the Cholesky factors Bh (host, nq x n x n); and the
+// (transition) three-body density <bra|E_pq E_rs E_tu|ket> (host n^6) of device
+// CI vectors.
+void ci_apply_v(int n, int na, int nb, int nq, const double* Bh, hipStream_t st, const double* c, double* out);
+void ci_rdm3(int n, int na, int nb, hipStream_t st, const double* bra, const double* ket, double scale, double* out);
 void ci_rdm12(int n, int na, int nb, hipStream_t st, const double* bra, const double* ket, double scale,
               double* gamma, double* Gamma, double* overlap);
 

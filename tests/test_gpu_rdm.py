@@ -132,3 +132,82 @@ def test_rdms_of_dmrg_roots_equal_fci():
     assert np.abs(g10 - sgn * r10).max() <= 1e-7 and np.abs(G10 - sgn * R10).max() <= 1e-7
     assert abs(fci.energy_from_rdm(h, B, g10, G10)) <= 1e-8
     assert abs(fci.energy_from_rdm(h, B, g00, G00, e0) - res["energies"][0]) <= 1e-9
+
+
+def _v_ref(space, B, c):
+    g = fci.eri(B)
+    return fci.sigma(space, 0.5 * np.einsum("prrq->pq", g), g, c)
+
+
+@pytest.mark.parametrize("n,na,nb,nq", [(4, 2, 2, 5), (6, 3, 3, 8), (8, 4, 4, 32), (10, 5, 4, 12)])
+def test_ci_apply_v_matches_oracle(n, na, nb, nq):
+    """V c (the two-electron block streamed through the Cholesky factors)
+    against the oracle's Hamiltonian action without its one-body part."""
+    torch = _torch()
+    import paper_2609_09990_amd as pk
+    print(f"apply_v n={n} ({na},{nb}) nq={nq}", flush=True)
+    h, B, e0 = synth.make_hamiltonian(n, nq, 1)
+    prob = pk.Problem(h, B, na, nb, e0)
+    space = fci.DetSpace(n, na, nb)
+    c = np.random.default_rng(n).normal(size=space.shape)
+    got = prob.ci_apply_v(torch.from_numpy(c).cuda()).cpu().numpy()
+    ref = _v_ref(space, B, c)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("n,na,nb,full", [(3, 2, 1, True), (4, 2, 2, True), (5, 3, 2, True), (8, 4, 4, False),
+                                          (10, 5, 5, False)])
+def test_ci_rdm3_matches_oracle(n, na, nb, full):
+    """<bra|E_pq E_rs E_tu|ket>: every element (n <= 5) or 60 sampled elements
+    and the trace identity sum_t Gamma3[pqrstt] = N <bra|E_pq E_rs|ket> (n = 8,
+    and n = 10 where the determinants take two passes)."""
+    torch = _torch()
+    import paper_2609_09990_amd as pk
+    print(f"rdm3 n={n} ({na},{nb})", flush=True)
+    h, B, e0 = synth.make_hamiltonian(n, 4, 0)
+    prob = pk.Problem(h, B, na, nb, e0)
+    space = fci.DetSpace(n, na, nb)
+    rng = np.random.default_rng(3 * n)
+    bra, ket = rng.normal(size=(2,) + space.shape)
+    db, dk = torch.from_numpy(bra).cuda(), torch.from_numpy(ket).cuda()
+    G3 = prob.ci_rdm3(db, dk)
+    if full:
+        ref = fci.rdm3(space, bra, ket)
+        assert np.abs(G3 - ref).max() <= 1e-12 * np.abs(ref).max()
+        return
+    picks = [tuple(int(x) for x in rng.integers(0, n, size=6)) for _ in range(60)]
+    ref = fci.rdm3(space, bra, ket, picks)
+    scale = np.abs(G3).max()
+    for x, r in zip(picks, ref):
+        assert abs(G3[x] - r) <= 1e-12 * scale, x
+    g, G, _ = prob.ci_rdm12(db, dk)
+    EE = G + np.einsum("qr,ps->pqrs", np.eye(n), g)
+    assert np.abs(np.einsum("pqrstt->pqrs", G3) - (na + nb) * EE).max() <= 1e-11 * scale
+
+
+def test_fused_four_body_contraction_cas8():
+    """CAS(8,8), N_Q = 32, the DMRG ground state's CI vector c: the
+    four-particle density contracted with the two-electron block,
+    sum_vwxy (vw|xy)/2 <c|E_pq E_rs E_tu E_vw E_xy|c>, as the three-body density
+    of (c, V c) (the n^8 object never formed), against the oracle on 40 sampled
+    elements; and its full contraction with delta_pq delta_rs delta_tu equals
+    N^3 <c|V|c>."""
+    torch = _torch()
+    import paper_2609_09990_amd as pk
+    h, B, e0 = synth.make_hamiltonian(8, 32, 0)
+    prob = pk.Problem(h, B, 4, 4, e0)
+    sol = pk.Solver(prob, M=256, tol=1e-10)
+    sol.sweep(3)
+    c = sol.mps_to_ci()
+    vc = prob.ci_apply_v(c)
+    F = prob.ci_rdm3(c, vc)
+    space = fci.DetSpace(8, 4, 4)
+    ch = c.cpu().numpy()
+    vref = _v_ref(space, B, ch)
+    rng = np.random.default_rng(8)
+    picks = [tuple(int(x) for x in rng.integers(0, 8, size=6)) for _ in range(40)]
+    ref = fci.rdm3(space, ch, vref, picks)
+    scale = np.abs(F).max()
+    for x, r in zip(picks, ref):
+        assert abs(F[x] - r) <= 1e-11 * scale, x
+    assert abs(np.einsum("pprrtt->", F) - 8 ** 3 * float(np.sum(ch * vref))) <= 1e-10 * abs(8 ** 3 * np.sum(ch * vref))

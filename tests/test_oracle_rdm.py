@@ -86,3 +86,45 @@ def test_transition_rdms_give_hamiltonian_matrix_elements():
             g, G = fci.trdm12(space, vs[i], vs[j])
             e = fci.energy_from_rdm(h, B, g, G) + (e0 if i == j else 0.0)
             assert abs(e - (w[i] if i == j else 0.0)) < 1e-9, (i, j, e)
+
+
+def test_apply_v_equals_sigma_without_one_body_part():
+    """V = 1/2 sum (pq|rs) E_pq E_rs is the Hamiltonian of fci.sigma with
+    h = 1/2 sum_r (pr|rq) (its one-body shift then cancels)."""
+    n, na, nb = 4, 2, 1
+    h, B, _ = synth.make_hamiltonian(n, 5, 7)
+    space = fci.DetSpace(n, na, nb)
+    C = np.random.default_rng(1).normal(size=space.shape)
+    g = fci.eri(B)
+    ref = fci.sigma(space, 0.5 * np.einsum("prrq->pq", g), g, C)
+    assert np.abs(fci.apply_v(space, B, C) - ref).max() < 1e-12
+
+
+@pytest.mark.parametrize("n,na,nb", [(3, 2, 1), (3, 1, 1)])
+def test_rdm3_equals_fock_space_operator_products(n, na, nb):
+    space = fci.DetSpace(n, na, nb)
+    rng = np.random.default_rng(20 + n + na)
+    bra, ket = rng.normal(size=(2,) + space.shape)
+    G3 = fci.rdm3(space, bra, ket)
+    E, basis = {}, None
+    for p in range(n):
+        for q in range(n):
+            E[p, q], basis = _fock_one_body(n, na, nb, p, q)
+    fb, fk = _to_fock(space, bra, basis), _to_fock(space, ket, basis)
+    for idx in np.ndindex(*(n,) * 6):
+        p, q, r, s, t, u = idx
+        ref = fb @ (E[p, q] @ (E[r, s] @ (E[t, u] @ fk)))
+        assert abs(G3[idx] - ref) < 1e-12, idx
+
+
+def test_rdm3_trace_and_picks():
+    n, na, nb = 4, 2, 2
+    space = fci.DetSpace(n, na, nb)
+    rng = np.random.default_rng(6)
+    bra, ket = rng.normal(size=(2,) + space.shape)
+    G3 = fci.rdm3(space, bra, ket)
+    g, G = fci.trdm12(space, bra, ket)
+    EE = G + np.einsum("qr,ps->pqrs", np.eye(n), g)
+    assert np.abs(np.einsum("pqrstt->pqrs", G3) - (na + nb) * EE).max() < 1e-11
+    picks = [(0, 1, 2, 3, 1, 0), (3, 3, 0, 2, 2, 1)]
+    assert np.allclose(fci.rdm3(space, bra, ket, picks), [G3[x] for x in picks], atol=1e-13)
