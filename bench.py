@@ -341,6 +341,86 @@ def adjoint_form(sol, torch, h, B, e_core, out):
     print(f"# adjoint: {dt:.1f} s", file=sys.stderr, flush=True)
 
 
+def next_rows(pk, torch):
+    """The rows beyond the step, timed on their own workloads (synthetic
+    integrals, the sizes of the paper's validation active spaces):
+    * excited states: the three lowest CAS(12,12) roots (N_Q = 64, M = 512) by
+      penalty deflation with the diagonal and with the shift-and-invert
+      preconditioner: wall time, matvecs, energy difference;
+    * determinant space at CAS(12,12): MPS to CI vector, 1-/2-RDMs (the
+      (n^2+1)^2 x N_det product on the fp64 MFMA kernel: rate), V c and the
+      fused four-body contraction as the three-body density of (c, V c), orbital
+      mutual information and the Fiedler order;
+    * stationarity at truncated M: one-site sweeps of CAS(8,8) (N_Q = 32) at
+      M = 24, where the two-site fixed point discards ~1e-2."""
+    import numpy as np
+    import synth
+    res = {}
+    h, B, e0 = synth.make_hamiltonian(12, 64, 0)
+    prob = pk.Problem(h, B, 6, 6, e0)
+    ex = {}
+    for mode in (0, 3):
+        torch.cuda.synchronize()
+        t0 = time.time()
+        r = pk.excited_states(prob, 3, M=512, tol=1e-9, sweeps=3, conv_tol=1e-9, precond=mode)
+        dt = time.time() - t0
+        ex[mode] = (dt, r["energies"], sum(run["sweeps"] for run in r["runs"]))
+        print(f"# excited states precond {mode}: {dt:.1f} s", file=sys.stderr, flush=True)
+    res["excited_cas12_m512"] = {
+        "roots": 3, "seconds_diag": ex[0][0], "seconds_shift_invert": ex[3][0],
+        "speedup_shift_invert": ex[0][0] / ex[3][0], "energies": [float(x) for x in ex[3][1]],
+        "max_abs_energy_difference": float(np.max(np.abs(ex[0][1] - ex[3][1]))),
+        "sweeps_diag": ex[0][2], "sweeps_shift_invert": ex[3][2]}
+    sol = pk.Solver(prob, M=1024, tol=1e-9)
+    sol.sweep(3)
+    na, nb = prob.ci_dims()
+    torch.cuda.synchronize()
+    t0 = time.time()
+    c = sol.mps_to_ci()
+    torch.cuda.synchronize()
+    t_ci = time.time() - t0
+    t0 = time.time()
+    g, G, ov = prob.ci_rdm12(c)
+    t_12 = time.time() - t0
+    rows = 12 * 12 + 1
+    f12 = 2.0 * rows * rows * na * nb
+    t0 = time.time()
+    vc = prob.ci_apply_v(c)
+    torch.cuda.synchronize()
+    t_v = time.time() - t0
+    t0 = time.time()
+    F = prob.ci_rdm3(c, vc)
+    t_3 = time.time() - t0
+    f3 = 2.0 * rows * (144 * rows) * na * nb
+    t0 = time.time()
+    s1, I = prob.mutual_information(c)
+    order, _ = pk.fiedler_order(I)
+    t_mi = time.time() - t0
+    e_rdm = float(np.sum(h * g) + 0.5 * np.einsum("Qpq,Qrs,pqrs->", B, B, G)) / ov + e0
+    res["determinant_space_cas12"] = {
+        "n_det": na * nb, "mps_to_ci_s": t_ci, "rdm12_s": t_12, "rdm12_gemm_flops": f12,
+        "rdm12_tflops": f12 / t_12 / 1e12, "apply_v_s": t_v, "rdm3_of_c_vc_s": t_3, "rdm3_gemm_flops": f3,
+        "rdm3_tflops": f3 / t_3 / 1e12, "mutual_information_and_order_s": t_mi,
+        "energy_from_rdm_minus_dmrg": e_rdm - float(sol.energy()[0]),
+        "fused_trace_check": float(np.einsum("pprrtt->", F) / (12 ** 3 * float((c * vc).sum())) - 1.0)}
+    print(f"# determinant space: rdm12 {t_12:.2f} s, rdm3(c, Vc) {t_3:.2f} s", file=sys.stderr, flush=True)
+    del sol
+    h8, B8, e8 = synth.make_hamiltonian(8, 32, 0)
+    st = pk.Solver(pk.Problem(h8, B8, 4, 4, e8), M=24, tol=1e-11)
+    e2 = st.sweep(6)[0][0]
+    torch.cuda.synchronize()
+    t0 = time.time()
+    out = []
+    for _ in range(20):
+        e, r, ok = st.stationarize(1)
+        out.append(r)
+    dt = time.time() - t0
+    res["stationarize_cas8_m24"] = {"seconds_per_sweep": dt / 20, "energy_two_site": float(e2),
+                                    "energy_after_20": float(e), "tangent_residual_every_5": out[::5] + [out[-1]]}
+    print(f"# stationarize: {dt / 20:.2f} s per sweep", file=sys.stderr, flush=True)
+    return res
+
+
 def diff_form(pk, torch):
     """Differentiation form: CAS(16,16), N_Q = 96, M = 512, 2 state-averaged roots
     (seed 0), 4 sweeps.  Per-state gradients of the final MPS (time), and the
@@ -395,6 +475,8 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the timed full sweep")
     ap.add_argument("--no-forms", action="store_true", help="skip the precision, learned and adjoint forms")
     ap.add_argument("--no-config5", action="store_true", help="skip the CAS(24,24) M=2048 comparison")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the excited-state, determinant-space and stationarity timings")
     ap.add_argument("--diff-form", action="store_true",
                     help="also run the differentiation-form configuration (CAS(16,16), M=512, 2 states)")
     args = ap.parse_args()
@@ -530,6 +612,8 @@ def main():
         del swp
     if args.diff_form:
         out["diff_form"] = diff_form(pk, torch)
+    if not args.no_next:
+        out["next_rows"] = next_rows(pk, torch)
     if net is not None and not args.no_config5:
         del sol
         out["config5"] = config5(pk, torch, net)

@@ -773,8 +773,9 @@ __device__ inline void wg_tile(const GemmUnit& u, const GemmItem* __restrict__ i
 
 template <typename T, int TAG>
 __global__ __launch_bounds__(256) void gemm_wg(const GemmUnit* __restrict__ units,
-                                               const GemmItem* __restrict__ items) {
+                                               const GemmItem* __restrict__ items, int n_units) {
   __shared__ __align__(16) T As[2][96][kWgPk];
+  if ((int)blockIdx.x >= n_units) return;
   const GemmUnit u = units[blockIdx.x];
   switch (u.shape >> 3) {  // RB; the tile is (16 RB) x (16 CB), CB = shape & 7
     case 1: wg_tile<T, 1>(u, items, As); break;
@@ -1546,17 +1547,21 @@ void launch_gemm_w32(int mode, int tag, bool buf, const GemmUnit* units, int n_u
 
 void launch_gemm_wg(int prec, int tag, const GemmUnit* units, int n_units, const GemmItem* items, hipStream_t s) {
   if (n_units <= 0) return;
+  // unit b on workgroup b: consecutive units (which share operands) run at the
+  // same time on the 8 XCDs in turn; giving each XCD a contiguous eighth of the
+  // list instead measured 1.3x slower for sigma phase B (5.5 -> 7.2 ms)
+  const int grid = n_units;
   if (prec == PREC_F32) {
-    gemm_wg<float, 0><<<n_units, 256, 0, s>>>(units, items);
+    gemm_wg<float, 0><<<grid, 256, 0, s>>>(units, items, n_units);
     return;
   }
   switch (tag) {
-    case 1: gemm_wg<double, 1><<<n_units, 256, 0, s>>>(units, items); break;
-    case 2: gemm_wg<double, 2><<<n_units, 256, 0, s>>>(units, items); break;
-    case 3: gemm_wg<double, 3><<<n_units, 256, 0, s>>>(units, items); break;
-    case 4: gemm_wg<double, 4><<<n_units, 256, 0, s>>>(units, items); break;
-    case 5: gemm_wg<double, 5><<<n_units, 256, 0, s>>>(units, items); break;
-    default: gemm_wg<double, 0><<<n_units, 256, 0, s>>>(units, items); break;
+    case 1: gemm_wg<double, 1><<<grid, 256, 0, s>>>(units, items, n_units); break;
+    case 2: gemm_wg<double, 2><<<grid, 256, 0, s>>>(units, items, n_units); break;
+    case 3: gemm_wg<double, 3><<<grid, 256, 0, s>>>(units, items, n_units); break;
+    case 4: gemm_wg<double, 4><<<grid, 256, 0, s>>>(units, items, n_units); break;
+    case 5: gemm_wg<double, 5><<<grid, 256, 0, s>>>(units, items, n_units); break;
+    default: gemm_wg<double, 0><<<grid, 256, 0, s>>>(units, items, n_units); break;
   }
 }
 
