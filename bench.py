@@ -27,7 +27,7 @@ N_ORB, N_CHOL, M, SEED = 20, 120, 1024, 0
 MID = N_ORB // 2 - 1
 PEAK_FP64 = 78.6  # TFLOP/s, MI355X dense FP64 matrix
 # HBM bytes per launch of the dominant kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
-# runs (profiles/sigma_phaseB_wg_merged_cas20_m1024_fp64.md), scaled by the same counters on a
+# runs (profiles/sigma_step_kernels_cas20_m1024_fp64_counters.md), scaled by the same counters on a
 # plain copy (fetch x2.0, write x1.0); set to None whenever that kernel changes.
 TRAFFIC = 2.49e10
 
@@ -341,6 +341,41 @@ def adjoint_form(sol, torch, h, B, e_core, out):
     print(f"# adjoint: {dt:.1f} s", file=sys.stderr, flush=True)
 
 
+def oracle_beside(pk, torch):
+    """The CPU oracle timed beside the device on the same inputs (small cases the
+    oracle finishes in seconds): 1-/2-RDMs at CAS(8,8), the three-body density at
+    CAS(5,5), mutual information at CAS(6,6); random CI vectors."""
+    import numpy as np
+    import synth
+    from oracle import fci, orbital
+    out = {}
+    for name, (n, na, nb) in (("rdm12_cas8", (8, 4, 4)), ("rdm3_cas5", (5, 3, 2)), ("mutual_information_cas6", (6, 3, 3))):
+        h, B, e0 = synth.make_hamiltonian(n, 8, 0)
+        prob = pk.Problem(h, B, na, nb, e0)
+        space = fci.DetSpace(n, na, nb)
+        c = np.random.default_rng(n).normal(size=space.shape)
+        dc = torch.from_numpy(c).cuda()
+        t0 = time.time()
+        if name.startswith("rdm12"):
+            g, G, _ = prob.ci_rdm12(dc)
+        elif name.startswith("rdm3"):
+            G = prob.ci_rdm3(dc)
+        else:
+            s1, G = prob.mutual_information(dc)
+        t_gpu = time.time() - t0
+        t0 = time.time()
+        if name.startswith("rdm12"):
+            rg, rG = fci.rdm12(space, c)
+        elif name.startswith("rdm3"):
+            rG = fci.rdm3(space, c, c)
+        else:
+            rs1, rG = orbital.mutual_information(space, c)
+        t_cpu = time.time() - t0
+        out[name] = {"gpu_s": t_gpu, "oracle_cpu_s": t_cpu, "max_abs_diff": float(np.abs(G - rG).max())}
+        print(f"# oracle beside {name}: gpu {t_gpu:.3f} s, oracle {t_cpu:.2f} s", file=sys.stderr, flush=True)
+    return out
+
+
 def next_rows(pk, torch):
     """The rows beyond the step, timed on their own workloads (synthetic
     integrals, the sizes of the paper's validation active spaces):
@@ -403,7 +438,10 @@ def next_rows(pk, torch):
         "rdm3_tflops": f3 / t_3 / 1e12, "mutual_information_and_order_s": t_mi,
         "energy_from_rdm_minus_dmrg": e_rdm - float(sol.energy()[0]),
         "fused_trace_check": float(np.einsum("pprrtt->", F) / (12 ** 3 * float((c * vc).sum())) - 1.0)}
+    res["determinant_space_cas12"]["rdm12_frac_fp64_peak"] = f12 / t_12 / 1e12 / PEAK_FP64
+    res["determinant_space_cas12"]["rdm3_frac_fp64_peak"] = f3 / t_3 / 1e12 / PEAK_FP64
     print(f"# determinant space: rdm12 {t_12:.2f} s, rdm3(c, Vc) {t_3:.2f} s", file=sys.stderr, flush=True)
+    res["oracle_beside"] = oracle_beside(pk, torch)
     del sol
     h8, B8, e8 = synth.make_hamiltonian(8, 32, 0)
     st = pk.Solver(pk.Problem(h8, B8, 4, 4, e8), M=24, tol=1e-11)
