@@ -37,11 +37,13 @@ int plan_threads() {
   }();
   return n;
 }
-// f(t, begin, end) on contiguous ranges of [0, n), one per thread; the ranges
-// follow thread order, so results gathered by thread index are in serial order.
+// f(t, begin, end) on contiguous ranges of [0, n), one per thread, at least
+// `grain` elements each (starting threads costs tens of microseconds, so light
+// per-element work takes a large grain); the ranges follow thread order, so
+// results gathered by thread index are in serial order.
 template <class F>
-void parallel_ranges(long n, F&& f) {
-  const int nt = (int)std::min<long>(plan_threads(), std::max<long>(n / 4, 1));
+void parallel_ranges(long n, F&& f, long grain = 4) {
+  const int nt = (int)std::min<long>(plan_threads(), std::max<long>(n / grain, 1));
   if (nt <= 1) {
     f(0, 0L, n);
     return;
@@ -54,6 +56,13 @@ void parallel_ranges(long n, F&& f) {
   for (auto& x : th) x.join();
 }
 }  // namespace
+
+// Grain of loops over a phase's units: about 4096 items per thread.
+template <class PH>
+long unit_grain(const PH& ph) {
+  const long nu = (long)ph.units.size(), ni = (long)ph.items.size();
+  return std::max<long>(4, ni > 0 ? nu * 4096 / ni : nu);
+}
 
 bool same_sectors(const std::vector<Sector>& a, const std::vector<Sector>& b) {
   if (a.size() != b.size()) return false;
@@ -303,7 +312,7 @@ static bool validate_phase(const Phase& ph, const long* sizes, const size_t* esz
           reach[t] = 0;
       }
     }
-  });
+  }, unit_grain(ph));
   for (char b : bad) {
     if (b == 1) throw Error(ST_EINVAL, "plan: output block out of bounds");
     if (b == 2) throw Error(ST_EINVAL, "plan: operand block out of bounds");
@@ -350,7 +359,7 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
       items[i].pad = 0;
       items[i].coef = p.coef;
     }
-  });
+  }, 4096);
   ph.buf_ok[slot] = buf_ok;
   // fp64 / fp32 NT phases with long item lists (sigma phase B) take the
   // workgroup block kernel: whole-block tiles up to 96 x 64, operands read once
@@ -397,7 +406,7 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
         for (int i = u.ib; i < u.ie; ++i) w += (long)((u.M + 31) / 32) * ((u.N + 31) / 32) * ((ph.items[i].K + 3) / 4);
         wunit[x] = w;
       }
-    });
+    }, unit_grain(ph));
     double work = 0;
     {
       long wsum = 0;
@@ -447,7 +456,7 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
           q.n_slot += nc * ts.tm * ts.tn;
         }
       }
-    });
+    }, unit_grain(ph));
     for (char b : too_big) DMRG_REQUIRE(!b, ST_EINVAL, "split-K tile larger than the reduction covers");
     // offsets, then pass 2 (parallel): units, tiles and slot offsets in place
     std::vector<long> uat(nu), tat(nu), sat(nu);
@@ -490,7 +499,7 @@ void Solver::run_phase(Phase& ph, int prec, void* const* bases, size_t const* es
                      q.cuts[c].first, q.cuts[c].second, 2, q.ts[t].shape};
           }
       }
-    });
+    }, unit_grain(ph));
     ph.slot_base[slot] = splitk_.p;
   } else {
     std::vector<GemmUnit> v;

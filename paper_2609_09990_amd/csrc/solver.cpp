@@ -1991,9 +1991,10 @@ std::vector<double> Solver::mps_energy() {
     hip_check(hipMemcpyAsync(h, sc.p, 16, hipMemcpyDeviceToHost, st), "energy");
     hip_check(hipStreamSynchronize(st), "energy");
     // psi . H_eff psi = <Psi|H|Psi> in any gauge (the left block of step 0 is the
-    // vacuum); psi . psi is <Psi|Psi> only for right-orthonormal sites 2.., so a
-    // single state takes its norm from the whole chain
-    if (nr == 1) {
+    // vacuum); psi . psi is <Psi|Psi> only for right-orthonormal sites 2.. (the
+    // centre on site 0 or 1), so otherwise a single state takes its norm from the
+    // whole chain
+    if (nr == 1 && center_site_ != 0 && center_site_ != 1) {
       const MPSView me{&bonds_, &mps_};
       h[1] = chain_overlap(me, me);
     }
