@@ -443,6 +443,20 @@ def next_rows(pk, torch):
     print(f"# determinant space: rdm12 {t_12:.2f} s, rdm3(c, Vc) {t_3:.2f} s", file=sys.stderr, flush=True)
     res["oracle_beside"] = oracle_beside(pk, torch)
     del sol
+    # mutual information and order from the MPS itself at the bench active space (M = 256)
+    h20, B20, e20 = synth.make_hamiltonian(N_ORB, N_CHOL, SEED)
+    s20 = pk.Solver(pk.Problem(h20, B20, N_ORB // 2, N_ORB // 2, e20), M=256, tol=1e-7)
+    s20.sweep(2)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    rho, s1, I = s20.orbital_entanglement()
+    order, _ = pk.fiedler_order(I)
+    t_mi = time.time() - t0
+    res["ordering_cas20_m256"] = {"orbital_entanglement_s": t_mi, "order": [int(x) for x in order],
+                                  "s1_max": float(s1.max()), "I_max": float(I.max()),
+                                  "trace_error": float(np.abs(np.trace(rho, axis1=1, axis2=2) - 1).max())}
+    print(f"# ordering at CAS(20,20) M=256: {t_mi:.2f} s", file=sys.stderr, flush=True)
+    del s20
     h8, B8, e8 = synth.make_hamiltonian(8, 32, 0)
     st = pk.Solver(pk.Problem(h8, B8, 4, 4, e8), M=24, tol=1e-11)
     e2 = st.sweep(6)[0][0]

@@ -362,6 +362,15 @@ dmrg_status dmrg_orbital_rdm2(const dmrg_problem* p, const double* c, double* rh
  * density matrices) and mutual information I[n*n] = (s_i + s_j - s_ij) / 2
  * (zero diagonal), host outputs. */
 dmrg_status dmrg_mutual_information(const dmrg_problem* p, const double* c, double* s1, double* I, void* stream);
+/* The same density matrices and mutual information straight from the solver's
+ * MPS (root 0, as stored, any active-space size the solver holds): every
+ * element is the derivative of <Psi|O|Psi> by one closing entry of an MPO whose
+ * channels open |t><s| on orbital i, carry the Jordan-Wigner parity across the
+ * orbitals between, and close with |t_j><s_j| on orbital j, evaluated by the
+ * per-site contractions of dmrg_grad; the MPO's environments hold 16 channels
+ * per orbital to the left of each cut.  rho: host [n(n-1)/2][16][16], s1 / I as
+ * dmrg_mutual_information; each may be NULL (s1 and I together). */
+dmrg_status dmrg_mps_orbital_rdm2(dmrg_solver* s, double* rho, double* s1, double* I);
 /* Orbital order from a mutual-information matrix (host only, 2..64 orbitals):
  * the eigenvector of the second-smallest eigenvalue of diag(sum_j I_ij) - I,
  * sign fixed so that its largest-magnitude component (first such) is

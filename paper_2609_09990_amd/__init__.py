@@ -51,6 +51,7 @@ from ._lib import (  # noqa: F401
     dmrg_ci_rdm3,
     dmrg_correction,
     dmrg_fiedler_order,
+    dmrg_mps_orbital_rdm2,
     dmrg_mps_to_ci,
     dmrg_mutual_information,
     dmrg_orbital_rdm2,

@@ -88,6 +88,7 @@ dmrg_ci_apply_v = _decl("dmrg_ci_apply_v", [_p, _p, _p, _p])
 dmrg_ci_rdm3 = _decl("dmrg_ci_rdm3", [_p, _p, _p, _p, _p])
 dmrg_mutual_information = _decl("dmrg_mutual_information", [_p, _p, _p, _p, _p])
 dmrg_fiedler_order = _decl("dmrg_fiedler_order", [_i, _p, _p, _p])
+dmrg_mps_orbital_rdm2 = _decl("dmrg_mps_orbital_rdm2", [_p, _p, _p, _p])
 dmrg_ci_dims = _decl("dmrg_ci_dims", [_p, _p, _p])
 dmrg_mps_to_ci = _decl("dmrg_mps_to_ci", [_p, _i, _p, _i64])
 dmrg_ci_rdm12 = _decl("dmrg_ci_rdm12", [_p, _p, _p, _p, _p, _p, _p])
@@ -507,6 +508,14 @@ class Solver:
         g, G, o = np.zeros((n, n)), np.zeros((n, n, n, n)), C.c_double()
         self._grow(lambda: _check(dmrg_rdm12(self.h, bra, ket, _ptr(g), _ptr(G), C.byref(o))))
         return g, G, o.value
+
+    def orbital_entanglement(self):
+        """(two-orbital density matrices [n(n-1)/2, 16, 16], s1[n], I[n, n]) of the
+        MPS as stored, from the MPS itself (no CI vector)."""
+        n = self.problem.n
+        rho, s1, I = np.zeros((n * (n - 1) // 2, 16, 16)), np.zeros(n), np.zeros((n, n))
+        self._grow(lambda: _check(dmrg_mps_orbital_rdm2(self.h, _ptr(rho), _ptr(s1), _ptr(I))))
+        return rho, s1, I
 
     def deflate_project(self, k, j, out):
         """Projection of lower state j into step k's two-site space (device out)."""

@@ -482,6 +482,15 @@ dmrg_status dmrg_mutual_information(const dmrg_problem* p, const double* c, doub
   });
 }
 
+dmrg_status dmrg_mps_orbital_rdm2(dmrg_solver* s, double* rho, double* s1, double* I) {
+  return solver_call(s, [&] {
+    DMRG_REQUIRE(s, ST_EINVAL, "NULL argument");
+    const std::vector<double> r = s->s->pair_rdm_mps();
+    if (rho) std::copy(r.begin(), r.end(), rho);
+    if (s1 && I) mutual_information_of(s->prob->p.n, r, s1, I);
+  });
+}
+
 dmrg_status dmrg_fiedler_order(int n, const double* I, int* order, double* fiedler) {
   return guard([&] {
     DMRG_REQUIRE(I && order, ST_EINVAL, "NULL argument");

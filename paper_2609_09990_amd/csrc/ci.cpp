@@ -345,6 +345,10 @@ void orbital_rdm2(int n, int na, int nb, hipStream_t st, const double* c, std::v
 void mutual_information(int n, int na, int nb, hipStream_t st, const double* c, double* s1, double* I) {
   std::vector<double> rho;
   orbital_rdm2(n, na, nb, st, c, rho);
+  mutual_information_of(n, rho, s1, I);
+}
+
+void mutual_information_of(int n, const std::vector<double>& rho, double* s1, double* I) {
   std::vector<double> s2((size_t)n * n, 0.0);
   std::vector<double> one(n, -1.0);
   int p = 0;

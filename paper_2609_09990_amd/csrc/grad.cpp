@@ -305,4 +305,41 @@ void Solver::grad(const std::vector<double>& w, std::vector<double>& dh, std::ve
   st_.grad_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
+// Two-orbital density matrices of the stored MPS (root 0), every pair i < j, in
+// the determinant convention of the CI route (local creators moved to the front
+// in the order i alpha, j alpha, i beta, j beta): each element is the
+// derivative of <Psi|O|Psi> by one closing entry of the pair MPO (the same
+// per-site contractions as the integral gradient), over <Psi|Psi>.  The MPO
+// gives them with the site creators in chain order (i alpha, i beta, j alpha,
+// j beta); reordering to the determinant convention flips the sign of a local
+// state holding beta on i and alpha on j.
+std::vector<double> Solver::pair_rdm_mps() {
+  materialize();
+  Problem p2;
+  p2.n = L_;
+  p2.n_alpha = prob_->n_alpha;
+  p2.n_beta = prob_->n_beta;
+  std::vector<PairClosing> closings;
+  p2.mpo = build_pair_mpo(L_, closings);
+  Options o;
+  o.M = 1;
+  Solver s2(&p2, o, st);
+  s2.adopt_mps(*this);
+  s2.centers_.clear();  // the MPS as stored
+  std::vector<std::vector<double>> gs(L_);
+  double norm = 0.0;
+  for (int k = 0; k < L_; ++k) s2.grad_site(k, gs[k], k == 0 ? &norm : nullptr);
+  DMRG_REQUIRE(norm > 0.0 && std::isfinite(norm), ST_ESTATE, "MPS has zero norm");
+  const int np = L_ * (L_ - 1) / 2;
+  std::vector<double> rho((size_t)np * 256, 0.0);
+  auto pair_index = [&](int i, int j) { return i * L_ - i * (i + 1) / 2 + (j - i - 1); };
+  auto tau = [](int ti, int tj) { return ((ti & 2) && (tj & 1)) ? -1.0 : 1.0; };
+  for (const PairClosing& c : closings) {
+    const int Lb = c.t + 4 * c.tj, Lk = c.s + 4 * c.sj;
+    rho[(size_t)pair_index(c.i, c.j) * 256 + Lb * 16 + Lk] =
+        tau(c.t, c.tj) * tau(c.s, c.sj) * gs[c.j][c.entry] / norm;
+  }
+  return rho;
+}
+
 }  // namespace dmrg

@@ -477,4 +477,84 @@ MPO build_spin_mpo(int L) {
   return m;
 }
 
+MPO build_pair_mpo(int L, std::vector<PairClosing>& closings) {
+  DMRG_REQUIRE(L >= 2 && L <= 64, ST_EINVAL, "n_orb must be in [2, 64]");
+  MPO m;
+  m.L = L;
+  m.nq = 0;
+  m.cmid = L / 2;
+  // ops: 0 identity, 1 parity, 2 + 4 t + s: |t><s|
+  Mat4 id{}, par{};
+  for (int u = 0; u < 4; ++u) {
+    id[u * 4 + u] = 1.0;
+    par[u * 4 + u] = (u == 1 || u == 2) ? -1.0 : 1.0;
+  }
+  m.ops = {id, par};
+  for (int t = 0; t < 4; ++t)
+    for (int s = 0; s < 4; ++s) {
+      Mat4 o{};
+      o[t * 4 + s] = 1.0;
+      m.ops.push_back(o);
+    }
+  auto odd = [](int t, int s) { return (__builtin_popcount(t) + __builtin_popcount(s)) & 1; };
+  // channels per cut, sorted by (dq, key): I (cuts 0..L-1), H (cuts 1..L), and
+  // (i, t, s) for i < c <= L-1
+  const uint64_t kI = key0(CK_I), kH = key0(CK_H);
+  auto kO = [](int i, int t, int s) { return ((uint64_t)CK_N1 << 56) | ((uint64_t)i << 8) | (uint64_t)(4 * t + s); };
+  m.chans.resize(L + 1);
+  m.chan_I.assign(L + 1, -1);
+  m.chan_H.assign(L + 1, -1);
+  std::vector<std::map<uint64_t, int>> idx(L + 1);
+  for (int c = 0; c <= L; ++c) {
+    std::vector<std::pair<std::pair<QN, uint64_t>, int>> live;  // ((dq, key), kind)
+    if (c < L) live.push_back({{QN{0, 0}, kI}, CK_I});
+    if (c > 0) live.push_back({{QN{0, 0}, kH}, CK_H});
+    if (c < L)
+      for (int i = 0; i < c; ++i)
+        for (int t = 0; t < 4; ++t)
+          for (int s = 0; s < 4; ++s) live.push_back({{site_qn(t) - site_qn(s), kO(i, t, s)}, CK_N1});
+    std::sort(live.begin(), live.end(), [](const auto& x, const auto& y) {
+      if (x.first.first != y.first.first) return x.first.first < y.first.first;
+      return x.first.second < y.first.second;
+    });
+    for (size_t j = 0; j < live.size(); ++j) {
+      idx[c][live[j].first.second] = (int)j;
+      m.chans[c].push_back({live[j].first.second, live[j].second, live[j].first.first});
+      if (live[j].second == CK_I) m.chan_I[c] = (int)j;
+      if (live[j].second == CK_H) m.chan_H[c] = (int)j;
+    }
+  }
+  m.W.resize(L);
+  m.prov.resize(L);
+  closings.clear();
+  for (int k = 0; k < L; ++k) {
+    auto at = [&](int c, uint64_t key) {
+      auto it = idx[c].find(key);
+      return it == idx[c].end() ? -1 : it->second;
+    };
+    auto add = [&](int a, int b, double c, int op) {
+      if (a >= 0 && b >= 0) m.W[k].push_back({a, b, c, op});
+    };
+    add(at(k, kI), at(k + 1, kI), 1.0, 0);
+    if (k == 0) add(at(0, kI), at(1, kH), 0.0, 0);  // keeps H at cut 1 (the norm's right channel)
+    for (int t = 0; t < 4; ++t)
+      for (int s = 0; s < 4; ++s) add(at(k, kI), at(k + 1, kO(k, t, s)), 1.0, 2 + 4 * t + s);
+    for (int i = 0; i < k; ++i)
+      for (int t = 0; t < 4; ++t)
+        for (int s = 0; s < 4; ++s) {
+          const int a = at(k, kO(i, t, s));
+          add(a, at(k + 1, kO(i, t, s)), 1.0, odd(t, s) ? 1 : 0);
+          const QN d = site_qn(s) - site_qn(t);  // what the closing operator must change
+          for (int tj = 0; tj < 4; ++tj)
+            for (int sj = 0; sj < 4; ++sj) {
+              if (site_qn(tj) - site_qn(sj) != d) continue;
+              closings.push_back({k, (int)m.W[k].size(), i, t, s, tj, sj});
+              add(a, at(k + 1, kH), 1.0, 2 + 4 * tj + sj);
+            }
+        }
+    if (k > 0) add(at(k, kH), at(k + 1, kH), 1.0, 0);
+  }
+  return m;
+}
+
 }  // namespace dmrg

@@ -73,4 +73,17 @@ MPO build_mpo(int L, int nq, const double* h, const double* B);
 // even, so no Jordan-Wigner strings cross sites.  Host only.
 MPO build_spin_mpo(int L);
 
+// MPO whose entries carry the two-orbital operators of every pair i < j:
+// channel (i, t, s) opens at site i with |t><s| and runs through the sites
+// between with the identity (|t><s| even) or the parity diag(1, -1, -1, 1) (odd:
+// the Jordan-Wigner string), and closes at site j with every |t_j><s_j| that
+// conserves N and S_z.  Each closing entry belongs to one term, so the
+// derivative of <Psi|O|Psi> by its coefficient is the expectation value
+// <(|t><s|)_i P (|t_j><s_j|)_j>.  `closings` lists them: (site j, entry index
+// in W[j], i, t, s, t_j, s_j).  Host only.
+struct PairClosing {
+  int j, entry, i, t, s, tj, sj;
+};
+MPO build_pair_mpo(int L, std::vector<PairClosing>& closings);
+
 }  // namespace dmrg

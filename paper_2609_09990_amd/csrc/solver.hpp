@@ -367,6 +367,9 @@ class Solver {
   // CI vector (row-major c[I_a][I_b], colex strings) of this MPS (state 0) or of
   // held state `state` (1..n_deflated), as stored
   void mps_to_ci(int state, double* c);
+  // two-orbital density matrices of the stored MPS for every pair i < j (host
+  // [pair][16][16], determinant convention, trace 1)
+  std::vector<double> pair_rdm_mps();
   int correction_host_theta(int k, int mode, const double* x, const double* r, const double* d, double theta,
                             double* t);
   void features_host_theta(int k, const double* r, const double* d, double theta, float* X);
@@ -545,6 +548,7 @@ long ci_dimension(int n, int na, int nb);
 // of orbitals by the Fiedler vector of I's graph Laplacian (host only).
 void orbital_rdm2(int n, int na, int nb, hipStream_t st, const double* c, std::vector<double>& rho);
 void mutual_information(int n, int na, int nb, hipStream_t st, const double* c, double* s1, double* I);
+void mutual_information_of(int n, const std::vector<double>& rho, double* s1, double* I);
 void fiedler_order(int n, const double* I, int* order, double* fiedler);
 // V c for the all-active two-electron operator V = 1/2 sum (pq|rs) E_pq E_rs,
 // streamed through the Cholesky factors Bh (host, nq x n x n); and the
