@@ -305,7 +305,9 @@ dmrg_status dmrg_s_squared(dmrg_solver* s, double* s2);
  * ascending orbital order, all alpha first; strings are ranked
  * colexicographically (rank = sum_t C(o_t, t+1) over sorted occupied orbitals);
  * a CI vector is the row-major matrix c[I_a][I_b], I_a < C(n, n_alpha),
- * I_b < C(n, n_beta).  Device memory is the caller's unless said otherwise. */
+ * I_b < C(n, n_beta).  Device memory is the caller's unless said otherwise; every call that takes
+ * device CI vectors takes their length n, which must be C(n_orb,n_alpha) C(n_orb,n_beta)
+ * (DMRG_EINVAL otherwise). */
 /* String counts C(n_orb, n_alpha) and C(n_orb, n_beta).  Host only. */
 dmrg_status dmrg_ci_dims(const dmrg_problem* p, int64_t* n_alpha_strings, int64_t* n_beta_strings);
 /* The CI vector of an MPS, as stored (no normalisation): state 0 = the
@@ -325,7 +327,7 @@ dmrg_status dmrg_mps_to_ci(dmrg_solver* s, int state, double* c, int64_t n);
  * kernel over string-excitation tables), then one fp64 MFMA product of
  * (n^2 + 1) x (n^2 + 1) over the determinants; runs on `stream` and returns
  * when the outputs are written. */
-dmrg_status dmrg_ci_rdm12(const dmrg_problem* p, const double* bra, const double* ket, double* gamma, double* Gamma,
+dmrg_status dmrg_ci_rdm12(const dmrg_problem* p, int64_t n, const double* bra, const double* ket, double* gamma, double* Gamma,
                           double* overlap, void* stream);
 /* The all-active two-electron operator on a device CI vector (the fused
  * four-particle contraction of Sec. III: the two-electron block is contracted
@@ -335,14 +337,15 @@ dmrg_status dmrg_ci_rdm12(const dmrg_problem* p, const double* bra, const double
  * streamed through the problem's Cholesky factors (E_rs c for all rs, two
  * GEMMs over the factors, one gather sum); out: device, same length as c, not
  * aliasing it.  At most 16 orbitals. */
-dmrg_status dmrg_ci_apply_v(const dmrg_problem* p, const double* c, double* out, void* stream);
+dmrg_status dmrg_ci_apply_v(const dmrg_problem* p, int64_t n, const double* c, double* out, void* stream);
 /* Transition three-body density of device CI vectors (unnormalised):
  *   Gamma3[((((p*n+q)*n+r)*n+s)*n+t)*n+u] = <bra|E_pq E_rs E_tu|ket>
  * (host, n^6 doubles).  E_tu ket is kept for all tu, E_rs of each is formed in
  * passes of determinants and the fp64 MFMA split-K product with the bra's
  * copies accumulates the density.  At most 12 orbitals.  With ket = V c
  * (dmrg_ci_apply_v) it gives sum_vwxy (vw|xy)/2 <bra|E_pq E_rs E_tu E_vw E_xy|c>. */
-dmrg_status dmrg_ci_rdm3(const dmrg_problem* p, const double* bra, const double* ket, double* Gamma3, void* stream);
+dmrg_status dmrg_ci_rdm3(const dmrg_problem* p, int64_t n, const double* bra, const double* ket, double* Gamma3,
+                         void* stream);
 /* The same for MPS states (numbering as dmrg_mps_to_ci), each normalised:
  * gamma, Gamma and overlap of <bra|.|ket> / (|bra| |ket|). */
 dmrg_status dmrg_rdm12(dmrg_solver* s, int bra_state, int ket_state, double* gamma, double* Gamma, double* overlap);
@@ -357,11 +360,12 @@ dmrg_status dmrg_rdm12(dmrg_solver* s, int bra_state, int ket_state, double* gam
  * rho: host [n(n-1)/2][16][16].  Computed by one kernel over determinants and
  * pairs (each environment of a pair taken once, <= 4 amplitudes, fixed-order
  * sums). */
-dmrg_status dmrg_orbital_rdm2(const dmrg_problem* p, const double* c, double* rho, void* stream);
+dmrg_status dmrg_orbital_rdm2(const dmrg_problem* p, int64_t n, const double* c, double* rho, void* stream);
 /* One-orbital entropies s1[n] (natural log, from the diagonal one-orbital
  * density matrices) and mutual information I[n*n] = (s_i + s_j - s_ij) / 2
  * (zero diagonal), host outputs. */
-dmrg_status dmrg_mutual_information(const dmrg_problem* p, const double* c, double* s1, double* I, void* stream);
+dmrg_status dmrg_mutual_information(const dmrg_problem* p, int64_t n, const double* c, double* s1, double* I,
+                                    void* stream);
 /* The same density matrices and mutual information straight from the solver's
  * MPS (root 0, as stored, any active-space size the solver holds): every
  * element is the derivative of <Psi|O|Psi> by one closing entry of an MPO whose
@@ -450,11 +454,13 @@ dmrg_status dmrg_record_triples(dmrg_solver* s, int capacity, int sample);
  * target[cap][sample] (fp32), writes the count and empties the store. */
 dmrg_status dmrg_take_triples(dmrg_solver* s, float* X, float* target, int cap, int* count);
 /* The 8 features (device X[n][8], fp32) of the two-site step k for device
- * vectors r (residual) and d (diagonal of H_eff) and eigenvalue estimate theta. */
-dmrg_status dmrg_precond_features(dmrg_solver* s, int k, const double* r, const double* d, double theta,
+ * vectors r (residual) and d (diagonal of H_eff) and eigenvalue estimate theta;
+ * n must be the step's two-site length (DMRG_EINVAL otherwise). */
+dmrg_status dmrg_precond_features(dmrg_solver* s, int k, int64_t n, const double* r, const double* d, double theta,
                                   float* X);
 /* One correction vector of the preconditioner family (Sec. III) at two-site step
- * k, as a Davidson iteration forms it: device vectors of the step's length n,
+ * k, as a Davidson iteration forms it: device vectors of the step's length n
+ * (checked: DMRG_EINVAL otherwise),
  * x the Ritz vector (unit norm), r = H_eff x - theta x its residual, d the
  * diagonal of H_eff (dmrg_diag); t (device, n, caller-owned) receives
  * DMRG_PRECOND_DIAG: (theta - d)^-1 r (each |theta - d_i| floored at 1e-8),
@@ -463,7 +469,7 @@ dmrg_status dmrg_precond_features(dmrg_solver* s, int k, const double* r, const 
  * step's H_eff in fp64 (without deflation penalties; the solver's pcg_steps and
  * pcg_rtol); *products (may be NULL)
  * receives the sigma products it made.  DMRG_PRECOND_LEARNED is rejected. */
-dmrg_status dmrg_correction(dmrg_solver* s, int k, int mode, const double* x, const double* r, const double* d,
+dmrg_status dmrg_correction(dmrg_solver* s, int k, int mode, int64_t n, const double* x, const double* r, const double* d,
                             double theta, double* t, int* products);
 
 /* Diagnostic export of an environment of the current MPS: side 0 = left block

@@ -80,18 +80,18 @@ dmrg_set_precond = _decl("dmrg_set_precond", [_p, _i, _p])
 dmrg_set_precision = _decl("dmrg_set_precision", [_p, _i])
 dmrg_record_triples = _decl("dmrg_record_triples", [_p, _i, _i])
 dmrg_take_triples = _decl("dmrg_take_triples", [_p, _p, _p, _i, C.POINTER(_i)])
-dmrg_precond_features = _decl("dmrg_precond_features", [_p, _i, _p, _p, _d, _p])
-dmrg_correction = _decl("dmrg_correction", [_p, _i, _i, _p, _p, _p, _d, _p, _p])
+dmrg_precond_features = _decl("dmrg_precond_features", [_p, _i, _i64, _p, _p, _d, _p])
+dmrg_correction = _decl("dmrg_correction", [_p, _i, _i, _i64, _p, _p, _p, _d, _p, _p])
 dmrg_stationarize = _decl("dmrg_stationarize", [_p, _i, _p, _p])
-dmrg_orbital_rdm2 = _decl("dmrg_orbital_rdm2", [_p, _p, _p, _p])
-dmrg_ci_apply_v = _decl("dmrg_ci_apply_v", [_p, _p, _p, _p])
-dmrg_ci_rdm3 = _decl("dmrg_ci_rdm3", [_p, _p, _p, _p, _p])
-dmrg_mutual_information = _decl("dmrg_mutual_information", [_p, _p, _p, _p, _p])
+dmrg_orbital_rdm2 = _decl("dmrg_orbital_rdm2", [_p, _i64, _p, _p, _p])
+dmrg_ci_apply_v = _decl("dmrg_ci_apply_v", [_p, _i64, _p, _p, _p])
+dmrg_ci_rdm3 = _decl("dmrg_ci_rdm3", [_p, _i64, _p, _p, _p, _p])
+dmrg_mutual_information = _decl("dmrg_mutual_information", [_p, _i64, _p, _p, _p, _p])
 dmrg_fiedler_order = _decl("dmrg_fiedler_order", [_i, _p, _p, _p])
 dmrg_mps_orbital_rdm2 = _decl("dmrg_mps_orbital_rdm2", [_p, _p, _p, _p])
 dmrg_ci_dims = _decl("dmrg_ci_dims", [_p, _p, _p])
 dmrg_mps_to_ci = _decl("dmrg_mps_to_ci", [_p, _i, _p, _i64])
-dmrg_ci_rdm12 = _decl("dmrg_ci_rdm12", [_p, _p, _p, _p, _p, _p, _p])
+dmrg_ci_rdm12 = _decl("dmrg_ci_rdm12", [_p, _i64, _p, _p, _p, _p, _p, _p])
 dmrg_rdm12 = _decl("dmrg_rdm12", [_p, _i, _i, _p, _p, _p])
 dmrg_last_error = _decl("dmrg_last_error", [], C.c_char_p)
 
@@ -153,7 +153,7 @@ class Problem:
             stream = torch.cuda.current_stream().cuda_stream
         n = self.n
         g, G, o = np.zeros((n, n)), np.zeros((n, n, n, n)), C.c_double()
-        _check(dmrg_ci_rdm12(self.h, _ptr(bra), _ptr(ket), _ptr(g), _ptr(G), C.byref(o), stream))
+        _check(dmrg_ci_rdm12(self.h, na * nb, _ptr(bra), _ptr(ket), _ptr(g), _ptr(G), C.byref(o), stream))
         return g, G, o.value
 
     def ci_apply_v(self, c, out=None, stream=None):
@@ -165,7 +165,7 @@ class Problem:
         Solver._dev_f64(out, "out", na * nb)
         if stream is None and torch is not None:
             stream = torch.cuda.current_stream().cuda_stream
-        _check(dmrg_ci_apply_v(self.h, _ptr(c), _ptr(out), stream))
+        _check(dmrg_ci_apply_v(self.h, na * nb, _ptr(c), _ptr(out), stream))
         return out
 
     def ci_rdm3(self, bra, ket=None, stream=None):
@@ -178,7 +178,7 @@ class Problem:
             stream = torch.cuda.current_stream().cuda_stream
         n = self.n
         out = np.zeros((n,) * 6)
-        _check(dmrg_ci_rdm3(self.h, _ptr(bra), _ptr(ket), _ptr(out), stream))
+        _check(dmrg_ci_rdm3(self.h, na * nb, _ptr(bra), _ptr(ket), _ptr(out), stream))
         return out
 
     def orbital_rdm2(self, c, stream=None):
@@ -189,7 +189,7 @@ class Problem:
             stream = torch.cuda.current_stream().cuda_stream
         n = self.n
         rho = np.zeros((n * (n - 1) // 2, 16, 16))
-        _check(dmrg_orbital_rdm2(self.h, _ptr(c), _ptr(rho), stream))
+        _check(dmrg_orbital_rdm2(self.h, na * nb, _ptr(c), _ptr(rho), stream))
         return rho
 
     def mutual_information(self, c, stream=None):
@@ -200,7 +200,7 @@ class Problem:
             stream = torch.cuda.current_stream().cuda_stream
         n = self.n
         s1, I = np.zeros(n), np.zeros((n, n))
-        _check(dmrg_mutual_information(self.h, _ptr(c), _ptr(s1), _ptr(I), stream))
+        _check(dmrg_mutual_information(self.h, na * nb, _ptr(c), _ptr(s1), _ptr(I), stream))
         return s1, I
 
     def mpo_site(self, k):
@@ -462,13 +462,21 @@ class Solver:
         return cnt.value
 
     def features(self, k, r, d, theta, X):
-        _check(dmrg_precond_features(self.h, k, _ptr(r), _ptr(d), float(theta), _ptr(X)))
+        self._dev_f64(r, "r")
+        self._dev_f64(d, "d", r.numel())
+        if not (X.is_cuda and X.dtype == torch.float32 and X.is_contiguous() and X.numel() == 8 * r.numel()):
+            raise TypeError("X must be a contiguous float32 CUDA tensor of 8 n elements")
+        _check(dmrg_precond_features(self.h, k, r.numel(), _ptr(r), _ptr(d), float(theta), _ptr(X)))
 
     def correction(self, k, mode, x, r, d, theta, t):
         """One correction of the preconditioner family into device t; returns the
         sigma products it made."""
+        self._dev_f64(x, "x")
+        for v, name in ((r, "r"), (d, "d"), (t, "t")):
+            self._dev_f64(v, name, x.numel())
         mv = C.c_int()
-        _check(dmrg_correction(self.h, k, mode, _ptr(x), _ptr(r), _ptr(d), float(theta), _ptr(t), C.byref(mv)))
+        _check(dmrg_correction(self.h, k, mode, x.numel(), _ptr(x), _ptr(r), _ptr(d), float(theta), _ptr(t),
+                               C.byref(mv)))
         return mv.value
 
     def set_kernel_tag(self, tag):

@@ -443,41 +443,54 @@ dmrg_status dmrg_mps_to_ci(dmrg_solver* s, int state, double* c, int64_t n) {
   });
 }
 
-dmrg_status dmrg_ci_rdm12(const dmrg_problem* p, const double* bra, const double* ket, double* gamma, double* Gamma,
-                          double* overlap, void* stream) {
+static void require_ci_length(const dmrg_problem* p, int64_t n) {
+  const long len = ci_dimension(p->p.n, p->p.n_alpha, p->p.n_beta);
+  DMRG_REQUIRE(n == len, ST_EINVAL, "vector length " + std::to_string(n) + " is not the CI dimension " +
+                                        std::to_string(len));
+}
+
+dmrg_status dmrg_ci_rdm12(const dmrg_problem* p, int64_t n, const double* bra, const double* ket, double* gamma,
+                          double* Gamma, double* overlap, void* stream) {
   return guard([&] {
     DMRG_REQUIRE(p && bra && ket, ST_EINVAL, "NULL argument");
+    require_ci_length(p, n);
     ci_rdm12(p->p.n, p->p.n_alpha, p->p.n_beta, (hipStream_t)stream, bra, ket, 1.0, gamma, Gamma, overlap);
   });
 }
 
-dmrg_status dmrg_ci_apply_v(const dmrg_problem* p, const double* c, double* out, void* stream) {
+dmrg_status dmrg_ci_apply_v(const dmrg_problem* p, int64_t n, const double* c, double* out, void* stream) {
   return guard([&] {
     DMRG_REQUIRE(p && c && out, ST_EINVAL, "NULL argument");
+    require_ci_length(p, n);
     DMRG_REQUIRE(c != out, ST_EINVAL, "out must not alias c");
     ci_apply_v(p->p.n, p->p.n_alpha, p->p.n_beta, p->p.nq, p->p.B.data(), (hipStream_t)stream, c, out);
   });
 }
 
-dmrg_status dmrg_ci_rdm3(const dmrg_problem* p, const double* bra, const double* ket, double* Gamma3, void* stream) {
+dmrg_status dmrg_ci_rdm3(const dmrg_problem* p, int64_t n, const double* bra, const double* ket, double* Gamma3,
+                         void* stream) {
   return guard([&] {
     DMRG_REQUIRE(p && bra && ket && Gamma3, ST_EINVAL, "NULL argument");
+    require_ci_length(p, n);
     ci_rdm3(p->p.n, p->p.n_alpha, p->p.n_beta, (hipStream_t)stream, bra, ket, 1.0, Gamma3);
   });
 }
 
-dmrg_status dmrg_orbital_rdm2(const dmrg_problem* p, const double* c, double* rho, void* stream) {
+dmrg_status dmrg_orbital_rdm2(const dmrg_problem* p, int64_t n, const double* c, double* rho, void* stream) {
   return guard([&] {
     DMRG_REQUIRE(p && c && rho, ST_EINVAL, "NULL argument");
+    require_ci_length(p, n);
     std::vector<double> r;
     orbital_rdm2(p->p.n, p->p.n_alpha, p->p.n_beta, (hipStream_t)stream, c, r);
     std::copy(r.begin(), r.end(), rho);
   });
 }
 
-dmrg_status dmrg_mutual_information(const dmrg_problem* p, const double* c, double* s1, double* I, void* stream) {
+dmrg_status dmrg_mutual_information(const dmrg_problem* p, int64_t n, const double* c, double* s1, double* I,
+                                    void* stream) {
   return guard([&] {
     DMRG_REQUIRE(p && c && s1 && I, ST_EINVAL, "NULL argument");
+    require_ci_length(p, n);
     mutual_information(p->p.n, p->p.n_alpha, p->p.n_beta, (hipStream_t)stream, c, s1, I);
   });
 }
@@ -646,20 +659,22 @@ dmrg_status dmrg_take_triples(dmrg_solver* s, float* X, float* target, int cap, 
   });
 }
 
-dmrg_status dmrg_precond_features(dmrg_solver* s, int k, const double* r, const double* d, double theta,
+dmrg_status dmrg_precond_features(dmrg_solver* s, int k, int64_t n, const double* r, const double* d, double theta,
                                   float* X) {
   return solver_call(s, [&] {
     DMRG_REQUIRE(s && r && d && X, ST_EINVAL, "NULL argument");
     DMRG_REQUIRE(k >= 0 && k + 1 < s->prob->p.n, ST_EINVAL, "two-site step out of range");
+    DMRG_REQUIRE(n == s->s->twosite_size(k), ST_EINVAL, "vector length is not the two-site length");
     s->s->features_host_theta(k, r, d, theta, X);
   });
 }
 
-dmrg_status dmrg_correction(dmrg_solver* s, int k, int mode, const double* x, const double* r, const double* d,
-                            double theta, double* t, int* products) {
+dmrg_status dmrg_correction(dmrg_solver* s, int k, int mode, int64_t n, const double* x, const double* r,
+                            const double* d, double theta, double* t, int* products) {
   return solver_call(s, [&] {
     DMRG_REQUIRE(s && x && r && d && t, ST_EINVAL, "NULL argument");
     DMRG_REQUIRE(k >= 0 && k + 1 < s->prob->p.n, ST_EINVAL, "two-site step out of range");
+    DMRG_REQUIRE(n == s->s->twosite_size(k), ST_EINVAL, "vector length is not the two-site length");
     DMRG_REQUIRE(mode == DMRG_PRECOND_DIAG || mode == DMRG_PRECOND_OLSEN || mode == DMRG_PRECOND_SHIFT_INVERT,
                  ST_EINVAL, "mode must be DIAG, OLSEN or SHIFT_INVERT");
     int mv = s->s->correction_host_theta(k, mode, x, r, d, theta, t);

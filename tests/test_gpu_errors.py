@@ -68,3 +68,32 @@ def test_excited_state_gradient_needs_centre_tensors():
     assert e.value.code == -6
     dh, dB, en = sol.grad(np.array([1.0, 0.0]))
     assert np.isfinite(dh).all() and abs(np.trace(dh) - 6.0) < 1e-10
+
+
+def test_device_vector_lengths_are_checked():
+    """Entry points that take device vectors check their length on the host
+    (a wrong length is DMRG_EINVAL, nothing is launched): the CI calls against
+    the CI dimension, the correction call against the two-site length."""
+    import ctypes as C
+
+    import torch
+    pk = _pk()
+    from paper_2609_09990_amd import _lib
+    sol = _solver(pk, M=16)
+    prob = sol.problem
+    na, nb = prob.ci_dims()
+    c = torch.zeros(na * nb + 1, dtype=torch.float64, device="cuda")
+    g, G, o = np.zeros((6, 6)), np.zeros((6,) * 4), C.c_double()
+    stream = torch.cuda.current_stream().cuda_stream
+    assert _lib.dmrg_ci_rdm12(prob.h, na * nb + 1, _lib._ptr(c), _lib._ptr(c), _lib._ptr(g), _lib._ptr(G),
+                              C.byref(o), stream) == -1
+    assert _lib.dmrg_ci_apply_v(prob.h, na * nb - 1, _lib._ptr(c), _lib._ptr(c[1:]), stream) == -1
+    with pytest.raises(ValueError):
+        prob.ci_rdm12(c)  # the binding refuses the tensor before the call
+    n = sol.prepare(2)
+    x = torch.zeros(n + 3, dtype=torch.float64, device="cuda")
+    mv = C.c_int()
+    assert _lib.dmrg_correction(sol.h, 2, 0, n + 3, _lib._ptr(x), _lib._ptr(x), _lib._ptr(x), 0.0, _lib._ptr(x),
+                                C.byref(mv)) == -1
+    e, tau, ok = sol.sweep(1)  # still usable
+    assert np.isfinite(e[0])
