@@ -565,6 +565,12 @@ class Solver:
                          _ptr(dB) if p.n_chol > 0 else None, _ptr(e)))
         return dh, dB, e
 
+    def rdm1(self):
+        """The spin-summed 1-RDM gamma_pq = <E_pq> of the MPS as stored (root 0),
+        from the MPS itself at any size: it is dE/dh of dmrg_grad."""
+        dh, _, _ = self.grad()
+        return dh
+
     def stats(self):
         s = np.zeros(30)
         _check(dmrg_get_stats(self.h, _ptr(s), 30))

@@ -211,3 +211,27 @@ def test_fused_four_body_contraction_cas8():
     for x, r in zip(picks, ref):
         assert abs(F[x] - r) <= 1e-11 * scale, x
     assert abs(np.einsum("pprrtt->", F) - 8 ** 3 * float(np.sum(ch * vref))) <= 1e-10 * abs(8 ** 3 * np.sum(ch * vref))
+
+
+def test_mps_rdm1_from_the_gradient_at_any_size():
+    """gamma = dE/dh (dmrg_grad) is the 1-RDM of the MPS at any size: equal to
+    the CI route at CAS(10,10) after two sweeps at M = 64, and at CAS(16,16)
+    M = 128 (no CI vector) symmetric with trace N and natural occupations in
+    [0, 2]."""
+    _torch()
+    import paper_2609_09990_amd as pk
+    h, B, e0 = synth.make_hamiltonian(10, 16, 2)
+    prob = pk.Problem(h, B, 5, 5, e0)
+    sol = pk.Solver(prob, M=64, tol=1e-8)
+    sol.sweep(2)
+    g_mps = sol.rdm1()
+    g_ci, _, _ = sol.rdm12()
+    assert np.abs(g_mps - g_ci).max() <= 1e-11
+    h, B, e0 = synth.make_hamiltonian(16, 32, 1)
+    sol = pk.Solver(pk.Problem(h, B, 8, 8, e0), M=128, tol=1e-7)
+    sol.sweep(2)
+    g = sol.rdm1()
+    w = np.linalg.eigvalsh(0.5 * (g + g.T))
+    print(f"CAS(16,16) natural occupations {w.min():.4f} .. {w.max():.4f}", flush=True)
+    assert np.abs(g - g.T).max() <= 1e-10 and abs(np.trace(g) - 16) <= 1e-9
+    assert w.min() >= -1e-10 and w.max() <= 2 + 1e-10
