@@ -592,55 +592,18 @@ void ci_rdm12(int n, int na, int nb, hipStream_t st, const double* bra, const do
   const long per_pass = std::max<long>(1, (512L << 20) / ((long)rows * CL * 8)) * CL;
   const long pass = std::min(per_pass, (N + CL - 1) / CL * CL);
   const bool same = bra == ket;
-  DevMem Tb, Tk, G, dg, dG, slots, ditems, dunits, dtiles;
+  DevMem Tb, Tk, G, dg, dG;
   Tb.reserve((size_t)rows * pass * 8);
   if (!same) Tk.reserve((size_t)rows * pass * 8);
   const double* TK = same ? Tb.as<double>() : Tk.as<double>();
   G.reserve((size_t)rows * rows * 8);
-  // output tiles of the block kernel: strips of 96 rows and 64 columns, the last
-  // of each rounded up to a multiple of 16
-  struct Tile {
-    int m0, n0, tm, tn;
-  };
-  std::vector<Tile> tl;
-  for (int m0 = 0; m0 < rows; m0 += 96)
-    for (int n0 = 0; n0 < rows; n0 += 64)
-      tl.push_back({m0, n0, std::min(96, (rows - m0 + 15) / 16 * 16), std::min(64, (rows - n0 + 15) / 16 * 16)});
-  const long nt = (long)tl.size();
   for (long d0 = 0; d0 < N; d0 += pass) {
     const long dend = std::min(N, d0 + pass), nch = (dend - d0 + CL - 1) / CL;
     launch_ci_excite(bra, NA, NB, n2, ta.as<int>(), tb.as<int>(), Tb.as<double>(), CL, d0, dend, st);
     if (!same) launch_ci_excite(ket, NA, NB, n2, ta.as<int>(), tb.as<int>(), Tk.as<double>(), CL, d0, dend, st);
-    std::vector<GemmItem> items;
-    for (long g = 0; g < nch; ++g) {
-      const int K = (int)std::min(CL, dend - d0 - g * CL);
-      DMRG_REQUIRE(buffer_reach_ok(GEMM_NT, rows, rows, K, (int)CL, (int)CL, 8, 8), ST_EINVAL, "determinant chunk beyond the block kernel reach");
-      items.push_back({Tb.as<double>() + g * rows * CL, TK + g * rows * CL, (int)CL, (int)CL, K, 0, 1.0});
-    }
-    // about 2048 workgroups: the items split into ng contiguous groups per tile
-    const long ng = std::max<long>(1, std::min<long>(nch, 2048 / nt));
-    std::vector<SplitTile> tiles;
-    std::vector<GemmUnit> units;
-    long so = 0;
-    for (const Tile& t : tl) {
-      tiles.push_back({G.p, so, rows, rows, rows, t.m0, t.n0, (int)ng, t.tm, t.tn, d0 > 0 ? 1 : 0, 0});
-      so += ng * t.tm * t.tn;
-    }
-    slots.reserve((size_t)so * 8);
-    for (long gi = 0; gi < ng; ++gi) {
-      const int ib = (int)(nch * gi / ng), ie = (int)(nch * (gi + 1) / ng);
-      for (long t = 0; t < nt; ++t) {
-        const SplitTile& s = tiles[t];
-        units.push_back({slots.as<double>() + s.s0 + gi * s.tm * s.tn, s.tn, rows, rows, s.m0, s.n0, ib, ie, 2,
-                         8 * (s.tm / 16) + s.tn / 16});
-      }
-    }
-    upload(ditems, items, st);
-    upload(dunits, units, st);
-    upload(dtiles, tiles, st);
-    launch_gemm_wg(PREC_F64, 5, dunits.as<GemmUnit>(), (int)units.size(), ditems.as<GemmItem>(), st);
-    launch_splitk_reduce(dtiles.as<SplitTile>(), (int)nt, slots.as<double>(), st);
-    hip_check(hipStreamSynchronize(st), "rdm pass");
+    std::vector<int> K;
+    for (long g = 0; g < nch; ++g) K.push_back((int)std::min(CL, dend - d0 - g * CL));
+    splitk_nt(Tb.as<double>(), rows * CL, TK, rows * CL, CL, rows, rows, K, G.as<double>(), d0 > 0, st);
   }
   dg.reserve((size_t)n2 * 8);
   dG.reserve((size_t)n2 * n2 * 8);
