@@ -545,6 +545,8 @@ def main():
     ap.add_argument("--no-config5", action="store_true", help="skip the CAS(24,24) M=2048 comparison")
     ap.add_argument("--no-next", action="store_true",
                     help="skip the excited-state, determinant-space and stationarity timings")
+    ap.add_argument("--rows-only", action="store_true",
+                    help="run only those timings and print them as one JSON line (for profiling)")
     ap.add_argument("--diff-form", action="store_true",
                     help="also run the differentiation-form configuration (CAS(16,16), M=512, 2 states)")
     args = ap.parse_args()
@@ -557,6 +559,9 @@ def main():
     import paper_2609_09990_amd as pk
     import synth
 
+    if args.rows_only:
+        print(json.dumps({"next_rows": next_rows(pk, torch)}), flush=True)
+        return
     h, B, e0 = synth.make_hamiltonian(N_ORB, N_CHOL, SEED)
     prob = pk.Problem(h, B, N_ORB // 2, N_ORB // 2, e0)
     sol = pk.Solver(prob, M=M, tol=1e-8, precision=args.precision)

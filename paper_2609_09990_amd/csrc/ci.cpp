@@ -275,9 +275,9 @@ void ci_rdm3(int n, int na, int nb, hipStream_t st, const double* bra, const dou
   for (long d0 = 0; d0 < N; d0 += pass) {
     const long dend = std::min(N, d0 + pass), nch = (dend - d0 + CL - 1) / CL;
     launch_ci_excite(bra, NA, NB, n2, ta.as<int>(), tb.as<int>(), T1.as<double>(), CL, d0, dend, st);
-    for (int x = 0; x < n2; ++x)  // chunk g of E_rs (E_x ket) at T2 + g nbr CL + x rows CL
-      launch_ci_excite(Tk.as<double>() + (long)x * N, NA, NB, n2, ta.as<int>(), tb.as<int>(),
-                       T2.as<double>() + (long)x * rows * CL, CL, d0, dend, st, (long)nbr * CL);
+    // chunk g of E_rs (E_x ket) at T2 + g nbr CL + x rows CL, every x in one launch
+    launch_ci_excite(Tk.as<double>(), NA, NB, n2, ta.as<int>(), tb.as<int>(), T2.as<double>(), CL, d0, dend, st,
+                     (long)nbr * CL, n2, N, (long)rows * CL);
     std::vector<int> K;
     for (long g = 0; g < nch; ++g) K.push_back((int)std::min(CL, dend - d0 - g * CL));
     splitk_nt(T1.as<double>(), rows * CL, T2.as<double>(), (long)nbr * CL, CL, rows, nbr, K, G.as<double>(), d0 > 0,

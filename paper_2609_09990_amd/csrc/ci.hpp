@@ -40,9 +40,11 @@ void launch_ci_scatter(const double* amp, const CiSector* secs, int n_secs, cons
 // T[(g * rows + x) * cl + j] = (E_rs c)[d] for x = r n + s < n2 and c[d] for
 // x = n2 (rows = n2 + 1), d = d0 + g cl + j.  ta[x * na + J] (tb likewise) is
 // +-(I + 1) when E_rs |I> = +-|J> within one spin's strings, 0 when no I.
-// gstride: elements between consecutive chunks (<= 0: (n2 + 1) cl).
+// gstride: elements between consecutive chunks (<= 0: (n2 + 1) cl).  nvec source
+// vectors c + v cstride in one launch, written from T + v vstride.
 void launch_ci_excite(const double* c, long na, long nb, int n2, const int* ta, const int* tb, double* T, long cl,
-                      long d0, long dend, hipStream_t s, long gstride = 0);
+                      long d0, long dend, hipStream_t s, long gstride = 0, int nvec = 1, long cstride = 0,
+                      long vstride = 0);
 // out[d] = scale * sum_{x < n2} (E_x U_x)[d] over the rows U_x = U + x ldu.
 void launch_ci_apply_sum(const double* U, long ldu, long na, long nb, int n2, const int* ta, const int* tb,
                          double scale, double* out, long ndet, hipStream_t s);

@@ -29,15 +29,17 @@ __global__ void ci_scatter_kernel(const double* __restrict__ amp, const CiSector
   }
 }
 
-// blockIdx.y: row x of the copies, blockIdx.z: chunk g; threads over the chunk.
-// Consecutive threads take consecutive beta strings of one alpha string, so the
-// alpha-excitation reads are row gathers of c and the beta ones stay in a row.
-__global__ void ci_excite_kernel(const double* __restrict__ c, long na, long nb, int n2,
+// blockIdx.y: row x of the copies, blockIdx.z: (source vector v, chunk g) as
+// v nch + g; threads over the chunk.  Consecutive threads take consecutive beta
+// strings of one alpha string, so the alpha-excitation reads are row gathers of
+// c and the beta ones stay in a row.
+__global__ void ci_excite_kernel(const double* __restrict__ c0, long cstride, long na, long nb, int n2,
                                  const int* __restrict__ ta, const int* __restrict__ tb, double* __restrict__ T,
-                                 long cl, long gstride, long d0, long dend) {
+                                 long vstride, long nch, long cl, long gstride, long d0, long dend) {
   const int x = blockIdx.y;
-  const long g = blockIdx.z;
-  double* out = T + g * gstride + (long)x * cl;
+  const long v = blockIdx.z / nch, g = blockIdx.z - v * nch;
+  const double* __restrict__ c = c0 + v * cstride;
+  double* out = T + v * vstride + g * gstride + (long)x * cl;
   for (long j = (long)blockIdx.x * blockDim.x + threadIdx.x; j < cl; j += (long)gridDim.x * blockDim.x) {
     const long d = d0 + g * cl + j;
     if (d >= dend) break;
@@ -156,12 +158,12 @@ void launch_ci_scatter(const double* amp, const CiSector* secs, int n_secs, cons
 }
 
 void launch_ci_excite(const double* c, long na, long nb, int n2, const int* ta, const int* tb, double* T, long cl,
-                      long d0, long dend, hipStream_t s, long gstride) {
+                      long d0, long dend, hipStream_t s, long gstride, int nvec, long cstride, long vstride) {
   const long nch = (dend - d0 + cl - 1) / cl;
-  if (nch <= 0) return;
+  if (nch <= 0 || nvec <= 0) return;
   if (gstride <= 0) gstride = (long)(n2 + 1) * cl;
-  ci_excite_kernel<<<dim3(grid_cap(cl, 64), n2 + 1, (unsigned)nch), 256, 0, s>>>(c, na, nb, n2, ta, tb, T, cl,
-                                                                                 gstride, d0, dend);
+  ci_excite_kernel<<<dim3(grid_cap(cl, 64), n2 + 1, (unsigned)(nch * nvec)), 256, 0, s>>>(
+      c, cstride, na, nb, n2, ta, tb, T, vstride, nch, cl, gstride, d0, dend);
 }
 
 // out[d] = scale * sum_{x < n2} (E_x U_x)[d], U_x the rows of U (row-major, ldu).
