@@ -1326,130 +1326,164 @@ __global__ void add_squares_kernel(double* __restrict__ d, const double* __restr
 }
 
 // Symmetric eigensolver for k <= 64 in one workgroup: cyclic Jacobi with the
-// round-robin (circle) pairing, so each round rotates k/2 disjoint pairs in parallel.
+// round-robin (circle) pairing, so each round rotates the n/2 disjoint pairs
+// (p, q) together (n = k rounded up to even; a pair holding the padding index
+// is not rotated).  A pair is rotated when its coupling is significant against
+// its diagonal entries.  A round maps each 2 x 2 block of A (rows of pair a,
+// columns of pair b) to R_a^T A_ab R_b and each block of V to V_ab R_b; every
+// thread derives the angles of its blocks' two pairs from the round's input A
+// and writes the other copy of A and V, so a round has one barrier.  Per
+// element this is the arithmetic of rotating all rows, then all columns.  The
+// iteration ends when no pair is significant (a sweep would rotate nothing) or
+// the off-diagonal part is at the rounding level.
+__device__ inline void jacobi_pair(int round, int t, int n, int& p, int& q) {
+  if (t == 0) {
+    p = round % (n - 1);
+    q = n - 1;
+  } else {
+    p = (round + t) % (n - 1);
+    q = (round - t + (n - 1)) % (n - 1);
+  }
+  if (p > q) {
+    const int x = p;
+    p = q;
+    q = x;
+  }
+}
+__device__ inline bool jacobi_significant(double apq, double app, double aqq) {
+  return fabs(apq) > 1e-300 && fabs(apq) > 1e-15 * sqrt(fabs(app * aqq));
+}
+// rotation of pair (p, q), p < q < k: c = 1, s = 0 when the coupling is not significant
+__device__ inline void jacobi_angle(const double (*A)[65], int p, int q, double& c, double& s) {
+  c = 1.0;
+  s = 0.0;
+  const double apq = A[p][q], app = A[p][p], aqq = A[q][q];
+  if (jacobi_significant(apq, app, aqq)) {
+    const double theta = (aqq - app) / (2.0 * apq);
+    const double tt = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+    c = 1.0 / sqrt(tt * tt + 1.0);
+    s = tt * c;
+  }
+}
+
 __global__ __launch_bounds__(256) void jacobi_eig_kernel(const double* __restrict__ G, int ldg, int k,
                                                          double* __restrict__ evals,
                                                          double* __restrict__ evecs) {
-  __shared__ double A[64][65];
-  __shared__ double V[64][65];
-  __shared__ double cs[32], sn[32];
-  __shared__ int P[32], Q[32];
-  __shared__ double red[256];
+  __shared__ double A[2][64][65];
+  __shared__ double V[2][64][65];
+  __shared__ double red[3][256];
   __shared__ int order[64];
-  __shared__ int rotated;
   const int t = threadIdx.x;
   for (int e = t; e < k * k; e += blockDim.x) {  // lower triangle holds the matrix
-    int i = e / k, j = e % k;
-    A[i][j] = i >= j ? G[(long)i * ldg + j] : G[(long)j * ldg + i];
-    V[i][j] = (i == j) ? 1.0 : 0.0;
+    const int i = e / k, j = e % k;
+    A[0][i][j] = i >= j ? G[(long)i * ldg + j] : G[(long)j * ldg + i];
+    V[0][i][j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
   const int n = k + (k & 1);
   const int half = n / 2;
+  int cur = 0;
   for (int sweep = 0; sweep < 40 && k > 1; ++sweep) {
-    double off = 0.0, dg = 0.0;
+    double off = 0.0, dg = 0.0, sig = 0.0;
     for (int e = t; e < k * k; e += blockDim.x) {
-      int i = e / k, j = e % k;
-      if (i != j) off += A[i][j] * A[i][j];
-      else dg += A[i][j] * A[i][j];
+      const int i = e / k, j = e % k;
+      const double a = A[cur][i][j];
+      if (i != j) off += a * a;
+      else dg += a * a;
+      if (i < j && jacobi_significant(a, A[cur][i][i], A[cur][j][j])) sig += 1.0;
     }
-    red[t] = off;
+    red[0][t] = off;
+    red[1][t] = dg;
+    red[2][t] = sig;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
-      if (t < s) red[t] += red[t + s];
+      if (t < s) {
+        red[0][t] += red[0][t + s];
+        red[1][t] += red[1][t + s];
+        red[2][t] += red[2][t + s];
+      }
       __syncthreads();
     }
-    double offsum = red[0];
-    __syncthreads();
-    red[t] = dg;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (t < s) red[t] += red[t + s];
-      __syncthreads();
-    }
-    double dgsum = red[0];
-    __syncthreads();
-    if (offsum <= 1e-32 * (dgsum > 1e-300 ? dgsum : 1e-300)) break;
-    if (t == 0) rotated = 0;
-    __syncthreads();
+    const double offsum = red[0][0], dgsum = red[1][0], nsig = red[2][0];
+    __syncthreads();  // red is written again by the next sweep's check
+    if (nsig == 0.0 || offsum <= 1e-32 * (dgsum > 1e-300 ? dgsum : 1e-300)) break;  // uniform
     for (int round = 0; round < n - 1; ++round) {
-      if (t < half) {
-        int p, q;
-        if (t == 0) {
-          p = round % (n - 1);
-          q = n - 1;
-        } else {
-          p = (round + t) % (n - 1);
-          q = (round - t + (n - 1)) % (n - 1);
+      const double(*Ai)[65] = A[cur];
+      const double(*Vi)[65] = V[cur];
+      double(*Ao)[65] = A[cur ^ 1];
+      double(*Vo)[65] = V[cur ^ 1];
+      for (int e = t; e < half * half; e += blockDim.x) {
+        const int a = e / half, b = e % half;
+        int pa, qa, pb, qb;
+        jacobi_pair(round, a, n, pa, qa);
+        jacobi_pair(round, b, n, pb, qb);
+        const bool va = qa < k, vb = qb < k;  // false: the pair holds the padding index
+        double ca = 1.0, sa = 0.0, cb = 1.0, sb = 0.0;
+        if (va) jacobi_angle(Ai, pa, qa, ca, sa);
+        if (vb) jacobi_angle(Ai, pb, qb, cb, sb);
+        double x00 = Ai[pa][pb], x01 = vb ? Ai[pa][qb] : 0.0;
+        double x10 = va ? Ai[qa][pb] : 0.0, x11 = (va && vb) ? Ai[qa][qb] : 0.0;
+        double w00 = Vi[pa][pb], w01 = vb ? Vi[pa][qb] : 0.0;
+        double w10 = va ? Vi[qa][pb] : 0.0, w11 = (va && vb) ? Vi[qa][qb] : 0.0;
+        if (va) {  // rows p_a, q_a
+          const double y00 = ca * x00 - sa * x10, y10 = sa * x00 + ca * x10;
+          const double y01 = ca * x01 - sa * x11, y11 = sa * x01 + ca * x11;
+          x00 = y00;
+          x10 = y10;
+          x01 = y01;
+          x11 = y11;
         }
-        if (p > q) {
-          int tmp = p;
-          p = q;
-          q = tmp;
+        if (vb) {  // columns p_b, q_b of A and of V
+          const double y00 = cb * x00 - sb * x01, y01 = sb * x00 + cb * x01;
+          const double y10 = cb * x10 - sb * x11, y11 = sb * x10 + cb * x11;
+          x00 = y00;
+          x01 = y01;
+          x10 = y10;
+          x11 = y11;
+          const double z00 = cb * w00 - sb * w01, z01 = sb * w00 + cb * w01;
+          const double z10 = cb * w10 - sb * w11, z11 = sb * w10 + cb * w11;
+          w00 = z00;
+          w01 = z01;
+          w10 = z10;
+          w11 = z11;
         }
-        double c = 1.0, s = 0.0;
-        if (q < k) {
-          // rotate only pairs whose coupling is significant against their diagonal
-          // entries; a sweep without rotations ends the iteration (the off-diagonal
-          // part is then at the rounding level)
-          double apq = A[p][q];
-          if (fabs(apq) > 1e-300 && fabs(apq) > 1e-15 * sqrt(fabs(A[p][p] * A[q][q]))) {
-            double theta = (A[q][q] - A[p][p]) / (2.0 * apq);
-            double tt = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-            c = 1.0 / sqrt(tt * tt + 1.0);
-            s = tt * c;
-            rotated = 1;
-          }
+        Ao[pa][pb] = x00;
+        Vo[pa][pb] = w00;
+        if (vb) {
+          Ao[pa][qb] = x01;
+          Vo[pa][qb] = w01;
         }
-        P[t] = p;
-        Q[t] = q;
-        cs[t] = c;
-        sn[t] = s;
+        if (va) {
+          Ao[qa][pb] = x10;
+          Vo[qa][pb] = w10;
+        }
+        if (va && vb) {
+          Ao[qa][qb] = x11;
+          Vo[qa][qb] = w11;
+        }
       }
       __syncthreads();
-      for (int e = t; e < half * k; e += blockDim.x) {  // rows
-        int pr = e / k, j = e % k;
-        int p = P[pr], q = Q[pr];
-        if (q >= k) continue;
-        double c = cs[pr], s = sn[pr];
-        double ap = A[p][j], aq = A[q][j];
-        A[p][j] = c * ap - s * aq;
-        A[q][j] = s * ap + c * aq;
-      }
-      __syncthreads();
-      for (int e = t; e < half * k; e += blockDim.x) {  // columns, and V
-        int pr = e / k, i = e % k;
-        int p = P[pr], q = Q[pr];
-        if (q >= k) continue;
-        double c = cs[pr], s = sn[pr];
-        double ap = A[i][p], aq = A[i][q];
-        A[i][p] = c * ap - s * aq;
-        A[i][q] = s * ap + c * aq;
-        double vp = V[i][p], vq = V[i][q];
-        V[i][p] = c * vp - s * vq;
-        V[i][q] = s * vp + c * vq;
-      }
-      __syncthreads();
+      cur ^= 1;
     }
-    if (!rotated) break;  // uniform: read after the last barrier of the sweep
-    __syncthreads();
   }
-  if (t == 0) {
-    for (int i = 0; i < k; ++i) order[i] = i;
-    for (int i = 0; i < k; ++i)
-      for (int j = i + 1; j < k; ++j)
-        if (A[order[j]][order[j]] < A[order[i]][order[i]]) {
-          int tmp = order[i];
-          order[i] = order[j];
-          order[j] = tmp;
-        }
+  // ascending order of the eigenvalues, equal ones by index (a NaN counts as
+  // +inf, so the ranks are a permutation): each thread ranks one value against
+  // all k (independent LDS reads instead of a serial sort on one thread)
+  for (int j = t; j < k; j += blockDim.x) {
+    const double dj = A[cur][j][j], kj = dj == dj ? dj : INFINITY;
+    int rank = 0;
+    for (int i = 0; i < k; ++i) {
+      const double di = A[cur][i][i], ki = di == di ? di : INFINITY;
+      rank += (ki < kj || (ki == kj && i < j)) ? 1 : 0;
+    }
+    order[rank] = j;
   }
   __syncthreads();
   for (int e = t; e < k * k; e += blockDim.x) {
     int j = e / k, i = e % k;  // eigenvector j, component i
-    evecs[(long)j * k + i] = V[i][order[j]];
+    evecs[(long)j * k + i] = V[cur][i][order[j]];
   }
-  for (int j = t; j < k; j += blockDim.x) evals[j] = A[order[j]][order[j]];
+  for (int j = t; j < k; j += blockDim.x) evals[j] = A[cur][order[j]][order[j]];
 }
 
 // Subspace rotation in place: V[:, i] = sum_j V[:, j] Y[i * k + j] for i < keep
@@ -1721,7 +1755,8 @@ void launch_subspace_rotate(double* V, long ldv, int k, const double* Y, int kee
 
 void launch_jacobi_eig(const double* G, int ldg, int k, double* evals, double* evecs,
                        hipStream_t s) {
-  jacobi_eig_kernel<<<1, 256, 0, s>>>(G, ldg, k, evals, evecs);
+  if (k > 64) throw std::runtime_error("subspace eigensolver: k <= 64");
+  if (k > 0) jacobi_eig_kernel<<<1, 256, 0, s>>>(G, ldg, k, evals, evecs);
 }
 
 void launch_f64_to_f32(const double* x, float* y, long n, hipStream_t s) {

@@ -1029,14 +1029,18 @@ int Solver::davidson(int k, std::vector<DevMem>& guess, std::vector<double>& eva
   auto append = [&](const double* src, int sprec, double min_ratio = 1e-20) -> bool {
     if (src != t) launch_copy(t, src, n, st);
     launch_dots(t, n, 1, t, n, part, sc + 1, st);
-    double n0 = host_scalar(sc + 1);
-    if (!(n0 > 0) || !std::isfinite(n0)) return false;
     for (int pass = 0; pass < 2 && kcur > 0; ++pass) {
       launch_dots(V, n, kcur, t, n, part, sc + 8, st);
       launch_gemv(V, n, kcur, sc + 8, -1.0, t, 1.0, n, st);
     }
     launch_dots(t, n, 1, t, n, part, sc, st);
-    double nn = host_scalar(sc);
+    // both squared norms in one read (t is scratch: a rejected candidate leaves
+    // V and AV untouched)
+    double nq[2];
+    hip_check(hipMemcpyAsync(nq, sc, 16, hipMemcpyDeviceToHost, st), "norms");
+    hip_check(hipStreamSynchronize(st), "norms");
+    const double nn = nq[0], n0 = nq[1];
+    if (!(n0 > 0) || !std::isfinite(n0)) return false;
     if (!(nn > min_ratio * n0) || !std::isfinite(nn)) return false;
     launch_scale_by_norm(t, n, sc, st);
     launch_copy(V + (long)kcur * n, t, n, st);
