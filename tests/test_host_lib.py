@@ -127,3 +127,30 @@ def test_fiedler_order_matches_oracle():
         I[perm[k], perm[k + 1]] = I[perm[k + 1], perm[k]] = 1.0
     order, _ = pk.fiedler_order(I)
     assert list(order) in (list(perm), list(perm[::-1]))
+
+
+def test_ci_dimensions_and_length_refusals():
+    """The CI matrix shape is (C(n, n_alpha), C(n, n_beta)), and every call on
+    device CI vectors refuses a length other than their product with
+    DMRG_EINVAL before any device work (the vector pointers below are never
+    dereferenced: the host check comes first)."""
+    from math import comb
+    pk = _lib()
+    h, B, _ = synth.make_hamiltonian(6, 3, 0)
+    prob = pk.Problem(h, B, 4, 2)
+    assert prob.ci_dims() == (comb(6, 4), comb(6, 2))
+    n = comb(6, 4) * comb(6, 2)
+    fake = ctypes.c_void_p(1 << 20)
+    host = np.zeros(6 ** 6)
+    hp = host.ctypes.data_as(ctypes.c_void_p)
+    calls = {
+        "dmrg_ci_rdm12": lambda m: pk.dmrg_ci_rdm12(prob.h, m, fake, fake, hp, hp, hp, None),
+        "dmrg_ci_apply_v": lambda m: pk.dmrg_ci_apply_v(prob.h, m, fake, ctypes.c_void_p(2 << 20), None),
+        "dmrg_ci_rdm3": lambda m: pk.dmrg_ci_rdm3(prob.h, m, fake, fake, hp, None),
+        "dmrg_orbital_rdm2": lambda m: pk.dmrg_orbital_rdm2(prob.h, m, fake, hp, None),
+        "dmrg_mutual_information": lambda m: pk.dmrg_mutual_information(prob.h, m, fake, hp, hp, None),
+    }
+    for name, call in calls.items():
+        for m in (0, n - 1, n + 1, -n):
+            assert call(m) == -1, (name, m)
+            assert b"CI dimension" in pk.dmrg_last_error(), name
