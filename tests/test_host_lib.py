@@ -154,3 +154,14 @@ def test_ci_dimensions_and_length_refusals():
         for m in (0, n - 1, n + 1, -n):
             assert call(m) == -1, (name, m)
             assert b"CI dimension" in pk.dmrg_last_error(), name
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: asked for several it exits with status 2 and
+    says why, before touching any device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
